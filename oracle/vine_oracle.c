@@ -1,0 +1,1107 @@
+/*
+ * vine_oracle.c -- plain FP64 CPU oracle for the quasi-static growth step of a
+ * soft growing ("vine") robot, arXiv 2509.15180 ("Parallel Simulation of Contact
+ * and Actuation for Soft Growing Robots").
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark load this library.  It shares no code, header, table or
+ * helper with the HIP path, and it is written for clarity, not speed: dense
+ * Hessians by finite differences, all link/obstacle pairs, adaptive quadrature.
+ *
+ * What it computes, in the paper's order (section / equation):
+ *   Sec. 3.1, Eq. 1a-d   sPAM force-strain law; G(eps) = F_t / P_act for an actuator
+ *                        unit of length l0 equal to the link length.
+ *   Sec. 3.2, Eq. 2a-b   wrinkling-based restoring moment M(theta).
+ *   Sec. 3.3, Eq. 3a-b   strain eps = (2R + R_act) theta / l and the net joint moment.
+ *   Sec. 4.1, Eq. 4      the next state minimises a cost of bending, growth and contact;
+ *                        read as the potential energy
+ *                          Pi(theta) = sum_j E_j(theta_j) + k_c/2 sum_{links,obstacles} pen^2,
+ *                        E_j the integral of the joint moment, so dPi/dtheta = 0 is the
+ *                        joint moment balance under penalty contact.
+ *   Sec. 4.1, Alg. 1     one growth step: append a link and descend to that equilibrium.
+ *                        The fixed 50 gradient steps are replaced by a converged damped
+ *                        Newton descent (scaled residual <= tol).
+ * Readings of points the paper leaves open are listed in the design notes
+ * (parameter choices, contact geometry, growth sub-steps, solver rules).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define VO_PI 3.14159265358979323846
+
+#include <stdio.h>
+int vo_verbose = 0; /* per-iteration trace of chain_solve on stderr (debugging aid) */
+
+/* ------------------------------------------------------------------------- */
+/* parameters                                                                */
+
+typedef struct {
+  double Rc, Ract, acorr;   /* sPAM constriction radius, actuator radius, correction a (Sec. 3.1) */
+  double epsc;              /* critical wrinkling strain (Sec. 3.2) */
+  double kc;                /* penalty stiffness, N/m (contact term of Eq. 4) */
+  double tol;               /* convergence: max_j |r_j| / M_max <= tol */
+  int max_iter;             /* Newton iterations per solve */
+  int substeps;             /* growth sub-steps per appended link */
+  double fd_h;              /* finite-difference step for the Hessian */
+  double c1;                /* Armijo constant */
+  double c_mu;              /* damping per unit residual: mu = c_mu max_j |r_j| (1/rad) */
+  double step_max;          /* cap on max_j |step_j| (rad) */
+  int cheb_n;               /* Chebyshev degree of the G fit */
+} vo_prm;
+
+static void prm_from(const double* p, vo_prm* P) {
+  P->Rc = p[0];
+  P->Ract = p[1];
+  P->acorr = p[2];
+  P->epsc = p[3];
+  P->kc = p[4];
+  P->tol = p[5];
+  P->max_iter = (int)p[6];
+  P->substeps = (int)p[7];
+  P->fd_h = p[8];
+  P->c1 = p[9];
+  P->c_mu = p[10];
+  P->cheb_n = (int)p[11];
+  P->step_max = p[12];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Carlson's symmetric elliptic integrals (B. C. Carlson, "Numerical computation
+ * of real or complex elliptic integrals", Numer. Algorithms 10, 1995):
+ * duplication until the arguments agree to 1e-3, then the truncated series. */
+
+double vo_rf(double x, double y, double z) {
+  for (int k = 0; k < 200; ++k) {
+    double mu = (x + y + z) / 3.0;
+    double X = 1.0 - x / mu, Y = 1.0 - y / mu, Z = 1.0 - z / mu;
+    double e = fmax(fabs(X), fmax(fabs(Y), fabs(Z)));
+    if (e < 1e-3) {
+      double E2 = X * Y - Z * Z, E3 = X * Y * Z;
+      return (1.0 - E2 / 10.0 + E3 / 14.0 + E2 * E2 / 24.0 - 3.0 * E2 * E3 / 44.0) / sqrt(mu);
+    }
+    double sx = sqrt(x), sy = sqrt(y), sz = sqrt(z);
+    double lam = sx * sy + sy * sz + sz * sx;
+    x = 0.25 * (x + lam);
+    y = 0.25 * (y + lam);
+    z = 0.25 * (z + lam);
+  }
+  return NAN;
+}
+
+double vo_rd(double x, double y, double z) {
+  double sum = 0.0, fac = 1.0;
+  for (int k = 0; k < 200; ++k) {
+    double mu = (x + y + 3.0 * z) / 5.0;
+    double X = 1.0 - x / mu, Y = 1.0 - y / mu, Z = 1.0 - z / mu;
+    double e = fmax(fabs(X), fmax(fabs(Y), fabs(Z)));
+    if (e < 1e-3) {
+      double ea = X * Y, eb = Z * Z;
+      double E2 = ea - 6.0 * eb;
+      double E3 = (3.0 * ea - 8.0 * eb) * Z;
+      double E4 = 3.0 * (ea - eb) * eb;
+      double E5 = ea * Z * eb;
+      double s = 1.0 - 3.0 * E2 / 14.0 + E3 / 6.0 + 9.0 * E2 * E2 / 88.0 - 3.0 * E4 / 22.0 -
+                 9.0 * E2 * E3 / 52.0 + 3.0 * E5 / 26.0;
+      return 3.0 * sum + fac * s / (mu * sqrt(mu));
+    }
+    double sx = sqrt(x), sy = sqrt(y), sz = sqrt(z);
+    double lam = sx * sy + sy * sz + sz * sx;
+    sum += fac / (sz * (z + lam));
+    fac *= 0.25;
+    x = 0.25 * (x + lam);
+    y = 0.25 * (y + lam);
+    z = 0.25 * (z + lam);
+  }
+  return NAN;
+}
+
+/* Incomplete elliptic integrals in the parameter convention (m = k^2),
+ * 0 <= phi <= pi/2: F(phi|m) = sin(phi) R_F(c^2, 1 - m s^2, 1),
+ * E(phi|m) = F - (m/3) s^3 R_D(c^2, 1 - m s^2, 1). */
+double vo_ellf(double phi, double m) {
+  double s = sin(phi), c = cos(phi);
+  return s * vo_rf(c * c, 1.0 - m * s * s, 1.0);
+}
+
+double vo_elle(double phi, double m) {
+  double s = sin(phi), c = cos(phi);
+  double d = 1.0 - m * s * s;
+  return s * vo_rf(c * c, d, 1.0) - (m / 3.0) * s * s * s * vo_rd(c * c, d, 1.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* sPAM model, Sec. 3.1 (Eq. 1a-d).  For a contraction parameter m in (0, 1/2]:
+ *  unsaturated: l_a = l0 and phi in (0, phi_Rc] is the smallest root of Eq. 1b,
+ *      F(phi|m)/(sqrt(m) cos phi) = (l_a/R_c)(1 + a/(2 m cos^2 phi));
+ *  saturated (no such root): phi = phi_Rc (Eq. 1c) and Eq. 1b gives l_a;
+ *  then Eq. 1a gives the strain, eps = (l_a - 2 R_c (E - F/2)/(sqrt(m) cos phi)) / l0,
+ *  and Eq. 1d the force per unit pressure, G = pi R_c^2 (1 - 2m) / (2 m cos^2 phi). */
+
+static double eq1b_resid(double phi, double m, double l0, const vo_prm* P) {
+  /* Eq. 1b multiplied by cos^2(phi) so that both sides stay finite. */
+  double c = cos(phi);
+  return vo_ellf(phi, m) * c / sqrt(m) - (l0 / P->Rc) * (c * c + P->acorr / (2.0 * m));
+}
+
+int vo_spam_state(double m, double l0, const double* prm, double* eps, double* G, double* phi_out) {
+  vo_prm P;
+  prm_from(prm, &P);
+  double phiRc = acos(P.Rc / P.Ract);
+  const int NS = 512;
+  double phi = -1.0, la = l0;
+  int sat = 0;
+  double a = 0.0, ga = eq1b_resid(1e-12, m, l0, &P);
+  for (int k = 1; k <= NS; ++k) {
+    double b = phiRc * (double)k / NS;
+    double gb = eq1b_resid(b, m, l0, &P);
+    if (ga < 0.0 && gb >= 0.0) {
+      for (int it = 0; it < 200 && b - a > 1e-16; ++it) {
+        double c = 0.5 * (a + b);
+        if (eq1b_resid(c, m, l0, &P) < 0.0) a = c; else b = c;
+      }
+      phi = 0.5 * (a + b);
+      break;
+    }
+    a = b;
+    ga = gb;
+  }
+  if (phi < 0.0) {
+    sat = 1;
+    phi = phiRc;
+    double c = cos(phi);
+    la = P.Rc * vo_ellf(phi, m) / (sqrt(m) * c * (1.0 + P.acorr / (2.0 * m * c * c)));
+  }
+  double c = cos(phi);
+  double F = vo_ellf(phi, m), E = vo_elle(phi, m);
+  *eps = (la - 2.0 * P.Rc * (E - 0.5 * F) / (sqrt(m) * c)) / l0;
+  *G = VO_PI * P.Rc * P.Rc * (1.0 - 2.0 * m) / (2.0 * m * c * c);
+  if (phi_out) *phi_out = phi;
+  return sat;
+}
+
+static double spam_eps(double m, double l0, const double* prm) {
+  double e, G;
+  vo_spam_state(m, l0, prm, &e, &G, NULL);
+  return e;
+}
+
+/* m0: contraction parameter of zero strain; eps(m) increases on [m0, 1/2]. */
+static double spam_m0(double l0, const double* prm) {
+  double a = 1e-6, b = 0.5;
+  for (int it = 0; it < 200 && b - a > 1e-17; ++it) {
+    double c = 0.5 * (a + b);
+    if (spam_eps(c, l0, prm) < 0.0) a = c; else b = c;
+  }
+  return 0.5 * (a + b);
+}
+
+/* Exact G(eps) for 0 <= eps <= eps_max by bisection on m; 0 beyond eps_max (slack). */
+static double spam_G_exact_mm(double eps, double l0, const double* prm, double m0, double emax) {
+  if (eps >= emax) return 0.0;
+  double a = m0, b = 0.5;
+  if (eps > 0.0) {
+    for (int it = 0; it < 200 && b - a > 1e-17; ++it) {
+      double c = 0.5 * (a + b);
+      if (spam_eps(c, l0, prm) < eps) a = c; else b = c;
+    }
+  } else {
+    b = m0;
+  }
+  double e, G;
+  vo_spam_state(eps > 0.0 ? 0.5 * (a + b) : m0, l0, prm, &e, &G, NULL);
+  return G;
+}
+
+double vo_spam_G_exact(double eps, double l0, const double* prm) {
+  return spam_G_exact_mm(eps, l0, prm, spam_m0(l0, prm), spam_eps(0.5, l0, prm));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chebyshev representation of G on [0, eps_max] (bulk evaluation).  G(eps) has a
+ * pole a little below eps = 0, so the degree is high (default 128). */
+
+#define VO_CHEB_MAX 256
+typedef struct {
+  double l0, emax, G0;
+  int N;
+  double c[VO_CHEB_MAX + 2];  /* G  = sum' c_j T_j(x), x = 2 eps/emax - 1 (c_0 halved) */
+  double d[VO_CHEB_MAX + 2];  /* dG/dx */
+  double q[VO_CHEB_MAX + 3];  /* integral in x from -1 */
+} vo_gfit;
+
+static double cheb_eval(const double* c, int N, double x) {
+  /* Clenshaw, c[0] already halved */
+  double b1 = 0.0, b2 = 0.0;
+  for (int j = N; j >= 1; --j) {
+    double t = 2.0 * x * b1 - b2 + c[j];
+    b2 = b1;
+    b1 = t;
+  }
+  return x * b1 - b2 + c[0];
+}
+
+static void gfit_build(vo_gfit* g, double l0, const double* prm, int N) {
+  if (N > VO_CHEB_MAX) N = VO_CHEB_MAX;
+  g->l0 = l0;
+  g->N = N;
+  g->emax = spam_eps(0.5, l0, prm);
+  double m0 = spam_m0(l0, prm);
+  double f[VO_CHEB_MAX + 1];
+  for (int k = 0; k <= N; ++k) {
+    double x = cos(VO_PI * (k + 0.5) / (N + 1));
+    f[k] = spam_G_exact_mm(0.5 * (x + 1.0) * g->emax, l0, prm, m0, g->emax);
+  }
+  for (int j = 0; j <= N; ++j) {
+    double s = 0.0;
+    for (int k = 0; k <= N; ++k) s += f[k] * cos(VO_PI * j * (k + 0.5) / (N + 1));
+    g->c[j] = 2.0 * s / (N + 1);
+  }
+  g->c[0] *= 0.5;
+  g->c[N + 1] = 0.0;
+  /* derivative series: a'_{j-1} = a'_{j+1} + 2 j a_j (full a_0 convention) */
+  double a[VO_CHEB_MAX + 3] = {0}, da[VO_CHEB_MAX + 3] = {0};
+  for (int j = 0; j <= N + 2; ++j) a[j] = (j <= N) ? g->c[j] : 0.0;
+  a[0] *= 2.0;
+  da[N + 1] = da[N + 2] = 0.0;
+  da[N] = 0.0;
+  for (int j = N; j >= 1; --j) da[j - 1] = da[j + 1] + 2.0 * j * a[j];
+  for (int j = 0; j <= N + 1; ++j) g->d[j] = da[j];
+  g->d[0] *= 0.5;
+  /* integral series: A_j = (a_{j-1} - a_{j+1}) / (2 j), constant fixed so that Q(-1) = 0 */
+  for (int j = 1; j <= N + 1; ++j) g->q[j] = (a[j - 1] - a[j + 1]) / (2.0 * j);
+  g->q[0] = 0.0;
+  g->q[N + 2] = 0.0;
+  double at_m1 = cheb_eval(g->q, N + 1, -1.0);
+  g->q[0] = -at_m1;
+  g->G0 = cheb_eval(g->c, N, -1.0);
+}
+
+/* process-wide cache of fits, keyed by l0 and the sPAM constants */
+#define VO_GCACHE 64
+static vo_gfit* gcache[VO_GCACHE];
+static double gkey[VO_GCACHE][5];
+static int gcount = 0;
+
+static const vo_gfit* gfit_get(double l0, const double* prm) {
+  const vo_gfit* out = NULL;
+#ifdef _OPENMP
+#pragma omp critical(vo_gfit_cache)
+#endif
+  {
+    for (int k = 0; k < gcount && !out; ++k)
+      if (gkey[k][0] == l0 && gkey[k][1] == prm[0] && gkey[k][2] == prm[1] &&
+          gkey[k][3] == prm[2] && gkey[k][4] == prm[11])
+        out = gcache[k];
+    if (!out) {
+      vo_gfit* g = (vo_gfit*)malloc(sizeof(vo_gfit));
+      gfit_build(g, l0, prm, (int)prm[11]);
+      if (gcount < VO_GCACHE) {
+        gcache[gcount] = g;
+        gkey[gcount][0] = l0;
+        gkey[gcount][1] = prm[0];
+        gkey[gcount][2] = prm[1];
+        gkey[gcount][3] = prm[2];
+        gkey[gcount][4] = prm[11];
+        ++gcount;
+      }
+      out = g;
+    }
+  }
+  return out;
+}
+
+/* G, dG/deps and int_0^eps G for 0 <= eps; slack (0, 0, const) beyond eps_max */
+static void gfit_eval(const vo_gfit* g, double eps, double* G, double* dG, double* IG) {
+  if (eps >= g->emax) {
+    if (G) *G = 0.0;
+    if (dG) *dG = 0.0;
+    if (IG) *IG = 0.5 * g->emax * cheb_eval(g->q, g->N + 1, 1.0);
+    return;
+  }
+  double x = 2.0 * eps / g->emax - 1.0;
+  if (G) *G = cheb_eval(g->c, g->N, x);
+  if (dG) *dG = cheb_eval(g->d, g->N - 1, x) * 2.0 / g->emax;
+  if (IG) *IG = 0.5 * g->emax * cheb_eval(g->q, g->N + 1, x);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Wrinkling-based restoring moment, Sec. 3.2 (Eq. 2a-b), as a fraction of
+ * M_max = pi P_vine R^3:  M = M_max f(gamma0),
+ *   f(g) = (sin 2g + 2 pi - 2 g) / (4 (sin g + (pi - g) cos g)),
+ *   gamma0 = acos(2 eps_c / sin(theta/2) - 1).
+ * Below wrinkling onset (theta < theta_on = 2 asin(eps_c)) Eq. 2b is undefined;
+ * the moment rises linearly from 0 to f(0) = 1/2 there.  |theta| is clamped at pi. */
+
+static double wr_f(double g) {
+  return (sin(2.0 * g) + 2.0 * VO_PI - 2.0 * g) / (4.0 * (sin(g) + (VO_PI - g) * cos(g)));
+}
+
+double vo_wr_h(double x, double epsc) {
+  double th_on = 2.0 * asin(epsc);
+  if (x <= th_on) return x / (2.0 * th_on);
+  if (x > VO_PI) x = VO_PI;
+  double arg = 2.0 * epsc / sin(0.5 * x) - 1.0;
+  if (arg > 1.0) arg = 1.0;
+  if (arg < -1.0) arg = -1.0;
+  return wr_f(acos(arg));
+}
+
+/* Gauss-Legendre nodes by Newton iteration on P_n (textbook construction). */
+#define VO_GL 20
+static double gl_x[VO_GL], gl_w[VO_GL];
+static int gl_ready = 0;
+
+static void gl_init(void) {
+  if (gl_ready) return;
+  int n = VO_GL;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(VO_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      double dz = p1 / pp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    gl_x[i] = z;
+    gl_w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+  gl_ready = 1;
+}
+
+static double gl_rule(double (*f)(double, double), double par, double a, double b) {
+  double h = 0.5 * (b - a), c = 0.5 * (a + b), s = 0.0;
+  for (int i = 0; i < VO_GL; ++i) s += gl_w[i] * f(c + h * gl_x[i], par);
+  return s * h;
+}
+
+static double adapt(double (*f)(double, double), double par, double a, double b, double whole,
+                    double tol, int depth) {
+  double m = 0.5 * (a + b);
+  double l = gl_rule(f, par, a, m), r = gl_rule(f, par, m, b);
+  /* stop at the tolerance or at the round-off level of the pieces */
+  if (depth > 30 || fabs(l + r - whole) <= fmax(tol, 1e-13 * (fabs(l) + fabs(r)))) return l + r;
+  return adapt(f, par, a, m, l, 0.5 * tol, depth + 1) + adapt(f, par, m, b, r, 0.5 * tol, depth + 1);
+}
+
+/* dh/dx for x >= 0 (one-sided from below at the onset, 0 beyond pi) */
+double vo_wr_dh(double x, double epsc) {
+  double th_on = 2.0 * asin(epsc);
+  if (x <= th_on) return 1.0 / (2.0 * th_on);
+  if (x >= VO_PI) return 0.0;
+  double s = sin(0.5 * x);
+  double u = 2.0 * epsc / s - 1.0;
+  if (u > 1.0) u = 1.0;
+  double g = acos(u);
+  double du = -epsc * cos(0.5 * x) / (s * s);
+  double one_m_u2 = 4.0 * epsc * (s - epsc) / (s * s); /* 1 - u^2 without cancellation */
+  double dg = -du / sqrt(one_m_u2);
+  double N = sin(2.0 * g) + 2.0 * VO_PI - 2.0 * g, dN = 2.0 * cos(2.0 * g) - 2.0;
+  double D = 4.0 * (sin(g) + (VO_PI - g) * cos(g)), dD = -4.0 * (VO_PI - g) * sin(g);
+  return (dN * D - N * dD) / (D * D) * dg;
+}
+
+static double wr_h_cb(double x, double epsc) { return vo_wr_h(x, epsc); }
+
+/* int_0^x h(t) dt for x >= 0 (energy of the body moment per M_max) */
+double vo_wr_int(double x, double epsc) {
+  gl_init();
+  double th_on = 2.0 * asin(epsc);
+  if (x <= th_on) return x * x / (4.0 * th_on);
+  double s = th_on / 4.0;
+  double hi = x < VO_PI ? x : VO_PI;
+  s += adapt(wr_h_cb, epsc, th_on, hi, gl_rule(wr_h_cb, epsc, th_on, hi), 1e-16, 0);
+  if (x > VO_PI) s += vo_wr_h(VO_PI, epsc) * (x - VO_PI);
+  return s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Contact geometry.  The body of link i (Sec. 4.1: rigid segments in contact with
+ * obstacles, Eq. 4's penetration term) is sampled by two disks of radius R, the
+ * tube radius, centred on the link axis at its midpoint and at its distal end.
+ * Each (disk, obstacle) pair contributes k_c/2 pen^2 with pen = max(0, -g) and
+ *   g = dist(centre, obstacle) - R,
+ * dist = |x - c| - rho for a circle and the signed distance to the rectangle
+ * (negative inside).  n = d(dist)/dx is the outward unit normal at the centre. */
+
+/* kappa: curvature of the distance field at x (its Hessian is kappa tau tau^T, tau the
+ * unit tangent); 1/|x - c| for a circle, 1/(distance to the corner) in a rectangle's
+ * corner region, 0 on its side regions and inside it. */
+double vo_dist_circle(double x, double y, const double* o, double* nx, double* ny, double* kappa) {
+  double vx = x - o[0], vy = y - o[1];
+  double d = sqrt(vx * vx + vy * vy);
+  if (d > 0.0) {
+    *nx = vx / d;
+    *ny = vy / d;
+    *kappa = 1.0 / d;
+  } else {
+    *nx = 1.0;
+    *ny = 0.0;
+    *kappa = 0.0;
+  }
+  return d - o[2];
+}
+
+/* rectangle centre o[0..1], half-extents o[2..3] */
+double vo_dist_box(double x, double y, const double* o, double* nx, double* ny, double* kappa) {
+  double sx = x >= o[0] ? 1.0 : -1.0, sy = y >= o[1] ? 1.0 : -1.0;
+  double dx = fabs(x - o[0]) - o[2], dy = fabs(y - o[1]) - o[3];
+  *kappa = 0.0;
+  if (dx > 0.0 || dy > 0.0) {
+    double ox = dx > 0.0 ? dx : 0.0, oy = dy > 0.0 ? dy : 0.0;
+    double d = sqrt(ox * ox + oy * oy);
+    *nx = sx * ox / d;
+    *ny = sy * oy / d;
+    if (dx > 0.0 && dy > 0.0) *kappa = 1.0 / d;
+    return d;
+  }
+  /* inside: distance to the nearest side, negative */
+  if (dx >= dy) {
+    *nx = sx;
+    *ny = 0.0;
+    return dx;
+  }
+  *nx = 0.0;
+  *ny = sy;
+  return dy;
+}
+
+/* ------------------------------------------------------------------------- */
+/* one chain */
+
+typedef struct {
+  const vo_prm* P;
+  const vo_gfit* G;
+  int n;                 /* links present */
+  double l, R, Pv, bx, by, bpsi;
+  double last_len;       /* length of the tip link (growth sub-steps) */
+  double arm, Mmax;
+  const double *Pp, *Pm; /* pressure-weighted sPAM coverage per joint, +/- side */
+  int K;
+  const int* kind;
+  const double* obs;
+} vo_chain;
+
+/* joint moment q_j(theta) (Eq. 3b with Eq. 2) and its energy E_j(theta) = int_0^theta q_j */
+static void joint_law(const vo_chain* c, int j, double th, double* q, double* E) {
+  const vo_prm* P = c->P;
+  double ath = fabs(th);
+  double Mb = (th >= 0.0 ? 1.0 : -1.0) * c->Mmax * vo_wr_h(ath, P->epsc);
+  double ep = th > 0.0 ? c->arm * th / c->l : 0.0;
+  double em = th < 0.0 ? -c->arm * th / c->l : 0.0;
+  double Gp, Gm, IGp, IGm;
+  gfit_eval(c->G, ep, &Gp, NULL, &IGp);
+  gfit_eval(c->G, em, &Gm, NULL, &IGm);
+  double pp = c->Pp[j], pm = c->Pm[j];
+  if (q) *q = Mb - c->arm * (pp * Gp - pm * Gm);
+  if (E) {
+    double Eb = c->Mmax * vo_wr_int(ath, P->epsc);
+    double G0 = c->G->G0;
+    double Ea = (th >= 0.0) ? (-c->l * pp * IGp + c->arm * pm * G0 * th)
+                            : (-c->arm * pp * G0 * th - c->l * pm * IGm);
+    *E = Eb + Ea;
+  }
+}
+
+typedef struct {
+  int i, k;
+  double lam, xx, xy, nx, ny, pen, kappa;
+} vo_contact;
+
+/* scratch for one chain: poses and unit link directions */
+typedef struct {
+  double *px, *py, *tx, *ty;
+} vo_pose;
+
+static void pose_alloc(vo_pose* w, int n) {
+  w->px = (double*)malloc(sizeof(double) * (size_t)(4 * n + 8));
+  w->py = w->px + n + 2;
+  w->tx = w->py + n + 2;
+  w->ty = w->tx + n + 2;
+}
+
+/* Poses (Sec. 4.1, minimal coordinates: heading of link i = base heading + sum_{j<=i}
+ * theta_j), residual r = dPi/dtheta (nullable), energy Pi (when want_E), and the
+ * contacts (nullable list, capacity cap; count in *ncl). */
+static double chain_eval(const vo_chain* c, const double* th, double* r, int want_E,
+                         vo_contact* cl, int cap, int* ncl, vo_pose* w) {
+  const vo_prm* P = c->P;
+  int n = c->n;
+  double *px = w->px, *py = w->py, *tx = w->tx, *ty = w->ty;
+  double phi = c->bpsi;
+  px[0] = c->bx;
+  py[0] = c->by;
+  double Pi = 0.0;
+  for (int i = 0; i < n; ++i) {
+    phi += th[i];
+    tx[i] = cos(phi);
+    ty[i] = sin(phi);
+    double L = (i == n - 1) ? c->last_len : c->l;
+    px[i + 1] = px[i] + L * tx[i];
+    py[i + 1] = py[i] + L * ty[i];
+  }
+  for (int j = 0; j < n; ++j) {
+    double q, E;
+    joint_law(c, j, th[j], r ? &q : NULL, want_E ? &E : NULL);
+    if (want_E) Pi += E;
+    if (r) r[j] = q;
+  }
+  int cnt = 0;
+  for (int i = 0; i < n; ++i) {
+    double L = (i == n - 1) ? c->last_len : c->l;
+    for (int h = 1; h <= 2; ++h) {        /* disks at s = L/2 and s = L */
+      double s = 0.5 * h * L;
+      double xx = px[i] + s * tx[i], xy = py[i] + s * ty[i];
+      for (int k = 0; k < c->K; ++k) {
+        double nx, ny, kap;
+        const double* o = c->obs + 4 * k;
+        double g = (c->kind[k] == 0 ? vo_dist_circle(xx, xy, o, &nx, &ny, &kap)
+                                     : vo_dist_box(xx, xy, o, &nx, &ny, &kap)) - c->R;
+        if (g < 0.0) {
+          double pen = -g, lam = P->kc * pen;
+          Pi += 0.5 * P->kc * pen * pen;
+          if (r) {
+            /* dPi/dtheta_j for every joint j <= i: -lam times the moment arm (x - p_j) x n */
+            for (int j = 0; j <= i; ++j) r[j] -= lam * ((xx - px[j]) * ny - (xy - py[j]) * nx);
+          }
+          if (cl && cnt < cap) {
+            vo_contact* e = &cl[cnt];
+            e->i = i;
+            e->k = k;
+            e->lam = lam;
+            e->xx = xx;
+            e->xy = xy;
+            e->nx = nx;
+            e->ny = ny;
+            e->pen = pen;
+            e->kappa = kap;
+          }
+          ++cnt;
+        }
+      }
+    }
+  }
+  if (ncl) *ncl = cnt;
+  return Pi;
+}
+
+/* dq_j/dtheta (one-sided conventions: below onset at |theta| = theta_on; at theta = 0 the
+ * mean of the two one-sided actuator slopes) */
+static double joint_dq(const vo_chain* c, int j, double th) {
+  const vo_prm* P = c->P;
+  double d = c->Mmax * vo_wr_dh(fabs(th), P->epsc);
+  double k = c->arm * c->arm / c->l;
+  double pp = c->Pp[j], pm = c->Pm[j];
+  if (th > 0.0) {
+    double dG;
+    gfit_eval(c->G, c->arm * th / c->l, NULL, &dG, NULL);
+    d -= k * pp * dG;
+  } else if (th < 0.0) {
+    double dG;
+    gfit_eval(c->G, -c->arm * th / c->l, NULL, &dG, NULL);
+    d -= k * pm * dG;
+  } else {
+    double dG;
+    gfit_eval(c->G, 0.0, NULL, &dG, NULL);
+    d -= 0.5 * k * (pp + pm) * dG;
+  }
+  return d;
+}
+
+/* Exact Hessian of Pi (dense, row-major n x n) at the state whose poses are in w and
+ * whose penetrating contacts are cl[0..ncl).  For a disk centre x on link i with
+ * distance-field normal n, curvature kappa and force lam = k_c pen, with
+ * v_j = z x (x - p_j) the velocity of x under joint j (j <= i):
+ *   dg/dtheta_j = n.v_j = a_j,
+ *   d2g/dtheta_j dtheta_m = kappa (tau.v_j)(tau.v_m) - n.(x - p_max(j,m)),
+ * so the pair adds k_c a a^T - lam d2g. */
+static void chain_hessian(const vo_chain* c, const double* th, const vo_contact* cl, int ncl,
+                          const vo_pose* w, double* H, double* a, double* b, double* u) {
+  int n = c->n;
+  memset(H, 0, sizeof(double) * (size_t)n * n);
+  for (int j = 0; j < n; ++j) H[j * n + j] = joint_dq(c, j, th[j]);
+  for (int e = 0; e < ncl; ++e) {
+    const vo_contact* q = &cl[e];
+    int i = q->i;
+    double tx = -q->ny, ty = q->nx; /* tangent */
+    for (int j = 0; j <= i; ++j) {
+      double vx = -(q->xy - w->py[j]), vy = q->xx - w->px[j];
+      a[j] = q->nx * vx + q->ny * vy;
+      b[j] = tx * vx + ty * vy;
+      u[j] = q->nx * w->px[j] + q->ny * w->py[j];
+    }
+    double nxx = q->nx * q->xx + q->ny * q->xy;
+    double kc = c->P->kc, lk = q->lam * q->kappa;
+    for (int j = 0; j <= i; ++j)
+      for (int m = 0; m <= i; ++m) {
+        int mx = j > m ? j : m;
+        H[j * n + m] += kc * a[j] * a[m] - lk * b[j] * b[m] + q->lam * (nxx - u[mx]);
+      }
+  }
+}
+
+/* dense (H + mu I) x = b by Gaussian elimination with partial pivoting; 0 on success */
+static int dense_solve(int n, const double* H, double mu, const double* b, double* x, double* W) {
+  int w = n + 1;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) W[i * w + j] = H[i * n + j] + (i == j ? mu : 0.0);
+    W[i * w + n] = b[i];
+  }
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = fabs(W[k * w + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(W[i * w + k]) > best) {
+        best = fabs(W[i * w + k]);
+        p = i;
+      }
+    if (!(best > 0.0)) return -1;
+    if (p != k)
+      for (int j = k; j <= n; ++j) {
+        double t = W[k * w + j];
+        W[k * w + j] = W[p * w + j];
+        W[p * w + j] = t;
+      }
+    for (int i = k + 1; i < n; ++i) {
+      double f = W[i * w + k] / W[k * w + k];
+      if (f != 0.0)
+        for (int j = k; j <= n; ++j) W[i * w + j] -= f * W[k * w + j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = W[i * w + n];
+    for (int j = i + 1; j < n; ++j) s -= W[i * w + j] * x[j];
+    x[i] = s / W[i * w + i];
+  }
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(x[i])) return -1;
+  return 0;
+}
+
+typedef struct {
+  int iters, backtracks, mu_raises, status;
+  double rho;
+} vo_solve_stats;
+
+/* Damped Newton descent of Pi from th (in place).
+ *  - H: exact Hessian of Pi (analytic; by central differences of r when fd_h > 0);
+ *  - step (H + mu I) d = -r with mu = c_mu max_j |r_j|: an implicit Euler step of the
+ *    overdamped motion (gradient flow) that the quasi-static model stands for, which
+ *    becomes Newton's step as the residual vanishes; mu is raised tenfold until the
+ *    step descends (r.d < 0);
+ *  - Armijo backtracking on Pi (halving, constant c1), skipped once the predicted
+ *    decrease -r.d is below 1e-12 M_max (round-off level of Pi);
+ *  - stop when rho = max_j |r_j| / M_max <= tol.
+ * status: 0 converged, 1 iteration limit, 2 no descent / line search failure,
+ * 4 non-finite state. */
+static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_pose* w) {
+  const vo_prm* P = c->P;
+  int n = c->n;
+  size_t nn = (size_t)n;
+  double* buf = (double*)malloc(sizeof(double) * (nn * nn + nn * (nn + 1) + 9 * nn + 16));
+  double* H = buf;
+  double* W = H + nn * nn;
+  double* r = W + nn * (nn + 1);
+  double* rp = r + nn;
+  double* rm = rp + nn;
+  double* d = rm + nn;
+  double* tt = d + nn;
+  double* ha = tt + nn;
+  double* hb = ha + nn;
+  double* hu = hb + nn;
+  int capc = 2 * n * (c->K > 0 ? c->K : 1) + 1, ncl = 0;
+  vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+  memset(st, 0, sizeof(*st));
+  st->status = 1;
+  double Pi = chain_eval(c, th, r, 1, cl, capc, &ncl, w);
+  for (int it = 0; it <= P->max_iter; ++it) {
+    double rmax = 0.0;
+    for (int j = 0; j < n; ++j) rmax = fmax(rmax, fabs(r[j]));
+    st->rho = rmax / c->Mmax;
+    if (!isfinite(st->rho) || !isfinite(Pi)) {
+      st->status = 4;
+      break;
+    }
+    if (st->rho <= P->tol) {
+      st->status = 0;
+      break;
+    }
+    if (it == P->max_iter) break;
+    st->iters++;
+    if (P->fd_h > 0.0) {
+      /* Hessian by central differences of r (cross-check mode) */
+      double h = P->fd_h;
+      for (int j = 0; j < n; ++j) {
+        memcpy(tt, th, sizeof(double) * nn);
+        tt[j] = th[j] + h;
+        chain_eval(c, tt, rp, 0, NULL, 0, NULL, w);
+        tt[j] = th[j] - h;
+        chain_eval(c, tt, rm, 0, NULL, 0, NULL, w);
+        for (int i = 0; i < n; ++i) H[i * n + j] = (rp[i] - rm[i]) / (2.0 * h);
+      }
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+          double a = 0.5 * (H[i * n + j] + H[j * n + i]);
+          H[i * n + j] = H[j * n + i] = a;
+        }
+      chain_eval(c, th, NULL, 0, NULL, 0, NULL, w); /* restore poses */
+    } else {
+      chain_hessian(c, th, cl, ncl < capc ? ncl : capc, w, H, ha, hb, hu);
+    }
+    for (int i = 0; i < n; ++i) rp[i] = -r[i];
+    /* implicit Euler step of the gradient flow with mu = 1/h = c_mu |r|_inf; raise mu
+     * tenfold (floor 1e-8 M_max) until the step descends */
+    int ok = 0;
+    double slope = 0.0;
+    double mu = P->c_mu * rmax;
+    for (int tries = 0; tries < 24; ++tries) {
+      if (tries > 0) {
+        mu = fmax(10.0 * mu, 1e-8 * c->Mmax);
+        st->mu_raises++;
+      }
+      if (dense_solve(n, H, mu, rp, d, W) != 0) continue;
+      slope = 0.0;
+      for (int i = 0; i < n; ++i) slope += r[i] * d[i];
+      if (slope < 0.0) {
+        ok = 1;
+        break;
+      }
+    }
+    if (!ok) {
+      st->status = 2;
+      break;
+    }
+    /* cap the joint-space step length so that the iterates follow the flow */
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(d[i]));
+    if (dmax > P->step_max) {
+      double f = P->step_max / dmax;
+      for (int i = 0; i < n; ++i) d[i] *= f;
+      slope *= f;
+    }
+    double alpha = 1.0, Pn = 0.0;
+    int accepted = 0;
+    int skip = (-slope < 1e-12 * c->Mmax);
+    for (int ls = 0; ls < 40; ++ls) {
+      for (int i = 0; i < n; ++i) tt[i] = th[i] + alpha * d[i];
+      Pn = chain_eval(c, tt, rm, 1, cl, capc, &ncl, w);
+      if (skip || Pn <= Pi + P->c1 * alpha * slope) {
+        accepted = 1;
+        break;
+      }
+      alpha *= 0.5;
+      st->backtracks++;
+    }
+    if (!accepted) {
+      st->status = 2;
+      break;
+    }
+    if (vo_verbose)
+      fprintf(stderr, "it %d rho %.3e mu %.3e slope %.3e alpha %.3e Pi %.12e\n", it, st->rho, mu,
+              slope, alpha, Pn);
+    memcpy(th, tt, sizeof(double) * nn);
+    memcpy(r, rm, sizeof(double) * nn);
+    Pi = Pn;
+  }
+  free(cl);
+  free(buf);
+}
+
+/* ------------------------------------------------------------------------- */
+/* rollout driver */
+
+static uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+/* per-joint pressure-weighted sPAM coverage: w = |[s0,s1] ∩ [j l,(j+1) l]| / l */
+static void spam_coverage(int n, double l, const double* spam, int ns, double* Pp, double* Pm) {
+  for (int j = 0; j < n; ++j) Pp[j] = Pm[j] = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const double* e = spam + 4 * s;
+    for (int j = 0; j < n; ++j) {
+      double lo = fmax(e[0], j * l), hi = fmin(e[1], (j + 1) * l);
+      if (hi > lo) {
+        double w = (hi - lo) / l;
+        if (e[2] > 0.0) Pp[j] += w * e[3]; else Pm[j] += w * e[3];
+      }
+    }
+  }
+}
+
+static void chain_init(vo_chain* c, const vo_prm* P, const double* prm, const double* d, int K,
+                       const int* kind, const double* obs) {
+  memset(c, 0, sizeof(*c));
+  c->P = P;
+  c->l = d[0];
+  c->R = d[1];
+  c->Pv = d[2];
+  c->bx = d[3];
+  c->by = d[4];
+  c->bpsi = d[5];
+  c->arm = 2.0 * c->R + P->Ract;
+  c->Mmax = VO_PI * c->Pv * c->R * c->R * c->R;
+  c->K = K;
+  c->kind = kind;
+  c->obs = obs;
+  c->last_len = c->l;
+  c->G = gfit_get(c->l, prm);
+}
+
+/* Roll out every instance for n_steps growth steps (Alg. 1 repeated).  Arrays as in
+ * the workload module.  Outputs (all nullable except theta):
+ *  theta  [B][n_max]        final joint angles
+ *  tip    [B][T][3]         tip x, y, heading after each step
+ *  rho    [B][T], iters [B][T], status [B][T] (-1 once the instance is full grown),
+ *  ncont  [B][T], chash [B][T] (order-free hash of the contact set), maxpen [B][T]
+ *  traj   [B][T][n_max]     joint angles after each step
+ *  stats  [B][4]            total Newton iterations, backtracks, damping raises, max contacts */
+int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spam,
+               const int* obs_kind, const double* obs_d, const double* prm, int n_steps,
+               int n_threads, int n_max, double* theta, double* tip, double* rho, int* iters,
+               int* status, int* ncont, uint64_t* chash, double* maxpen, double* traj,
+               double* stats) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  for (int b = 0; b < B; ++b) gfit_get(inst_d[6 * b], prm); /* build fits up front */
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int b = 0; b < B; ++b) {
+    const int* ii = inst_i + 5 * b;
+    int ntar = ii[0];
+    int nalloc = ntar > 0 ? ntar : 1;
+    vo_chain c;
+    chain_init(&c, &P, prm, inst_d + 6 * b, ii[4], obs_kind + ii[3], obs_d + 4 * (size_t)ii[3]);
+    double* Pp = (double*)calloc((size_t)nalloc * 2, sizeof(double));
+    double* Pm = Pp + nalloc;
+    spam_coverage(ntar, c.l, spam + 4 * (size_t)ii[1], ii[2], Pp, Pm);
+    c.Pp = Pp;
+    c.Pm = Pm;
+    double* th = (double*)calloc((size_t)nalloc, sizeof(double));
+    vo_pose w;
+    pose_alloc(&w, nalloc);
+    int capc = 2 * nalloc * (c.K > 0 ? c.K : 1) + 1;
+    vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+    double tot_it = 0, tot_bt = 0, tot_mu = 0, max_c = 0;
+    c.n = 0;
+    for (int t = 0; t < n_steps; ++t) {
+      int st_worst = 0, it_sum = 0;
+      double rho_last = 0.0;
+      if (c.n < ntar) {
+        c.n += 1;
+        th[c.n - 1] = 0.0;
+        for (int s = 1; s <= P.substeps; ++s) {
+          c.last_len = c.l * (double)s / P.substeps;
+          vo_solve_stats st;
+          chain_solve(&c, th, &st, &w);
+          it_sum += st.iters;
+          tot_bt += st.backtracks;
+          tot_mu += st.mu_raises;
+          if (st.status > st_worst) st_worst = st.status;
+          rho_last = st.rho;
+        }
+      } else {
+        c.last_len = c.l;
+        st_worst = -1;
+      }
+      tot_it += it_sum;
+      int ncl = 0;
+      if (c.n > 0) chain_eval(&c, th, NULL, 0, cl, capc, &ncl, &w);
+      if (ncl > max_c) max_c = ncl;
+      size_t bt = (size_t)b * n_steps + t;
+      if (tip) {
+        double hd = c.bpsi;
+        for (int i = 0; i < c.n; ++i) hd += th[i];
+        tip[3 * bt + 0] = c.n > 0 ? w.px[c.n] : c.bx;
+        tip[3 * bt + 1] = c.n > 0 ? w.py[c.n] : c.by;
+        tip[3 * bt + 2] = hd;
+      }
+      if (rho) rho[bt] = rho_last;
+      if (iters) iters[bt] = it_sum;
+      if (status) status[bt] = st_worst;
+      {
+        /* contact set: (link, obstacle) pairs in which either disk of the link penetrates */
+        uint64_t hsh = 0;
+        double mp = 0.0;
+        int npair = 0;
+        for (int e = 0; e < ncl && e < capc; ++e) {
+          int dup = 0;
+          for (int f = 0; f < e; ++f)
+            if (cl[f].i == cl[e].i && cl[f].k == cl[e].k) dup = 1;
+          if (!dup) {
+            hsh += splitmix64((uint64_t)cl[e].i * 1024u + (uint64_t)cl[e].k);
+            ++npair;
+          }
+          if (cl[e].pen > mp) mp = cl[e].pen;
+        }
+        if (ncont) ncont[bt] = npair;
+        if (chash) chash[bt] = hsh;
+        if (maxpen) maxpen[bt] = mp;
+      }
+      if (traj)
+        for (int i = 0; i < n_max; ++i) traj[bt * n_max + i] = (i < c.n) ? th[i] : 0.0;
+    }
+    for (int i = 0; i < n_max; ++i) theta[(size_t)b * n_max + i] = (i < ntar) ? th[i] : 0.0;
+    if (stats) {
+      stats[4 * b + 0] = tot_it;
+      stats[4 * b + 1] = tot_bt;
+      stats[4 * b + 2] = tot_mu;
+      stats[4 * b + 3] = max_c;
+    }
+    free(Pp);
+    free(th);
+    free(w.px);
+    free(cl);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* single-chain hooks for the tests */
+
+/* Residual r [n], energy Pi (returned), contacts for one chain of n links.
+ * contacts (nullable) receives up to cap rows (i, k, lam, x, y, nx, ny, pen). */
+double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                     const double* obs, const double* prm, double last_len, const double* th,
+                     double* r, int* ncontact, double* contacts, int cap) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  vo_chain c;
+  chain_init(&c, &P, prm, d, K, kind, obs);
+  double* Pp = (double*)calloc((size_t)n * 2 + 2, sizeof(double));
+  spam_coverage(n, c.l, spam, ns, Pp, Pp + n + 1);
+  c.Pp = Pp;
+  c.Pm = Pp + n + 1;
+  c.n = n;
+  c.last_len = last_len > 0.0 ? last_len : c.l;
+  vo_pose w;
+  pose_alloc(&w, n + 1);
+  int capc = 2 * n * (K > 0 ? K : 1) + 1;
+  vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+  int ncl = 0;
+  double Pi = chain_eval(&c, th, r, 1, cl, capc, &ncl, &w);
+  if (ncontact) *ncontact = ncl;
+  if (contacts)
+    for (int e = 0; e < ncl && e < cap && e < capc; ++e) {
+      double* o = contacts + 8 * e;
+      o[0] = cl[e].i;
+      o[1] = cl[e].k;
+      o[2] = cl[e].lam;
+      o[3] = cl[e].xx;
+      o[4] = cl[e].xy;
+      o[5] = cl[e].nx;
+      o[6] = cl[e].ny;
+      o[7] = cl[e].pen;
+    }
+  free(cl);
+  free(w.px);
+  free(Pp);
+  return Pi;
+}
+
+/* Solve one equilibrium from th (in place); returns status; info = iters, backtracks,
+ * damping raises, rho */
+int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                   const double* obs, const double* prm, double last_len, double* th,
+                   double* info) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  vo_chain c;
+  chain_init(&c, &P, prm, d, K, kind, obs);
+  double* Pp = (double*)calloc((size_t)n * 2 + 2, sizeof(double));
+  spam_coverage(n, c.l, spam, ns, Pp, Pp + n + 1);
+  c.Pp = Pp;
+  c.Pm = Pp + n + 1;
+  c.n = n;
+  c.last_len = last_len > 0.0 ? last_len : c.l;
+  vo_pose w;
+  pose_alloc(&w, n + 1);
+  vo_solve_stats st;
+  chain_solve(&c, th, &st, &w);
+  if (info) {
+    info[0] = st.iters;
+    info[1] = st.backtracks;
+    info[2] = st.mu_raises;
+    info[3] = st.rho;
+  }
+  free(w.px);
+  free(Pp);
+  return st.status;
+}
+
+/* G, dG/deps, int_0^eps G from the Chebyshev fit; info = G(0), eps_max, tail size */
+void vo_gfit_eval(double l0, const double* prm, int n, const double* eps, double* G, double* dG,
+                  double* IG, double* info) {
+  const vo_gfit* g = gfit_get(l0, prm);
+  for (int i = 0; i < n; ++i)
+    gfit_eval(g, eps[i], G ? &G[i] : NULL, dG ? &dG[i] : NULL, IG ? &IG[i] : NULL);
+  if (info) {
+    info[0] = g->G0;
+    info[1] = g->emax;
+    info[2] = fabs(g->c[g->N]) + fabs(g->c[g->N - 1]);
+  }
+}
+
+void vo_spam_coverage(int n, double l, const double* spam, int ns, double* Pp, double* Pm) {
+  spam_coverage(n, l, spam, ns, Pp, Pm);
+}
+
+/* joint moment and energy for explicit per-joint pressures (for tests) */
+void vo_joint_law(const double* d, double pp, double pm, const double* prm, int n,
+                  const double* th, double* q, double* E) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  vo_chain c;
+  chain_init(&c, &P, prm, d, 0, NULL, NULL);
+  double Pp = pp, Pm = pm;
+  c.Pp = &Pp;
+  c.Pm = &Pm;
+  for (int i = 0; i < n; ++i) joint_law(&c, 0, th[i], q ? &q[i] : NULL, E ? &E[i] : NULL);
+}
+
+/* analytic Hessian H [n][n] of Pi for one chain (for tests) */
+void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                      const double* obs, const double* prm, double last_len, const double* th,
+                      double* H) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  vo_chain c;
+  chain_init(&c, &P, prm, d, K, kind, obs);
+  double* Pp = (double*)calloc((size_t)n * 2 + 2, sizeof(double));
+  spam_coverage(n, c.l, spam, ns, Pp, Pp + n + 1);
+  c.Pp = Pp;
+  c.Pm = Pp + n + 1;
+  c.n = n;
+  c.last_len = last_len > 0.0 ? last_len : c.l;
+  vo_pose w;
+  pose_alloc(&w, n + 1);
+  int capc = 2 * n * (K > 0 ? K : 1) + 1, ncl = 0;
+  vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)(3 * n + 3));
+  chain_eval(&c, th, NULL, 0, cl, capc, &ncl, &w);
+  chain_hessian(&c, th, cl, ncl, &w, H, tmp, tmp + n + 1, tmp + 2 * n + 2);
+  free(tmp);
+  free(cl);
+  free(w.px);
+  free(Pp);
+}
