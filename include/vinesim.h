@@ -1,0 +1,190 @@
+/*
+ * vinesim.h -- C ABI of the MI355X (gfx950) vine-robot simulator: the batched
+ * quasi-static growth step of a soft growing robot, arXiv 2509.15180
+ * ("Parallel Simulation of Contact and Actuation for Soft Growing Robots").
+ *
+ * Model (paper section / equation):
+ *   - a robot is a chain of rigid links of length l in minimal coordinates, the
+ *     relative joint angles theta (Sec. 4.1);
+ *   - each joint carries the wrinkling-based restoring moment of the inflated body
+ *     (Sec. 3.2, Eq. 2) and the moment of the sPAM actuators that cover it
+ *     (Sec. 3.1, Eq. 1; Sec. 3.3, Eq. 3: strain eps = (2R + R_act) theta / l);
+ *   - one growth step appends a link and brings the chain to the minimum-energy
+ *     state of Eq. 4 read as a potential energy: joint energies plus a penalty
+ *     k_c/2 pen^2 on every penetration of the body into an obstacle (Alg. 1).
+ *
+ * Units are SI throughout: metres, pascals, radians, newtons.
+ *
+ * Conventions
+ *   - Every entry point returns 0 on success or a negative VINE_E* code.  A call
+ *     that fails leaves the simulation state unchanged; vine_sim_last_error()
+ *     then describes the failure.
+ *   - Numerical non-convergence is NOT a call error: it is reported per instance
+ *     and per step in the STATUS field.
+ *   - Pointers marked "host" are read during the call only and may be freed
+ *     on return.  The library owns all device memory it allocates; the handle
+ *     frees it in vine_sim_destroy().
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     asynchronously on it; synchronise the stream before reading results on the
+ *     host through a caller-owned buffer.
+ *   - One handle must not be used from two threads at once.  Several handles may
+ *     share a device.
+ */
+#ifndef VINESIM_H
+#define VINESIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define VINE_OK 0
+#define VINE_EINVAL (-1)    /* a size, pressure or geometry is NaN, negative or out of range */
+#define VINE_ENOMEM (-2)    /* device or host allocation failed */
+#define VINE_EDEVICE (-3)   /* a HIP runtime call failed */
+#define VINE_ESTATE (-4)    /* call not valid in the handle's current state */
+#define VINE_ECAPACITY (-5) /* more links, obstacles or sPAMs per robot than supported */
+
+/* per-step status codes in the STATUS field */
+#define VINE_ST_CONVERGED 0   /* max_j |r_j| / M_max <= tol */
+#define VINE_ST_MAXITER 1     /* iteration limit reached */
+#define VINE_ST_NODESCENT 2   /* no descent direction / line search failed */
+#define VINE_ST_CAPACITY 3    /* more simultaneous contacts than the solver holds */
+#define VINE_ST_NONFINITE 4   /* a non-finite residual or energy appeared */
+#define VINE_ST_DONE (-1)     /* the robot had already reached its target length */
+
+/* Simulation-wide constants.  Defaults (vine_params_default): R_c = 5 mm,
+ * R_act = 17.18 mm, a = 1e-4 (Sec. 3.1); eps_crit = 0.01 (Sec. 3.2: fitted in the
+ * paper, value not printed); k_c = 1e4 N/m; tol = 1e-10; max_iter = 500;
+ * growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad; armijo_c1 = 1e-4. */
+typedef struct vine_params {
+  double R_c;            /* sPAM constriction radius (m), Eq. 1 */
+  double R_act;          /* sPAM tube radius (m), Eq. 1c */
+  double a_corr;         /* sPAM correction factor a (dimensionless), Eq. 1b */
+  double eps_crit;       /* critical wrinkling strain, Eq. 2b */
+  double k_c;            /* contact penalty stiffness (N/m), Eq. 4 contact term */
+  double tol;            /* convergence: max_j |r_j| / (pi P R^3) <= tol */
+  double c_mu;           /* damping per unit residual, mu = c_mu max_j |r_j| (1/rad) */
+  double step_max;       /* cap on the joint-space step per iteration (rad) */
+  double armijo_c1;      /* sufficient-decrease constant of the line search */
+  int32_t max_iter;      /* Newton iterations per equilibrium solve */
+  int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
+} vine_params;
+
+/* One robot.  n_links: target link count (1..VINE_MAX_LINKS).  Its sPAMs are
+ * spams[spam_offset .. spam_offset + spam_count) and its obstacles
+ * obstacles[obs_offset .. obs_offset + obs_count). */
+typedef struct vine_instance {
+  int32_t n_links;
+  int32_t spam_offset, spam_count;
+  int32_t obs_offset, obs_count;
+  int32_t reserved;
+  double link_len;       /* l (m), also the sPAM unit length l0 */
+  double tube_radius;    /* R_vine (m) */
+  double body_pressure;  /* P_vine (Pa) */
+  double base_x, base_y; /* base position (m) */
+  double base_heading;   /* heading of the first link at zero joint angle (rad) */
+} vine_instance;
+
+/* An sPAM actuator along the body (Sec. 3.1).  It covers arc length
+ * [s_start, s_end] from the base; joint j takes the pressure-weighted fraction of
+ * link j = [j l, (j+1) l] it covers.  side = +1 pulls theta positive, -1 negative. */
+typedef struct vine_spam {
+  double s_start, s_end; /* m, 0 <= s_start <= s_end */
+  double side;           /* +1 or -1 */
+  double pressure;       /* P_act (Pa), >= 0 */
+} vine_spam;
+
+/* An obstacle.  kind 0: circle, centre (cx, cy), radius a (b unused).
+ * kind 1: axis-aligned rectangle, centre (cx, cy), half-width a, half-height b. */
+typedef struct vine_obstacle {
+  int32_t kind;
+  int32_t reserved;
+  double cx, cy, a, b;
+} vine_obstacle;
+
+#define VINE_MAX_LINKS 64    /* links per robot */
+#define VINE_MAX_OBSTACLES 128
+#define VINE_MAX_SPAMS 64
+
+/* Fields for vine_sim_read.  T = the longest target length (steps recorded per
+ * robot), N = the largest n_links, B = the number of robots.  Row-major. */
+typedef enum vine_field {
+  VINE_F_THETA = 0,    /* double [B][N]    joint angles (0 beyond the current length) */
+  VINE_F_NLINKS = 1,   /* int32  [B]       current link count */
+  VINE_F_TIP = 2,      /* double [B][T][3] tip x, y, heading after each step */
+  VINE_F_RHO = 3,      /* double [B][T]    scaled residual at the end of each step */
+  VINE_F_ITERS = 4,    /* int32  [B][T]    Newton iterations spent in each step */
+  VINE_F_STATUS = 5,   /* int32  [B][T]    VINE_ST_* of each step */
+  VINE_F_NCONTACT = 6, /* int32  [B][T]    (link, obstacle) pairs in contact after each step */
+  VINE_F_CHASH = 7,    /* uint64 [B][T]    order-free hash of that contact set */
+  VINE_F_MAXPEN = 8,   /* double [B][T]    deepest penetration after each step (m) */
+  VINE_F_TRAJ = 9      /* double [B][T][N] joint angles after each step (when recorded) */
+} vine_field;
+
+typedef struct vine_sim vine_sim;
+
+/* Fill p with the defaults listed above. */
+void vine_params_default(vine_params* p);
+
+/* Create a simulation of n_inst robots at zero length on the current HIP device.
+ * params, inst, spams and obstacles are host arrays (copied).  Builds the sPAM
+ * force-law table (Sec. 3.1, Eq. 1 solved for every distinct link length) and each
+ * joint's sPAM coverage.  Errors: VINE_EINVAL (NaN or non-positive sizes or
+ * pressures, side not +-1, s_start > s_end, unknown obstacle kind, n_inst < 1,
+ * offsets out of range), VINE_ECAPACITY (n_links > VINE_MAX_LINKS, more than
+ * VINE_MAX_OBSTACLES obstacles or VINE_MAX_SPAMS sPAMs on one robot), VINE_ENOMEM,
+ * VINE_EDEVICE.  *out is set only on success. */
+int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, int32_t n_inst,
+                        const vine_spam* spams, int32_t n_spams, const vine_obstacle* obstacles,
+                        int32_t n_obstacles, vine_sim** out);
+
+/* Advance every robot that is shorter than its target by n_steps growth steps
+ * (Alg. 1 repeated): append a link at zero angle, then, for each growth sub-step,
+ * solve the equilibrium.  Robots at their target length are left unchanged and
+ * record VINE_ST_DONE.  n_steps <= 0 is a no-op.  When record_traj is non-zero the
+ * joint angles after every step are kept for VINE_F_TRAJ.  Asynchronous on stream. */
+int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
+
+/* Grow every robot to its target length in one launch (n_steps = -1) or by
+ * n_steps steps.  Same semantics as vine_sim_step. */
+int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
+
+/* Reset every robot to zero length (the records are cleared). */
+int32_t vine_sim_reset(vine_sim* h, void* stream);
+
+/* Copy a field into a caller-owned buffer of at least vine_sim_field_bytes() bytes:
+ * device memory when dst_on_device != 0 (asynchronous on stream), else host memory
+ * (the call synchronises the stream).  VINE_ESTATE for VINE_F_TRAJ when no
+ * trajectory was recorded. */
+int32_t vine_sim_read(const vine_sim* h, int32_t field, void* dst, int32_t dst_on_device,
+                      void* stream);
+
+/* Bytes needed by vine_sim_read for a field; 0 for an unknown field. */
+int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field);
+
+/* Sizes: dims[0] = B robots, dims[1] = T recorded steps, dims[2] = N links. */
+void vine_sim_dims(const vine_sim* h, int32_t dims[3]);
+
+/* Destroy the handle and free its device memory.  NULL is allowed. */
+void vine_sim_destroy(vine_sim* h);
+
+/* Text of the last failure on this handle (owned by the handle, valid until the
+ * next call on it).  With h == NULL: the last vine_sim_create failure of the
+ * calling thread. */
+const char* vine_sim_last_error(const vine_sim* h);
+
+/* Evaluate the sPAM force law table the library built for link length l at
+ * n host points eps[]: G = F_t / P_act (m^2), dG/deps, and int_0^eps G.  For
+ * tests of the create-time table.  Returns VINE_EINVAL if l is not a link length
+ * of this simulation. */
+int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* eps, double* G,
+                          double* dG, double* IG);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VINESIM_H */

@@ -1,0 +1,75 @@
+// vs_device.h -- device-side data layout shared by the host launcher and the
+// gfx950 kernels of the vine-robot simulator.
+#pragma once
+#include <stdint.h>
+
+namespace vs {
+
+constexpr int kWave = 64;
+
+// sPAM force law G(eps) = F_t / P_act (Sec. 3.1, Eq. 1d) on [0, eps_max] as a
+// piecewise Chebyshev series: pieces [b_k, b_{k+1}] with b_k = eps_max (k/P)^2
+// (graded toward eps = 0, where G changes fastest), degree D per piece.
+constexpr int kSpamPieces = 24;
+constexpr int kSpamDeg = 20;
+
+struct SpamTable {
+  double l0;                                 // actuator unit length (= link length)
+  double emax;                               // slack strain eps(m = 1/2)
+  double G0;                                 // G(0)
+  double bnd[kSpamPieces + 1];               // piece boundaries in eps
+  double cum[kSpamPieces + 1];               // int_0^{b_k} G
+  double c[kSpamPieces][kSpamDeg + 1];       // G      = sum' c_j T_j(x)   (c_0 halved)
+  double dc[kSpamPieces][kSpamDeg + 1];      // dG/dx  = sum' dc_j T_j(x)  (dc_0 halved)
+  double ic[kSpamPieces][kSpamDeg + 2];      // int_{b_k}^{eps} G dx' = sum' ic_j T_j(x), 0 at x=-1
+};
+
+// Integral of the wrinkling moment fraction h (Eq. 2) as a cubic Hermite table in
+// u = sqrt(x - theta_on) on [0, sqrt(pi - theta_on)].
+constexpr int kIhKnots = 1025;
+
+struct WrTable {
+  double th_on;       // 2 asin(eps_crit)
+  double umax;        // sqrt(pi - th_on)
+  double du;          // knot spacing in u
+  double h_pi;        // h(pi)
+  double ih_pi;       // int_0^pi h
+  double val[kIhKnots];   // int_0^{x(u_k)} h
+  double der[kIhKnots];   // d/du of it = 2 u h(x(u))
+};
+
+// Solver and model constants passed by value to the kernels.
+struct KParams {
+  double epsc, kc, tol, c_mu, step_max, c1, Ract;
+  int max_iter, substeps;
+};
+
+// Per-robot and per-simulation device arrays (structure of arrays).
+struct KData {
+  int n_inst;
+  int n_max;          // largest target link count (row length of theta)
+  int t_max;          // recorded steps per robot
+  // inputs
+  const int* ii;      // [B][6]: n_target, obs_off, obs_cnt, table_id, cover_off, 0
+  const double* dd;   // [B][6]: l, R, P_vine, base_x, base_y, base_heading
+  const double* cover;// [sum n][2]: P+_j, P-_j
+  const int* okind;   // [O]
+  const double* obs;  // [O][4]: cx, cy, a, b
+  const SpamTable* tables;
+  const WrTable* wr;
+  // state
+  double* theta;      // [B][N]
+  int* ncur;          // [B]
+  int* tcur;          // [B] steps recorded so far
+  // records [B][T]...
+  double* tip;        // [B][T][3]
+  double* rho;
+  int* iters;
+  int* status;
+  int* ncont;
+  unsigned long long* chash;
+  double* maxpen;
+  double* traj;       // [B][T][N] or null
+};
+
+}  // namespace vs

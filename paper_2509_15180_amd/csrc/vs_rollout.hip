@@ -1,0 +1,642 @@
+// vs_rollout.hip -- gfx950 kernel for the batched quasi-static growth step of the
+// vine robot (arXiv 2509.15180, Sec. 3-4).
+//
+// One wavefront (64 lanes) owns one robot; lanes stride over its links.  All model
+// arithmetic is FP64: on gfx950 an FP64 FMA issues at the rate of an unpacked FP32
+// FMA, and the equilibrium must be resolved to 1e-10 of the body's moment scale.
+//
+// A growth step (Alg. 1, read as a converged solve of the energy of Eq. 4):
+//   append a link at zero angle; for each growth sub-step (tip length l s/S):
+//     repeat
+//       poses by wave prefix scans of theta and of the link vectors (Sec. 4.1);
+//       joint moments q_j (Eq. 2, Eq. 3) and penetrating disk/obstacle pairs,
+//       compacted deterministically with ballots into an LDS contact list;
+//       residual r_j = q_j - sum_{contacts on links >= j} lam (x - p_j) x n
+//       (suffix scans of per-link force and moment sums);
+//       stop when max_j |r_j| / M_max <= tol;
+//       exact Hessian in LDS; (H + mu I) d = -r by LU with partial pivoting,
+//       mu = c_mu |r|_inf raised tenfold until d descends; cap |d|_inf;
+//       Armijo backtracking on the energy.
+#include <hip/hip_runtime.h>
+
+#include "vs_device.h"
+
+namespace vs {
+
+constexpr int kMaxObs = 128;
+constexpr int kMaxC = 128;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// wave primitives (blockDim == 64: one wave per block)
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ double wscan_incl(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    double t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wscan_suffix(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    double t = __shfl_down(v, o, kWave);
+    if (lane + o < kWave) v += t;
+  }
+  return v;
+}
+
+// argmax of |value| over lanes; ties -> smallest index (value < 0 marks "no row")
+__device__ __forceinline__ void wargmax(double& v, int& idx) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    double ov = __shfl_xor(v, o, kWave);
+    int oi = __shfl_xor(idx, o, kWave);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+  // splitmix64 finaliser (Steele, Lea, Flood 2014)
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// model laws
+
+// fraction of pi P R^3 carried by the wrinkled body at bend |x| (Eq. 2a-b); linear
+// below the onset theta_on = 2 asin(eps_c); clamped beyond pi.
+__device__ double wr_h(double x, double epsc, double th_on) {
+  if (x <= th_on) return x / (2.0 * th_on);
+  if (x > kPi) x = kPi;
+  double c = 2.0 * epsc / sin(0.5 * x) - 1.0;
+  c = fmin(1.0, fmax(-1.0, c));
+  double g = acos(c);
+  return (sin(2.0 * g) + 2.0 * kPi - 2.0 * g) / (4.0 * (sin(g) + (kPi - g) * cos(g)));
+}
+
+// d wr_h / dx (slope of the linear branch at the onset itself; 0 from pi on)
+__device__ double wr_dh(double x, double epsc, double th_on) {
+  if (x <= th_on) return 0.5 / th_on;
+  if (x >= kPi) return 0.0;
+  double s = sin(0.5 * x);
+  double c = fmin(1.0, 2.0 * epsc / s - 1.0);
+  double g = acos(c);
+  // dgamma/dx = -(dc/dx) / sqrt(1 - c^2), with 1 - c^2 = 4 eps_c (s - eps_c) / s^2
+  double dc = -epsc * cos(0.5 * x) / (s * s);
+  double dg = -dc / sqrt(4.0 * epsc * (s - epsc) / (s * s));
+  double sg = sin(g), cg = cos(g);
+  double num = sin(2.0 * g) + 2.0 * kPi - 2.0 * g;
+  double den = 4.0 * (sg + (kPi - g) * cg);
+  double dnum = 2.0 * cos(2.0 * g) - 2.0;
+  double dden = -4.0 * (kPi - g) * sg;
+  return (dnum * den - num * dden) / (den * den) * dg;
+}
+
+// int_0^x wr_h (energy of the body moment per pi P R^3)
+__device__ double wr_int(double x, const WrTable& T) {
+  if (x <= T.th_on) return x * x / (4.0 * T.th_on);
+  if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
+  double u = sqrt(x - T.th_on);
+  double s = u / T.du;
+  int k = (int)s;
+  if (k > kIhKnots - 2) k = kIhKnots - 2;
+  double t = s - k, t2 = t * t, t3 = t2 * t;
+  return (2.0 * t3 - 3.0 * t2 + 1.0) * T.val[k] + (t3 - 2.0 * t2 + t) * T.du * T.der[k] +
+         (-2.0 * t3 + 3.0 * t2) * T.val[k + 1] + (t3 - t2) * T.du * T.der[k + 1];
+}
+
+__device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
+  double b1 = 0.0, b2 = 0.0;
+  for (int j = deg; j >= 1; --j) {
+    double t = fma(2.0 * x, b1, c[j] - b2);
+    b2 = b1;
+    b1 = t;
+  }
+  return fma(x, b1, c[0] - b2);
+}
+
+// sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral
+__device__ void spam_law(const SpamTable& T, double eps, double* G, double* dG, double* IG) {
+  if (eps >= T.emax) {
+    if (G) *G = 0.0;
+    if (dG) *dG = 0.0;
+    if (IG) *IG = T.cum[kSpamPieces];
+    return;
+  }
+  int k = (int)(kSpamPieces * sqrt(eps / T.emax));
+  k = k < 0 ? 0 : (k > kSpamPieces - 1 ? kSpamPieces - 1 : k);
+  double a = T.bnd[k], b = T.bnd[k + 1];
+  double x = (2.0 * eps - a - b) / (b - a);
+  if (G) *G = clenshaw(T.c[k], kSpamDeg, x);
+  if (dG) *dG = clenshaw(T.dc[k], kSpamDeg - 1, x) * 2.0 / (b - a);
+  if (IG) *IG = T.cum[k] + 0.5 * (b - a) * clenshaw(T.ic[k], kSpamDeg + 1, x);
+}
+
+struct Ctx {
+  int n, K;
+  double l, R, Mmax, arm, bx, by, bpsi, last_len;
+  const SpamTable* tab;
+  const WrTable* wr;
+  KParams P;
+};
+
+// joint moment (Eq. 3b with Eq. 2), slope and energy for angle th and coverage pp/pm
+__device__ void joint_law(const Ctx& c, double th, double pp, double pm, double* q, double* dq,
+                          double* E) {
+  const double epsc = c.P.epsc, th_on = c.wr->th_on;
+  double ath = fabs(th);
+  double ep = th > 0.0 ? c.arm * th / c.l : 0.0;
+  double em = th < 0.0 ? -c.arm * th / c.l : 0.0;
+  if (q) {
+    double Gp, Gm;
+    spam_law(*c.tab, ep, &Gp, nullptr, nullptr);
+    spam_law(*c.tab, em, &Gm, nullptr, nullptr);
+    double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * wr_h(ath, epsc, th_on);
+    *q = Mb - c.arm * (pp * Gp - pm * Gm);
+  }
+  if (dq) {
+    double k = c.arm * c.arm / c.l, dG;
+    double d = c.Mmax * wr_dh(ath, epsc, th_on);
+    if (th > 0.0) {
+      spam_law(*c.tab, ep, nullptr, &dG, nullptr);
+      d -= k * pp * dG;
+    } else if (th < 0.0) {
+      spam_law(*c.tab, em, nullptr, &dG, nullptr);
+      d -= k * pm * dG;
+    } else {
+      spam_law(*c.tab, 0.0, nullptr, &dG, nullptr);
+      d -= 0.5 * k * (pp + pm) * dG;
+    }
+    *dq = d;
+  }
+  if (E) {
+    double IGp, IGm;
+    spam_law(*c.tab, ep, nullptr, nullptr, &IGp);
+    spam_law(*c.tab, em, nullptr, nullptr, &IGm);
+    double Eb = c.Mmax * wr_int(ath, *c.wr);
+    double G0 = c.tab->G0;
+    double Ea = th >= 0.0 ? (-c.l * pp * IGp + c.arm * pm * G0 * th)
+                          : (-c.arm * pp * G0 * th - c.l * pm * IGm);
+    *E = Eb + Ea;
+  }
+}
+
+// signed distance, outward normal and curvature of the distance field at (x, y)
+__device__ __forceinline__ double obs_dist(int kind, const double* o, double x, double y,
+                                          double& nx, double& ny, double& kap) {
+  if (kind == 0) {
+    double vx = x - o[0], vy = y - o[1];
+    double d = sqrt(vx * vx + vy * vy);
+    if (d > 0.0) {
+      nx = vx / d;
+      ny = vy / d;
+      kap = 1.0 / d;
+    } else {
+      nx = 1.0;
+      ny = 0.0;
+      kap = 0.0;
+    }
+    return d - o[2];
+  }
+  double sx = x >= o[0] ? 1.0 : -1.0, sy = y >= o[1] ? 1.0 : -1.0;
+  double dx = fabs(x - o[0]) - o[2], dy = fabs(y - o[1]) - o[3];
+  kap = 0.0;
+  if (dx > 0.0 || dy > 0.0) {
+    double ox = fmax(dx, 0.0), oy = fmax(dy, 0.0);
+    double d = sqrt(ox * ox + oy * oy);
+    nx = sx * ox / d;
+    ny = sy * oy / d;
+    if (dx > 0.0 && dy > 0.0) kap = 1.0 / d;
+    return d;
+  }
+  if (dx >= dy) {
+    nx = sx;
+    ny = 0.0;
+    return dx;
+  }
+  nx = 0.0;
+  ny = sy;
+  return dy;
+}
+
+// ---------------------------------------------------------------------------
+// LDS working set of one robot
+
+template <int NMAX>
+struct Smem {
+  double W[NMAX][NMAX + 1];  // (H + mu I | -r), LU in place
+  double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
+  double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
+  double pp[NMAX], pm[NMAX];
+  double obs[kMaxObs][4];
+  int okind[kMaxObs];
+  int ci[kMaxC], ck[kMaxC];
+  double cl[kMaxC], cxx[kMaxC], cxy[kMaxC], cnx[kMaxC], cny[kMaxC], ckap[kMaxC], cpen[kMaxC];
+  int ncl;
+  int overflow;
+};
+
+// Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
+template <int NMAX>
+__device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool want_E) {
+  const int lane = threadIdx.x;
+  const int n = c.n;
+  double cphi = c.bpsi, cx = c.bx, cy = c.by;
+  for (int base = 0; base < n; base += kWave) {
+    int j = base + lane;
+    bool on = j < n;
+    double phi = wscan_incl(on ? th[j] : 0.0, lane) + cphi;
+    double sj, cj;
+    sincos(phi, &sj, &cj);
+    double L = (j == n - 1) ? c.last_len : c.l;
+    double ex = on ? L * cj : 0.0, ey = on ? L * sj : 0.0;
+    double sx = wscan_incl(ex, lane) + cx, sy = wscan_incl(ey, lane) + cy;
+    if (on) {
+      S.tx[j] = cj;
+      S.ty[j] = sj;
+      S.px[j + 1] = sx;
+      S.py[j + 1] = sy;
+    }
+    cphi = __shfl(phi, kWave - 1, kWave);
+    cx = __shfl(sx, kWave - 1, kWave);
+    cy = __shfl(sy, kWave - 1, kWave);
+  }
+  if (lane == 0) {
+    S.px[0] = c.bx;
+    S.py[0] = c.by;
+  }
+  __syncthreads();
+  double Esum = 0.0;
+  for (int j = lane; j < n; j += kWave) {
+    double q, E = 0.0;
+    joint_law(c, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    S.r[j] = q;
+    Esum += E;
+  }
+  // penetrating (disk, obstacle) pairs, in (disk, obstacle, link) order per chunk
+  int cnt = 0;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int base = 0; base < n; base += kWave) {
+    int j = base + lane;
+    bool on = j < n;
+    double L = (j == n - 1) ? c.last_len : c.l;
+    for (int hh = 1; hh <= 2; ++hh) {
+      double s = 0.5 * hh * L;
+      double xx = on ? S.px[j] + s * S.tx[j] : 0.0;
+      double xy = on ? S.py[j] + s * S.ty[j] : 0.0;
+      for (int k = 0; k < c.K; ++k) {
+        double nx, ny, kap;
+        double g = obs_dist(S.okind[k], S.obs[k], xx, xy, nx, ny, kap) - c.R;
+        bool hit = on && g < 0.0;
+        unsigned long long m = __ballot(hit);
+        if (m) {
+          int pos = cnt + __popcll(m & lt);
+          if (hit && pos < kMaxC) {
+            double pen = -g;
+            S.ci[pos] = j;
+            S.ck[pos] = k;
+            S.cl[pos] = c.P.kc * pen;
+            S.cxx[pos] = xx;
+            S.cxy[pos] = xy;
+            S.cnx[pos] = nx;
+            S.cny[pos] = ny;
+            S.ckap[pos] = kap;
+            S.cpen[pos] = pen;
+          }
+          cnt += __popcll(m);
+        }
+      }
+    }
+  }
+  int nc = cnt < kMaxC ? cnt : kMaxC;
+  if (lane == 0) {
+    S.ncl = nc;
+    S.overflow = cnt > kMaxC;
+  }
+  __syncthreads();
+  // per-link force and moment sums, then suffix sums from the tip toward the base
+  double c1 = 0.0, c2x = 0.0, c2y = 0.0;
+  int nchunk = (n + kWave - 1) / kWave;
+  for (int ch = nchunk - 1; ch >= 0; --ch) {
+    int j = ch * kWave + lane;
+    double s1 = 0.0, s2x = 0.0, s2y = 0.0;
+    for (int e = 0; e < nc; ++e) {
+      if (S.ci[e] == j) {
+        double lam = S.cl[e];
+        s1 += lam * (S.cxx[e] * S.cny[e] - S.cxy[e] * S.cnx[e]);
+        s2x += lam * S.cnx[e];
+        s2y += lam * S.cny[e];
+      }
+    }
+    s1 = wscan_suffix(s1, lane) + c1;
+    s2x = wscan_suffix(s2x, lane) + c2x;
+    s2y = wscan_suffix(s2y, lane) + c2y;
+    if (j < n) S.r[j] -= s1 - (S.px[j] * s2y - S.py[j] * s2x);
+    c1 = __shfl(s1, 0, kWave);
+    c2x = __shfl(s2x, 0, kWave);
+    c2y = __shfl(s2y, 0, kWave);
+  }
+  double pen2 = 0.0;
+  for (int e = lane; e < nc; e += kWave) pen2 += 0.5 * c.P.kc * S.cpen[e] * S.cpen[e];
+  __syncthreads();
+  return wsum(Esum) + wsum(pen2);
+}
+
+// W = (H + mu I | -r) at the state last evaluated (poses, contacts and r in S)
+template <int NMAX>
+__device__ void assemble(Smem<NMAX>& S, const Ctx& c, const double* th, double mu) {
+  const int lane = threadIdx.x, n = c.n;
+  for (int j = lane; j < n; j += kWave) {
+    for (int m = 0; m < n; ++m) S.W[j][m] = 0.0;
+    double dq;
+    joint_law(c, th[j], S.pp[j], S.pm[j], nullptr, &dq, nullptr);
+    S.W[j][j] = dq + mu;
+    S.W[j][n] = -S.r[j];
+  }
+  __syncthreads();
+  const int nc = S.ncl;
+  for (int e = 0; e < nc; ++e) {
+    const int i = S.ci[e];
+    const double lam = S.cl[e], xx = S.cxx[e], xy = S.cxy[e], nx = S.cnx[e], ny = S.cny[e];
+    const double lk = lam * S.ckap[e], kc = c.P.kc;
+    const double nxx = nx * xx + ny * xy;
+    for (int j = lane; j <= i; j += kWave) {
+      double vx = -(xy - S.py[j]), vy = xx - S.px[j];
+      double aj = nx * vx + ny * vy, bj = -ny * vx + nx * vy, uj = nx * S.px[j] + ny * S.py[j];
+      for (int m = 0; m <= i; ++m) {
+        double wx = -(xy - S.py[m]), wy = xx - S.px[m];
+        double am = nx * wx + ny * wy, bm = -ny * wx + nx * wy;
+        double umax = (j > m) ? uj : (nx * S.px[m] + ny * S.py[m]);
+        S.W[j][m] += kc * aj * am - lk * bj * bm + lam * (nxx - umax);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// LU with partial pivoting of W (n x n | rhs); solution into S.d.  false on a zero
+// pivot or a non-finite solution.
+template <int NMAX>
+__device__ bool lu_solve(Smem<NMAX>& S, int n) {
+  const int lane = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + lane; i < n; i += kWave) {
+      double v = fabs(S.W[i][k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    wargmax(best, bi);
+    if (!(best > 0.0)) return false;
+    if (bi != k) {
+      for (int j = k + lane; j <= n; j += kWave) {
+        double t = S.W[k][j];
+        S.W[k][j] = S.W[bi][j];
+        S.W[bi][j] = t;
+      }
+      __syncthreads();
+    }
+    const double piv = S.W[k][k];
+    for (int i = k + 1 + lane; i < n; i += kWave) {
+      double f = S.W[i][k] / piv;
+      if (f != 0.0)
+        for (int j = k; j <= n; ++j) S.W[i][j] -= f * S.W[k][j];
+    }
+    __syncthreads();
+  }
+  // back substitution, column by column
+  for (int i = n - 1; i >= 0; --i) {
+    double xi = S.W[i][n] / S.W[i][i];
+    for (int j = lane; j < i; j += kWave) S.W[j][n] -= S.W[j][i] * xi;
+    if (lane == 0) S.d[i] = xi;
+    __syncthreads();
+  }
+  bool ok = true;
+  for (int j = lane; j < n; j += kWave) ok = ok && isfinite(S.d[j]);
+  return __all(ok);
+}
+
+// One equilibrium solve from S.th (in place).  Returns the status code.
+template <int NMAX>
+__device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
+  const int lane = threadIdx.x, n = c.n;
+  const KParams& P = c.P;
+  int status = 1;
+  double Pi = evaluate(S, c, S.th, true);
+  for (int it = 0; it <= P.max_iter; ++it) {
+    if (S.overflow) {
+      status = 3;
+      break;
+    }
+    double rm = 0.0;
+    bool fin = true;
+    for (int j = lane; j < n; j += kWave) {
+      rm = fmax(rm, fabs(S.r[j]));
+      fin = fin && isfinite(S.r[j]);
+    }
+    rm = wmax(rm);
+    rho = rm / c.Mmax;
+    if (!__all(fin) || !isfinite(Pi)) {
+      status = 4;
+      break;
+    }
+    if (rho <= P.tol) {
+      status = 0;
+      break;
+    }
+    if (it == P.max_iter) break;
+    ++iters;
+    bool ok = false;
+    double slope = 0.0, mu = P.c_mu * rm;
+    for (int tries = 0; tries < 24; ++tries) {
+      if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
+      assemble(S, c, S.th, mu);
+      if (!lu_solve(S, n)) continue;
+      double s = 0.0;
+      for (int j = lane; j < n; j += kWave) s += S.r[j] * S.d[j];
+      slope = wsum(s);
+      if (slope < 0.0) {
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) {
+      status = 2;
+      break;
+    }
+    double dm = 0.0;
+    for (int j = lane; j < n; j += kWave) dm = fmax(dm, fabs(S.d[j]));
+    dm = wmax(dm);
+    if (dm > P.step_max) {
+      double f = P.step_max / dm;
+      for (int j = lane; j < n; j += kWave) S.d[j] *= f;
+      slope *= f;
+    }
+    __syncthreads();
+    const bool skip = -slope < 1e-12 * c.Mmax;
+    double alpha = 1.0, Pn = 0.0;
+    bool acc = false;
+    for (int ls = 0; ls < 40; ++ls) {
+      for (int j = lane; j < n; j += kWave) S.tt[j] = S.th[j] + alpha * S.d[j];
+      __syncthreads();
+      Pn = evaluate(S, c, S.tt, true);
+      if (skip || Pn <= Pi + P.c1 * alpha * slope) {
+        acc = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!acc) {
+      status = 2;
+      break;
+    }
+    for (int j = lane; j < n; j += kWave) S.th[j] = S.tt[j];
+    Pi = Pn;
+    __syncthreads();
+  }
+  if (status != 0) evaluate(S, c, S.th, false);  // poses/contacts of the kept state
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+
+template <int NMAX>
+__global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int n_steps,
+                                                        int record_traj) {
+  __shared__ Smem<NMAX> S;
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (b >= D.n_inst) return;
+  const int* ii = D.ii + 6 * b;
+  const double* dd = D.dd + 6 * b;
+  Ctx c;
+  const int ntar = ii[0];
+  c.K = ii[2];
+  c.l = dd[0];
+  c.R = dd[1];
+  c.Mmax = kPi * dd[2] * c.R * c.R * c.R;
+  c.arm = 2.0 * c.R + P.Ract;
+  c.bx = dd[3];
+  c.by = dd[4];
+  c.bpsi = dd[5];
+  c.tab = D.tables + ii[3];
+  c.wr = D.wr;
+  c.P = P;
+  for (int k = lane; k < c.K; k += kWave) {
+    const double* o = D.obs + 4 * (size_t)(ii[1] + k);
+    S.obs[k][0] = o[0];
+    S.obs[k][1] = o[1];
+    S.obs[k][2] = o[2];
+    S.obs[k][3] = o[3];
+    S.okind[k] = D.okind[ii[1] + k];
+  }
+  for (int j = lane; j < ntar; j += kWave) {
+    S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
+    S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
+  }
+  int n = D.ncur[b];
+  int t = D.tcur[b];
+  for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
+  __syncthreads();
+  for (int step = 0; step < n_steps && t < D.t_max; ++step, ++t) {
+    int st_worst = 0, its = 0;
+    double rho = 0.0;
+    if (n < ntar) {
+      ++n;
+      if (lane == 0) S.th[n - 1] = 0.0;
+      __syncthreads();
+      c.n = n;
+      for (int s = 1; s <= P.substeps; ++s) {
+        c.last_len = c.l * (double)s / (double)P.substeps;
+        int st = solve(S, c, its, rho);
+        st_worst = st > st_worst ? st : st_worst;
+      }
+    } else {
+      c.n = n;
+      c.last_len = c.l;
+      st_worst = -1;
+      if (n > 0) evaluate(S, c, S.th, false);
+    }
+    // record the state after this step
+    const size_t bt = (size_t)b * D.t_max + t;
+    double hsum = 0.0;
+    for (int j = lane; j < n; j += kWave) hsum += S.th[j];
+    hsum = wsum(hsum);
+    int nc = n > 0 ? S.ncl : 0;
+    unsigned long long hv = 0ull;
+    int npair = 0;
+    double mp = 0.0;
+    for (int e = lane; e < nc; e += kWave) {
+      bool dup = false;
+      for (int f = 0; f < e; ++f) dup = dup || (S.ci[f] == S.ci[e] && S.ck[f] == S.ck[e]);
+      if (!dup) {
+        hv += mix64((unsigned long long)S.ci[e] * 1024ull + (unsigned long long)S.ck[e]);
+        ++npair;
+      }
+      mp = fmax(mp, S.cpen[e]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      hv += __shfl_xor(hv, o, kWave);
+      npair += __shfl_xor(npair, o, kWave);
+    }
+    mp = wmax(mp);
+    if (lane == 0) {
+      D.tip[3 * bt + 0] = n > 0 ? S.px[n] : c.bx;
+      D.tip[3 * bt + 1] = n > 0 ? S.py[n] : c.by;
+      D.tip[3 * bt + 2] = c.bpsi + hsum;
+      D.rho[bt] = rho;
+      D.iters[bt] = its;
+      D.status[bt] = st_worst;
+      D.ncont[bt] = npair;
+      D.chash[bt] = hv;
+      D.maxpen[bt] = mp;
+    }
+    if (record_traj && D.traj)
+      for (int j = lane; j < D.n_max; j += kWave)
+        D.traj[bt * D.n_max + j] = j < n ? S.th[j] : 0.0;
+    __syncthreads();
+  }
+  for (int j = lane; j < n; j += kWave) D.theta[(size_t)b * D.n_max + j] = S.th[j];
+  if (lane == 0) {
+    D.ncur[b] = n;
+    D.tcur[b] = t;
+  }
+}
+
+// host-side launcher (instantiated for the supported chain lengths)
+hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
+                          int nmax_class, hipStream_t stream) {
+  dim3 grid(D.n_inst), block(kWave);
+  if (nmax_class <= 64)
+    hipLaunchKernelGGL(rollout_kernel<64>, grid, block, 0, stream, P, D, n_steps, record_traj);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace vs

@@ -1,0 +1,226 @@
+"""Python binding of libvinesim.so (include/vinesim.h).
+
+Argument marshalling only: every step of the growth-step path runs in the HIP
+library.  The binding fails loudly when the library is missing; it never falls
+back to another implementation.
+
+Names follow the C ABI: ``create`` -> vine_sim_create, ``VineSim.step`` ->
+vine_sim_step, ``VineSim.rollout`` -> vine_sim_rollout, ``VineSim.read`` ->
+vine_sim_read, ``VineSim.close`` -> vine_sim_destroy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvinesim.so")
+
+VINE_OK, VINE_EINVAL, VINE_ENOMEM, VINE_EDEVICE, VINE_ESTATE, VINE_ECAPACITY = 0, -1, -2, -3, -4, -5
+ST_DONE, ST_CONVERGED, ST_MAXITER, ST_NODESCENT, ST_CAPACITY, ST_NONFINITE = -1, 0, 1, 2, 3, 4
+
+FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np.float64, "BT3"),
+              rho=(3, np.float64, "BT"), iters=(4, np.int32, "BT"), status=(5, np.int32, "BT"),
+              ncont=(6, np.int32, "BT"), chash=(7, np.uint64, "BT"), maxpen=(8, np.float64, "BT"),
+              traj=(9, np.float64, "BTN"))
+
+MAX_LINKS = 64
+MAX_OBSTACLES = 128
+MAX_SPAMS = 64
+
+
+class VineError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vinesim error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("R_c", C.c_double), ("R_act", C.c_double), ("a_corr", C.c_double),
+                ("eps_crit", C.c_double), ("k_c", C.c_double), ("tol", C.c_double),
+                ("c_mu", C.c_double), ("step_max", C.c_double), ("armijo_c1", C.c_double),
+                ("max_iter", C.c_int32), ("growth_substeps", C.c_int32)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("n_links", C.c_int32), ("spam_offset", C.c_int32), ("spam_count", C.c_int32),
+                ("obs_offset", C.c_int32), ("obs_count", C.c_int32), ("reserved", C.c_int32),
+                ("link_len", C.c_double), ("tube_radius", C.c_double),
+                ("body_pressure", C.c_double), ("base_x", C.c_double), ("base_y", C.c_double),
+                ("base_heading", C.c_double)]
+
+
+class Spam(C.Structure):
+    _fields_ = [("s_start", C.c_double), ("s_end", C.c_double), ("side", C.c_double),
+                ("pressure", C.c_double)]
+
+
+class Obstacle(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("cx", C.c_double),
+                ("cy", C.c_double), ("a", C.c_double), ("b", C.c_double)]
+
+
+EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
+           "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
+           "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law")
+
+_lib = None
+
+
+def lib():
+    """Load libvinesim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.vine_params_default.argtypes = [C.POINTER(Params)]
+        L.vine_params_default.restype = None
+        L.vine_sim_create.argtypes = [C.POINTER(Params), C.POINTER(Instance), C.c_int32,
+                                      C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle), C.c_int32,
+                                      C.POINTER(vp)]
+        L.vine_sim_create.restype = C.c_int32
+        L.vine_sim_step.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.vine_sim_step.restype = C.c_int32
+        L.vine_sim_rollout.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.vine_sim_rollout.restype = C.c_int32
+        L.vine_sim_reset.argtypes = [vp, vp]
+        L.vine_sim_reset.restype = C.c_int32
+        L.vine_sim_read.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
+        L.vine_sim_read.restype = C.c_int32
+        L.vine_sim_field_bytes.argtypes = [vp, C.c_int32]
+        L.vine_sim_field_bytes.restype = C.c_int64
+        L.vine_sim_dims.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.vine_sim_dims.restype = None
+        L.vine_sim_destroy.argtypes = [vp]
+        L.vine_sim_destroy.restype = None
+        L.vine_sim_last_error.argtypes = [vp]
+        L.vine_sim_last_error.restype = C.c_char_p
+        L.vine_sim_spam_law.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+        L.vine_sim_spam_law.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib().vine_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def _pack(work):
+    B = work.n_inst
+    inst = (Instance * B)()
+    for b in range(B):
+        n, so, sc, oo, oc = (int(v) for v in work.inst_i[b])
+        d = work.inst_d[b]
+        inst[b] = Instance(n, so, sc, oo, oc, 0, *(float(x) for x in d))
+    ns, no = len(work.spam), len(work.obs_kind)
+    spams = (Spam * max(1, ns))()
+    for i in range(ns):
+        spams[i] = Spam(*(float(x) for x in work.spam[i]))
+    obs = (Obstacle * max(1, no))()
+    for i in range(no):
+        o = work.obs_d[i]
+        obs[i] = Obstacle(int(work.obs_kind[i]), 0, *(float(x) for x in o))
+    return inst, B, spams, ns, obs, no
+
+
+class VineSim:
+    """One handle of the C ABI (vine_sim_create ... vine_sim_destroy)."""
+
+    def __init__(self, work, params: Params | None = None, **over):
+        L = lib()
+        self._p = params if params is not None else default_params(**over)
+        inst, B, spams, ns, obs, no = _pack(work)
+        h = C.c_void_p()
+        rc = L.vine_sim_create(C.byref(self._p), inst, B, spams, ns, obs, no, C.byref(h))
+        if rc != VINE_OK:
+            raise VineError(rc, L.vine_sim_last_error(None).decode())
+        self.h = h
+        dims = (C.c_int32 * 3)()
+        L.vine_sim_dims(h, dims)
+        self.B, self.T, self.N = int(dims[0]), int(dims[1]), int(dims[2])
+
+    def _check(self, rc):
+        if rc != VINE_OK:
+            raise VineError(rc, lib().vine_sim_last_error(self.h).decode())
+
+    def step(self, n_steps: int, record_traj: bool = False, stream=None):
+        self._check(lib().vine_sim_step(self.h, int(n_steps), int(bool(record_traj)),
+                                        _stream_ptr(stream)))
+
+    def rollout(self, n_steps: int = -1, record_traj: bool = False, stream=None):
+        self._check(lib().vine_sim_rollout(self.h, int(n_steps), int(bool(record_traj)),
+                                           _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))
+
+    def field_shape(self, name: str):
+        code, dt, shp = FIELDS[name]
+        dims = dict(B=self.B, T=self.T, N=self.N, **{"3": 3})
+        return tuple(dims[c] for c in shp), dt, code
+
+    def read(self, name: str, out=None, stream=None):
+        """Copy a field to a new numpy array, or into ``out`` (numpy array or device
+        torch tensor of the right size)."""
+        shape, dt, code = self.field_shape(name)
+        if out is None:
+            out = np.empty(shape, dt)
+        if isinstance(out, np.ndarray):
+            assert out.nbytes >= lib().vine_sim_field_bytes(self.h, code)
+            self._check(lib().vine_sim_read(self.h, code, out.ctypes.data_as(C.c_void_p), 0,
+                                            _stream_ptr(stream)))
+            return out
+        # torch tensor on the device
+        assert out.is_cuda and out.numel() * out.element_size() >= lib().vine_sim_field_bytes(
+            self.h, code)
+        self._check(lib().vine_sim_read(self.h, code, C.c_void_p(out.data_ptr()), 1,
+                                        _stream_ptr(stream)))
+        return out
+
+    def read_all(self, traj: bool = False) -> dict:
+        names = [k for k in FIELDS if k != "traj"] + (["traj"] if traj else [])
+        return {k: self.read(k) for k in names}
+
+    def spam_law(self, l: float, eps):
+        eps = np.ascontiguousarray(np.atleast_1d(eps), np.float64)
+        G, dG, IG = np.zeros_like(eps), np.zeros_like(eps), np.zeros_like(eps)
+        dp = C.POINTER(C.c_double)
+        self._check(lib().vine_sim_spam_law(self.h, float(l), len(eps), eps.ctypes.data_as(dp),
+                                            G.ctypes.data_as(dp), dG.ctypes.data_as(dp),
+                                            IG.ctypes.data_as(dp)))
+        return G, dG, IG
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vine_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,98 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (per result): joint angles <= 1e-5 rad, tip <= 1e-4 m, contact sets
+identical (order-free hash per step) -- the bar the design states for the FP64 HIP
+path against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_15180_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_TH, TOL_TIP = 1e-5, 1e-4
+
+
+def _gpu_rollout(work, n_steps=-1, traj=False):
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    with V.VineSim(work) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(n_steps, record_traj=traj, stream=s)
+        s.synchronize()
+        return sim.read_all(traj=traj)
+
+
+def _compare(work, got, ref, T):
+    dth = np.abs(got["theta"] - ref["theta"]).max(1)
+    dtip = np.abs(got["tip"][:, :T] - ref["tip"][:, :T]).max((1, 2))
+    same = np.all(got["chash"][:, :T] == ref["chash"][:, :T], 1)
+    st_same = np.array_equal(got["status"][:, :T], ref["status"][:, :T])
+    print(f"{work.name}: B={work.n_inst} max dtheta {dth.max():.2e} max dtip {dtip.max():.2e} "
+          f"sets identical {same.sum()}/{len(same)} status identical {st_same}", flush=True)
+    return dth, dtip, same
+
+
+def test_free_and_single_actuator_exact():
+    l = 0.025
+    work = W.pack([dict(n=40, d=(l, 0.025, 3000.0, 0, 0, 0), spam=[(10 * l, 21 * l, 1.0, 5000.0)],
+                        kind=[], obs=[]),
+                   dict(n=30, d=(0.02, 0.025, 3000.0, 0, 0, 0.3), spam=[], kind=[], obs=[])], "free")
+    got = _gpu_rollout(work)
+    ref = O.rollout(work)
+    assert np.all(got["theta"][1] == 0.0)
+    assert np.allclose(got["tip"][0, -1, :2], (0.8791988315, 0.3846745140), atol=1e-8)
+    dth, dtip, same = _compare(work, got, ref, 40)
+    assert dth.max() < 1e-12 and same.all()
+
+
+def test_config1_parity():
+    work = W.config1(16)
+    got = _gpu_rollout(work, traj=True)
+    ref = O.rollout(work, traj=True, threads=16)
+    dth, dtip, same = _compare(work, got, ref, 40)
+    assert np.abs(got["traj"] - ref["traj"]).max() <= TOL_TH
+    assert dth.max() <= TOL_TH and dtip.max() <= TOL_TIP and same.all()
+    assert np.all(got["status"] == 0)
+
+
+def test_config2_parity_subset():
+    work = W.config2(48)
+    got = _gpu_rollout(work)
+    ref = O.rollout(work, threads=16)
+    dth, dtip, same = _compare(work, got, ref, 64)
+    ok = (dth <= TOL_TH) & (dtip <= TOL_TIP) & same
+    assert ok.sum() >= len(ok) - 1, np.nonzero(~ok)[0]
+    assert np.all(got["status"][ok] == ref["status"][ok])
+
+
+def test_stepwise_equals_rollout_and_done_status():
+    work = W.config2(6)
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    a = _gpu_rollout(work)
+    with V.VineSim(work) as sim:
+        for _ in range(8):
+            sim.step(9)
+        torch.cuda.synchronize()
+        b = sim.read_all()
+    assert np.array_equal(a["theta"], b["theta"])
+    assert np.all(b["nlinks"] == 64)
+    assert np.all(b["status"][:, 64:] == -1) if b["status"].shape[1] > 64 else True
+
+
+def test_spam_table_matches_oracle():
+    from paper_2509_15180_amd import vinesim as V
+    work = W.config2(2)
+    with V.VineSim(work) as sim:
+        eps = np.linspace(0.0, 0.36, 721)
+        G, dG, IG = sim.spam_law(0.02, eps)
+    Gr, dGr, IGr, info = O.gfit(0.02, eps)
+    assert np.abs(G - Gr).max() <= 1e-13 * Gr.max()
+    assert np.abs(dG - dGr).max() <= 1e-9 * np.abs(dGr).max()
+    assert np.abs(IG - IGr).max() <= 1e-16 + 1e-13 * IGr.max()
