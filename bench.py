@@ -1,0 +1,161 @@
+"""Benchmark of the batched growth step on one MI355X.
+
+One bench step = one rollout of the whole batch to full length: 4096 robots of 64
+links (2 cm links, 5 cm tube, 0-4 sPAMs, 10 circles + 10 rectangles), i.e. 64 growth
+steps per robot and 4096 * 2080 = 8.52e6 joint-updates (a joint brought to the
+converged equilibrium of one growth step).
+
+Prints one JSON line with the driver's fields plus:
+  roofline      the rollout kernel against the FP64 VALU peak (see the design doc for the
+                per-joint-evaluation FLOP count), timed with HIP events on the stream
+                the kernel is launched on;
+  per_instance  the same kernel launched once per robot (batch of one), serial on one
+                stream, on a sample of the robots;
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload on the host
+                cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "joint-updates/sec batched vs plain per-instance at 1e-5 rad; p99 rollout latency"
+PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64 (256 CUs x 128 FLOP/clk x 2.4 GHz)
+
+
+def flops_per_joint_eval(K: int) -> float:
+    """Algorithmic FP64 operations of one joint's share of one residual+energy
+    evaluation: pose scan 7, joint moment 150, joint energy 150, residual 18, and
+    two body disks against K obstacles at 8.5 each (transcendentals count 1)."""
+    return 325.0 + 17.0 * K
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
+    ap.add_argument("--cpu-robots", type=int, default=64, help="robots in the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): robots are "
+              f"independent, so several GPUs would each run their own share; not measured here.",
+              flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    from paper_2509_15180_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    work = W.config2(args.batch)
+    K = int(work.inst_i[:, 4].max())
+    ju = work.joint_updates()
+    sim = V.VineSim(work)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        sim.reset(stream=stream)
+        sim.rollout(-1, stream=stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        one_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    out = sim.read_all()
+    jevals = float(out["jevals"].sum())
+    nsolves = float(out["nsolves"].sum())
+    status = out["status"]
+    # kernel-only time of one rollout launch (no reset), same stream
+    sim.reset(stream=stream)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    sim.rollout(-1, stream=stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = k0.elapsed_time(k1)
+    flops = jevals * flops_per_joint_eval(K)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    value = ju / (ms * 1e-3)
+
+    # plain per-instance form: one launch per robot, serial on one stream
+    pi_idx = np.linspace(0, args.batch - 1, args.per_instance).astype(int)
+    sims = [V.VineSim(work.subset([i])) for i in pi_idx]
+    for s in sims:
+        s.rollout(-1, stream=stream)
+    torch.cuda.synchronize()
+    for s in sims:
+        s.reset(stream=stream)
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for s in sims:
+        s.rollout(-1, stream=stream)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    pi_ms = p0.elapsed_time(p1)
+    pi_ju = work.subset(pi_idx).joint_updates()
+    pi_rate = pi_ju / (pi_ms * 1e-3)
+    for s in sims:
+        s.close()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        threads = max(1, min(int(threads), 16))
+        sub = work.subset(np.arange(args.cpu_robots))
+        c0 = time.perf_counter()
+        O.rollout(sub, threads=threads)
+        csec = time.perf_counter() - c0
+        cpu = {"value": sub.joint_updates() / csec, "unit": "joint-updates/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {args.cpu_robots} robots of the same 4096-robot batch, full "
+                         f"rollouts ({sub.joint_updates()} joint-updates in {csec:.1f} s)"}
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "joint-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform batch: {args.batch} robots x 64 links (2 cm), 10 circles "
+                               f"+ 10 rectangles, 0-4 sPAMs; rollout to full length",
+                   "robots": args.batch, "links": 64, "obstacles": K,
+                   "joint_updates_per_step": ju},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "rollout_kernel", "kernel_ms": kern_ms,
+                     "joint_evaluations": jevals, "flop_per_joint_eval": flops_per_joint_eval(K),
+                     "linear_solves": nsolves},
+        "per_instance": {"value": pi_rate, "unit": "joint-updates/s", "robots": int(len(pi_idx)),
+                         "speedup_batched": value / pi_rate},
+        "cpu_baseline": cpu,
+        "quality": {"converged_steps": int((status == 0).sum()),
+                    "other_steps": int(((status != 0) & (status != -1)).sum()),
+                    "max_penetration_m": float(out["maxpen"].max())},
+        "wall_s": wall,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

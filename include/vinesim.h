@@ -121,7 +121,10 @@ typedef enum vine_field {
   VINE_F_NCONTACT = 6, /* int32  [B][T]    (link, obstacle) pairs in contact after each step */
   VINE_F_CHASH = 7,    /* uint64 [B][T]    order-free hash of that contact set */
   VINE_F_MAXPEN = 8,   /* double [B][T]    deepest penetration after each step (m) */
-  VINE_F_TRAJ = 9      /* double [B][T][N] joint angles after each step (when recorded) */
+  VINE_F_TRAJ = 9,     /* double [B][T][N] joint angles after each step (when recorded) */
+  VINE_F_JEVALS = 10,  /* double [B]       work counter: sum over residual evaluations of the
+                          link count (since create or the last reset) */
+  VINE_F_NSOLVES = 11  /* double [B]       work counter: linear solves of the Newton system */
 } vine_field;
 
 typedef struct vine_sim vine_sim;
@@ -182,6 +185,16 @@ const char* vine_sim_last_error(const vine_sim* h);
  * of this simulation. */
 int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* eps, double* G,
                           double* dG, double* IG);
+
+/* Diagnostics: record one row per accepted Newton iteration of robot `robot`
+ * (step, sub-step, iteration, rho, mu, slope, step factor alpha, energy, 0,
+ * contacts) into a device buffer of `capacity` rows on later step/rollout calls.
+ * robot = -1 switches tracing off. */
+int32_t vine_sim_trace(vine_sim* h, int32_t robot, int32_t capacity);
+
+/* Copy up to `capacity` trace rows (10 doubles each) to host memory; returns the
+ * number of rows copied, or a negative VINE_E* code. */
+int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ struct SpamTable {
   double ic[kSpamPieces][kSpamDeg + 2];      // int_{b_k}^{eps} G dx' = sum' ic_j T_j(x), 0 at x=-1
 };
 
-// Integral of the wrinkling moment fraction h (Eq. 2) as a cubic Hermite table in
+// Integral of the wrinkling moment fraction h (Eq. 2) at knots uniform in
 // u = sqrt(x - theta_on) on [0, sqrt(pi - theta_on)].
 constexpr int kIhKnots = 1025;
 
@@ -35,7 +35,6 @@ struct WrTable {
   double h_pi;        // h(pi)
   double ih_pi;       // int_0^pi h
   double val[kIhKnots];   // int_0^{x(u_k)} h
-  double der[kIhKnots];   // d/du of it = 2 u h(x(u))
 };
 
 // Solver and model constants passed by value to the kernels.
@@ -70,6 +69,15 @@ struct KData {
   unsigned long long* chash;
   double* maxpen;
   double* traj;       // [B][T][N] or null
+  // work counters per robot (accumulated over calls)
+  double* jevals;     // [B] sum over residual/energy evaluations of the link count
+  double* nsolves;    // [B] dense (H + mu I) solves
+  // solver trace of one robot (diagnostics): rows of kTraceCols doubles
+  int trace_robot;    // -1: off
+  int trace_cap;      // rows
+  double* trace;      // [cap][kTraceCols]; trace_n[0] counts rows written
+  int* trace_n;
 };
+constexpr int kTraceCols = 10;  // step, substep, iter, rho, mu, slope, alpha, Pi, tries, ncontacts
 
 }  // namespace vs

@@ -254,7 +254,6 @@ void build_wr_table(WrTable* T, double epsc) {
   T->du = T->umax / (vs::kIhKnots - 1);
   const GaussRule& g = gauss48();
   T->val[0] = T->th_on / 4.0;
-  T->der[0] = 0.0;
   for (int k = 1; k < vs::kIhKnots; ++k) {
     double a = T->du * (k - 1), b = T->du * k, c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
     for (int i = 0; i < g.n; ++i) {
@@ -262,8 +261,6 @@ void build_wr_table(WrTable* T, double epsc) {
       s += g.w[i] * h * 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
     }
     T->val[k] = T->val[k - 1] + s;
-    double u = b;
-    T->der[k] = 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
   }
   T->h_pi = wr_h_host(kPi, epsc);
   T->ih_pi = T->val[vs::kIhKnots - 1];
@@ -299,6 +296,11 @@ struct vine_sim {
   unsigned long long* chash = nullptr;
   double* maxpen = nullptr;
   double* traj = nullptr;
+  double* jevals = nullptr;
+  double* nsolves = nullptr;
+  int trace_robot = -1, trace_cap = 0;
+  double* trace = nullptr;
+  int* trace_n = nullptr;
   bool traj_valid = false;
   std::string err;
 };
@@ -313,7 +315,7 @@ int fail(vine_sim* h, int code, const std::string& msg) {
 void free_all(vine_sim* h) {
   void* ptrs[] = {h->ii, h->dd, h->cover, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
-                  h->maxpen, h->traj};
+                  h->maxpen, h->traj, h->jevals, h->nsolves, h->trace, h->trace_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -360,6 +362,12 @@ vs::KData kdata(vine_sim* h) {
   D.chash = h->chash;
   D.maxpen = h->maxpen;
   D.traj = h->traj;
+  D.jevals = h->jevals;
+  D.nsolves = h->nsolves;
+  D.trace_robot = h->trace ? h->trace_robot : -1;
+  D.trace_cap = h->trace_cap;
+  D.trace = h->trace;
+  D.trace_n = h->trace_n;
   return D;
 }
 
@@ -512,6 +520,8 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->chash, B * TT));
   A(dalloc(&h->maxpen, B * TT));
   A(dalloc(&h->traj, B * TT * NN));
+  A(dalloc(&h->jevals, B));
+  A(dalloc(&h->nsolves, B));
   if (e != hipSuccess) {
     free_all(h);
     delete h;
@@ -567,6 +577,8 @@ int32_t vine_sim_reset(vine_sim* h, void* stream) {
   A(hipMemsetAsync(h->ncont, 0, sizeof(int) * B * TT, s));
   A(hipMemsetAsync(h->chash, 0, sizeof(unsigned long long) * B * TT, s));
   A(hipMemsetAsync(h->maxpen, 0, sizeof(double) * B * TT, s));
+  A(hipMemsetAsync(h->jevals, 0, sizeof(double) * B, s));
+  A(hipMemsetAsync(h->nsolves, 0, sizeof(double) * B, s));
   h->traj_valid = false;
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("reset: ") + hipGetErrorString(e));
   return VINE_OK;
@@ -606,6 +618,8 @@ int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {
     case VINE_F_CHASH: return 8 * B * T;
     case VINE_F_MAXPEN: return 8 * B * T;
     case VINE_F_TRAJ: return 8 * B * T * N;
+    case VINE_F_JEVALS: return 8 * B;
+    case VINE_F_NSOLVES: return 8 * B;
     default: return 0;
   }
 }
@@ -629,6 +643,8 @@ int32_t vine_sim_read(const vine_sim* hc, int32_t field, void* dst, int32_t dst_
       if (!h->traj_valid) return fail(h, VINE_ESTATE, "no trajectory was recorded");
       src = h->traj;
       break;
+    case VINE_F_JEVALS: src = h->jevals; break;
+    case VINE_F_NSOLVES: src = h->nsolves; break;
     default: return fail(h, VINE_EINVAL, "unknown field");
   }
   size_t bytes = (size_t)vine_sim_field_bytes(h, field);
@@ -655,6 +671,37 @@ void vine_sim_destroy(vine_sim* h) {
 
 const char* vine_sim_last_error(const vine_sim* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int32_t vine_sim_trace(vine_sim* h, int32_t robot, int32_t capacity) {
+  if (!h || robot < -1 || robot >= h->B || capacity < 0) return fail(h, VINE_EINVAL, "bad arguments");
+  if (h->trace) (void)hipFree(h->trace);
+  if (h->trace_n) (void)hipFree(h->trace_n);
+  h->trace = nullptr;
+  h->trace_n = nullptr;
+  h->trace_robot = -1;
+  h->trace_cap = 0;
+  if (robot < 0 || capacity == 0) return VINE_OK;
+  hipError_t e = dalloc(&h->trace, (size_t)capacity * vs::kTraceCols);
+  if (e == hipSuccess) e = dalloc(&h->trace_n, 1);
+  if (e == hipSuccess) e = hipMemset(h->trace_n, 0, sizeof(int));
+  if (e != hipSuccess) return fail(h, VINE_ENOMEM, "trace buffer");
+  h->trace_robot = robot;
+  h->trace_cap = capacity;
+  return VINE_OK;
+}
+
+int32_t vine_sim_trace_read(const vine_sim* hc, double* dst, int32_t capacity) {
+  vine_sim* h = const_cast<vine_sim*>(hc);
+  if (!h || !dst || !h->trace) return fail(h, VINE_ESTATE, "no trace buffer");
+  int n = 0;
+  hipError_t e = hipMemcpy(&n, h->trace_n, sizeof(int), hipMemcpyDeviceToHost);
+  if (n > capacity) n = capacity;
+  if (n > h->trace_cap) n = h->trace_cap;
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpy(dst, h->trace, sizeof(double) * vs::kTraceCols * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, "trace read");
+  return n;
 }
 
 int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double* eps, double* G,

@@ -113,17 +113,24 @@ __device__ double wr_dh(double x, double epsc, double th_on) {
   return (dnum * den - num * dden) / (den * den) * dg;
 }
 
-// int_0^x wr_h (energy of the body moment per pi P R^3)
-__device__ double wr_int(double x, const WrTable& T) {
+// int_0^x wr_h (energy of the body moment per pi P R^3): the tabulated integral at
+// the knot below u = sqrt(x - theta_on), plus the rest of the interval by two-point
+// Gauss-Legendre in u.  The integrand 2 u h(theta_on + u^2) is smooth in u, so the
+// result and its slope in x (= wr_h) agree with the moment law to round-off, also
+// just above the onset.
+__device__ double wr_int(double x, const WrTable& T, double epsc) {
   if (x <= T.th_on) return x * x / (4.0 * T.th_on);
   if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
   double u = sqrt(x - T.th_on);
-  double s = u / T.du;
-  int k = (int)s;
+  int k = (int)(u / T.du);
   if (k > kIhKnots - 2) k = kIhKnots - 2;
-  double t = s - k, t2 = t * t, t3 = t2 * t;
-  return (2.0 * t3 - 3.0 * t2 + 1.0) * T.val[k] + (t3 - 2.0 * t2 + t) * T.du * T.der[k] +
-         (-2.0 * t3 + 3.0 * t2) * T.val[k + 1] + (t3 - t2) * T.du * T.der[k + 1];
+  double u0 = k * T.du;
+  double c = 0.5 * (u0 + u), h = 0.5 * (u - u0);
+  const double g = 0.57735026918962576451;  // 1/sqrt(3)
+  double ua = c - h * g, ub = c + h * g;
+  double fa = 2.0 * ua * wr_h(T.th_on + ua * ua, epsc, T.th_on);
+  double fb = 2.0 * ub * wr_h(T.th_on + ub * ub, epsc, T.th_on);
+  return T.val[k] + h * (fa + fb);
 }
 
 __device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
@@ -155,6 +162,10 @@ __device__ void spam_law(const SpamTable& T, double eps, double* G, double* dG, 
 
 struct Ctx {
   int n, K;
+  int step, sub;           // for the solver trace
+  double* trace;           // non-null only for the traced robot
+  int* trace_n;
+  int trace_cap;
   double l, R, Mmax, arm, bx, by, bpsi, last_len;
   const SpamTable* tab;
   const WrTable* wr;
@@ -194,7 +205,7 @@ __device__ void joint_law(const Ctx& c, double th, double pp, double pm, double*
     double IGp, IGm;
     spam_law(*c.tab, ep, nullptr, nullptr, &IGp);
     spam_law(*c.tab, em, nullptr, nullptr, &IGm);
-    double Eb = c.Mmax * wr_int(ath, *c.wr);
+    double Eb = c.Mmax * wr_int(ath, *c.wr, epsc);
     double G0 = c.tab->G0;
     double Ea = th >= 0.0 ? (-c.l * pp * IGp + c.arm * pm * G0 * th)
                           : (-c.arm * pp * G0 * th - c.l * pm * IGm);
@@ -255,6 +266,7 @@ struct Smem {
   double cl[kMaxC], cxx[kMaxC], cxy[kMaxC], cnx[kMaxC], cny[kMaxC], ckap[kMaxC], cpen[kMaxC];
   int ncl;
   int overflow;
+  double jevals, nsolves;  // work counters (lane 0 updates)
 };
 
 // Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
@@ -262,6 +274,7 @@ template <int NMAX>
 __device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool want_E) {
   const int lane = threadIdx.x;
   const int n = c.n;
+  if (lane == 0) S.jevals += n;
   double cphi = c.bpsi, cx = c.bx, cy = c.by;
   for (int base = 0; base < n; base += kWave) {
     int j = base + lane;
@@ -475,6 +488,7 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
       assemble(S, c, S.th, mu);
+      if (lane == 0) S.nsolves += 1.0;
       if (!lu_solve(S, n)) continue;
       double s = 0.0;
       for (int j = lane; j < n; j += kWave) s += S.r[j] * S.d[j];
@@ -514,6 +528,15 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
       status = 2;
       break;
     }
+    if (c.trace && lane == 0) {
+      int row = c.trace_n[0];
+      if (row < c.trace_cap) {
+        double* t = c.trace + (size_t)row * kTraceCols;
+        t[0] = c.step; t[1] = c.sub; t[2] = it; t[3] = rho; t[4] = mu; t[5] = slope;
+        t[6] = alpha; t[7] = Pn; t[8] = 0; t[9] = S.ncl;
+        c.trace_n[0] = row + 1;
+      }
+    }
     for (int j = lane; j < n; j += kWave) S.th[j] = S.tt[j];
     Pi = Pn;
     __syncthreads();
@@ -546,6 +569,9 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
   c.tab = D.tables + ii[3];
   c.wr = D.wr;
   c.P = P;
+  c.trace = (b == D.trace_robot) ? D.trace : nullptr;
+  c.trace_n = D.trace_n;
+  c.trace_cap = D.trace_cap;
   for (int k = lane; k < c.K; k += kWave) {
     const double* o = D.obs + 4 * (size_t)(ii[1] + k);
     S.obs[k][0] = o[0];
@@ -560,6 +586,10 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
   }
   int n = D.ncur[b];
   int t = D.tcur[b];
+  if (lane == 0) {
+    S.jevals = 0.0;
+    S.nsolves = 0.0;
+  }
   for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
   __syncthreads();
   for (int step = 0; step < n_steps && t < D.t_max; ++step, ++t) {
@@ -572,6 +602,8 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
       c.n = n;
       for (int s = 1; s <= P.substeps; ++s) {
         c.last_len = c.l * (double)s / (double)P.substeps;
+        c.step = t;
+        c.sub = s;
         int st = solve(S, c, its, rho);
         st_worst = st > st_worst ? st : st_worst;
       }
@@ -625,6 +657,8 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
   if (lane == 0) {
     D.ncur[b] = n;
     D.tcur[b] = t;
+    D.jevals[b] += S.jevals;
+    D.nsolves[b] += S.nsolves;
   }
 }
 

@@ -24,7 +24,8 @@ ST_DONE, ST_CONVERGED, ST_MAXITER, ST_NODESCENT, ST_CAPACITY, ST_NONFINITE = -1,
 FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np.float64, "BT3"),
               rho=(3, np.float64, "BT"), iters=(4, np.int32, "BT"), status=(5, np.int32, "BT"),
               ncont=(6, np.int32, "BT"), chash=(7, np.uint64, "BT"), maxpen=(8, np.float64, "BT"),
-              traj=(9, np.float64, "BTN"))
+              traj=(9, np.float64, "BTN"), jevals=(10, np.float64, "B"),
+              nsolves=(11, np.float64, "B"))
 
 MAX_LINKS = 64
 MAX_OBSTACLES = 128
@@ -64,7 +65,8 @@ class Obstacle(C.Structure):
 
 EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
-           "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law")
+           "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
+           "vine_sim_trace_read")
 
 _lib = None
 
@@ -103,6 +105,10 @@ def lib():
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.vine_sim_spam_law.restype = C.c_int32
+        L.vine_sim_trace.argtypes = [vp, C.c_int32, C.c_int32]
+        L.vine_sim_trace.restype = C.c_int32
+        L.vine_sim_trace_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
+        L.vine_sim_trace_read.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -207,6 +213,19 @@ class VineSim:
                                             G.ctypes.data_as(dp), dG.ctypes.data_as(dp),
                                             IG.ctypes.data_as(dp)))
         return G, dG, IG
+
+    def trace(self, robot: int, capacity: int = 100000):
+        """Record the solver decisions of one robot on later step/rollout calls."""
+        self._check(lib().vine_sim_trace(self.h, int(robot), int(capacity)))
+        self._trace_cap = int(capacity)
+
+    def trace_read(self):
+        buf = np.zeros((self._trace_cap, 10))
+        n = lib().vine_sim_trace_read(self.h, buf.ctypes.data_as(C.POINTER(C.c_double)),
+                                      self._trace_cap)
+        if n < 0:
+            self._check(n)
+        return buf[:n]
 
     def close(self):
         if getattr(self, "h", None):
