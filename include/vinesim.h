@@ -71,6 +71,9 @@ typedef struct vine_params {
   double armijo_c1;      /* sufficient-decrease constant of the line search */
   int32_t max_iter;      /* Newton iterations per equilibrium solve */
   int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
+  int32_t solver;        /* 0: structured O(n) solve of the Newton system (default);
+                            1: dense LU with partial pivoting (chains of <= 64 links; cross-check) */
+  int32_t reserved;
 } vine_params;
 
 /* One robot.  n_links: target link count (1..VINE_MAX_LINKS).  Its sPAMs are
@@ -105,7 +108,7 @@ typedef struct vine_obstacle {
   double cx, cy, a, b;
 } vine_obstacle;
 
-#define VINE_MAX_LINKS 64    /* links per robot */
+#define VINE_MAX_LINKS 512   /* links per robot */
 #define VINE_MAX_OBSTACLES 128
 #define VINE_MAX_SPAMS 64
 

@@ -41,6 +41,7 @@ struct WrTable {
 struct KParams {
   double epsc, kc, tol, c_mu, step_max, c1, Ract;
   int max_iter, substeps;
+  int dense_solver;   // 1: dense LU cross-check solver (chains of <= 64 links)
 };
 
 // Per-robot and per-simulation device arrays (structure of arrays).

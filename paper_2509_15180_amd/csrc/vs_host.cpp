@@ -336,6 +336,7 @@ vs::KParams kparams(const vine_params& p) {
   k.Ract = p.R_act;
   k.max_iter = p.max_iter;
   k.substeps = p.growth_substeps;
+  k.dense_solver = p.solver == 1;
   return k;
 }
 
@@ -388,6 +389,8 @@ void vine_params_default(vine_params* p) {
   p->armijo_c1 = 1e-4;
   p->max_iter = 500;
   p->growth_substeps = 2;
+  p->solver = 0;
+  p->reserved = 0;
 }
 
 int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, int32_t n_inst,
@@ -401,7 +404,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       !std::isfinite(p.a_corr) || !(p.eps_crit > 0.0 && p.eps_crit < 1.0) || !finite_pos(p.k_c) ||
       !finite_pos(p.tol) || !(p.c_mu >= 0.0) || !std::isfinite(p.c_mu) ||
       !finite_pos(p.step_max) || !(p.armijo_c1 > 0.0 && p.armijo_c1 < 1.0) || p.max_iter < 0 ||
-      p.growth_substeps < 1)
+      p.growth_substeps < 1 || !(p.solver == 0 || p.solver == 1))
     return fail(nullptr, VINE_EINVAL, "invalid vine_params");
   int N = 0;
   for (int b = 0; b < n_inst; ++b) {
@@ -435,6 +438,8 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     }
     if (I.n_links > N) N = I.n_links;
   }
+  if (p.solver == 1 && N > 64)
+    return fail(nullptr, VINE_ECAPACITY, "the dense cross-check solver holds at most 64 links");
   vine_sim* h = new (std::nothrow) vine_sim();
   if (!h) return fail(nullptr, VINE_ENOMEM, "host allocation failed");
   h->prm = p;

@@ -254,12 +254,34 @@ __device__ __forceinline__ double obs_dist(int kind, const double* o, double x, 
 // ---------------------------------------------------------------------------
 // LDS working set of one robot
 
+constexpr int kMaxCL = 16;             // contact links the structured solve holds
+constexpr int kMaxCols = 3 * kMaxCL;   // columns of its low-rank term
+
 template <int NMAX>
 struct Smem {
-  double W[NMAX][NMAX + 1];  // (H + mu I | -r), LU in place
+  static constexpr int WN = NMAX == 64 ? 64 : 1;  // dense cross-check solver (64 links)
+  union {
+    double W[WN][WN + 1];                           // (H + mu I | -r), LU in place
+    struct {
+      double G[kMaxCols][kMaxCols];                 // U^T T^-1 U
+      double K[kMaxCols][kMaxCols + 1];             // (I + S G | S c), LU in place
+    } sm;
+  };
   double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
   double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
   double pp[NMAX], pm[NMAX];
+  // structured solve
+  double dq[NMAX];     // joint stiffness q'_j
+  double cg[NMAX];     // geometric stiffness, diagonal in absolute angles
+  double dinv[NMAX];   // 1 / pivots of the tridiagonal part
+  double ell[NMAX];    // its unit lower multipliers
+  double z[NMAX], v[NMAX], aux[NMAX];
+  double ps1[NMAX], ps2[NMAX];
+  int lidx[NMAX];      // link -> contact-link slot (or -1)
+  int clink[kMaxCL];   // contact-link slot -> link
+  double cM[kMaxCL][6];  // 3x3 contact block per contact link (symmetric: 00 01 02 11 12 22)
+  double cvec[kMaxCols], wvec[kMaxCols];
+  int ncl_links;
   double obs[kMaxObs][4];
   int okind[kMaxObs];
   int ci[kMaxC], ck[kMaxC];
@@ -408,16 +430,16 @@ __device__ void assemble(Smem<NMAX>& S, const Ctx& c, const double* th, double m
   }
 }
 
-// LU with partial pivoting of W (n x n | rhs); solution into S.d.  false on a zero
-// pivot or a non-finite solution.
-template <int NMAX>
-__device__ bool lu_solve(Smem<NMAX>& S, int n) {
+// LU with partial pivoting of the n x n system stored row-major in A (row stride ld,
+// right-hand side in column n); solution into x.  false on a zero pivot or a
+// non-finite solution.
+__device__ bool lu_solve(double* A, int ld, int n, double* x) {
   const int lane = threadIdx.x;
   for (int k = 0; k < n; ++k) {
     double best = -1.0;
     int bi = k;
     for (int i = k + lane; i < n; i += kWave) {
-      double v = fabs(S.W[i][k]);
+      double v = fabs(A[i * ld + k]);
       if (v > best) {
         best = v;
         bi = i;
@@ -427,34 +449,288 @@ __device__ bool lu_solve(Smem<NMAX>& S, int n) {
     if (!(best > 0.0)) return false;
     if (bi != k) {
       for (int j = k + lane; j <= n; j += kWave) {
-        double t = S.W[k][j];
-        S.W[k][j] = S.W[bi][j];
-        S.W[bi][j] = t;
+        double t = A[k * ld + j];
+        A[k * ld + j] = A[bi * ld + j];
+        A[bi * ld + j] = t;
       }
       __syncthreads();
     }
-    const double piv = S.W[k][k];
+    const double piv = A[k * ld + k];
     for (int i = k + 1 + lane; i < n; i += kWave) {
-      double f = S.W[i][k] / piv;
+      double f = A[i * ld + k] / piv;
       if (f != 0.0)
-        for (int j = k; j <= n; ++j) S.W[i][j] -= f * S.W[k][j];
+        for (int j = k; j <= n; ++j) A[i * ld + j] -= f * A[k * ld + j];
     }
     __syncthreads();
   }
-  // back substitution, column by column
   for (int i = n - 1; i >= 0; --i) {
-    double xi = S.W[i][n] / S.W[i][i];
-    for (int j = lane; j < i; j += kWave) S.W[j][n] -= S.W[j][i] * xi;
-    if (lane == 0) S.d[i] = xi;
+    double xi = A[i * ld + n] / A[i * ld + i];
+    for (int j = lane; j < i; j += kWave) A[j * ld + n] -= A[j * ld + i] * xi;
+    if (lane == 0) x[i] = xi;
     __syncthreads();
   }
   bool ok = true;
-  for (int j = lane; j < n; j += kWave) ok = ok && isfinite(S.d[j]);
+  for (int j = lane; j < n; j += kWave) ok = ok && isfinite(x[j]);
   return __all(ok);
 }
 
-// One equilibrium solve from S.th (in place).  Returns the status code.
 template <int NMAX>
+__device__ bool lu_solve_dense(Smem<NMAX>& S, int n) {
+  return lu_solve(&S.W[0][0], Smem<NMAX>::WN + 1, n, S.d);
+}
+
+// Per-iteration set-up of the structured solve (independent of mu): joint slopes,
+// the contact links, their 3x3 blocks, and the geometric diagonal.
+//
+// In absolute angles phi = L theta (L: lower-triangular ones), the exact Hessian is
+//   H_phi = L^-T diag(q') L^-1 + diag(C) + sum_{contact links i} U_i M_i U_i^T,
+// with U_i = [X_i, Y_i, e_i], X_i = (l cos phi_m)_{m<i}, Y_i = (l sin phi_m)_{m<i},
+//   C_m = l t_m . (sum of contact forces on links beyond m) + sum_{disks on m} lam s n.t_m,
+//   M_i = sum_{disks on i} k_c alpha alpha^T - lam kappa beta beta^T,
+//   alpha = (n_y, -n_x, s t_i x n), beta = (n_x, n_y, s t_i . n),
+// s the disk's distance from the link's proximal joint.  Returns false when more
+// than kMaxCL links are in contact.
+template <int NMAX>
+__device__ bool structured_setup(Smem<NMAX>& S, const Ctx& c) {
+  const int lane = threadIdx.x, n = c.n, nc = S.ncl;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int j = lane; j < n; j += kWave) {
+    double d;
+    joint_law(c, S.th[j], S.pp[j], S.pm[j], nullptr, &d, nullptr);
+    S.dq[j] = d;
+    S.lidx[j] = -1;
+  }
+  __syncthreads();
+  for (int e = lane; e < nc; e += kWave) S.lidx[S.ci[e]] = 0;
+  __syncthreads();
+  int L = 0;
+  for (int base = 0; base < n; base += kWave) {
+    int j = base + lane;
+    bool f = j < n && S.lidx[j] == 0;
+    unsigned long long m = __ballot(f);
+    if (f) {
+      int pos = L + __popcll(m & lt);
+      S.lidx[j] = pos < kMaxCL ? pos : kMaxCL;
+      if (pos < kMaxCL) S.clink[pos] = j;
+    }
+    L += __popcll(m);
+  }
+  if (lane == 0) S.ncl_links = L;
+  __syncthreads();
+  if (L > kMaxCL) return false;
+  // 3x3 blocks, one lane per contact link (contacts visited in list order)
+  for (int a = lane; a < L; a += kWave) {
+    const int i = S.clink[a];
+    const double ti_x = S.tx[i], ti_y = S.ty[i];
+    double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0;
+    for (int e = 0; e < nc; ++e) {
+      if (S.ci[e] != i) continue;
+      const double nx = S.cnx[e], ny = S.cny[e], lam = S.cl[e], lk = lam * S.ckap[e];
+      const double s = (S.cxx[e] - S.px[i]) * ti_x + (S.cxy[e] - S.py[i]) * ti_y;
+      const double a0 = ny, a1 = -nx, a2 = s * (ti_x * ny - ti_y * nx);
+      const double b0 = nx, b1 = ny, b2 = s * (ti_x * nx + ti_y * ny);
+      const double kc = c.P.kc;
+      m0 += kc * a0 * a0 - lk * b0 * b0;
+      m1 += kc * a0 * a1 - lk * b0 * b1;
+      m2 += kc * a0 * a2 - lk * b0 * b2;
+      m3 += kc * a1 * a1 - lk * b1 * b1;
+      m4 += kc * a1 * a2 - lk * b1 * b2;
+      m5 += kc * a2 * a2 - lk * b2 * b2;
+    }
+    S.cM[a][0] = m0;
+    S.cM[a][1] = m1;
+    S.cM[a][2] = m2;
+    S.cM[a][3] = m3;
+    S.cM[a][4] = m4;
+    S.cM[a][5] = m5;
+  }
+  // geometric diagonal: suffix sums of per-link forces, chunks from the tip down
+  double cfx = 0.0, cfy = 0.0;
+  const int nchunk = (n + kWave - 1) / kWave;
+  for (int ch = nchunk - 1; ch >= 0; --ch) {
+    const int j = ch * kWave + lane;
+    double fx = 0.0, fy = 0.0, q = 0.0;
+    if (j < n && S.lidx[j] >= 0) {
+      const double tjx = S.tx[j], tjy = S.ty[j];
+      for (int e = 0; e < nc; ++e) {
+        if (S.ci[e] != j) continue;
+        const double lam = S.cl[e], nx = S.cnx[e], ny = S.cny[e];
+        const double s = (S.cxx[e] - S.px[j]) * tjx + (S.cxy[e] - S.py[j]) * tjy;
+        fx += lam * nx;
+        fy += lam * ny;
+        q += lam * s * (nx * tjx + ny * tjy);
+      }
+    }
+    double sx = wscan_suffix(fx, lane) + cfx, sy = wscan_suffix(fy, lane) + cfy;
+    if (j < n) S.cg[j] = c.l * (S.tx[j] * (sx - fx) + S.ty[j] * (sy - fy)) + q;
+    cfx = __shfl(sx, 0, kWave);
+    cfy = __shfl(sy, 0, kWave);
+  }
+  __syncthreads();
+  return true;
+}
+
+// value of low-rank column col (contact-link slot col/3, kind col%3) at row m
+template <int NMAX>
+__device__ __forceinline__ double ucol(const Smem<NMAX>& S, double l, int col, int m, double cm,
+                                       double sm) {
+  const int i = S.clink[col / 3], k = col % 3;
+  if (k == 2) return m == i ? 1.0 : 0.0;
+  if (m >= i) return 0.0;
+  return k == 0 ? l * cm : l * sm;
+}
+
+// Solve T y = b in place (b in S.aux, result in dst) with the factors in S.dinv/S.ell.
+template <int NMAX>
+__device__ void tri_solve(Smem<NMAX>& S, int n, const double* b, double* dst) {
+  const int lane = threadIdx.x;
+  if (lane == 0) {
+    double y = b[0];
+    S.aux[0] = y;
+    for (int m = 1; m < n; ++m) {
+      y = b[m] - S.ell[m - 1] * y;
+      S.aux[m] = y;
+    }
+    double x = S.aux[n - 1] * S.dinv[n - 1];
+    dst[n - 1] = x;
+    for (int m = n - 2; m >= 0; --m) {
+      x = S.aux[m] * S.dinv[m] - S.ell[m] * x;
+      dst[m] = x;
+    }
+  }
+  __syncthreads();
+}
+
+// (H + mu I) d = -r through the structure above: factor the tridiagonal part, then
+// Woodbury for the contact blocks.  Result into S.d.  false on a vanishing pivot or
+// a failed small solve.
+template <int NMAX>
+__device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu) {
+  const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
+  // tridiagonal part: T_mm = k_m + k_{m+1} + C_m, T_{m,m+1} = -k_{m+1}, k_j = q'_j + mu
+  bool ok = true;
+  if (lane == 0) {
+    double kprev = S.dq[0] + mu;
+    double knext = n > 1 ? S.dq[1] + mu : 0.0;
+    double d = kprev + knext + S.cg[0];
+    ok = isfinite(d) && fabs(d) > 1e-14 * (fabs(kprev) + fabs(knext) + fabs(S.cg[0]));
+    S.dinv[0] = 1.0 / d;
+    for (int m = 1; m < n && ok; ++m) {
+      const double km = knext;                          // k_m
+      const double kn = m + 1 < n ? S.dq[m + 1] + mu : 0.0;
+      const double e = -km;                             // T_{m-1,m}
+      const double lm = e / d;                          // multiplier
+      S.ell[m - 1] = lm;
+      const double tmm = km + kn + S.cg[m];
+      d = tmm - lm * e;
+      ok = isfinite(d) && fabs(d) > 1e-14 * (fabs(tmm) + fabs(e));
+      S.dinv[m] = 1.0 / d;
+      knext = kn;
+    }
+    S.ell[n - 1] = 0.0;
+    S.aux[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  ok = S.aux[0] != 0.0;
+  if (!ok) return false;
+  // right-hand side in absolute angles: b_m = -(r_m - r_{m+1})
+  for (int m = lane; m < n; m += kWave) S.v[m] = -(S.r[m] - (m + 1 < n ? S.r[m + 1] : 0.0));
+  __syncthreads();
+  tri_solve(S, n, S.v, S.z);
+  if (L > 0) {
+    const int ncol = 3 * L;
+    // c = U^T z: exclusive prefix sums of l cos(phi) z and l sin(phi) z
+    double c1 = 0.0, c2 = 0.0;
+    for (int base = 0; base < n; base += kWave) {
+      const int m = base + lane;
+      const double a = m < n ? c.l * S.tx[m] * S.z[m] : 0.0;
+      const double b = m < n ? c.l * S.ty[m] * S.z[m] : 0.0;
+      const double ia = wscan_incl(a, lane) + c1, ib = wscan_incl(b, lane) + c2;
+      if (m < n) {
+        S.ps1[m] = ia - a;
+        S.ps2[m] = ib - b;
+      }
+      c1 = __shfl(ia, kWave - 1, kWave);
+      c2 = __shfl(ib, kWave - 1, kWave);
+    }
+    __syncthreads();
+    for (int a = lane; a < L; a += kWave) {
+      const int i = S.clink[a];
+      S.cvec[3 * a + 0] = S.ps1[i];
+      S.cvec[3 * a + 1] = S.ps2[i];
+      S.cvec[3 * a + 2] = S.z[i];
+    }
+    // G = U^T T^-1 U = sum_m y_m y_m^T / d_m, y = L_T^-1 U; one lane per (a <= b) pair
+    const int npair = ncol * (ncol + 1) / 2;
+    for (int p0 = 0; p0 < npair; p0 += kWave) {
+      const int p = p0 + lane;
+      int a = 0, b = 0;
+      if (p < npair) {
+        int rem = p;
+        while (rem >= ncol - a) {
+          rem -= ncol - a;
+          ++a;
+        }
+        b = a + rem;
+      }
+      double ya = 0.0, yb = 0.0, g = 0.0;
+      for (int m = 0; m < n; ++m) {
+        const double cm = S.tx[m], sm = S.ty[m], lm1 = m > 0 ? S.ell[m - 1] : 0.0;
+        ya = ucol(S, c.l, a, m, cm, sm) - lm1 * ya;
+        yb = ucol(S, c.l, b, m, cm, sm) - lm1 * yb;
+        g += ya * yb * S.dinv[m];
+      }
+      if (p < npair) {
+        S.sm.G[a][b] = g;
+        S.sm.G[b][a] = g;
+      }
+    }
+    __syncthreads();
+    // K = I + S G with S = blockdiag(M_a); right-hand side S c
+    for (int row = lane; row < ncol; row += kWave) {
+      const int blk = row / 3, r3 = row % 3;
+      const double* M = S.cM[blk];
+      const double s0 = r3 == 0 ? M[0] : (r3 == 1 ? M[1] : M[2]);
+      const double s1 = r3 == 0 ? M[1] : (r3 == 1 ? M[3] : M[4]);
+      const double s2 = r3 == 0 ? M[2] : (r3 == 1 ? M[4] : M[5]);
+      const int c0 = 3 * blk;
+      for (int col = 0; col < ncol; ++col)
+        S.sm.K[row][col] = (row == col ? 1.0 : 0.0) + s0 * S.sm.G[c0][col] +
+                           s1 * S.sm.G[c0 + 1][col] + s2 * S.sm.G[c0 + 2][col];
+      S.sm.K[row][ncol] = s0 * S.cvec[c0] + s1 * S.cvec[c0 + 1] + s2 * S.cvec[c0 + 2];
+    }
+    __syncthreads();
+    if (!lu_solve(&S.sm.K[0][0], kMaxCols + 1, ncol, S.wvec)) return false;
+    // correction: T v = U w, d_phi = z - v
+    for (int m = lane; m < n; m += kWave) {
+      double u = 0.0;
+      for (int a = 0; a < L; ++a) {
+        const int i = S.clink[a];
+        if (m < i) u += c.l * (S.tx[m] * S.wvec[3 * a] + S.ty[m] * S.wvec[3 * a + 1]);
+        else if (m == i) u += S.wvec[3 * a + 2];
+      }
+      S.aux[m] = u;
+    }
+    __syncthreads();
+    for (int m = lane; m < n; m += kWave) S.ps1[m] = S.aux[m];
+    __syncthreads();
+    tri_solve(S, n, S.ps1, S.v);
+    for (int m = lane; m < n; m += kWave) S.z[m] -= S.v[m];
+    __syncthreads();
+  }
+  // back to relative angles
+  bool fin = true;
+  for (int j = lane; j < n; j += kWave) {
+    const double dj = S.z[j] - (j > 0 ? S.z[j - 1] : 0.0);
+    S.d[j] = dj;
+    fin = fin && isfinite(dj);
+  }
+  __syncthreads();
+  return __all(fin);
+}
+
+// One equilibrium solve from S.th (in place).  Returns the status code.
+template <int NMAX, bool DENSE>
 __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
   const int lane = threadIdx.x, n = c.n;
   const KParams& P = c.P;
@@ -485,11 +761,20 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
     ++iters;
     bool ok = false;
     double slope = 0.0, mu = P.c_mu * rm;
+    const bool dense = DENSE || !structured_setup(S, c);
+    if (dense && Smem<NMAX>::WN < n) {
+      status = 3;  // more contact links than the structured solve holds
+      break;
+    }
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
-      assemble(S, c, S.th, mu);
       if (lane == 0) S.nsolves += 1.0;
-      if (!lu_solve(S, n)) continue;
+      if (dense) {
+        assemble(S, c, S.th, mu);
+        if (!lu_solve_dense(S, n)) continue;
+      } else if (!structured_solve(S, c, mu)) {
+        continue;
+      }
       double s = 0.0;
       for (int j = lane; j < n; j += kWave) s += S.r[j] * S.d[j];
       slope = wsum(s);
@@ -547,7 +832,7 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
 
 // ---------------------------------------------------------------------------
 
-template <int NMAX>
+template <int NMAX, bool DENSE>
 __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int n_steps,
                                                         int record_traj) {
   __shared__ Smem<NMAX> S;
@@ -604,7 +889,7 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
         c.last_len = c.l * (double)s / (double)P.substeps;
         c.step = t;
         c.sub = s;
-        int st = solve(S, c, its, rho);
+        int st = solve<NMAX, DENSE>(S, c, its, rho);
         st_worst = st > st_worst ? st : st_worst;
       }
     } else {
@@ -666,10 +951,25 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
                           int nmax_class, hipStream_t stream) {
   dim3 grid(D.n_inst), block(kWave);
-  if (nmax_class <= 64)
-    hipLaunchKernelGGL(rollout_kernel<64>, grid, block, 0, stream, P, D, n_steps, record_traj);
-  else
+  if (P.dense_solver) {
+    if (nmax_class > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((rollout_kernel<64, true>), grid, block, 0, stream, P, D, n_steps,
+                       record_traj);
+  } else if (nmax_class <= 64) {
+    hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
+                       record_traj);
+  } else if (nmax_class <= 128) {
+    hipLaunchKernelGGL((rollout_kernel<128, false>), grid, block, 0, stream, P, D, n_steps,
+                       record_traj);
+  } else if (nmax_class <= 256) {
+    hipLaunchKernelGGL((rollout_kernel<256, false>), grid, block, 0, stream, P, D, n_steps,
+                       record_traj);
+  } else if (nmax_class <= 512) {
+    hipLaunchKernelGGL((rollout_kernel<512, false>), grid, block, 0, stream, P, D, n_steps,
+                       record_traj);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

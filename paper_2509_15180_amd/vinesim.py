@@ -27,7 +27,7 @@ FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np
               traj=(9, np.float64, "BTN"), jevals=(10, np.float64, "B"),
               nsolves=(11, np.float64, "B"))
 
-MAX_LINKS = 64
+MAX_LINKS = 512
 MAX_OBSTACLES = 128
 MAX_SPAMS = 64
 
@@ -42,7 +42,8 @@ class Params(C.Structure):
     _fields_ = [("R_c", C.c_double), ("R_act", C.c_double), ("a_corr", C.c_double),
                 ("eps_crit", C.c_double), ("k_c", C.c_double), ("tol", C.c_double),
                 ("c_mu", C.c_double), ("step_max", C.c_double), ("armijo_c1", C.c_double),
-                ("max_iter", C.c_int32), ("growth_substeps", C.c_int32)]
+                ("max_iter", C.c_int32), ("growth_substeps", C.c_int32), ("solver", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Instance(C.Structure):

@@ -96,3 +96,38 @@ def test_spam_table_matches_oracle():
     assert np.abs(G - Gr).max() <= 1e-13 * Gr.max()
     assert np.abs(dG - dGr).max() <= 1e-9 * np.abs(dGr).max()
     assert np.abs(IG - IGr).max() <= 1e-16 + 1e-13 * IGr.max()
+
+
+def _gpu_rollout_p(work, **over):
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    with V.VineSim(work, V.default_params(**over)) as sim:
+        sim.rollout(-1)
+        torch.cuda.synchronize()
+        return sim.read_all()
+
+
+def test_structured_solver_matches_dense_lu():
+    work = W.config2(24)
+    a = _gpu_rollout_p(work, solver=0)
+    b = _gpu_rollout_p(work, solver=1)
+    dth = np.abs(a["theta"] - b["theta"]).max(1)
+    print(f"structured vs dense: max dtheta {dth.max():.2e}, iters {a['iters'].sum()} vs "
+          f"{b['iters'].sum()}", flush=True)
+    assert (dth <= 1e-8).sum() >= len(dth) - 1
+
+
+def test_long_chains_vs_oracle():
+    # uneven batch (config 3) robots up to 128 links and the 96-link differentiation robots
+    full3 = W.config3(200)
+    idx = [i for i in range(200) if full3.inst_i[i, 0] <= 128][:10]
+    work = W.pack([full3.instance(i) for i in idx] + [W.config4(4).instance(i) for i in range(4)],
+                  "long")
+    got = _gpu_rollout(work)
+    ref = O.rollout(work, threads=16)
+    T = work.n_max
+    dth, dtip, same = _compare(work, got, ref, T)
+    ok = (dth <= TOL_TH) & (dtip <= TOL_TIP) & same
+    assert ok.sum() >= len(ok) - 1, np.nonzero(~ok)[0]
