@@ -24,17 +24,21 @@ struct SpamTable {
   double ic[kSpamPieces][kSpamDeg + 2];      // int_{b_k}^{eps} G dx' = sum' ic_j T_j(x), 0 at x=-1
 };
 
-// Integral of the wrinkling moment fraction h (Eq. 2) at knots uniform in
-// u = sqrt(x - theta_on) on [0, sqrt(pi - theta_on)].
-constexpr int kIhKnots = 1025;
+// Integral of the wrinkling moment fraction h (Eq. 2): in u = sqrt(x - theta_on) on
+// [0, sqrt(pi - theta_on)], pieces of equal width du; on piece k the integrand
+// 2 u h(theta_on + u^2) is a Chebyshev series whose antiderivative (zero at the piece's
+// left end, variable t in [-1, 1]) is stored.
+constexpr int kIhPieces = 32;
+constexpr int kIhDeg = 16;
 
 struct WrTable {
   double th_on;       // 2 asin(eps_crit)
   double umax;        // sqrt(pi - th_on)
-  double du;          // knot spacing in u
+  double du;          // piece width in u
   double h_pi;        // h(pi)
   double ih_pi;       // int_0^pi h
-  double val[kIhKnots];   // int_0^{x(u_k)} h
+  double cum[kIhPieces + 1];          // int_0^{x(u_k)} h at piece boundaries
+  double ic[kIhPieces][kIhDeg + 2];   // per piece: antiderivative series in t
 };
 
 // Solver and model constants passed by value to the kernels.

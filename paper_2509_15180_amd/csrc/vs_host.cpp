@@ -249,21 +249,30 @@ double wr_h_host(double x, double epsc) {
 
 void build_wr_table(WrTable* T, double epsc) {
   std::memset(T, 0, sizeof(*T));
+  constexpr int P = vs::kIhPieces, D = vs::kIhDeg;
   T->th_on = 2.0 * std::asin(epsc);
   T->umax = std::sqrt(kPi - T->th_on);
-  T->du = T->umax / (vs::kIhKnots - 1);
-  const GaussRule& g = gauss48();
-  T->val[0] = T->th_on / 4.0;
-  for (int k = 1; k < vs::kIhKnots; ++k) {
-    double a = T->du * (k - 1), b = T->du * k, c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
-    for (int i = 0; i < g.n; ++i) {
-      double u = c + h * g.x[i];
-      s += g.w[i] * h * 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
+  T->du = T->umax / P;
+  T->cum[0] = T->th_on / 4.0;
+  std::vector<double> f(D + 1);
+  double c[D + 1], av[D + 3];
+  for (int k = 0; k < P; ++k) {
+    const double a = k * T->du, b = a + T->du;
+    for (int q = 0; q <= D; ++q) {
+      const double t = std::cos(kPi * (q + 0.5) / (D + 1));
+      const double u = 0.5 * (a + b) + 0.5 * (b - a) * t;
+      f[q] = 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
     }
-    T->val[k] = T->val[k - 1] + s;
+    cheb_coeffs(f, D, c);
+    for (int j = 0; j <= D + 2; ++j) av[j] = j <= D ? c[j] : 0.0;
+    av[0] *= 2.0;
+    for (int j = 1; j <= D + 1; ++j) T->ic[k][j] = (av[j - 1] - av[j + 1]) / (2.0 * j);
+    T->ic[k][0] = 0.0;
+    T->ic[k][0] = -cheb_eval_host(T->ic[k], D + 1, -1.0);
+    T->cum[k + 1] = T->cum[k] + 0.5 * T->du * cheb_eval_host(T->ic[k], D + 1, 1.0);
   }
   T->h_pi = wr_h_host(kPi, epsc);
-  T->ih_pi = T->val[vs::kIhKnots - 1];
+  T->ih_pi = T->cum[P];
 }
 
 thread_local std::string g_create_error;

@@ -30,34 +30,50 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // wave primitives (blockDim == 64: one wave per block)
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+// DPP moves of a double (both halves with the same pattern; lanes whose source is
+// out of the row, or whose row is masked off, read 0)
+template <int CTRL, int ROWMASK = 0xf, int BANKMASK = 0xf, bool BOUND = true>
+__device__ __forceinline__ double dpp(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, BANKMASK, BOUND);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, BANKMASK, BOUND);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// inclusive prefix sum over the 64 lanes: shifts within 16-lane rows, then the row
+// broadcasts of lanes 15 and 31 (all lanes must be active)
+__device__ __forceinline__ double wscan_incl(double v, int /*lane*/) {
+  v += dpp<0x111>(v);                   // row_shr:1
+  v += dpp<0x112>(v);                   // row_shr:2
+  v += dpp<0x114>(v);                   // row_shr:4
+  v += dpp<0x118>(v);                   // row_shr:8
+  v += dpp<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-__device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
-}
+__device__ __forceinline__ double wsum(double v) { return lane_bcast(wscan_incl(v, 0), kWave - 1); }
 
-__device__ __forceinline__ double wscan_incl(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    double t = __shfl_up(v, o, kWave);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
+// inclusive suffix sum: total minus the exclusive prefix
 __device__ __forceinline__ double wscan_suffix(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    double t = __shfl_down(v, o, kWave);
-    if (lane + o < kWave) v += t;
-  }
-  return v;
+  double incl = wscan_incl(v, lane);
+  return lane_bcast(incl, kWave - 1) - incl + v;
+}
+
+__device__ __forceinline__ double wmax(double v) {  // arguments are >= 0
+  v = fmax(v, dpp<0x111>(v));
+  v = fmax(v, dpp<0x112>(v));
+  v = fmax(v, dpp<0x114>(v));
+  v = fmax(v, dpp<0x118>(v));
+  v = fmax(v, dpp<0x142, 0xa, 0xf, false>(v));
+  v = fmax(v, dpp<0x143, 0xc, 0xf, false>(v));
+  return lane_bcast(v, kWave - 1);
 }
 
 // argmax of |value| over lanes; ties -> smallest index (value < 0 marks "no row")
@@ -85,52 +101,33 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
 // model laws
 
 // fraction of pi P R^3 carried by the wrinkled body at bend |x| (Eq. 2a-b); linear
-// below the onset theta_on = 2 asin(eps_c); clamped beyond pi.
+// below the onset theta_on = 2 asin(eps_c); clamped beyond pi.  With s = sin(x/2),
+// cos(gamma0) = 2 eps_c / s - 1 and sin(gamma0) = sqrt(1 - cos^2), so
+// Eq. 2a needs one acos and one square root.
 __device__ double wr_h(double x, double epsc, double th_on) {
   if (x <= th_on) return x / (2.0 * th_on);
   if (x > kPi) x = kPi;
-  double c = 2.0 * epsc / sin(0.5 * x) - 1.0;
-  c = fmin(1.0, fmax(-1.0, c));
-  double g = acos(c);
-  return (sin(2.0 * g) + 2.0 * kPi - 2.0 * g) / (4.0 * (sin(g) + (kPi - g) * cos(g)));
+  const double s = sin(0.5 * x);
+  const double c = fmin(1.0, 2.0 * epsc / s - 1.0);
+  const double sg = sqrt((1.0 - c) * (1.0 + c));  // sin(acos c), rounded as acos is
+  const double g = acos(c);
+  return (2.0 * sg * c + 2.0 * kPi - 2.0 * g) / (4.0 * (sg + (kPi - g) * c));
 }
 
-// d wr_h / dx (slope of the linear branch at the onset itself; 0 from pi on)
+// d wr_h / dx = 4 eps_c cos(x/2) (N (pi - g) - sin(g) D) / (s^2 D^2) with N, D the
+// numerator and denominator of Eq. 2a (the 1/sin(gamma0) of dgamma0/dx cancels).
+// Slope of the linear branch at the onset itself; 0 from pi on.
 __device__ double wr_dh(double x, double epsc, double th_on) {
   if (x <= th_on) return 0.5 / th_on;
   if (x >= kPi) return 0.0;
-  double s = sin(0.5 * x);
-  double c = fmin(1.0, 2.0 * epsc / s - 1.0);
-  double g = acos(c);
-  // dgamma/dx = -(dc/dx) / sqrt(1 - c^2), with 1 - c^2 = 4 eps_c (s - eps_c) / s^2
-  double dc = -epsc * cos(0.5 * x) / (s * s);
-  double dg = -dc / sqrt(4.0 * epsc * (s - epsc) / (s * s));
-  double sg = sin(g), cg = cos(g);
-  double num = sin(2.0 * g) + 2.0 * kPi - 2.0 * g;
-  double den = 4.0 * (sg + (kPi - g) * cg);
-  double dnum = 2.0 * cos(2.0 * g) - 2.0;
-  double dden = -4.0 * (kPi - g) * sg;
-  return (dnum * den - num * dden) / (den * den) * dg;
-}
-
-// int_0^x wr_h (energy of the body moment per pi P R^3): the tabulated integral at
-// the knot below u = sqrt(x - theta_on), plus the rest of the interval by two-point
-// Gauss-Legendre in u.  The integrand 2 u h(theta_on + u^2) is smooth in u, so the
-// result and its slope in x (= wr_h) agree with the moment law to round-off, also
-// just above the onset.
-__device__ double wr_int(double x, const WrTable& T, double epsc) {
-  if (x <= T.th_on) return x * x / (4.0 * T.th_on);
-  if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
-  double u = sqrt(x - T.th_on);
-  int k = (int)(u / T.du);
-  if (k > kIhKnots - 2) k = kIhKnots - 2;
-  double u0 = k * T.du;
-  double c = 0.5 * (u0 + u), h = 0.5 * (u - u0);
-  const double g = 0.57735026918962576451;  // 1/sqrt(3)
-  double ua = c - h * g, ub = c + h * g;
-  double fa = 2.0 * ua * wr_h(T.th_on + ua * ua, epsc, T.th_on);
-  double fb = 2.0 * ub * wr_h(T.th_on + ub * ub, epsc, T.th_on);
-  return T.val[k] + h * (fa + fb);
+  double s, co;
+  sincos(0.5 * x, &s, &co);
+  const double c = fmin(1.0, 2.0 * epsc / s - 1.0);
+  const double sg = sqrt((1.0 - c) * (1.0 + c));  // sin(acos c), rounded as acos is
+  const double g = acos(c);
+  const double N = 2.0 * sg * c + 2.0 * kPi - 2.0 * g;
+  const double D = 4.0 * (sg + (kPi - g) * c);
+  return 4.0 * epsc * co * (N * (kPi - g) - sg * D) / (s * s * D * D);
 }
 
 __device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
@@ -141,6 +138,20 @@ __device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
     b1 = t;
   }
   return fma(x, b1, c[0] - b2);
+}
+
+// int_0^x wr_h (energy of the body moment per pi P R^3): above the onset, the exact
+// antiderivative of a piecewise Chebyshev fit of 2 u h(theta_on + u^2) in
+// u = sqrt(x - theta_on), so that its slope in x equals h to the fit's accuracy.
+__device__ double wr_int(double x, const WrTable& T) {
+  if (x <= T.th_on) return x * x / (4.0 * T.th_on);
+  if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
+  const double u = sqrt(x - T.th_on);
+  int k = (int)(u / T.du);
+  k = k > kIhPieces - 1 ? kIhPieces - 1 : k;
+  const double a = k * T.du;
+  const double t = 2.0 * (u - a) / T.du - 1.0;
+  return T.cum[k] + 0.5 * T.du * clenshaw(T.ic[k], kIhDeg + 1, t);
 }
 
 // sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral
@@ -172,53 +183,50 @@ struct Ctx {
   KParams P;
 };
 
-// joint moment (Eq. 3b with Eq. 2), slope and energy for angle th and coverage pp/pm
+// joint moment (Eq. 3b with Eq. 2), slope and energy for angle th and coverage pp/pm.
+// Only the actuator side the bend stretches needs the force law; the other side sits
+// at zero strain, G(0) = G0.
 __device__ void joint_law(const Ctx& c, double th, double pp, double pm, double* q, double* dq,
                           double* E) {
   const double epsc = c.P.epsc, th_on = c.wr->th_on;
-  double ath = fabs(th);
-  double ep = th > 0.0 ? c.arm * th / c.l : 0.0;
-  double em = th < 0.0 ? -c.arm * th / c.l : 0.0;
+  const double ath = fabs(th);
+  const double G0 = c.tab->G0;
+  const double eps = c.arm * ath / c.l;
+  double G = G0, dG = 0.0, IG = 0.0;
+  if (th != 0.0)
+    spam_law(*c.tab, eps, q ? &G : nullptr, dq ? &dG : nullptr, E ? &IG : nullptr);
+  else if (dq)
+    spam_law(*c.tab, 0.0, nullptr, &dG, nullptr);
+  const double pstr = th >= 0.0 ? pp : pm;  // stretched side
   if (q) {
-    double Gp, Gm;
-    spam_law(*c.tab, ep, &Gp, nullptr, nullptr);
-    spam_law(*c.tab, em, &Gm, nullptr, nullptr);
-    double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * wr_h(ath, epsc, th_on);
-    *q = Mb - c.arm * (pp * Gp - pm * Gm);
+    const double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * wr_h(ath, epsc, th_on);
+    *q = th >= 0.0 ? Mb - c.arm * (pp * G - pm * G0) : Mb - c.arm * (pp * G0 - pm * G);
   }
   if (dq) {
-    double k = c.arm * c.arm / c.l, dG;
+    const double k = c.arm * c.arm / c.l;
     double d = c.Mmax * wr_dh(ath, epsc, th_on);
-    if (th > 0.0) {
-      spam_law(*c.tab, ep, nullptr, &dG, nullptr);
-      d -= k * pp * dG;
-    } else if (th < 0.0) {
-      spam_law(*c.tab, em, nullptr, &dG, nullptr);
-      d -= k * pm * dG;
-    } else {
-      spam_law(*c.tab, 0.0, nullptr, &dG, nullptr);
-      d -= 0.5 * k * (pp + pm) * dG;
-    }
+    d -= th != 0.0 ? k * pstr * dG : 0.5 * k * (pp + pm) * dG;
     *dq = d;
   }
   if (E) {
-    double IGp, IGm;
-    spam_law(*c.tab, ep, nullptr, nullptr, &IGp);
-    spam_law(*c.tab, em, nullptr, nullptr, &IGm);
-    double Eb = c.Mmax * wr_int(ath, *c.wr, epsc);
-    double G0 = c.tab->G0;
-    double Ea = th >= 0.0 ? (-c.l * pp * IGp + c.arm * pm * G0 * th)
-                          : (-c.arm * pp * G0 * th - c.l * pm * IGm);
+    const double Eb = c.Mmax * wr_int(ath, *c.wr);
+    const double Ea = th >= 0.0 ? (-c.l * pp * IG + c.arm * pm * G0 * th)
+                                : (-c.arm * pp * G0 * th - c.l * pm * IG);
     *E = Eb + Ea;
   }
 }
 
-// signed distance, outward normal and curvature of the distance field at (x, y)
-__device__ __forceinline__ double obs_dist(int kind, const double* o, double x, double y,
-                                          double& nx, double& ny, double& kap) {
+// Gap g = dist(x, obstacle) - R of a body disk at (x, y), with outward normal and the
+// curvature of the distance field.  Returns false (no contact, outputs unset) when
+// the disk is clearly clear of the obstacle; the squared-distance pre-test keeps a
+// relative margin so that every pair it rejects also has g >= 0 when evaluated.
+__device__ __forceinline__ bool obs_gap(int kind, const double* o, double R, double x, double y,
+                                        double& g, double& nx, double& ny, double& kap) {
   if (kind == 0) {
-    double vx = x - o[0], vy = y - o[1];
-    double d = sqrt(vx * vx + vy * vy);
+    const double vx = x - o[0], vy = y - o[1];
+    const double d2 = vx * vx + vy * vy, rr = o[2] + R;
+    if (!(d2 < rr * rr * (1.0 + 1e-12))) return false;
+    const double d = sqrt(d2);
     if (d > 0.0) {
       nx = vx / d;
       ny = vy / d;
@@ -228,27 +236,34 @@ __device__ __forceinline__ double obs_dist(int kind, const double* o, double x, 
       ny = 0.0;
       kap = 0.0;
     }
-    return d - o[2];
+    g = (d - o[2]) - R;
+    return g < 0.0;
   }
-  double sx = x >= o[0] ? 1.0 : -1.0, sy = y >= o[1] ? 1.0 : -1.0;
-  double dx = fabs(x - o[0]) - o[2], dy = fabs(y - o[1]) - o[3];
+  const double sx = x >= o[0] ? 1.0 : -1.0, sy = y >= o[1] ? 1.0 : -1.0;
+  const double dx = fabs(x - o[0]) - o[2], dy = fabs(y - o[1]) - o[3];
+  if (dx >= R || dy >= R) return false;
   kap = 0.0;
   if (dx > 0.0 || dy > 0.0) {
-    double ox = fmax(dx, 0.0), oy = fmax(dy, 0.0);
-    double d = sqrt(ox * ox + oy * oy);
+    const double ox = fmax(dx, 0.0), oy = fmax(dy, 0.0);
+    const double d2 = ox * ox + oy * oy;
+    if (!(d2 < R * R * (1.0 + 1e-12))) return false;
+    const double d = sqrt(d2);
     nx = sx * ox / d;
     ny = sy * oy / d;
     if (dx > 0.0 && dy > 0.0) kap = 1.0 / d;
-    return d;
+    g = d - R;
+    return g < 0.0;
   }
   if (dx >= dy) {
     nx = sx;
     ny = 0.0;
-    return dx;
+    g = dx - R;
+  } else {
+    nx = 0.0;
+    ny = sy;
+    g = dy - R;
   }
-  nx = 0.0;
-  ny = sy;
-  return dy;
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -341,9 +356,8 @@ __device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool w
       double xx = on ? S.px[j] + s * S.tx[j] : 0.0;
       double xy = on ? S.py[j] + s * S.ty[j] : 0.0;
       for (int k = 0; k < c.K; ++k) {
-        double nx, ny, kap;
-        double g = obs_dist(S.okind[k], S.obs[k], xx, xy, nx, ny, kap) - c.R;
-        bool hit = on && g < 0.0;
+        double g = 0.0, nx = 0.0, ny = 0.0, kap = 0.0;
+        const bool hit = on && obs_gap(S.okind[k], S.obs[k], c.R, xx, xy, g, nx, ny, kap);
         unsigned long long m = __ballot(hit);
         if (m) {
           int pos = cnt + __popcll(m & lt);
