@@ -17,10 +17,10 @@ _lib = None
 
 # parameter vector layout (see prm_from in vine_oracle.c)
 PARAM_NAMES = ("Rc", "Ract", "acorr", "epsc", "kc", "tol", "max_iter", "substeps", "fd_h", "c1",
-               "c_mu", "cheb_n", "step_max")
+               "c_mu", "cheb_n", "step_max", "mu_up")
 DEFAULTS = dict(Rc=0.005, Ract=0.01718, acorr=1e-4, epsc=0.01, kc=1e4, tol=1e-10, max_iter=500,
                 substeps=2, fd_h=0.0, c1=1e-4, c_mu=1.0, cheb_n=128,
-                step_max=0.05)
+                step_max=0.05, mu_up=10.0)
 
 
 def params(**over) -> np.ndarray:
@@ -72,6 +72,9 @@ def lib():
         L.vo_rollout.restype = C.c_int
         L.vo_rollout.argtypes = [C.c_int, ip, dp, dp, ip, dp, dp, C.c_int, C.c_int, C.c_int, dp,
                                  dp, dp, ip, ip, ip, C.POINTER(C.c_uint64), dp, dp, dp]
+        L.vo_gradient.restype = C.c_int
+        L.vo_gradient.argtypes = [C.c_int, ip, dp, dp, ip, dp, dp, C.c_int, C.c_int, dp, dp, dp,
+                                  C.c_int, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -247,3 +250,21 @@ def rollout(work, n_steps: int | None = None, prm=None, threads: int = 0, traj: 
     if traj:
         out["traj"] = tr
     return out
+
+
+def gradient(work, traj, weights=None, prm=None, threads: int = 0):
+    """dL/d(pressure, s_start, s_end) of every sPAM for L = sum_t w_t |tip_t - goal|^2 on
+    the equilibria in ``traj`` ([B][T][n_max], as rollout(traj=True) returns it); weights
+    None = the last step only.  Returns (dP, ds0, ds1, loss[B])."""
+    prm = params() if prm is None else prm
+    B = work.n_inst
+    traj = _f64(traj)
+    T, n_max = traj.shape[1], traj.shape[2]
+    ns = len(work.spam)
+    dP, d0, d1, loss = np.zeros(ns), np.zeros(ns), np.zeros(ns), np.zeros(B)
+    wts = None if weights is None else _f64(weights)
+    lib().vo_gradient(B, _i(_i32(work.inst_i)), _d(_f64(work.inst_d)),
+                      _d(_f64(work.spam.reshape(-1, 4))), _i(_i32(work.obs_kind)),
+                      _d(_f64(work.obs_d.reshape(-1, 4))), _d(prm), T, n_max, _d(traj), _d(wts),
+                      _d(_f64(work.goal)), threads, _d(dP), _d(d0), _d(d1), _d(loss))
+    return dP, d0, d1, loss

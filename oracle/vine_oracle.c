@@ -6,7 +6,8 @@
  * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
  * of the benchmark load this library.  It shares no code, header, table or
  * helper with the HIP path, and it is written for clarity, not speed: dense
- * Hessians by finite differences, all link/obstacle pairs, adaptive quadrature.
+ * analytic Hessians solved by Gaussian elimination, all link/obstacle pairs,
+ * adaptive quadrature.
  *
  * What it computes, in the paper's order (section / equation):
  *   Sec. 3.1, Eq. 1a-d   sPAM force-strain law; G(eps) = F_t / P_act for an actuator
@@ -21,6 +22,10 @@
  *   Sec. 4.1, Alg. 1     one growth step: append a link and descend to that equilibrium.
  *                        The fixed 50 gradient steps are replaced by a converged damped
  *                        Newton descent (scaled residual <= tol).
+ *   Sec. 5               the design search over sPAM placement and pressure; here the
+ *                        derivative of a tip-to-goal loss with respect to those
+ *                        parameters, by the adjoint of each step's equilibrium
+ *                        (vo_gradient), pinned against finite differences of rollouts.
  * Readings of points the paper leaves open are listed in the design notes
  * (parameter choices, contact geometry, growth sub-steps, solver rules).
  */
@@ -51,6 +56,7 @@ typedef struct {
   double c1;                /* Armijo constant */
   double c_mu;              /* damping per unit residual: mu = c_mu max_j |r_j| (1/rad) */
   double step_max;          /* cap on max_j |step_j| (rad) */
+  double mu_up;             /* factor by which mu is raised when a step does not descend */
   int cheb_n;               /* Chebyshev degree of the G fit */
 } vo_prm;
 
@@ -68,6 +74,7 @@ static void prm_from(const double* p, vo_prm* P) {
   P->c_mu = p[10];
   P->cheb_n = (int)p[11];
   P->step_max = p[12];
+  P->mu_up = p[13];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -766,7 +773,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
     double mu = P->c_mu * rmax;
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) {
-        mu = fmax(10.0 * mu, 1e-8 * c->Mmax);
+        mu = fmax(P->mu_up * mu, 1e-8 * c->Mmax);
         st->mu_raises++;
       }
       if (dense_solve(n, H, mu, rp, d, W) != 0) continue;
@@ -1104,4 +1111,118 @@ void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K,
   free(cl);
   free(w.px);
   free(Pp);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gradient of L = sum_t w_t |tip_t - goal|^2 with respect to each sPAM's pressure,
+ * start and end (arc length).  Every weighted step's state is a converged equilibrium,
+ * r_t(theta_t; p) = 0, and r_t does not depend on the previous step's state, so
+ *   dL/dp = - sum_t lam_t . dr_t/dp,   H_t lam_t = w_t dL_t/dtheta,
+ * with H_t the exact Hessian at theta_t (dense solve here).  p enters r only through
+ * the joint coverage: dq_j/dP+_j = -arm G(eps+_j), dq_j/dP-_j = +arm G(eps-_j), and
+ * P+-_j = sum_s w_sj P_s with w_sj = |[s0, s1] ^ [j l, (j+1) l]| / l.
+ * traj: [B][T][n_max] joint angles after each step (as vo_rollout writes them);
+ * weights: [T] (NULL: the last step only); goal: [B][2]; outputs indexed like spam. */
+int vo_gradient(int B, const int* inst_i, const double* inst_d, const double* spam,
+                const int* obs_kind, const double* obs_d, const double* prm, int T, int n_max,
+                const double* traj, const double* weights, const double* goal, int n_threads,
+                double* dP, double* ds0, double* ds1, double* loss) {
+  vo_prm P;
+  prm_from(prm, &P);
+  gl_init();
+  for (int b = 0; b < B; ++b) gfit_get(inst_d[6 * b], prm);
+  /* per-robot partial sums (robots may share sPAM records), added in robot order */
+  size_t* slot = (size_t*)malloc(sizeof(size_t) * ((size_t)B + 1));
+  slot[0] = 0;
+  for (int b = 0; b < B; ++b) slot[b + 1] = slot[b] + (size_t)inst_i[5 * b + 2];
+  double* part = (double*)calloc(3 * slot[B] + 1, sizeof(double));
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int b = 0; b < B; ++b) {
+    const int* ii = inst_i + 5 * b;
+    const int ntar = ii[0], ns = ii[2];
+    double* pb = part + 3 * slot[b];
+    const double* sp = spam + 4 * (size_t)ii[1];
+    vo_chain c;
+    chain_init(&c, &P, prm, inst_d + 6 * b, ii[4], obs_kind + ii[3], obs_d + 4 * (size_t)ii[3]);
+    double* Pp = (double*)calloc((size_t)ntar * 2 + 2, sizeof(double));
+    spam_coverage(ntar, c.l, sp, ns, Pp, Pp + ntar + 1);
+    c.Pp = Pp;
+    c.Pm = Pp + ntar + 1;
+    size_t nn = (size_t)ntar;
+    double* H = (double*)malloc(sizeof(double) * (nn * nn + nn * (nn + 1) + 8 * nn + 8));
+    double* Wm = H + nn * nn;
+    double* g = Wm + nn * (nn + 1);
+    double* lam = g + nn;
+    double* ha = lam + nn;
+    double* hb = ha + nn;
+    double* hu = hb + nn;
+    vo_pose w;
+    pose_alloc(&w, ntar + 1);
+    int capc = 2 * ntar * (c.K > 0 ? c.K : 1) + 1, ncl = 0;
+    vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+    double Lsum = 0.0;
+    for (int t = 0; t < T; ++t) {
+      double wt = weights ? weights[t] : (t == T - 1 ? 1.0 : 0.0);
+      if (wt == 0.0) continue;
+      int n = t + 1 < ntar ? t + 1 : ntar;
+      c.n = n;
+      c.last_len = c.l;
+      const double* th = traj + ((size_t)b * T + t) * n_max;
+      chain_eval(&c, th, NULL, 0, cl, capc, &ncl, &w);
+      double ex = w.px[n] - goal[2 * b], ey = w.py[n] - goal[2 * b + 1];
+      Lsum += wt * (ex * ex + ey * ey);
+      /* dL/dtheta_j = 2 w (tip - goal) . (z x (tip - p_j)) */
+      for (int j = 0; j < n; ++j) {
+        double vx = -(w.py[n] - w.py[j]), vy = w.px[n] - w.px[j];
+        g[j] = 2.0 * wt * (ex * vx + ey * vy);
+      }
+      chain_hessian(&c, th, cl, ncl < capc ? ncl : capc, &w, H, ha, hb, hu);
+      if (dense_solve(n, H, 0.0, g, lam, Wm) != 0) continue;
+      for (int s = 0; s < ns; ++s) {
+        const double* e = sp + 4 * s;
+        double gP = 0.0, g0 = 0.0, g1 = 0.0;
+        for (int j = 0; j < n; ++j) {
+          double lo = fmax(e[0], j * c.l), hi = fmin(e[1], (j + 1) * c.l);
+          if (!(hi > lo)) continue;
+          double th_j = th[j];
+          double eps = e[2] > 0.0 ? (th_j > 0.0 ? c.arm * th_j / c.l : 0.0)
+                                  : (th_j < 0.0 ? -c.arm * th_j / c.l : 0.0);
+          double G;
+          gfit_eval(c.G, eps, &G, NULL, NULL);
+          double dq = e[2] > 0.0 ? -c.arm * G : c.arm * G; /* dq_j / dP^side_j */
+          double wsj = (hi - lo) / c.l;
+          gP += -lam[j] * dq * wsj;
+          if (e[0] > j * c.l) g0 += -lam[j] * dq * (-e[3] / c.l);
+          if (e[1] < (j + 1) * c.l) g1 += -lam[j] * dq * (e[3] / c.l);
+        }
+        pb[3 * s + 0] += gP;
+        pb[3 * s + 1] += g0;
+        pb[3 * s + 2] += g1;
+      }
+    }
+    if (loss) loss[b] = Lsum;
+    free(cl);
+    free(w.px);
+    free(H);
+    free(Pp);
+  }
+  for (int b = 0; b < B; ++b)
+    for (int s = 0; s < inst_i[5 * b + 2]; ++s) {
+      const int k = inst_i[5 * b + 1] + s;
+      dP[k] = ds0[k] = ds1[k] = 0.0;
+    }
+  for (int b = 0; b < B; ++b)
+    for (int s = 0; s < inst_i[5 * b + 2]; ++s) {
+      const int k = inst_i[5 * b + 1] + s;
+      const double* pb = part + 3 * (slot[b] + (size_t)s);
+      dP[k] += pb[0];
+      ds0[k] += pb[1];
+      ds1[k] += pb[2];
+    }
+  free(part);
+  free(slot);
+  return 0;
 }
