@@ -158,6 +158,36 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
  * n_steps steps.  Same semantics as vine_sim_step. */
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
 
+/* Gradient of a tip-reaching loss with respect to the actuation design, by the
+ * adjoint of the equilibrium conditions (Sec. 5 searches sPAM placement and
+ * pressure with the simulator in the loop; the adjoint differentiates each step's
+ * fixed point r(theta; p) = 0 of the Eq. 4 energy).  For robot b
+ *     L_b = sum_t w_t |tip_b(t) - goal_b|^2
+ * over the equilibria theta_b(t) after step t, and for every sPAM record s given
+ * at create:  dL/dP_s, dL/ds_start_s, dL/ds_end_s of L = sum_b L_b (records shared
+ * by several robots collect the sum).  Each equilibrium contributes
+ *     -lam^T dr/dp with H lam = w_t dL_t/dtheta,
+ * H the exact Hessian of the energy at theta_b(t) (the one the growth solver uses,
+ * undamped).  Equilibria are taken as they were computed: the derivative of a
+ * step whose status is not VINE_ST_CONVERGED, or across a change of the contact
+ * set, is that of the smooth branch the state sits on.
+ *   goal          device, double [B][2]
+ *   step_weights  device, double [T] (T from vine_sim_dims), or NULL: the loss
+ *                 is then w = 1 on the current state alone.  With weights, steps
+ *                 not yet taken by a robot are skipped, and every step/rollout call
+ *                 since the last reset must have recorded the trajectory
+ *                 (record_traj), else VINE_ESTATE.
+ *   dL_dP, dL_ds_start, dL_ds_end   device, double [n_spams] (overwritten)
+ *   loss          device, double [B] (overwritten with L_b)
+ *   adj_status    device, int32 [B] or NULL: 0, or 1 when an adjoint system was
+ *                 singular or had more contacts than the solver holds (that
+ *                 step's term is then left out).
+ * Asynchronous on stream.  Errors: VINE_EINVAL (null pointers), VINE_ESTATE,
+ * VINE_EDEVICE. */
+int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,
+                      double* dL_dP, double* dL_ds_start, double* dL_ds_end, double* loss,
+                      int32_t* adj_status, void* stream);
+
 /* Reset every robot to zero length (the records are cleared). */
 int32_t vine_sim_reset(vine_sim* h, void* stream);
 

@@ -54,11 +54,14 @@ struct KData {
   int n_max;          // largest target link count (row length of theta)
   int t_max;          // recorded steps per robot
   // inputs
-  const int* ii;      // [B][6]: n_target, obs_off, obs_cnt, table_id, cover_off, 0
+  const int* ii;      // [B][8]: n_target, obs_off, obs_cnt, table_id, cover_off, spam_off,
+                      //         spam_cnt, 0
   const double* dd;   // [B][6]: l, R, P_vine, base_x, base_y, base_heading
   const double* cover;// [sum n][2]: P+_j, P-_j
   const int* okind;   // [O]
   const double* obs;  // [O][4]: cx, cy, a, b
+  const double* spam; // [S][4]: s_start, s_end, side, pressure (as given at create)
+  int n_spam;
   const SpamTable* tables;
   const WrTable* wr;
   // state

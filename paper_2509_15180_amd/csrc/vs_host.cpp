@@ -16,6 +16,9 @@
 namespace vs {
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
                           int nmax_class, hipStream_t stream);
+hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
+                       const double* weights, int T, double* dP, double* ds0, double* ds1,
+                       double* loss, int* status, int nmax_class, hipStream_t stream);
 }
 
 using vs::SpamTable;
@@ -283,13 +286,14 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 struct vine_sim {
   vine_params prm;
-  int B = 0, N = 0, T = 0;
+  int B = 0, N = 0, T = 0, S = 0;
   std::vector<double> link_lens;      // distinct link lengths (table ids)
   std::vector<SpamTable> tables_h;
   // device arrays
   int* ii = nullptr;
   double* dd = nullptr;
   double* cover = nullptr;
+  double* spam = nullptr;
   int* okind = nullptr;
   double* obs = nullptr;
   SpamTable* tables = nullptr;
@@ -310,7 +314,8 @@ struct vine_sim {
   int trace_robot = -1, trace_cap = 0;
   double* trace = nullptr;
   int* trace_n = nullptr;
-  bool traj_valid = false;
+  bool traj_valid = false;  // some step since the reset recorded its joint angles
+  bool traj_all = true;     // every step since the reset did
   std::string err;
 };
 
@@ -322,7 +327,7 @@ int fail(vine_sim* h, int code, const std::string& msg) {
 }
 
 void free_all(vine_sim* h) {
-  void* ptrs[] = {h->ii, h->dd, h->cover, h->okind, h->obs, h->tables, h->wr, h->theta,
+  void* ptrs[] = {h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
                   h->maxpen, h->traj, h->jevals, h->nsolves, h->trace, h->trace_n};
   for (void* p : ptrs)
@@ -357,6 +362,8 @@ vs::KData kdata(vine_sim* h) {
   D.ii = h->ii;
   D.dd = h->dd;
   D.cover = h->cover;
+  D.spam = h->spam;
+  D.n_spam = h->S;
   D.okind = h->okind;
   D.obs = h->obs;
   D.tables = h->tables;
@@ -455,8 +462,9 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   h->B = n_inst;
   h->N = N;
   h->T = N;
+  h->S = n_spams;
   // host-side derived inputs
-  std::vector<int> ii(6 * (size_t)n_inst);
+  std::vector<int> ii(8 * (size_t)n_inst);
   std::vector<double> dd(6 * (size_t)n_inst);
   std::vector<int> okind;
   std::vector<double> obs;
@@ -470,12 +478,14 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       tid = (int)h->link_lens.size();
       h->link_lens.push_back(I.link_len);
     }
-    ii[6 * b + 0] = I.n_links;
-    ii[6 * b + 1] = (int)okind.size();
-    ii[6 * b + 2] = I.obs_count;
-    ii[6 * b + 3] = tid;
-    ii[6 * b + 4] = (int)(cover.size() / 2);
-    ii[6 * b + 5] = 0;
+    ii[8 * b + 0] = I.n_links;
+    ii[8 * b + 1] = (int)okind.size();
+    ii[8 * b + 2] = I.obs_count;
+    ii[8 * b + 3] = tid;
+    ii[8 * b + 4] = (int)(cover.size() / 2);
+    ii[8 * b + 5] = I.spam_offset;
+    ii[8 * b + 6] = I.spam_count;
+    ii[8 * b + 7] = 0;
     dd[6 * b + 0] = I.link_len;
     dd[6 * b + 1] = I.tube_radius;
     dd[6 * b + 2] = I.body_pressure;
@@ -519,6 +529,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->ii, ii.size()));
   A(dalloc(&h->dd, dd.size()));
   A(dalloc(&h->cover, cover.size()));
+  A(dalloc(&h->spam, 4 * (size_t)n_spams));
   A(dalloc(&h->okind, okind.size()));
   A(dalloc(&h->obs, obs.size()));
   A(dalloc(&h->tables, h->tables_h.size()));
@@ -546,6 +557,16 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(hipMemcpy(h->dd, dd.data(), sizeof(double) * dd.size(), hipMemcpyHostToDevice));
   if (!cover.empty())
     A(hipMemcpy(h->cover, cover.data(), sizeof(double) * cover.size(), hipMemcpyHostToDevice));
+  if (n_spams > 0) {
+    std::vector<double> sp(4 * (size_t)n_spams);
+    for (int i = 0; i < n_spams; ++i) {
+      sp[4 * i + 0] = spams[i].s_start;
+      sp[4 * i + 1] = spams[i].s_end;
+      sp[4 * i + 2] = spams[i].side;
+      sp[4 * i + 3] = spams[i].pressure;
+    }
+    A(hipMemcpy(h->spam, sp.data(), sizeof(double) * sp.size(), hipMemcpyHostToDevice));
+  }
   if (!okind.empty()) {
     A(hipMemcpy(h->okind, okind.data(), sizeof(int) * okind.size(), hipMemcpyHostToDevice));
     A(hipMemcpy(h->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice));
@@ -594,6 +615,7 @@ int32_t vine_sim_reset(vine_sim* h, void* stream) {
   A(hipMemsetAsync(h->jevals, 0, sizeof(double) * B, s));
   A(hipMemsetAsync(h->nsolves, 0, sizeof(double) * B, s));
   h->traj_valid = false;
+  h->traj_all = true;
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("reset: ") + hipGetErrorString(e));
   return VINE_OK;
 }
@@ -605,7 +627,7 @@ static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_traj, void* 
   hipError_t e = vs::launch_rollout(kparams(h->prm), kdata(h), n_steps, record_traj, h->N,
                                     (hipStream_t)stream);
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
-  if (record_traj) h->traj_valid = true;
+  if (record_traj) h->traj_valid = true; else h->traj_all = false;
   return VINE_OK;
 }
 
@@ -616,6 +638,23 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
 
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
   return advance(h, n_steps < 0 ? -1 : n_steps, record_traj, stream);
+}
+
+int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,
+                      double* dL_dP, double* dL_ds_start, double* dL_ds_end, double* loss,
+                      int32_t* adj_status, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  if (!goal || !loss || (h->S > 0 && (!dL_dP || !dL_ds_start || !dL_ds_end)))
+    return fail(h, VINE_EINVAL, "null goal, loss or gradient pointer");
+  if (step_weights && !(h->traj_valid && h->traj_all))
+    return fail(h, VINE_ESTATE,
+                "step weights need the joint angles of every step since the reset "
+                "(record_traj on every step/rollout call)");
+  hipError_t e = vs::launch_grad(kparams(h->prm), kdata(h), goal, step_weights, h->T, dL_dP,
+                                 dL_ds_start, dL_ds_end, loss, adj_status, h->N,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return VINE_OK;
 }
 
 int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {

@@ -290,7 +290,7 @@ struct Smem {
   double cg[NMAX];     // geometric stiffness, diagonal in absolute angles
   double dinv[NMAX];   // 1 / pivots of the tridiagonal part
   double ell[NMAX];    // its unit lower multipliers
-  double z[NMAX], v[NMAX], aux[NMAX];
+  double z[NMAX], v[NMAX], aux[NMAX], b[NMAX];
   double ps1[NMAX], ps2[NMAX];
   int lidx[NMAX];      // link -> contact-link slot (or -1)
   int clink[kMaxCL];   // contact-link slot -> link
@@ -414,14 +414,15 @@ __device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool w
 
 // W = (H + mu I | -r) at the state last evaluated (poses, contacts and r in S)
 template <int NMAX>
-__device__ void assemble(Smem<NMAX>& S, const Ctx& c, const double* th, double mu) {
+__device__ void assemble(Smem<NMAX>& S, const Ctx& c, const double* th, double mu,
+                         const double* rhs) {
   const int lane = threadIdx.x, n = c.n;
   for (int j = lane; j < n; j += kWave) {
     for (int m = 0; m < n; ++m) S.W[j][m] = 0.0;
     double dq;
     joint_law(c, th[j], S.pp[j], S.pm[j], nullptr, &dq, nullptr);
     S.W[j][j] = dq + mu;
-    S.W[j][n] = -S.r[j];
+    S.W[j][n] = rhs[j];
   }
   __syncthreads();
   const int nc = S.ncl;
@@ -615,11 +616,11 @@ __device__ void tri_solve(Smem<NMAX>& S, int n, const double* b, double* dst) {
   __syncthreads();
 }
 
-// (H + mu I) d = -r through the structure above: factor the tridiagonal part, then
-// Woodbury for the contact blocks.  Result into S.d.  false on a vanishing pivot or
+// (H + mu I) d = rhs (theta space) through the structure above: factor the
+// tridiagonal part, then Woodbury for the contact blocks.  Result into S.d.  false on a vanishing pivot or
 // a failed small solve.
 template <int NMAX>
-__device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu) {
+__device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu, const double* rhs) {
   const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
   // tridiagonal part: T_mm = k_m + k_{m+1} + C_m, T_{m,m+1} = -k_{m+1}, k_j = q'_j + mu
   bool ok = true;
@@ -647,8 +648,8 @@ __device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu) {
   __syncthreads();
   ok = S.aux[0] != 0.0;
   if (!ok) return false;
-  // right-hand side in absolute angles: b_m = -(r_m - r_{m+1})
-  for (int m = lane; m < n; m += kWave) S.v[m] = -(S.r[m] - (m + 1 < n ? S.r[m + 1] : 0.0));
+  // right-hand side in absolute angles: b_m - b_{m+1}
+  for (int m = lane; m < n; m += kWave) S.v[m] = rhs[m] - (m + 1 < n ? rhs[m + 1] : 0.0);
   __syncthreads();
   tri_solve(S, n, S.v, S.z);
   if (L > 0) {
@@ -780,13 +781,15 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
       status = 3;  // more contact links than the structured solve holds
       break;
     }
+    for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
+    __syncthreads();
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
       if (lane == 0) S.nsolves += 1.0;
       if (dense) {
-        assemble(S, c, S.th, mu);
+        assemble(S, c, S.th, mu, S.b);
         if (!lu_solve_dense(S, n)) continue;
-      } else if (!structured_solve(S, c, mu)) {
+      } else if (!structured_solve(S, c, mu, S.b)) {
         continue;
       }
       double s = 0.0;
@@ -853,7 +856,7 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   if (b >= D.n_inst) return;
-  const int* ii = D.ii + 6 * b;
+  const int* ii = D.ii + 8 * b;
   const double* dd = D.dd + 6 * b;
   Ctx c;
   const int ntar = ii[0];
@@ -959,6 +962,159 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
     D.jevals[b] += S.jevals;
     D.nsolves[b] += S.nsolves;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the growth step.  For L = sum_t w_t |tip_t - goal|^2 over converged
+// states (r_t(theta_t; p) = 0, independent of the previous state):
+//   dL/dp = - sum_t lam_t . dr_t/dp,  H_t lam_t = w_t dL_t/dtheta,
+// H_t the exact Hessian (same structured solve, mu = 0).  An sPAM's pressure P_s and
+// its ends s0, s1 enter r only through the coverage of the joints it spans:
+//   dq_j/dP+-_j = -+arm G(eps+-_j),  w_sj = |[s0, s1] ^ [j l, (j+1) l]| / l.
+template <int NMAX>
+__global__ __launch_bounds__(kWave) void grad_kernel(KParams P, KData D, const double* goal,
+                                                     const double* weights, int T,
+                                                     double* dP, double* ds0, double* ds1,
+                                                     double* loss, int* status) {
+  __shared__ Smem<NMAX> S;
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b >= D.n_inst) return;
+  const int* ii = D.ii + 8 * b;
+  const double* dd = D.dd + 6 * b;
+  Ctx c;
+  const int ntar = ii[0];
+  c.K = ii[2];
+  c.l = dd[0];
+  c.R = dd[1];
+  c.Mmax = kPi * dd[2] * c.R * c.R * c.R;
+  c.arm = 2.0 * c.R + P.Ract;
+  c.bx = dd[3];
+  c.by = dd[4];
+  c.bpsi = dd[5];
+  c.tab = D.tables + ii[3];
+  c.wr = D.wr;
+  c.P = P;
+  c.trace = nullptr;
+  c.last_len = c.l;
+  for (int k = lane; k < c.K; k += kWave) {
+    const double* o = D.obs + 4 * (size_t)(ii[1] + k);
+    S.obs[k][0] = o[0];
+    S.obs[k][1] = o[1];
+    S.obs[k][2] = o[2];
+    S.obs[k][3] = o[3];
+    S.okind[k] = D.okind[ii[1] + k];
+  }
+  for (int j = lane; j < ntar; j += kWave) {
+    S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
+    S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
+  }
+  const int soff = ii[5], ns = ii[6];
+  const double gx = goal[2 * b], gy = goal[2 * b + 1];
+  double aP = 0.0, a0 = 0.0, a1 = 0.0, Lsum = 0.0;  // this lane's sPAM (lane < ns)
+  int st = 0;
+  const int taken = D.tcur[b];
+  for (int t = 0; t < (weights ? (T < taken ? T : taken) : 1); ++t) {
+    const double wt = weights ? weights[t] : 1.0;
+    if (wt == 0.0) continue;
+    int n;
+    if (weights) {
+      n = t + 1 < ntar ? t + 1 : ntar;
+      for (int j = lane; j < n; j += kWave) S.th[j] = D.traj[((size_t)b * D.t_max + t) * D.n_max + j];
+    } else {
+      n = D.ncur[b];
+      for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
+    }
+    if (n == 0) continue;
+    c.n = n;
+    __syncthreads();
+    evaluate(S, c, S.th, false);
+    const double ex = S.px[n] - gx, ey = S.py[n] - gy;
+    Lsum += wt * (ex * ex + ey * ey);
+    if (S.overflow) {  // contact list truncated: the Hessian would be wrong
+      st = 1;
+      continue;
+    }
+    for (int j = lane; j < n; j += kWave) {
+      const double vx = -(S.py[n] - S.py[j]), vy = S.px[n] - S.px[j];
+      S.b[j] = 2.0 * wt * (ex * vx + ey * vy);
+    }
+    __syncthreads();
+    bool ok;
+    if (structured_setup(S, c)) {
+      ok = structured_solve(S, c, 0.0, S.b);
+    } else if (Smem<NMAX>::WN >= n) {
+      assemble(S, c, S.th, 0.0, S.b);
+      ok = lu_solve_dense(S, n);
+    } else {
+      ok = false;
+    }
+    if (!ok) {
+      st = 1;
+      continue;
+    }
+    // one lane per sPAM of this robot (at most kWave of them)
+    if (lane < ns) {
+      const double* e = D.spam + 4 * (size_t)(soff + lane);
+      const int j0 = (int)floor(e[0] / c.l);
+      for (int j = j0 < 0 ? 0 : j0; j < n && j * c.l < e[1]; ++j) {
+        const double lo = fmax(e[0], j * c.l), hi = fmin(e[1], (j + 1) * c.l);
+        if (!(hi > lo)) continue;
+        const double th = S.th[j];
+        const double eps = e[2] > 0.0 ? (th > 0.0 ? c.arm * th / c.l : 0.0)
+                                      : (th < 0.0 ? -c.arm * th / c.l : 0.0);
+        double G;
+        spam_law(*c.tab, eps, &G, nullptr, nullptr);
+        const double lq = S.d[j] * (e[2] > 0.0 ? -c.arm * G : c.arm * G);  // lam_j dq_j/dP
+        aP -= lq * (hi - lo) / c.l;
+        if (e[0] > j * c.l) a0 += lq * e[3] / c.l;
+        if (e[1] < (j + 1) * c.l) a1 -= lq * e[3] / c.l;
+      }
+    }
+    __syncthreads();
+  }
+  // robots may share sPAM records: their contributions add up
+  if (lane < ns) {
+    atomicAdd(&dP[soff + lane], aP);
+    atomicAdd(&ds0[soff + lane], a0);
+    atomicAdd(&ds1[soff + lane], a1);
+  }
+  if (lane == 0) {
+    loss[b] = Lsum;
+    if (status) status[b] = st;
+  }
+}
+
+__global__ void zero3_kernel(double* a, double* b, double* c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = 0.0;
+    b[i] = 0.0;
+    c[i] = 0.0;
+  }
+}
+
+hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
+                       const double* weights, int T, double* dP, double* ds0, double* ds1,
+                       double* loss, int* status, int nmax_class, hipStream_t stream) {
+  if (D.n_spam > 0)
+    hipLaunchKernelGGL(zero3_kernel, dim3((D.n_spam + 255) / 256), dim3(256), 0, stream, dP, ds0,
+                       ds1, D.n_spam);
+  dim3 grid(D.n_inst), block(kWave);
+  if (nmax_class <= 64)
+    hipLaunchKernelGGL((grad_kernel<64>), grid, block, 0, stream, P, D, goal, weights, T, dP, ds0,
+                       ds1, loss, status);
+  else if (nmax_class <= 128)
+    hipLaunchKernelGGL((grad_kernel<128>), grid, block, 0, stream, P, D, goal, weights, T, dP,
+                       ds0, ds1, loss, status);
+  else if (nmax_class <= 256)
+    hipLaunchKernelGGL((grad_kernel<256>), grid, block, 0, stream, P, D, goal, weights, T, dP,
+                       ds0, ds1, loss, status);
+  else if (nmax_class <= 512)
+    hipLaunchKernelGGL((grad_kernel<512>), grid, block, 0, stream, P, D, goal, weights, T, dP,
+                       ds0, ds1, loss, status);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // host-side launcher (instantiated for the supported chain lengths)

@@ -6,7 +6,8 @@ back to another implementation.
 
 Names follow the C ABI: ``create`` -> vine_sim_create, ``VineSim.step`` ->
 vine_sim_step, ``VineSim.rollout`` -> vine_sim_rollout, ``VineSim.read`` ->
-vine_sim_read, ``VineSim.close`` -> vine_sim_destroy.
+vine_sim_read, ``VineSim.grad`` -> vine_sim_grad, ``VineSim.close`` ->
+vine_sim_destroy.
 """
 from __future__ import annotations
 
@@ -67,7 +68,7 @@ class Obstacle(C.Structure):
 EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
-           "vine_sim_trace_read")
+           "vine_sim_trace_read", "vine_sim_grad")
 
 _lib = None
 
@@ -110,6 +111,8 @@ def lib():
         L.vine_sim_trace.restype = C.c_int32
         L.vine_sim_trace_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
         L.vine_sim_trace_read.restype = C.c_int32
+        L.vine_sim_grad.argtypes = [vp] * 9
+        L.vine_sim_grad.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -163,6 +166,7 @@ class VineSim:
         dims = (C.c_int32 * 3)()
         L.vine_sim_dims(h, dims)
         self.B, self.T, self.N = int(dims[0]), int(dims[1]), int(dims[2])
+        self.S = int(len(work.spam))
 
     def _check(self, rc):
         if rc != VINE_OK:
@@ -227,6 +231,34 @@ class VineSim:
         if n < 0:
             self._check(n)
         return buf[:n]
+
+    def grad(self, goal, weights=None, stream=None):
+        """vine_sim_grad on device tensors.  ``goal`` [B][2] and ``weights`` [T] (or None:
+        the current state alone) may be numpy arrays or torch tensors; they are staged as
+        float64 device tensors.  Returns device tensors (dL_dP, dL_ds_start, dL_ds_end,
+        loss[B], adj_status[B]), valid once ``stream`` has been synchronised."""
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def staged(x, shape):
+            t = torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous()
+            assert tuple(t.shape) == shape, (tuple(t.shape), shape)
+            return t
+
+        g = staged(goal, (self.B, 2))
+        w = None if weights is None else staged(weights, (self.T,))
+        S = max(self.S, 1)
+        dP, d0, d1 = (torch.empty(S, dtype=torch.float64, device=dev) for _ in range(3))
+        loss = torch.empty(self.B, dtype=torch.float64, device=dev)
+        st = torch.empty(self.B, dtype=torch.int32, device=dev)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._check(lib().vine_sim_grad(self.h, ptr(g), ptr(w), ptr(dP), ptr(d0), ptr(d1),
+                                        ptr(loss), ptr(st), _stream_ptr(stream)))
+        self._keep = (g, w)  # inputs stay alive until the caller synchronises
+        return dP[:self.S], d0[:self.S], d1[:self.S], loss, st
 
     def close(self):
         if getattr(self, "h", None):

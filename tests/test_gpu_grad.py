@@ -1,0 +1,135 @@
+"""GPU adjoint (vine_sim_grad) against the oracle's adjoint and against central
+finite differences of GPU rollouts, on the differentiation workload (96 links,
+12 circles + 12 rectangles, 1-4 sPAMs with continuous placement, a goal each).
+
+Bars: where the GPU and oracle rollouts reach the same contact sets, the two
+adjoints agree to 1e-6 relative (they solve the same linear system at states that
+agree to ~1e-12 rad); the GPU adjoint matches central differences of GPU rollouts
+to 2e-5 relative (truncation at h = 1e-5 m is below 4e-6)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_15180_amd import workloads as W
+
+from fdcheck import cases_for, fd_values, losses, perturbed, smooth
+
+pytestmark = pytest.mark.gpu
+
+ROBOTS = [1, 2, 3, 6, 9, 10, 11, 12]
+
+
+def _sim(work):
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    return V.VineSim(work)
+
+
+def _gpu(work, weights=None, traj=True):
+    import torch
+    with _sim(work) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, record_traj=traj, stream=s)
+        g = sim.grad(work.goal, weights, stream=s)
+        s.synchronize()
+        out = sim.read_all()
+        return out, tuple(x.cpu().numpy() for x in g)
+
+
+def _rel(a, b, floor):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_grad_matches_oracle(weighted):
+    w = W.config4(16).subset(ROBOTS)
+    T = 96
+    weights = None
+    if weighted:
+        weights = np.zeros(T)
+        weights[20::9] = 0.25
+        weights[-1] = 1.0
+    out, (dP, d0, d1, loss, st) = _gpu(w, weights)
+    ref = O.rollout(w, traj=True, threads=16)
+    rP, r0, r1, rloss = O.gradient(w, ref["traj"], weights=weights, threads=16)
+    assert np.all(st == 0)
+    same = np.all(out["chash"] == ref["chash"], 1)
+    print(f"weighted={weighted}: contact sets identical on {same.sum()}/{len(same)} robots",
+          flush=True)
+    assert same.sum() >= len(same) - 1
+    np.testing.assert_allclose(loss[same], rloss[same], rtol=1e-9)
+    rows = np.concatenate([np.arange(w.inst_i[b, 1], w.inst_i[b, 1] + w.inst_i[b, 2])
+                           for b in np.nonzero(same)[0]])
+    for got, want in ((dP, rP), (d0, r0), (d1, r1)):
+        floor = 1e-6 * np.abs(want[rows]).max()
+        r = _rel(got[rows], want[rows], floor)
+        print(f"  max rel {r.max():.2e}", flush=True)
+        assert r.max() < 1e-6
+
+
+def test_grad_matches_fd_of_gpu_rollouts():
+    w = W.config4(16).subset(ROBOTS[:5])
+    base, (dP, d0, d1, loss, st) = _gpu(w)
+    cases = cases_for(w, range(w.n_inst))
+    wp = perturbed(w, cases)
+    import torch
+    with _sim(wp) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, stream=s)
+        s.synchronize()
+        o = sim.read_all()
+    fd = fd_values(cases, losses(o["tip"], wp.goal))
+    ok = smooth(cases, o["chash"], base["chash"])
+    g = {"P": dP, "s0": d0, "s1": d1}
+    adj = np.array([g[c.name][c.spam] for c in cases])
+    assert ok.sum() >= 10
+    r = _rel(adj[ok], fd[ok], 1e-3 * np.abs(adj[ok]).max())
+    print(f"FD: {ok.sum()} smooth cases, max rel {r.max():.2e}", flush=True)
+    assert r.max() < 2e-5
+
+
+def test_grad_needs_recorded_trajectory():
+    from paper_2509_15180_amd import vinesim as V
+    import torch
+    w = W.config4(16).subset([1])
+    with _sim(w) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(10, record_traj=True, stream=s)
+        sim.rollout(-1, record_traj=False, stream=s)
+        with pytest.raises(V.VineError) as ei:
+            sim.grad(w.goal, np.ones(sim.T), stream=s)
+        assert ei.value.code == V.VINE_ESTATE
+        # the final-state loss needs no trajectory
+        g = sim.grad(w.goal, None, stream=s)
+        s.synchronize()
+        assert np.isfinite(g[0].cpu().numpy()).all()
+
+
+def test_grad_full_batch_sampled():
+    """The whole 4096-robot differentiation batch in one launch; sampled robots are
+    checked against the oracle one by one."""
+    w = W.config4(4096)
+    out, (dP, d0, d1, loss, st) = _gpu(w, None, traj=False)
+    assert np.isfinite(dP).all() and np.isfinite(d0).all() and np.isfinite(d1).all()
+    conv = np.all(out["status"] == 0, 1)
+    print(f"full batch: {conv.sum()} robots converged on every step, adjoint status ok on "
+          f"{(st == 0).sum()}", flush=True)
+    assert (st == 0).sum() >= 4096 - 8
+    pick = [5, 1000, 2047, 3333]
+    sub = w.subset(pick)
+    ref = O.rollout(sub, traj=True, threads=16)
+    rP, r0, r1, rloss = O.gradient(sub, ref["traj"], threads=16)
+    checked = 0
+    for k, b in enumerate(pick):
+        if not np.all(out["chash"][b] == ref["chash"][k]):
+            continue
+        so, sc = int(w.inst_i[b, 1]), int(w.inst_i[b, 2])
+        ro = int(sub.inst_i[k, 1])
+        for got, want in ((dP, rP), (d0, r0), (d1, r1)):
+            g, x = got[so:so + sc], want[ro:ro + sc]
+            assert _rel(g, x, 1e-6 * max(np.abs(x).max(), 1e-30)).max() < 1e-6
+        assert abs(loss[b] - rloss[k]) <= 1e-9 * max(rloss[k], 1e-12)
+        checked += 1
+    assert checked >= 3
