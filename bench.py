@@ -1,14 +1,19 @@
 """Benchmark of the batched growth step on one MI355X.
 
-One bench step = one rollout of the whole batch to full length: 4096 robots of 64
-links (2 cm links, 5 cm tube, 0-4 sPAMs, 10 circles + 10 rectangles), i.e. 64 growth
-steps per robot and 4096 * 2080 = 8.52e6 joint-updates (a joint brought to the
-converged equilibrium of one growth step).
+Default workload (the headline line): one bench step = one rollout of the whole batch
+to full length, 4096 robots of 64 links (2 cm links, 5 cm tube, 0-4 sPAMs, 10 circles +
+10 rectangles), i.e. 64 growth steps per robot and 4096 * 2080 = 8.52e6 joint-updates
+(a joint brought to the converged equilibrium of one growth step).
+
+Other workloads (``--workload``), same JSON fields:
+  uneven  16384 robots of 16-256 links with 0-64 obstacles in one rollout call
+  grad    4096 robots of 96 links: rollout with the trajectory recorded, then the
+          adjoint of every step's equilibrium (vine_sim_grad, all steps weighted)
 
 Prints one JSON line with the driver's fields plus:
-  roofline      the rollout kernel against the FP64 VALU peak (see the design doc for the
-                per-joint-evaluation FLOP count), timed with HIP events on the stream
-                the kernel is launched on;
+  roofline      the rollout kernel against the FP64 VALU peak (per-joint-evaluation
+                FLOP count below), timed with HIP events on the stream the kernel is
+                launched on;
   per_instance  the same kernel launched once per robot (batch of one), serial on one
                 stream, on a sample of the robots;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload on the host
@@ -31,11 +36,15 @@ METRIC = "joint-updates/sec batched vs plain per-instance at 1e-5 rad; p99 rollo
 PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64 (256 CUs x 128 FLOP/clk x 2.4 GHz)
 
 
-def flops_per_joint_eval(K: int) -> float:
+def flops_per_joint_eval(K: float) -> float:
     """Algorithmic FP64 operations of one joint's share of one residual+energy
     evaluation: pose scan 7, joint moment 150, joint energy 150, residual 18, and
     two body disks against K obstacles at 8.5 each (transcendentals count 1)."""
     return 325.0 + 17.0 * K
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
 def main():
@@ -43,7 +52,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--workload", choices=("uniform", "uneven", "grad"), default="uniform")
+    ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
     ap.add_argument("--cpu-robots", type=int, default=64, help="robots in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -60,20 +70,41 @@ def main():
     from paper_2509_15180_amd import workloads as W
 
     torch.cuda.set_device(0)
-    work = W.config2(args.batch)
-    K = int(work.inst_i[:, 4].max())
+    wl = args.workload
+    if wl == "uniform":
+        B = args.batch or 4096
+        work = W.config2(B)
+        desc = (f"uniform batch: {B} robots x 64 links (2 cm), 10 circles + 10 rectangles, "
+                f"0-4 sPAMs; rollout to full length")
+    elif wl == "uneven":
+        B = args.batch or 16384
+        work = W.config3(B)
+        desc = (f"uneven batch: {B} robots x 16-256 links (2 cm), 0-64 obstacles, 0-6 sPAMs; "
+                f"rollout to full length in one call")
+    else:
+        B = args.batch or 4096
+        work = W.config4(B)
+        desc = (f"differentiation batch: {B} robots x 96 links, 12 circles + 12 rectangles, "
+                f"1-4 sPAMs, a goal each; rollout with trajectory + adjoint of every step")
+    n = work.inst_i[:, 0].astype(np.float64)
+    K_mean = float((work.inst_i[:, 4] * n * n).sum() / (n * n).sum())  # work-weighted obstacles
     ju = work.joint_updates()
     sim = V.VineSim(work)
     stream = torch.cuda.current_stream()
+    T = sim.T
+    weights = torch.ones(T, dtype=torch.float64, device="cuda") if wl == "grad" else None
+    goal = torch.as_tensor(work.goal, dtype=torch.float64).cuda()
 
     def one_step():
         sim.reset(stream=stream)
-        sim.rollout(-1, stream=stream)
+        sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
+        if wl == "grad":
+            sim.grad(goal, weights, stream=stream)
 
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0, ev1 = _events(torch)
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -86,27 +117,35 @@ def main():
     jevals = float(out["jevals"].sum())
     nsolves = float(out["nsolves"].sum())
     status = out["status"]
-    # kernel-only time of one rollout launch (no reset), same stream
+    # time of the rollout call alone (no reset), same stream
     sim.reset(stream=stream)
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0, k1 = _events(torch)
     k0.record(stream)
-    sim.rollout(-1, stream=stream)
+    sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
     k1.record(stream)
     torch.cuda.synchronize()
     kern_ms = k0.elapsed_time(k1)
-    flops = jevals * flops_per_joint_eval(K)
+    grad_ms = None
+    if wl == "grad":
+        g0, g1 = _events(torch)
+        g0.record(stream)
+        sim.grad(goal, weights, stream=stream)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        grad_ms = g0.elapsed_time(g1)
+    flops = jevals * flops_per_joint_eval(K_mean)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     value = ju / (ms * 1e-3)
 
     # plain per-instance form: one launch per robot, serial on one stream
-    pi_idx = np.linspace(0, args.batch - 1, args.per_instance).astype(int)
+    pi_idx = np.linspace(0, B - 1, args.per_instance).astype(int)
     sims = [V.VineSim(work.subset([i])) for i in pi_idx]
     for s in sims:
         s.rollout(-1, stream=stream)
     torch.cuda.synchronize()
     for s in sims:
         s.reset(stream=stream)
-    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0, p1 = _events(torch)
     p0.record(stream)
     for s in sims:
         s.rollout(-1, stream=stream)
@@ -123,28 +162,30 @@ def main():
         import oracle as O
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         threads = max(1, min(int(threads), 16))
-        sub = work.subset(np.arange(args.cpu_robots))
+        idx = np.arange(min(args.cpu_robots, B)) if wl != "uneven" else \
+            np.nonzero(work.inst_i[:, 0] <= 128)[0][:args.cpu_robots]
+        sub = work.subset(idx)
         c0 = time.perf_counter()
         O.rollout(sub, threads=threads)
         csec = time.perf_counter() - c0
         cpu = {"value": sub.joint_updates() / csec, "unit": "joint-updates/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"first {args.cpu_robots} robots of the same 4096-robot batch, full "
-                         f"rollouts ({sub.joint_updates()} joint-updates in {csec:.1f} s)"}
+               "sample": f"{len(idx)} robots of the same batch"
+                         f"{' (those of <= 128 links)' if wl == 'uneven' else ''}, full rollouts "
+                         f"({sub.joint_updates()} joint-updates in {csec:.1f} s)"}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "joint-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"uniform batch: {args.batch} robots x 64 links (2 cm), 10 circles "
-                               f"+ 10 rectangles, 0-4 sPAMs; rollout to full length",
-                   "robots": args.batch, "links": 64, "obstacles": K,
-                   "joint_updates_per_step": ju},
+        "config": {"workload": desc, "robots": B, "links_max": int(n.max()),
+                   "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "rollout_kernel", "kernel_ms": kern_ms,
-                     "joint_evaluations": jevals, "flop_per_joint_eval": flops_per_joint_eval(K),
+                     "joint_evaluations": jevals,
+                     "flop_per_joint_eval": flops_per_joint_eval(K_mean),
                      "linear_solves": nsolves},
         "per_instance": {"value": pi_rate, "unit": "joint-updates/s", "robots": int(len(pi_idx)),
                          "speedup_batched": value / pi_rate},
@@ -154,6 +195,8 @@ def main():
                     "max_penetration_m": float(out["maxpen"].max())},
         "wall_s": wall,
     }
+    if grad_ms is not None:
+        rec["adjoint_ms"] = grad_ms
     print(json.dumps(rec), flush=True)
 
 

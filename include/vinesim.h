@@ -188,6 +188,15 @@ int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weight
                       double* dL_dP, double* dL_ds_start, double* dL_ds_end, double* loss,
                       int32_t* adj_status, void* stream);
 
+/* Replace the sPAM records (placement and pressure; Sec. 3.1 and Sec. 5: the design
+ * variables of the search) without rebuilding the handle.  spams: host, n_spams
+ * records laid out as at create (each robot keeps its offset and count), which must
+ * equal the count given at create, else VINE_EINVAL; invalid records as at create
+ * give VINE_EINVAL and change nothing.  The robots' state is kept: call
+ * vine_sim_reset before a fresh rollout.  The update is ordered after the work
+ * already queued on `stream`; the call returns once it is done. */
+int32_t vine_sim_set_spams(vine_sim* h, const vine_spam* spams, int32_t n_spams, void* stream);
+
 /* Reset every robot to zero length (the records are cleared). */
 int32_t vine_sim_reset(vine_sim* h, void* stream);
 
@@ -228,6 +237,66 @@ int32_t vine_sim_trace(vine_sim* h, int32_t robot, int32_t capacity);
 /* Copy up to `capacity` trace rows (10 doubles each) to host memory; returns the
  * number of rows copied, or a negative VINE_E* code. */
 int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
+
+/* ------------------------------------------------------------------------- */
+/* Serving: continuous batching of rollout requests on one device.
+ *
+ * The paper's planner (Sec. 5) issues many short simulation jobs whose sizes vary
+ * (designs of different length, several environment samples each).  A server keeps a
+ * fixed set of robot slots resident on the device; queued robots are admitted into
+ * free slots at each tick, every active robot advances by a fixed number of growth
+ * steps, and finished robots free their slots at once, so long and short jobs share
+ * the device without waiting for each other's batch to drain.
+ *
+ * A request is a set of robots (e.g. one design on S environment samples); it
+ * completes when all of its robots have reached their target length.  Results are
+ * bitwise those of the same robots run through vine_sim_create / vine_sim_rollout
+ * (robots never interact, and the kernels are the same). */
+typedef struct vine_server vine_server;
+
+/* slots: robots resident at once; max_links / max_obstacles / max_spams bound each
+ * robot (<= VINE_MAX_LINKS / VINE_MAX_OBSTACLES / VINE_MAX_SPAMS).  Device memory is
+ * allocated here, once.  Up to 8 distinct link lengths are supported over the
+ * server's life (the force-law table is built on first use of a length).  Errors:
+ * VINE_EINVAL, VINE_ECAPACITY, VINE_ENOMEM, VINE_EDEVICE. */
+int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max_links,
+                           int32_t max_obstacles, int32_t max_spams, vine_server** out);
+
+/* Queue one request (FIFO).  Host arrays as for vine_sim_create (offsets relative to
+ * these arrays); copied.  request_id is the caller's and must not be queued twice at
+ * once.  Robots above the server's bounds give VINE_ECAPACITY, invalid input
+ * VINE_EINVAL; nothing is queued then. */
+int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instance* inst,
+                           int32_t n_inst, const vine_spam* spams, int32_t n_spams,
+                           const vine_obstacle* obstacles, int32_t n_obstacles);
+
+/* One scheduling round: admit queued robots into free slots, advance every active
+ * robot by `steps` growth steps (one launch per chain-length class), and retire the
+ * robots that reached their length.  Synchronises `stream` before returning.  Returns
+ * the number of requests completed in this round, or a negative VINE_E* code. */
+int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream);
+
+/* Completed requests not yet polled, oldest first: their ids into ids[] (host, up to
+ * cap entries) and, if worst_status is non-NULL, the largest per-step status over the
+ * request's robots (0 = every step converged).  Returns the number written. */
+int32_t vine_server_poll(vine_server* s, int64_t* ids, int32_t* worst_status, int32_t cap);
+
+/* Final state of robot `robot` (its index in the request) of a completed request:
+ * tip (x, y, heading) into tip[3] and, if theta is non-NULL, its joint angles into
+ * theta[0 .. n_links).  Results are kept until vine_server_release.  VINE_EINVAL for
+ * an unknown or unfinished request or robot. */
+int32_t vine_server_result(const vine_server* s, int64_t request_id, int32_t robot, double* tip,
+                           double* theta);
+
+/* Forget a completed request's results. */
+int32_t vine_server_release(vine_server* s, int64_t request_id);
+
+/* Counters: [0] robots queued, [1] robots active, [2] requests completed,
+ * [3] joint-updates done (sum over growth steps of the link count). */
+void vine_server_stats(const vine_server* s, int64_t out[4]);
+
+void vine_server_destroy(vine_server* s);
+const char* vine_server_last_error(const vine_server* s);
 
 #ifdef __cplusplus
 }

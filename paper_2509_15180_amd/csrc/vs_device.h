@@ -64,6 +64,9 @@ struct KData {
   int n_spam;
   const SpamTable* tables;
   const WrTable* wr;
+  // robots of the current launch: order[launch_first + blockIdx.x], launch_count blocks
+  const int* order;
+  int launch_first, launch_count;
   // state
   double* theta;      // [B][N]
   int* ncur;          // [B]

@@ -6,8 +6,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <deque>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/vinesim.h"
@@ -19,6 +22,8 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int rec
 hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
                        const double* weights, int T, double* dP, double* ds0, double* ds1,
                        double* loss, int* status, int nmax_class, hipStream_t stream);
+hipError_t launch_zero3(double* a, double* b, double* c, int n, hipStream_t stream);
+hipError_t launch_reset(const KData& D, hipStream_t stream);
 }
 
 using vs::SpamTable;
@@ -282,6 +287,31 @@ thread_local std::string g_create_error;
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+bool spam_ok(const vine_spam& S) {
+  return std::isfinite(S.s_start) && std::isfinite(S.s_end) && S.s_start >= 0.0 &&
+         S.s_end >= S.s_start && (S.side == 1.0 || S.side == -1.0) && std::isfinite(S.pressure) &&
+         S.pressure >= 0.0;
+}
+
+// Joint j of a robot takes the pressure-weighted fraction of link [j l, (j+1) l] that
+// each of its sPAMs covers, on the sPAM's side (appends 2 doubles per joint).
+void append_cover(const vine_instance& I, const vine_spam* spams, std::vector<double>& cover) {
+  const double l = I.link_len;
+  for (int j = 0; j < I.n_links; ++j) {
+    double pp = 0.0, pm = 0.0;
+    for (int s = 0; s < I.spam_count; ++s) {
+      const vine_spam& S = spams[I.spam_offset + s];
+      const double lo = std::fmax(S.s_start, j * l), hi = std::fmin(S.s_end, (j + 1) * l);
+      if (hi > lo) {
+        const double w = (hi - lo) / l;
+        if (S.side > 0.0) pp += w * S.pressure; else pm += w * S.pressure;
+      }
+    }
+    cover.push_back(pp);
+    cover.push_back(pm);
+  }
+}
+
 }  // namespace
 
 struct vine_sim {
@@ -289,6 +319,7 @@ struct vine_sim {
   int B = 0, N = 0, T = 0, S = 0;
   std::vector<double> link_lens;      // distinct link lengths (table ids)
   std::vector<SpamTable> tables_h;
+  std::vector<vine_instance> inst_h;  // as given at create (sPAM ranges, lengths)
   // device arrays
   int* ii = nullptr;
   double* dd = nullptr;
@@ -311,6 +342,13 @@ struct vine_sim {
   double* traj = nullptr;
   double* jevals = nullptr;
   double* nsolves = nullptr;
+  // robots grouped by chain-length class (64/128/256/512 links), longest expected work
+  // first within a class; each class runs as its own launch on its own stream
+  static constexpr int kClasses = 4;
+  int* order = nullptr;
+  int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
+  hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   int trace_robot = -1, trace_cap = 0;
   double* trace = nullptr;
   int* trace_n = nullptr;
@@ -327,7 +365,12 @@ int fail(vine_sim* h, int code, const std::string& msg) {
 }
 
 void free_all(vine_sim* h) {
-  void* ptrs[] = {h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
+  for (int c = 0; c < vine_sim::kClasses; ++c) {
+    if (h->cls_stream[c]) (void)hipStreamDestroy(h->cls_stream[c]);
+    if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  void* ptrs[] = {h->order, h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
                   h->maxpen, h->traj, h->jevals, h->nsolves, h->trace, h->trace_n};
   for (void* p : ptrs)
@@ -382,10 +425,52 @@ vs::KData kdata(vine_sim* h) {
   D.jevals = h->jevals;
   D.nsolves = h->nsolves;
   D.trace_robot = h->trace ? h->trace_robot : -1;
+  D.order = h->order;
+  D.launch_first = 0;
+  D.launch_count = 0;
   D.trace_cap = h->trace_cap;
   D.trace = h->trace;
   D.trace_n = h->trace_n;
   return D;
+}
+
+constexpr int kClassLinks[vine_sim::kClasses] = {64, 128, 256, 512};
+
+int link_class(int n) {
+  int c = 0;
+  while (c + 1 < vine_sim::kClasses && n > kClassLinks[c]) ++c;
+  return c;
+}
+
+// Run launch(class_links, D) for every non-empty class.  A single class goes on the
+// caller's stream; several fork onto the handle's class streams and join back, so
+// that short and long chains share the device.
+template <typename F>
+hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
+  int used = 0, only = -1;
+  for (int c = 0; c < vine_sim::kClasses; ++c)
+    if (h->cls_count[c] > 0) {
+      ++used;
+      only = c;
+    }
+  vs::KData D = kdata(h);
+  if (used <= 1) {
+    if (only < 0) return hipSuccess;
+    D.launch_first = h->cls_first[only];
+    D.launch_count = h->cls_count[only];
+    return launch(kClassLinks[only], D, stream);
+  }
+  hipError_t e = hipEventRecord(h->ev_fork, stream);
+  for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
+    if (h->cls_count[c] == 0) continue;
+    e = hipStreamWaitEvent(h->cls_stream[c], h->ev_fork, 0);
+    D.launch_first = h->cls_first[c];
+    D.launch_count = h->cls_count[c];
+    if (e == hipSuccess) e = launch(kClassLinks[c], D, h->cls_stream[c]);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_join[c], h->cls_stream[c]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, h->ev_join[c], 0);
+  }
+  return e;
 }
 
 }  // namespace
@@ -439,13 +524,9 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       return fail(nullptr, VINE_EINVAL, std::string(msg) + "sPAM/obstacle range out of bounds");
     if (I.obs_count > VINE_MAX_OBSTACLES || I.spam_count > VINE_MAX_SPAMS)
       return fail(nullptr, VINE_ECAPACITY, std::string(msg) + "too many obstacles or sPAMs");
-    for (int s = 0; s < I.spam_count; ++s) {
-      const vine_spam& S = spams[I.spam_offset + s];
-      if (!std::isfinite(S.s_start) || !std::isfinite(S.s_end) || S.s_start < 0.0 ||
-          S.s_end < S.s_start || !(S.side == 1.0 || S.side == -1.0) ||
-          !std::isfinite(S.pressure) || S.pressure < 0.0)
+    for (int s = 0; s < I.spam_count; ++s)
+      if (!spam_ok(spams[I.spam_offset + s]))
         return fail(nullptr, VINE_EINVAL, std::string(msg) + "invalid sPAM");
-    }
     for (int k = 0; k < I.obs_count; ++k) {
       const vine_obstacle& O = obstacles[I.obs_offset + k];
       if (!(O.kind == 0 || O.kind == 1) || !std::isfinite(O.cx) || !std::isfinite(O.cy) ||
@@ -500,22 +581,23 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       obs.push_back(O.a);
       obs.push_back(O.kind == 1 ? O.b : 0.0);
     }
-    // joint j takes the pressure-weighted fraction of link [j l, (j+1) l] each sPAM covers
-    const double l = I.link_len;
-    for (int j = 0; j < I.n_links; ++j) {
-      double pp = 0.0, pm = 0.0;
-      for (int s = 0; s < I.spam_count; ++s) {
-        const vine_spam& S = spams[I.spam_offset + s];
-        double lo = std::fmax(S.s_start, j * l), hi = std::fmin(S.s_end, (j + 1) * l);
-        if (hi > lo) {
-          double w = (hi - lo) / l;
-          if (S.side > 0.0) pp += w * S.pressure; else pm += w * S.pressure;
-        }
-      }
-      cover.push_back(pp);
-      cover.push_back(pm);
-    }
+    append_cover(I, spams, cover);
   }
+  h->inst_h.assign(inst, inst + n_inst);
+  // launch order: by class, then by decreasing n^2 (4 + K), a proxy of the work
+  std::vector<int> order(n_inst);
+  for (int b = 0; b < n_inst; ++b) order[b] = b;
+  auto cost = [&](int b) {
+    return (double)inst[b].n_links * inst[b].n_links * (4.0 + inst[b].obs_count);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ca = link_class(inst[a].n_links), cb = link_class(inst[b].n_links);
+    if (ca != cb) return ca < cb;
+    return cost(a) > cost(b);
+  });
+  for (int b = 0; b < n_inst; ++b) h->cls_count[link_class(inst[b].n_links)]++;
+  for (int c = 1; c < vine_sim::kClasses; ++c)
+    h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
   h->tables_h.resize(h->link_lens.size());
   for (size_t t = 0; t < h->link_lens.size(); ++t)
     build_spam_table(&h->tables_h[t], h->link_lens[t], p.R_c, p.R_act, p.a_corr);
@@ -526,6 +608,12 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   auto A = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
   };
+  A(dalloc(&h->order, order.size()));
+  for (int c = 0; c < vine_sim::kClasses; ++c) {
+    A(hipStreamCreateWithFlags(&h->cls_stream[c], hipStreamNonBlocking));
+    A(hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming));
+  }
+  A(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
   A(dalloc(&h->ii, ii.size()));
   A(dalloc(&h->dd, dd.size()));
   A(dalloc(&h->cover, cover.size()));
@@ -544,7 +632,6 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->ncont, B * TT));
   A(dalloc(&h->chash, B * TT));
   A(dalloc(&h->maxpen, B * TT));
-  A(dalloc(&h->traj, B * TT * NN));
   A(dalloc(&h->jevals, B));
   A(dalloc(&h->nsolves, B));
   if (e != hipSuccess) {
@@ -553,6 +640,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     return fail(nullptr, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
                 std::string("device allocation: ") + hipGetErrorString(e));
   }
+  A(hipMemcpy(h->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
   A(hipMemcpy(h->ii, ii.data(), sizeof(int) * ii.size(), hipMemcpyHostToDevice));
   A(hipMemcpy(h->dd, dd.data(), sizeof(double) * dd.size(), hipMemcpyHostToDevice));
   if (!cover.empty())
@@ -596,24 +684,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
 
 int32_t vine_sim_reset(vine_sim* h, void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t B = h->B, NN = h->N, TT = h->T;
-  hipError_t e = hipSuccess;
-  auto A = [&](hipError_t r) {
-    if (e == hipSuccess) e = r;
-  };
-  A(hipMemsetAsync(h->theta, 0, sizeof(double) * B * NN, s));
-  A(hipMemsetAsync(h->ncur, 0, sizeof(int) * B, s));
-  A(hipMemsetAsync(h->tcur, 0, sizeof(int) * B, s));
-  A(hipMemsetAsync(h->tip, 0, sizeof(double) * B * TT * 3, s));
-  A(hipMemsetAsync(h->rho, 0, sizeof(double) * B * TT, s));
-  A(hipMemsetAsync(h->iters, 0, sizeof(int) * B * TT, s));
-  A(hipMemsetAsync(h->status, 0, sizeof(int) * B * TT, s));
-  A(hipMemsetAsync(h->ncont, 0, sizeof(int) * B * TT, s));
-  A(hipMemsetAsync(h->chash, 0, sizeof(unsigned long long) * B * TT, s));
-  A(hipMemsetAsync(h->maxpen, 0, sizeof(double) * B * TT, s));
-  A(hipMemsetAsync(h->jevals, 0, sizeof(double) * B, s));
-  A(hipMemsetAsync(h->nsolves, 0, sizeof(double) * B, s));
+  const hipError_t e = vs::launch_reset(kdata(h), (hipStream_t)stream);
   h->traj_valid = false;
   h->traj_all = true;
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("reset: ") + hipGetErrorString(e));
@@ -624,8 +695,19 @@ static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_traj, void* 
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   if (n_steps < 0) n_steps = h->T;
   if (n_steps == 0) return VINE_OK;
-  hipError_t e = vs::launch_rollout(kparams(h->prm), kdata(h), n_steps, record_traj, h->N,
-                                    (hipStream_t)stream);
+  if (record_traj && !h->traj) {  // B * T * N doubles, allocated on first use
+    hipError_t e = dalloc(&h->traj, (size_t)h->B * h->T * h->N);
+    if (e != hipSuccess) {
+      h->traj = nullptr;
+      return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
+                  std::string("trajectory allocation: ") + hipGetErrorString(e));
+    }
+  }
+  const vs::KParams kp = kparams(h->prm);
+  hipError_t e = for_each_class(h, (hipStream_t)stream,
+                                [&](int links, const vs::KData& D, hipStream_t s) {
+                                  return vs::launch_rollout(kp, D, n_steps, record_traj, links, s);
+                                });
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   if (record_traj) h->traj_valid = true; else h->traj_all = false;
   return VINE_OK;
@@ -650,10 +732,45 @@ int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weight
     return fail(h, VINE_ESTATE,
                 "step weights need the joint angles of every step since the reset "
                 "(record_traj on every step/rollout call)");
-  hipError_t e = vs::launch_grad(kparams(h->prm), kdata(h), goal, step_weights, h->T, dL_dP,
-                                 dL_ds_start, dL_ds_end, loss, adj_status, h->N,
-                                 (hipStream_t)stream);
+  const vs::KParams kp = kparams(h->prm);
+  hipError_t e = vs::launch_zero3(dL_dP, dL_ds_start, dL_ds_end, h->S, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = for_each_class(h, (hipStream_t)stream, [&](int links, const vs::KData& D, hipStream_t s) {
+      return vs::launch_grad(kp, D, goal, step_weights, h->T, dL_dP, dL_ds_start, dL_ds_end,
+                             loss, adj_status, links, s);
+    });
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return VINE_OK;
+}
+
+int32_t vine_sim_set_spams(vine_sim* h, const vine_spam* spams, int32_t n_spams, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  if (n_spams != h->S || (n_spams > 0 && !spams))
+    return fail(h, VINE_EINVAL, "n_spams differs from the count given at create");
+  for (int i = 0; i < n_spams; ++i)
+    if (!spam_ok(spams[i])) return fail(h, VINE_EINVAL, "invalid sPAM");
+  std::vector<double> cover, sp(4 * (size_t)n_spams);
+  for (const vine_instance& I : h->inst_h) append_cover(I, spams, cover);
+  for (int i = 0; i < n_spams; ++i) {
+    sp[4 * i + 0] = spams[i].s_start;
+    sp[4 * i + 1] = spams[i].s_end;
+    sp[4 * i + 2] = spams[i].side;
+    sp[4 * i + 3] = spams[i].pressure;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  // ordered after the work already queued on the stream; the host buffers are
+  // released only once the copies are done
+  if (!cover.empty())
+    A(hipMemcpyAsync(h->cover, cover.data(), sizeof(double) * cover.size(),
+                     hipMemcpyHostToDevice, s));
+  if (n_spams > 0)
+    A(hipMemcpyAsync(h->spam, sp.data(), sizeof(double) * sp.size(), hipMemcpyHostToDevice, s));
+  A(hipStreamSynchronize(s));
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("set_spams: ") + hipGetErrorString(e));
   return VINE_OK;
 }
 
@@ -783,6 +900,358 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
     if (IG) IG[i] = T.cum[k] + 0.5 * (b - a) * cheb_eval_host(T.ic[k], D + 1, x);
   }
   return VINE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over a slab of resident robot slots.  The slab is an
+// ordinary handle whose per-robot rows are rewritten when a robot is admitted; the
+// kernels are the batch kernels, launched over the list of active slots.
+
+namespace vs {
+hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream);
+}
+
+struct vine_server {
+  vine_sim* h = nullptr;  // slab: B = slots, N = T = max_links
+  int slots = 0, max_links = 0, max_obs = 0, max_spams = 0;
+  static constexpr int kMaxTables = 8;
+  struct Robot {
+    int64_t req = 0;
+    int index = 0;  // within the request
+    vine_instance inst{};
+    std::vector<vine_spam> spams;
+    std::vector<vine_obstacle> obs;
+  };
+  struct Request {
+    int n_robots = 0, n_done = 0, worst = 0;
+    std::vector<double> tips;                 // 3 per robot
+    std::vector<std::vector<double>> theta;   // per robot
+  };
+  std::deque<Robot> queue;
+  std::vector<int> slot_robot;                // index into live, or -1
+  std::vector<Robot> live;                    // by slot
+  std::vector<int> ncur_before;               // host copy of the link counts
+  std::unordered_map<int64_t, Request> reqs;
+  std::deque<int64_t> completed;
+  int* d_slots = nullptr;                     // admitted slots of a round
+  int64_t joint_updates = 0, n_completed = 0;
+  std::string err;
+};
+
+namespace {
+
+int sfail(vine_server* s, int code, const std::string& msg) {
+  if (s) s->err = msg; else g_create_error = msg;
+  return code;
+}
+
+int table_for(vine_server* sv, double l) {
+  vine_sim* h = sv->h;
+  for (size_t t = 0; t < h->link_lens.size(); ++t)
+    if (h->link_lens[t] == l) return (int)t;
+  if ((int)h->link_lens.size() >= vine_server::kMaxTables) return -1;
+  SpamTable T;
+  build_spam_table(&T, l, h->prm.R_c, h->prm.R_act, h->prm.a_corr);
+  const int t = (int)h->link_lens.size();
+  if (hipMemcpy(h->tables + t, &T, sizeof(SpamTable), hipMemcpyHostToDevice) != hipSuccess)
+    return -2;
+  h->link_lens.push_back(l);
+  h->tables_h.push_back(T);
+  return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max_links,
+                           int32_t max_obstacles, int32_t max_spams, vine_server** out) {
+  if (!params || !out || slots < 1 || max_links < 1 || max_obstacles < 0 || max_spams < 0)
+    return sfail(nullptr, VINE_EINVAL, "null pointer or non-positive size");
+  if (max_links > VINE_MAX_LINKS || max_obstacles > VINE_MAX_OBSTACLES ||
+      max_spams > VINE_MAX_SPAMS)
+    return sfail(nullptr, VINE_ECAPACITY, "bounds above the library's limits");
+  if (params->solver != 0)
+    return sfail(nullptr, VINE_EINVAL, "the server runs the structured solver only");
+  // the slab: `slots` placeholder robots at the bounds (overwritten on admission)
+  vine_instance ph{};
+  ph.n_links = max_links;
+  ph.link_len = 0.02;
+  ph.tube_radius = 0.025;
+  ph.body_pressure = 1000.0;
+  std::vector<vine_instance> inst(slots, ph);
+  std::vector<vine_spam> sp((size_t)slots * (max_spams > 0 ? max_spams : 1),
+                            vine_spam{0.0, 0.0, 1.0, 0.0});
+  std::vector<vine_obstacle> ob((size_t)slots * (max_obstacles > 0 ? max_obstacles : 1),
+                                vine_obstacle{0, 0, 1e6, 1e6, 1.0, 1.0});
+  for (int b = 0; b < slots; ++b) {
+    inst[b].spam_offset = b * max_spams;
+    inst[b].spam_count = max_spams;
+    inst[b].obs_offset = b * max_obstacles;
+    inst[b].obs_count = max_obstacles;
+  }
+  vine_sim* h = nullptr;
+  int rc = vine_sim_create(params, inst.data(), slots, sp.data(), (int)sp.size(), ob.data(),
+                           (int)ob.size(), &h);
+  if (rc != VINE_OK) return rc;
+  vine_server* s = new (std::nothrow) vine_server();
+  if (!s) {
+    vine_sim_destroy(h);
+    return sfail(nullptr, VINE_ENOMEM, "host allocation failed");
+  }
+  s->h = h;
+  s->slots = slots;
+  s->max_links = max_links;
+  s->max_obs = max_obstacles;
+  s->max_spams = max_spams;
+  s->slot_robot.assign(slots, -1);
+  s->live.resize(slots);
+  s->ncur_before.assign(slots, 0);
+  // room for every link-length table the server may need
+  SpamTable* t8 = nullptr;
+  hipError_t e = dalloc(&t8, vine_server::kMaxTables);
+  if (e == hipSuccess)
+    e = hipMemcpy(t8, h->tables_h.data(), sizeof(SpamTable) * h->tables_h.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = dalloc(&s->d_slots, slots);
+  if (e != hipSuccess) {
+    if (t8) (void)hipFree(t8);
+    vine_server_destroy(s);
+    return sfail(nullptr, VINE_EDEVICE, std::string("server allocation: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(h->tables);
+  h->tables = t8;
+  *out = s;
+  return VINE_OK;
+}
+
+int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instance* inst,
+                           int32_t n_inst, const vine_spam* spams, int32_t n_spams,
+                           const vine_obstacle* obstacles, int32_t n_obstacles) {
+  if (!s || !inst || n_inst < 1 || n_spams < 0 || n_obstacles < 0 || (n_spams > 0 && !spams) ||
+      (n_obstacles > 0 && !obstacles))
+    return sfail(s, VINE_EINVAL, "null pointer or negative count");
+  if (s->reqs.count(request_id)) return sfail(s, VINE_EINVAL, "request id already in use");
+  for (int b = 0; b < n_inst; ++b) {
+    const vine_instance& I = inst[b];
+    if (I.n_links < 1 || !finite_pos(I.link_len) || !finite_pos(I.tube_radius) ||
+        !finite_pos(I.body_pressure) || !std::isfinite(I.base_x) || !std::isfinite(I.base_y) ||
+        !std::isfinite(I.base_heading) || I.spam_count < 0 || I.spam_offset < 0 ||
+        (int64_t)I.spam_offset + I.spam_count > n_spams || I.obs_count < 0 ||
+        I.obs_offset < 0 || (int64_t)I.obs_offset + I.obs_count > n_obstacles)
+      return sfail(s, VINE_EINVAL, "invalid instance");
+    if (I.n_links > s->max_links || I.obs_count > s->max_obs || I.spam_count > s->max_spams)
+      return sfail(s, VINE_ECAPACITY, "robot above the server's bounds");
+    for (int k = 0; k < I.spam_count; ++k)
+      if (!spam_ok(spams[I.spam_offset + k])) return sfail(s, VINE_EINVAL, "invalid sPAM");
+    for (int k = 0; k < I.obs_count; ++k) {
+      const vine_obstacle& O = obstacles[I.obs_offset + k];
+      if (!(O.kind == 0 || O.kind == 1) || !std::isfinite(O.cx) || !std::isfinite(O.cy) ||
+          !finite_pos(O.a) || (O.kind == 1 && !finite_pos(O.b)))
+        return sfail(s, VINE_EINVAL, "invalid obstacle");
+    }
+  }
+  vine_server::Request R;
+  R.n_robots = n_inst;
+  R.tips.assign(3 * (size_t)n_inst, 0.0);
+  R.theta.resize(n_inst);
+  s->reqs.emplace(request_id, std::move(R));
+  for (int b = 0; b < n_inst; ++b) {
+    vine_server::Robot r;
+    r.req = request_id;
+    r.index = b;
+    r.inst = inst[b];
+    r.spams.assign(spams + inst[b].spam_offset, spams + inst[b].spam_offset + inst[b].spam_count);
+    r.obs.assign(obstacles + inst[b].obs_offset,
+                 obstacles + inst[b].obs_offset + inst[b].obs_count);
+    r.inst.spam_offset = 0;
+    r.inst.obs_offset = 0;
+    s->queue.push_back(std::move(r));
+  }
+  return VINE_OK;
+}
+
+int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
+  if (!s || steps < 1) return sfail(s, VINE_EINVAL, "null server or steps < 1");
+  vine_sim* h = s->h;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  // admission: write the robot's rows into a free slot
+  std::vector<int> admitted;
+  std::vector<double> cover;
+  std::vector<double> obs_rows;
+  std::vector<int> kinds;
+  std::vector<double> spam_rows;
+  for (int slot = 0; slot < s->slots && !s->queue.empty(); ++slot) {
+    if (s->slot_robot[slot] >= 0) continue;
+    vine_server::Robot r = std::move(s->queue.front());
+    s->queue.pop_front();
+    const int tid = table_for(s, r.inst.link_len);
+    if (tid < 0) {
+      s->queue.push_front(std::move(r));
+      return sfail(s, tid == -1 ? VINE_ECAPACITY : VINE_EDEVICE,
+                   tid == -1 ? "more than 8 distinct link lengths" : "table upload failed");
+    }
+    const vine_instance& I = r.inst;
+    const int ii[8] = {I.n_links, slot * s->max_obs, I.obs_count, tid, slot * s->max_links,
+                       slot * s->max_spams, I.spam_count, 0};
+    const double dd[6] = {I.link_len, I.tube_radius, I.body_pressure, I.base_x, I.base_y,
+                          I.base_heading};
+    cover.clear();
+    append_cover(I, r.spams.data(), cover);
+    obs_rows.clear();
+    kinds.clear();
+    for (const vine_obstacle& O : r.obs) {
+      kinds.push_back(O.kind);
+      obs_rows.insert(obs_rows.end(), {O.cx, O.cy, O.a, O.kind == 1 ? O.b : 0.0});
+    }
+    spam_rows.clear();
+    for (const vine_spam& S : r.spams)
+      spam_rows.insert(spam_rows.end(), {S.s_start, S.s_end, S.side, S.pressure});
+    // synchronous copies: the host rows are reused for the next robot
+    A(hipMemcpy(h->ii + 8 * (size_t)slot, ii, sizeof ii, hipMemcpyHostToDevice));
+    A(hipMemcpy(h->dd + 6 * (size_t)slot, dd, sizeof dd, hipMemcpyHostToDevice));
+    A(hipMemcpy(h->cover + 2 * (size_t)slot * s->max_links, cover.data(),
+                sizeof(double) * cover.size(), hipMemcpyHostToDevice));
+    if (!kinds.empty()) {
+      A(hipMemcpy(h->okind + (size_t)slot * s->max_obs, kinds.data(), sizeof(int) * kinds.size(),
+                  hipMemcpyHostToDevice));
+      A(hipMemcpy(h->obs + 4 * (size_t)slot * s->max_obs, obs_rows.data(),
+                  sizeof(double) * obs_rows.size(), hipMemcpyHostToDevice));
+    }
+    if (!spam_rows.empty())
+      A(hipMemcpy(h->spam + 4 * (size_t)slot * s->max_spams, spam_rows.data(),
+                  sizeof(double) * spam_rows.size(), hipMemcpyHostToDevice));
+    s->live[slot] = std::move(r);
+    s->slot_robot[slot] = slot;
+    s->ncur_before[slot] = 0;
+    admitted.push_back(slot);
+  }
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("admission: ") + hipGetErrorString(e));
+  if (!admitted.empty()) {
+    A(hipMemcpyAsync(s->d_slots, admitted.data(), sizeof(int) * admitted.size(),
+                     hipMemcpyHostToDevice, st));
+    A(vs::launch_slot_reset(kdata(h), s->d_slots, (int)admitted.size(), st));
+  }
+  // launch order: active slots by class, longest expected work first
+  std::vector<int> order;
+  for (int slot = 0; slot < s->slots; ++slot)
+    if (s->slot_robot[slot] >= 0) order.push_back(slot);
+  if (order.empty()) return 0;
+  auto cost = [&](int b) {
+    const vine_instance& I = s->live[b].inst;
+    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
+    if (ca != cb) return ca < cb;
+    return cost(a) > cost(b);
+  });
+  for (int c = 0; c < vine_sim::kClasses; ++c) h->cls_count[c] = 0;
+  for (int b : order) h->cls_count[link_class(s->live[b].inst.n_links)]++;
+  h->cls_first[0] = 0;
+  for (int c = 1; c < vine_sim::kClasses; ++c)
+    h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
+  A(hipMemcpyAsync(h->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch set-up: ") + hipGetErrorString(e));
+  const vs::KParams kp = kparams(h->prm);
+  e = for_each_class(h, st, [&](int links, const vs::KData& D, hipStream_t ss) {
+    return vs::launch_rollout(kp, D, steps, 0, links, ss);
+  });
+  std::vector<int> ncur(s->slots);
+  A(hipMemcpyAsync(ncur.data(), h->ncur, sizeof(int) * s->slots, hipMemcpyDeviceToHost, st));
+  A(hipStreamSynchronize(st));
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("round: ") + hipGetErrorString(e));
+  // bookkeeping and retirement
+  int done_now = 0;
+  for (int b : order) {
+    const int n0 = s->ncur_before[b], n1 = ncur[b];
+    s->joint_updates += (int64_t)n1 * (n1 + 1) / 2 - (int64_t)n0 * (n0 + 1) / 2;
+    s->ncur_before[b] = n1;
+    vine_server::Robot& r = s->live[b];
+    if (n1 < r.inst.n_links) continue;
+    vine_server::Request& R = s->reqs[r.req];
+    const int n = r.inst.n_links;
+    std::vector<double> th(n);
+    std::vector<int> stat(n);
+    double tip[3];
+    A(hipMemcpy(th.data(), h->theta + (size_t)b * h->N, sizeof(double) * n, hipMemcpyDeviceToHost));
+    A(hipMemcpy(stat.data(), h->status + (size_t)b * h->T, sizeof(int) * n, hipMemcpyDeviceToHost));
+    A(hipMemcpy(tip, h->tip + 3 * ((size_t)b * h->T + n - 1), sizeof tip, hipMemcpyDeviceToHost));
+    for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, stat[t]);
+    std::copy(tip, tip + 3, R.tips.begin() + 3 * (size_t)r.index);
+    R.theta[r.index] = std::move(th);
+    if (++R.n_done == R.n_robots) {
+      s->completed.push_back(r.req);
+      ++s->n_completed;
+      ++done_now;
+    }
+    s->slot_robot[b] = -1;
+  }
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("retire: ") + hipGetErrorString(e));
+  return done_now;
+}
+
+int32_t vine_server_poll(vine_server* s, int64_t* ids, int32_t* worst_status, int32_t cap) {
+  if (!s || (cap > 0 && !ids)) return sfail(s, VINE_EINVAL, "null server or buffer");
+  int k = 0;
+  while (k < cap && !s->completed.empty()) {
+    const int64_t id = s->completed.front();
+    s->completed.pop_front();
+    ids[k] = id;
+    if (worst_status) worst_status[k] = s->reqs[id].worst;
+    ++k;
+  }
+  return k;
+}
+
+int32_t vine_server_result(const vine_server* sc, int64_t request_id, int32_t robot, double* tip,
+                           double* theta) {
+  vine_server* s = const_cast<vine_server*>(sc);
+  if (!s || !tip) return sfail(s, VINE_EINVAL, "null server or buffer");
+  auto it = s->reqs.find(request_id);
+  if (it == s->reqs.end() || it->second.n_done < it->second.n_robots || robot < 0 ||
+      robot >= it->second.n_robots)
+    return sfail(s, VINE_EINVAL, "unknown or unfinished request, or robot out of range");
+  std::copy(it->second.tips.begin() + 3 * (size_t)robot,
+            it->second.tips.begin() + 3 * (size_t)robot + 3, tip);
+  if (theta) std::copy(it->second.theta[robot].begin(), it->second.theta[robot].end(), theta);
+  return VINE_OK;
+}
+
+int32_t vine_server_release(vine_server* s, int64_t request_id) {
+  if (!s) return sfail(s, VINE_EINVAL, "null server");
+  auto it = s->reqs.find(request_id);
+  if (it == s->reqs.end() || it->second.n_done < it->second.n_robots)
+    return sfail(s, VINE_EINVAL, "unknown or unfinished request");
+  s->reqs.erase(it);
+  return VINE_OK;
+}
+
+void vine_server_stats(const vine_server* s, int64_t out[4]) {
+  if (!s || !out) return;
+  int64_t active = 0;
+  for (int b : s->slot_robot) active += b >= 0;
+  out[0] = (int64_t)s->queue.size();
+  out[1] = active;
+  out[2] = s->n_completed;
+  out[3] = s->joint_updates;
+}
+
+void vine_server_destroy(vine_server* s) {
+  if (!s) return;
+  if (s->d_slots) (void)hipFree(s->d_slots);
+  vine_sim_destroy(s->h);
+  delete s;
+}
+
+const char* vine_server_last_error(const vine_server* s) {
+  return s ? s->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

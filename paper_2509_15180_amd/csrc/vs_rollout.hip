@@ -23,7 +23,6 @@
 
 namespace vs {
 
-constexpr int kMaxObs = 128;
 constexpr int kMaxC = 128;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -87,6 +86,105 @@ __device__ __forceinline__ void wargmax(double& v, int& idx) {
       idx = oi;
     }
   }
+}
+
+// DPP move of a double whose lanes without a source (or in masked-off rows) keep idv
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_or(double v, double idv) {
+  int lo = __builtin_amdgcn_update_dpp(__double2loint(idv), __double2loint(v), CTRL, ROWMASK, 0xf,
+                                       false);
+  int hi = __builtin_amdgcn_update_dpp(__double2hiint(idv), __double2hiint(v), CTRL, ROWMASK, 0xf,
+                                       false);
+  return __hiloint2double(hi, lo);
+}
+
+// Scans of affine maps y -> A y + B over the 64 lanes.  compose(later, earlier) =
+// (A_l A_e, A_l B_e + B_l); identity (1, 0).
+__device__ __forceinline__ void aff_compose(double& A, double& B, double Ae, double Be) {
+  B = fma(A, Be, B);
+  A *= Ae;
+}
+
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ void aff_level(double& A, double& B) {
+  const double Ae = dpp_or<CTRL, ROWMASK>(A, 1.0), Be = dpp_or<CTRL, ROWMASK>(B, 0.0);
+  aff_compose(A, B, Ae, Be);
+}
+
+// lane i: f_i o f_{i-1} o ... o f_0
+__device__ __forceinline__ void aff_scan_prefix(double& A, double& B) {
+  aff_level<0x111>(A, B);        // row_shr:1
+  aff_level<0x112>(A, B);        // row_shr:2
+  aff_level<0x114>(A, B);        // row_shr:4
+  aff_level<0x118>(A, B);        // row_shr:8
+  aff_level<0x142, 0xa>(A, B);   // row_bcast:15 into rows 1 and 3
+  aff_level<0x143, 0xc>(A, B);   // row_bcast:31 into rows 2 and 3
+}
+
+// lane i: f_i o f_{i+1} o ... o f_63
+__device__ __forceinline__ void aff_scan_suffix(double& A, double& B, int lane) {
+  aff_level<0x101>(A, B);        // row_shl:1
+  aff_level<0x102>(A, B);        // row_shl:2
+  aff_level<0x104>(A, B);        // row_shl:4
+  aff_level<0x108>(A, B);        // row_shl:8
+  {  // rows 0 and 2 take the aggregates of rows 1 and 3 (held by lanes 16 and 48)
+    const double A16 = lane_bcast(A, 16), B16 = lane_bcast(B, 16);
+    const double A48 = lane_bcast(A, 48), B48 = lane_bcast(B, 48);
+    const int row = lane >> 4;
+    if (row == 0) aff_compose(A, B, A16, B16);
+    if (row == 2) aff_compose(A, B, A48, B48);
+  }
+  {  // rows 0 and 1 take the aggregate of rows 2-3 (lane 32)
+    const double A32 = lane_bcast(A, 32), B32 = lane_bcast(B, 32);
+    if (lane < 32) aff_compose(A, B, A32, B32);
+  }
+}
+
+// 2x2 matrices [a b; c d]; x <- x * e (x is the later factor)
+struct M2 {
+  double a, b, c, d;
+};
+
+__device__ __forceinline__ void m2_mul(M2& x, const M2& e) {
+  const double a = fma(x.a, e.a, x.b * e.c), b = fma(x.a, e.b, x.b * e.d);
+  const double c = fma(x.c, e.a, x.d * e.c), d = fma(x.c, e.b, x.d * e.d);
+  x.a = a;
+  x.b = b;
+  x.c = c;
+  x.d = d;
+}
+
+// scale by a power of two so that the largest entry lies in [0.5, 1): only ratios of
+// entries are used, and the exponent would otherwise drift over long products
+__device__ __forceinline__ void m2_norm(M2& x) {
+  const double m = fmax(fmax(fabs(x.a), fabs(x.b)), fmax(fabs(x.c), fabs(x.d)));
+  int e = 0;
+  if (m > 0.0 && m <= 1.7e308) (void)frexp(m, &e);
+  x.a = ldexp(x.a, -e);
+  x.b = ldexp(x.b, -e);
+  x.c = ldexp(x.c, -e);
+  x.d = ldexp(x.d, -e);
+}
+
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ void m2_level(M2& x) {
+  M2 e;
+  e.a = dpp_or<CTRL, ROWMASK>(x.a, 1.0);
+  e.b = dpp_or<CTRL, ROWMASK>(x.b, 0.0);
+  e.c = dpp_or<CTRL, ROWMASK>(x.c, 0.0);
+  e.d = dpp_or<CTRL, ROWMASK>(x.d, 1.0);
+  m2_mul(x, e);
+  m2_norm(x);
+}
+
+// lane i: M_i M_{i-1} ... M_0 (up to a positive scale)
+__device__ __forceinline__ void m2_scan_prefix(M2& x) {
+  m2_level<0x111>(x);
+  m2_level<0x112>(x);
+  m2_level<0x114>(x);
+  m2_level<0x118>(x);
+  m2_level<0x142, 0xa>(x);
+  m2_level<0x143, 0xc>(x);
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
@@ -180,6 +278,10 @@ struct Ctx {
   double l, R, Mmax, arm, bx, by, bpsi, last_len;
   const SpamTable* tab;
   const WrTable* wr;
+  // this robot's obstacles, read through the constant address space (scalar loads:
+  // the obstacle index is the same for the whole wave)
+  const __attribute__((address_space(4))) double* obs;  // [K][4]
+  const __attribute__((address_space(4))) int* okind;   // [K]
   KParams P;
 };
 
@@ -220,11 +322,12 @@ __device__ void joint_law(const Ctx& c, double th, double pp, double pm, double*
 // curvature of the distance field.  Returns false (no contact, outputs unset) when
 // the disk is clearly clear of the obstacle; the squared-distance pre-test keeps a
 // relative margin so that every pair it rejects also has g >= 0 when evaluated.
-__device__ __forceinline__ bool obs_gap(int kind, const double* o, double R, double x, double y,
-                                        double& g, double& nx, double& ny, double& kap) {
+__device__ __forceinline__ bool obs_gap(int kind, double ox, double oy, double oa, double ob,
+                                        double R, double x, double y, double& g, double& nx,
+                                        double& ny, double& kap) {
   if (kind == 0) {
-    const double vx = x - o[0], vy = y - o[1];
-    const double d2 = vx * vx + vy * vy, rr = o[2] + R;
+    const double vx = x - ox, vy = y - oy;
+    const double d2 = vx * vx + vy * vy, rr = oa + R;
     if (!(d2 < rr * rr * (1.0 + 1e-12))) return false;
     const double d = sqrt(d2);
     if (d > 0.0) {
@@ -236,11 +339,11 @@ __device__ __forceinline__ bool obs_gap(int kind, const double* o, double R, dou
       ny = 0.0;
       kap = 0.0;
     }
-    g = (d - o[2]) - R;
+    g = (d - oa) - R;
     return g < 0.0;
   }
-  const double sx = x >= o[0] ? 1.0 : -1.0, sy = y >= o[1] ? 1.0 : -1.0;
-  const double dx = fabs(x - o[0]) - o[2], dy = fabs(y - o[1]) - o[3];
+  const double sx = x >= ox ? 1.0 : -1.0, sy = y >= oy ? 1.0 : -1.0;
+  const double dx = fabs(x - ox) - oa, dy = fabs(y - oy) - ob;
   if (dx >= R || dy >= R) return false;
   kap = 0.0;
   if (dx > 0.0 || dy > 0.0) {
@@ -266,21 +369,31 @@ __device__ __forceinline__ bool obs_gap(int kind, const double* o, double R, dou
   return true;
 }
 
+// The pre-tests of obs_gap alone: false only for pairs obs_gap rejects.
+__device__ __forceinline__ bool obs_near(int kind, double ox, double oy, double oa, double ob,
+                                         double R, double x, double y) {
+  if (kind == 0) {
+    const double vx = x - ox, vy = y - oy, rr = oa + R;
+    return vx * vx + vy * vy < rr * rr * (1.0 + 1e-12);
+  }
+  return (int)(fabs(x - ox) - oa < R) & (int)(fabs(y - oy) - ob < R);
+}
+
 // ---------------------------------------------------------------------------
 // LDS working set of one robot
 
 constexpr int kMaxCL = 16;             // contact links the structured solve holds
 constexpr int kMaxCols = 3 * kMaxCL;   // columns of its low-rank term
 
-template <int NMAX>
+template <int NMAX, int WN_ = 1>
 struct Smem {
-  static constexpr int WN = NMAX == 64 ? 64 : 1;  // dense cross-check solver (64 links)
+  static constexpr int WN = WN_;  // order of the dense cross-check system (64, else unused)
   union {
     double W[WN][WN + 1];                           // (H + mu I | -r), LU in place
     struct {
-      double G[kMaxCols][kMaxCols];                 // U^T T^-1 U
-      double K[kMaxCols][kMaxCols + 1];             // (I + S G | S c), LU in place
+      double G[kMaxCols][kMaxCols + 1];  // U^T T^-1 U, then (I + S G | S c) and its LU in place
     } sm;
+    double F[kWave][17];  // one chunk of forward-substituted columns (Gram by MFMA; padded)
   };
   double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
   double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
@@ -296,9 +409,8 @@ struct Smem {
   int clink[kMaxCL];   // contact-link slot -> link
   double cM[kMaxCL][6];  // 3x3 contact block per contact link (symmetric: 00 01 02 11 12 22)
   double cvec[kMaxCols], wvec[kMaxCols];
+  double gcarry[16];   // forward-substitution carries between row chunks (Gram pass)
   int ncl_links;
-  double obs[kMaxObs][4];
-  int okind[kMaxObs];
   int ci[kMaxC], ck[kMaxC];
   double cl[kMaxC], cxx[kMaxC], cxy[kMaxC], cnx[kMaxC], cny[kMaxC], ckap[kMaxC], cpen[kMaxC];
   int ncl;
@@ -307,8 +419,8 @@ struct Smem {
 };
 
 // Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
-template <int NMAX>
-__device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool want_E) {
+template <class SM>
+__device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   const int lane = threadIdx.x;
   const int n = c.n;
   if (lane == 0) S.jevals += n;
@@ -344,30 +456,45 @@ __device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool w
     S.r[j] = q;
     Esum += E;
   }
-  // penetrating (disk, obstacle) pairs, in (disk, obstacle, link) order per chunk
+  // penetrating (disk, obstacle) pairs, compacted in (obstacle, disk, link) order per
+  // chunk.  The exact gap (square root, divisions) is taken only for pairs whose
+  // cheap pre-test some lane of the wave passes.
   int cnt = 0;
   const unsigned long long lt = (1ull << lane) - 1ull;
   for (int base = 0; base < n; base += kWave) {
-    int j = base + lane;
-    bool on = j < n;
-    double L = (j == n - 1) ? c.last_len : c.l;
-    for (int hh = 1; hh <= 2; ++hh) {
-      double s = 0.5 * hh * L;
-      double xx = on ? S.px[j] + s * S.tx[j] : 0.0;
-      double xy = on ? S.py[j] + s * S.ty[j] : 0.0;
-      for (int k = 0; k < c.K; ++k) {
+    const int j = base + lane;
+    const bool on = j < n;
+    const double L = (j == n - 1) ? c.last_len : c.l;
+    double xs[2], ys[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const double s = 0.5 * (hh + 1) * L;
+      xs[hh] = on ? S.px[j] + s * S.tx[j] : 0.0;
+      ys[hh] = on ? S.py[j] + s * S.ty[j] : 0.0;
+    }
+    for (int k = 0; k < c.K; ++k) {
+      const double ox = c.obs[4 * k], oy = c.obs[4 * k + 1], oa = c.obs[4 * k + 2],
+                   ob = c.obs[4 * k + 3];
+      const int kind = c.okind[k];
+      bool near[2];
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) near[hh] = on && obs_near(kind, ox, oy, oa, ob, c.R, xs[hh], ys[hh]);
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        if (__ballot(near[hh]) == 0ull) continue;
         double g = 0.0, nx = 0.0, ny = 0.0, kap = 0.0;
-        const bool hit = on && obs_gap(S.okind[k], S.obs[k], c.R, xx, xy, g, nx, ny, kap);
-        unsigned long long m = __ballot(hit);
+        const bool hit =
+            near[hh] && obs_gap(kind, ox, oy, oa, ob, c.R, xs[hh], ys[hh], g, nx, ny, kap);
+        const unsigned long long m = __ballot(hit);
         if (m) {
-          int pos = cnt + __popcll(m & lt);
+          const int pos = cnt + __popcll(m & lt);
           if (hit && pos < kMaxC) {
-            double pen = -g;
+            const double pen = -g;
             S.ci[pos] = j;
             S.ck[pos] = k;
             S.cl[pos] = c.P.kc * pen;
-            S.cxx[pos] = xx;
-            S.cxy[pos] = xy;
+            S.cxx[pos] = xs[hh];
+            S.cxy[pos] = ys[hh];
             S.cnx[pos] = nx;
             S.cny[pos] = ny;
             S.ckap[pos] = kap;
@@ -413,8 +540,8 @@ __device__ double evaluate(Smem<NMAX>& S, const Ctx& c, const double* th, bool w
 }
 
 // W = (H + mu I | -r) at the state last evaluated (poses, contacts and r in S)
-template <int NMAX>
-__device__ void assemble(Smem<NMAX>& S, const Ctx& c, const double* th, double mu,
+template <class SM>
+__device__ void assemble(SM& S, const Ctx& c, const double* th, double mu,
                          const double* rhs) {
   const int lane = threadIdx.x, n = c.n;
   for (int j = lane; j < n; j += kWave) {
@@ -489,9 +616,9 @@ __device__ bool lu_solve(double* A, int ld, int n, double* x) {
   return __all(ok);
 }
 
-template <int NMAX>
-__device__ bool lu_solve_dense(Smem<NMAX>& S, int n) {
-  return lu_solve(&S.W[0][0], Smem<NMAX>::WN + 1, n, S.d);
+template <class SM>
+__device__ bool lu_solve_dense(SM& S, int n) {
+  return lu_solve(&S.W[0][0], SM::WN + 1, n, S.d);
 }
 
 // Per-iteration set-up of the structured solve (independent of mu): joint slopes,
@@ -505,8 +632,8 @@ __device__ bool lu_solve_dense(Smem<NMAX>& S, int n) {
 //   alpha = (n_y, -n_x, s t_i x n), beta = (n_x, n_y, s t_i . n),
 // s the disk's distance from the link's proximal joint.  Returns false when more
 // than kMaxCL links are in contact.
-template <int NMAX>
-__device__ bool structured_setup(Smem<NMAX>& S, const Ctx& c) {
+template <class SM>
+__device__ bool structured_setup(SM& S, const Ctx& c) {
   const int lane = threadIdx.x, n = c.n, nc = S.ncl;
   const unsigned long long lt = (1ull << lane) - 1ull;
   for (int j = lane; j < n; j += kWave) {
@@ -585,137 +712,340 @@ __device__ bool structured_setup(Smem<NMAX>& S, const Ctx& c) {
   return true;
 }
 
-// value of low-rank column col (contact-link slot col/3, kind col%3) at row m
-template <int NMAX>
-__device__ __forceinline__ double ucol(const Smem<NMAX>& S, double l, int col, int m, double cm,
-                                       double sm) {
-  const int i = S.clink[col / 3], k = col % 3;
-  if (k == 2) return m == i ? 1.0 : 0.0;
-  if (m >= i) return 0.0;
-  return k == 0 ? l * cm : l * sm;
+// ---------------------------------------------------------------------------
+// Tridiagonal part by wave scans.  T_mm = t_m = k_m + k_{m+1} + C_m and
+// T_{m-1,m} = e_m = -k_m, k_j = q'_j + mu (k_n = 0).  The LDL^T pivots
+// D_m = t_m - e_m^2 / D_{m-1} are ratios p_m / p_{m-1} of leading principal minors,
+// which obey p_m = t_m p_{m-1} - e_m^2 p_{m-2}: a prefix product of the 2x2 matrices
+// [t_m, -e_m^2; 1, 0] (first column of the product = (p_m, p_{m-1})).  The
+// substitutions y_m = b_m - l_{m-1} y_{m-1} and x_m = y_m / D_m - l_m x_{m+1},
+// l_m = T_{m,m+1} / D_m, are affine recurrences: prefix and suffix scans of affine
+// maps.  Rows go 64 to a chunk; chunks are chained through the scan carries.
+// Returns false on a vanishing or non-finite pivot (the caller raises mu).
+template <class SM>
+__device__ bool tri_factor(SM& S, int n, double mu) {
+  const int lane = threadIdx.x;
+  M2 carry{1.0, 0.0, 0.0, 1.0};
+  bool ok = true;
+  for (int base = 0; base < n; base += kWave) {
+    const int m = base + lane;
+    const bool on = m < n;
+    double km = 0.0, kn = 0.0, cm = 0.0;
+    if (on) {
+      km = S.dq[m] + mu;
+      kn = m + 1 < n ? S.dq[m + 1] + mu : 0.0;
+      cm = S.cg[m];
+    }
+    const double t = km + kn + cm;
+    const double e = m >= 1 ? -km : 0.0;
+    M2 x = on ? M2{t, -e * e, 1.0, 0.0} : M2{1.0, 0.0, 0.0, 1.0};
+    m2_scan_prefix(x);
+    if (base > 0) {
+      m2_mul(x, carry);
+      m2_norm(x);
+    }
+    if (on) {
+      const double D = x.a / x.c;
+      ok = ok && isfinite(D) && fabs(D) > 1e-14 * (fabs(t) + fabs(e));
+      const double di = 1.0 / D;
+      S.dinv[m] = di;
+      S.ell[m] = m + 1 < n ? -kn * di : 0.0;
+    }
+    carry = M2{lane_bcast(x.a, kWave - 1), lane_bcast(x.b, kWave - 1), lane_bcast(x.c, kWave - 1),
+               lane_bcast(x.d, kWave - 1)};
+  }
+  __syncthreads();
+  return __all(ok);
 }
 
-// Solve T y = b in place (b in S.aux, result in dst) with the factors in S.dinv/S.ell.
-template <int NMAX>
-__device__ void tri_solve(Smem<NMAX>& S, int n, const double* b, double* dst) {
+// Forward substitution y = L^-1 b into dst (b and dst in LDS; dst may be b)
+template <class SM>
+__device__ void tri_fwd(SM& S, int n, const double* b, double* dst) {
   const int lane = threadIdx.x;
-  if (lane == 0) {
-    double y = b[0];
-    S.aux[0] = y;
-    for (int m = 1; m < n; ++m) {
-      y = b[m] - S.ell[m - 1] * y;
-      S.aux[m] = y;
+  double carry = 0.0;
+  for (int base = 0; base < n; base += kWave) {
+    const int m = base + lane;
+    double A = 1.0, B = 0.0;
+    if (m < n) {
+      A = m > 0 ? -S.ell[m - 1] : 0.0;
+      B = b[m];
     }
-    double x = S.aux[n - 1] * S.dinv[n - 1];
-    dst[n - 1] = x;
-    for (int m = n - 2; m >= 0; --m) {
-      x = S.aux[m] * S.dinv[m] - S.ell[m] * x;
-      dst[m] = x;
+    aff_scan_prefix(A, B);
+    const double y = fma(A, carry, B);
+    if (m < n) dst[m] = y;
+    carry = lane_bcast(y, kWave - 1);
+  }
+}
+
+// Back substitution x = D^-1 y - L^T-part, in place on y
+template <class SM>
+__device__ void tri_bwd(SM& S, int n, double* y) {
+  const int lane = threadIdx.x;
+  double carry = 0.0;
+  for (int base = (n - 1) / kWave * kWave; base >= 0; base -= kWave) {
+    const int m = base + lane;
+    double A = 1.0, B = 0.0;
+    if (m < n) {
+      A = -S.ell[m];
+      B = y[m] * S.dinv[m];
+    }
+    aff_scan_suffix(A, B, lane);
+    const double x = fma(A, carry, B);
+    if (m < n) y[m] = x;
+    carry = lane_bcast(x, 0);
+  }
+  __syncthreads();
+}
+
+// T x = b with the factors in S.dinv / S.ell (b and dst in LDS; dst may be b)
+template <class SM>
+__device__ void tri_solve(SM& S, int n, const double* b, double* dst) {
+  tri_fwd(S, n, b, dst);
+  tri_bwd(S, n, dst);
+}
+
+// value of low-rank column b (contact-link slot b/3; kinds X, Y, e) at row m
+template <class SM>
+__device__ __forceinline__ double ucol(const SM& S, double l, int b, int m) {
+  const int i = S.clink[b / 3], k = b % 3;
+  if (k == 2) return m == i ? 1.0 : 0.0;
+  if (m >= i) return 0.0;
+  return l * (k == 0 ? S.tx[m] : S.ty[m]);
+}
+
+// one level of a prefix scan of the affine maps (A, B_b), the same A for every column
+template <int CTRL, int ROWMASK, int NB>
+__device__ __forceinline__ void aff_level_multi(double& A, double (&B)[NB], unsigned act) {
+  const double Ae = dpp_or<CTRL, ROWMASK>(A, 1.0);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (act & (1u << i)) B[i] = fma(A, dpp_or<CTRL, ROWMASK>(B[i], 0.0), B[i]);
+  A *= Ae;
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Gram matrix of the contact columns by FP64 MFMA (ncol <= 15).  With T = L D L^T,
+//   G = U^T T^-1 U = F^T D^-1 F and c = U^T T^-1 v = F^T D^-1 y,
+// F = L^-1 U and y = L^-1 v: forward substitutions only, eight columns per pass of
+// scans (the recurrence coefficients are shared).  Per chunk of 64 rows the columns
+// [F | y] (16 wide, y last) go through LDS into 16 v_mfma_f64_16x16x4 steps that
+// accumulate [F | y]^T D^-1 [F | y].  y is also left in S.z for the back substitution.
+template <class SM>
+__device__ void gram_mfma(SM& S, const Ctx& c, int ncol) {
+  constexpr int NC = 16, NB = 8;  // columns 0..ncol-1: U; column NC-1: v
+  const int lane = threadIdx.x, n = c.n;
+  if (lane < NC) S.gcarry[lane] = 0.0;
+  __syncthreads();
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int base = 0; base < n; base += kWave) {
+    const int m = base + lane;
+    const bool on = m < n;
+    const double A0 = on ? (m > 0 ? -S.ell[m - 1] : 0.0) : 1.0;
+    for (int half = 0; half < NC / NB; ++half) {
+      unsigned act = 0u;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int b = NB * half + i;
+        if (b < ncol || b == NC - 1) act |= 1u << i;
+      }
+      if (act == 0u) continue;
+      double A = A0, B[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int b = NB * half + i;
+        B[i] = (on && (act & (1u << i))) ? (b == NC - 1 ? S.v[m] : ucol(S, c.l, b, m)) : 0.0;
+      }
+      aff_level_multi<0x111, 0xf>(A, B, act);  // row_shr:1
+      aff_level_multi<0x112, 0xf>(A, B, act);  // row_shr:2
+      aff_level_multi<0x114, 0xf>(A, B, act);  // row_shr:4
+      aff_level_multi<0x118, 0xf>(A, B, act);  // row_shr:8
+      aff_level_multi<0x142, 0xa>(A, B, act);  // row_bcast:15
+      aff_level_multi<0x143, 0xc>(A, B, act);  // row_bcast:31
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        if (!(act & (1u << i))) continue;
+        const int b = NB * half + i;
+        const double y = on ? fma(A, S.gcarry[b], B[i]) : 0.0;
+        S.F[lane][b] = y;
+        if (b == NC - 1 && on) S.z[m] = y;
+        if (lane == kWave - 1) S.gcarry[b] = y;
+      }
+    }
+    __syncthreads();
+    // lane l carries row 4 kb + l / 16, column l % 16 of both operands
+    const int rsub = lane >> 4, col = lane & 15;
+#pragma unroll 4
+    for (int kb = 0; kb < kWave / 4; ++kb) {
+      const int r = 4 * kb + rsub;
+      const double a = S.F[r][col];
+      const double di = base + r < n ? S.dinv[base + r] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a * di, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // lane l, register v holds entry (l / 16 + 4 v, l % 16)
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = (lane >> 4) + 4 * v, col = lane & 15;
+    if (row < ncol) {
+      if (col < ncol) S.sm.G[row][col] = acc[v];
+      else if (col == NC - 1) S.cvec[row] = acc[v];
     }
   }
   __syncthreads();
+}
+
+// out[(3a + k) * stride] = (U^T y)_{3a+k}: exclusive prefix sums of l cos(phi) y and
+// l sin(phi) y at contact link i_a, and y_{i_a}
+template <class SM>
+__device__ void ut_times(SM& S, const Ctx& c, const double* y, double* out, int stride) {
+  const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
+  double c1 = 0.0, c2 = 0.0;
+  for (int base = 0; base < n; base += kWave) {
+    const int m = base + lane;
+    const double a = m < n ? c.l * S.tx[m] * y[m] : 0.0;
+    const double b = m < n ? c.l * S.ty[m] * y[m] : 0.0;
+    const double ia = wscan_incl(a, lane) + c1, ib = wscan_incl(b, lane) + c2;
+    if (m < n) {
+      S.ps1[m] = ia - a;
+      S.ps2[m] = ib - b;
+    }
+    c1 = lane_bcast(ia, kWave - 1);
+    c2 = lane_bcast(ib, kWave - 1);
+  }
+  __syncthreads();
+  for (int a = lane; a < L; a += kWave) {
+    const int i = S.clink[a];
+    out[(3 * a + 0) * stride] = S.ps1[i];
+    out[(3 * a + 1) * stride] = S.ps2[i];
+    out[(3 * a + 2) * stride] = y[i];
+  }
+  __syncthreads();
+}
+
+// K = I + S G with S = blockdiag(M_a), in place in S.sm.G: the three rows of a block
+// depend on the same three rows of G only; the right-hand side S c goes to column ncol.
+template <class SM>
+__device__ void capacitance_matrix(SM& S, int L) {
+  const int ncol = 3 * L;
+  for (int blk = threadIdx.x; blk < L; blk += kWave) {
+    const double* M = S.cM[blk];
+    double* g0 = S.sm.G[3 * blk];
+    double* g1 = S.sm.G[3 * blk + 1];
+    double* g2 = S.sm.G[3 * blk + 2];
+    const int r0 = 3 * blk;
+    for (int col = 0; col <= ncol; ++col) {
+      const double a0 = col < ncol ? g0[col] : S.cvec[r0];
+      const double a1 = col < ncol ? g1[col] : S.cvec[r0 + 1];
+      const double a2 = col < ncol ? g2[col] : S.cvec[r0 + 2];
+      g0[col] = (col == r0 ? 1.0 : 0.0) + M[0] * a0 + M[1] * a1 + M[2] * a2;
+      g1[col] = (col == r0 + 1 ? 1.0 : 0.0) + M[1] * a0 + M[3] * a1 + M[4] * a2;
+      g2[col] = (col == r0 + 2 ? 1.0 : 0.0) + M[2] * a0 + M[4] * a1 + M[5] * a2;
+    }
+  }
+  __syncthreads();
+}
+
+// (K | S c) w for ncol <= 15, one row per lane: Gauss-Jordan with partial pivoting
+// over the rows not yet used as pivots.  Rows stay in LDS between pivot steps; a step
+// loads the lane's row and the pivot row whole, so its loads issue together.
+template <class SM>
+__device__ bool small_solve(SM& S, int ncol) {
+  constexpr int NC = 16;  // row length bound (ncol + 1 <= NC)
+  const int lane = threadIdx.x;
+  const bool row = lane < ncol;
+  double* Kr = S.sm.G[row ? lane : 0];
+  bool used = !row, ok = true;
+  int mycol = -1;
+  for (int k = 0; k < ncol; ++k) {
+    double v = used ? -1.0 : fabs(Kr[k]);
+    int idx = lane;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {  // rows live in lanes 0..15
+      const double ov = __shfl_xor(v, o, kWave);
+      const int oi = __shfl_xor(idx, o, kWave);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    const int p = __builtin_amdgcn_readlane(idx, 0);
+    if (!(lane_bcast(v, 0) > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double* Kp = S.sm.G[p];
+    double pr[NC], my[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      pr[j] = j <= ncol ? Kp[j] : 0.0;
+      my[j] = j <= ncol ? Kr[j] : 0.0;
+    }
+    const double inv = 1.0 / Kp[k], f = Kr[k] * inv;
+    __syncthreads();
+    if (row) {
+      if (lane == p) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          if (j > k && j <= ncol) Kr[j] = my[j] * inv;
+        Kr[k] = 1.0;
+        used = true;
+        mycol = k;
+      } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          if (j > k && j <= ncol) Kr[j] = fma(-f, pr[j], my[j]);
+        Kr[k] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (ok && mycol >= 0) S.wvec[mycol] = Kr[ncol];
+  __syncthreads();
+  if (!ok) return false;
+  bool fin = true;
+  for (int j = lane; j < ncol; j += kWave) fin = fin && isfinite(S.wvec[j]);
+  return __all(fin);
 }
 
 // (H + mu I) d = rhs (theta space) through the structure above: factor the
-// tridiagonal part, then Woodbury for the contact blocks.  Result into S.d.  false on a vanishing pivot or
-// a failed small solve.
-template <int NMAX>
-__device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu, const double* rhs) {
+// tridiagonal part, then Woodbury for the contact blocks,
+//   (T + U S U^T)^-1 v = z - T^-1 U w,  z = T^-1 v,  (I + S G) w = S U^T z,
+//   G = U^T T^-1 U (one column per tridiagonal solve).
+// Result into S.d.  false on a vanishing pivot or a failed small solve.
+template <class SM>
+__device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* rhs) {
   const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
-  // tridiagonal part: T_mm = k_m + k_{m+1} + C_m, T_{m,m+1} = -k_{m+1}, k_j = q'_j + mu
-  bool ok = true;
-  if (lane == 0) {
-    double kprev = S.dq[0] + mu;
-    double knext = n > 1 ? S.dq[1] + mu : 0.0;
-    double d = kprev + knext + S.cg[0];
-    ok = isfinite(d) && fabs(d) > 1e-14 * (fabs(kprev) + fabs(knext) + fabs(S.cg[0]));
-    S.dinv[0] = 1.0 / d;
-    for (int m = 1; m < n && ok; ++m) {
-      const double km = knext;                          // k_m
-      const double kn = m + 1 < n ? S.dq[m + 1] + mu : 0.0;
-      const double e = -km;                             // T_{m-1,m}
-      const double lm = e / d;                          // multiplier
-      S.ell[m - 1] = lm;
-      const double tmm = km + kn + S.cg[m];
-      d = tmm - lm * e;
-      ok = isfinite(d) && fabs(d) > 1e-14 * (fabs(tmm) + fabs(e));
-      S.dinv[m] = 1.0 / d;
-      knext = kn;
-    }
-    S.ell[n - 1] = 0.0;
-    S.aux[0] = ok ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  ok = S.aux[0] != 0.0;
-  if (!ok) return false;
+  if (!tri_factor(S, n, mu)) return false;
   // right-hand side in absolute angles: b_m - b_{m+1}
   for (int m = lane; m < n; m += kWave) S.v[m] = rhs[m] - (m + 1 < n ? rhs[m + 1] : 0.0);
   __syncthreads();
-  tri_solve(S, n, S.v, S.z);
+  const int ncol = 3 * L;
+  if (L == 0) {
+    tri_solve(S, n, S.v, S.z);
+  } else if (ncol <= 15) {
+    gram_mfma(S, c, ncol);  // G, c and the forward half of z
+    tri_bwd(S, n, S.z);
+    capacitance_matrix(S, L);
+    if (!small_solve(S, ncol)) return false;
+  } else {
+    tri_solve(S, n, S.v, S.z);
+    ut_times(S, c, S.z, S.cvec, 1);
+    for (int col = 0; col < ncol; ++col) {
+      const int i = S.clink[col / 3], k = col % 3;
+      for (int m = lane; m < n; m += kWave)
+        S.v[m] = k == 2 ? (m == i ? 1.0 : 0.0) : (m < i ? c.l * (k == 0 ? S.tx[m] : S.ty[m]) : 0.0);
+      __syncthreads();
+      tri_solve(S, n, S.v, S.aux);
+      ut_times(S, c, S.aux, &S.sm.G[0][col], kMaxCols + 1);
+    }
+    {
+      capacitance_matrix(S, L);
+      if (!lu_solve(&S.sm.G[0][0], kMaxCols + 1, ncol, S.wvec)) return false;
+    }
+  }
   if (L > 0) {
-    const int ncol = 3 * L;
-    // c = U^T z: exclusive prefix sums of l cos(phi) z and l sin(phi) z
-    double c1 = 0.0, c2 = 0.0;
-    for (int base = 0; base < n; base += kWave) {
-      const int m = base + lane;
-      const double a = m < n ? c.l * S.tx[m] * S.z[m] : 0.0;
-      const double b = m < n ? c.l * S.ty[m] * S.z[m] : 0.0;
-      const double ia = wscan_incl(a, lane) + c1, ib = wscan_incl(b, lane) + c2;
-      if (m < n) {
-        S.ps1[m] = ia - a;
-        S.ps2[m] = ib - b;
-      }
-      c1 = __shfl(ia, kWave - 1, kWave);
-      c2 = __shfl(ib, kWave - 1, kWave);
-    }
-    __syncthreads();
-    for (int a = lane; a < L; a += kWave) {
-      const int i = S.clink[a];
-      S.cvec[3 * a + 0] = S.ps1[i];
-      S.cvec[3 * a + 1] = S.ps2[i];
-      S.cvec[3 * a + 2] = S.z[i];
-    }
-    // G = U^T T^-1 U = sum_m y_m y_m^T / d_m, y = L_T^-1 U; one lane per (a <= b) pair
-    const int npair = ncol * (ncol + 1) / 2;
-    for (int p0 = 0; p0 < npair; p0 += kWave) {
-      const int p = p0 + lane;
-      int a = 0, b = 0;
-      if (p < npair) {
-        int rem = p;
-        while (rem >= ncol - a) {
-          rem -= ncol - a;
-          ++a;
-        }
-        b = a + rem;
-      }
-      double ya = 0.0, yb = 0.0, g = 0.0;
-      for (int m = 0; m < n; ++m) {
-        const double cm = S.tx[m], sm = S.ty[m], lm1 = m > 0 ? S.ell[m - 1] : 0.0;
-        ya = ucol(S, c.l, a, m, cm, sm) - lm1 * ya;
-        yb = ucol(S, c.l, b, m, cm, sm) - lm1 * yb;
-        g += ya * yb * S.dinv[m];
-      }
-      if (p < npair) {
-        S.sm.G[a][b] = g;
-        S.sm.G[b][a] = g;
-      }
-    }
-    __syncthreads();
-    // K = I + S G with S = blockdiag(M_a); right-hand side S c
-    for (int row = lane; row < ncol; row += kWave) {
-      const int blk = row / 3, r3 = row % 3;
-      const double* M = S.cM[blk];
-      const double s0 = r3 == 0 ? M[0] : (r3 == 1 ? M[1] : M[2]);
-      const double s1 = r3 == 0 ? M[1] : (r3 == 1 ? M[3] : M[4]);
-      const double s2 = r3 == 0 ? M[2] : (r3 == 1 ? M[4] : M[5]);
-      const int c0 = 3 * blk;
-      for (int col = 0; col < ncol; ++col)
-        S.sm.K[row][col] = (row == col ? 1.0 : 0.0) + s0 * S.sm.G[c0][col] +
-                           s1 * S.sm.G[c0 + 1][col] + s2 * S.sm.G[c0 + 2][col];
-      S.sm.K[row][ncol] = s0 * S.cvec[c0] + s1 * S.cvec[c0 + 1] + s2 * S.cvec[c0 + 2];
-    }
-    __syncthreads();
-    if (!lu_solve(&S.sm.K[0][0], kMaxCols + 1, ncol, S.wvec)) return false;
     // correction: T v = U w, d_phi = z - v
     for (int m = lane; m < n; m += kWave) {
       double u = 0.0;
@@ -724,12 +1054,10 @@ __device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu, const d
         if (m < i) u += c.l * (S.tx[m] * S.wvec[3 * a] + S.ty[m] * S.wvec[3 * a + 1]);
         else if (m == i) u += S.wvec[3 * a + 2];
       }
-      S.aux[m] = u;
+      S.v[m] = u;
     }
     __syncthreads();
-    for (int m = lane; m < n; m += kWave) S.ps1[m] = S.aux[m];
-    __syncthreads();
-    tri_solve(S, n, S.ps1, S.v);
+    tri_solve(S, n, S.v, S.v);
     for (int m = lane; m < n; m += kWave) S.z[m] -= S.v[m];
     __syncthreads();
   }
@@ -745,8 +1073,8 @@ __device__ bool structured_solve(Smem<NMAX>& S, const Ctx& c, double mu, const d
 }
 
 // One equilibrium solve from S.th (in place).  Returns the status code.
-template <int NMAX, bool DENSE>
-__device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
+template <class SM, bool DENSE>
+__device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
   const int lane = threadIdx.x, n = c.n;
   const KParams& P = c.P;
   int status = 1;
@@ -777,7 +1105,7 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
     bool ok = false;
     double slope = 0.0, mu = P.c_mu * rm;
     const bool dense = DENSE || !structured_setup(S, c);
-    if (dense && Smem<NMAX>::WN < n) {
+    if (dense && SM::WN < n) {
       status = 3;  // more contact links than the structured solve holds
       break;
     }
@@ -850,12 +1178,12 @@ __device__ int solve(Smem<NMAX>& S, const Ctx& c, int& iters, double& rho) {
 // ---------------------------------------------------------------------------
 
 template <int NMAX, bool DENSE>
-__global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int n_steps,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(KParams P, KData D, int n_steps,
                                                         int record_traj) {
-  __shared__ Smem<NMAX> S;
-  const int b = blockIdx.x;
+  __shared__ Smem<NMAX, DENSE ? 64 : 1> S;
+  if ((int)blockIdx.x >= D.launch_count) return;
+  const int b = D.order[D.launch_first + blockIdx.x];
   const int lane = threadIdx.x;
-  if (b >= D.n_inst) return;
   const int* ii = D.ii + 8 * b;
   const double* dd = D.dd + 6 * b;
   Ctx c;
@@ -874,14 +1202,8 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
   c.trace = (b == D.trace_robot) ? D.trace : nullptr;
   c.trace_n = D.trace_n;
   c.trace_cap = D.trace_cap;
-  for (int k = lane; k < c.K; k += kWave) {
-    const double* o = D.obs + 4 * (size_t)(ii[1] + k);
-    S.obs[k][0] = o[0];
-    S.obs[k][1] = o[1];
-    S.obs[k][2] = o[2];
-    S.obs[k][3] = o[3];
-    S.okind[k] = D.okind[ii[1] + k];
-  }
+  c.obs = (const __attribute__((address_space(4))) double*)(D.obs + 4 * (size_t)ii[1]);
+  c.okind = (const __attribute__((address_space(4))) int*)(D.okind + ii[1]);
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
@@ -906,7 +1228,7 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
         c.last_len = c.l * (double)s / (double)P.substeps;
         c.step = t;
         c.sub = s;
-        int st = solve<NMAX, DENSE>(S, c, its, rho);
+        int st = solve<Smem<NMAX, DENSE ? 64 : 1>, DENSE>(S, c, its, rho);
         st_worst = st > st_worst ? st : st_worst;
       }
     } else {
@@ -972,13 +1294,13 @@ __global__ __launch_bounds__(kWave) void rollout_kernel(KParams P, KData D, int 
 // its ends s0, s1 enter r only through the coverage of the joints it spans:
 //   dq_j/dP+-_j = -+arm G(eps+-_j),  w_sj = |[s0, s1] ^ [j l, (j+1) l]| / l.
 template <int NMAX>
-__global__ __launch_bounds__(kWave) void grad_kernel(KParams P, KData D, const double* goal,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void grad_kernel(KParams P, KData D, const double* goal,
                                                      const double* weights, int T,
                                                      double* dP, double* ds0, double* ds1,
                                                      double* loss, int* status) {
-  __shared__ Smem<NMAX> S;
-  const int b = blockIdx.x, lane = threadIdx.x;
-  if (b >= D.n_inst) return;
+  __shared__ Smem<NMAX, 1> S;
+  if ((int)blockIdx.x >= D.launch_count) return;
+  const int b = D.order[D.launch_first + blockIdx.x], lane = threadIdx.x;
   const int* ii = D.ii + 8 * b;
   const double* dd = D.dd + 6 * b;
   Ctx c;
@@ -996,14 +1318,8 @@ __global__ __launch_bounds__(kWave) void grad_kernel(KParams P, KData D, const d
   c.P = P;
   c.trace = nullptr;
   c.last_len = c.l;
-  for (int k = lane; k < c.K; k += kWave) {
-    const double* o = D.obs + 4 * (size_t)(ii[1] + k);
-    S.obs[k][0] = o[0];
-    S.obs[k][1] = o[1];
-    S.obs[k][2] = o[2];
-    S.obs[k][3] = o[3];
-    S.okind[k] = D.okind[ii[1] + k];
-  }
+  c.obs = (const __attribute__((address_space(4))) double*)(D.obs + 4 * (size_t)ii[1]);
+  c.okind = (const __attribute__((address_space(4))) int*)(D.okind + ii[1]);
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
@@ -1039,15 +1355,8 @@ __global__ __launch_bounds__(kWave) void grad_kernel(KParams P, KData D, const d
       S.b[j] = 2.0 * wt * (ex * vx + ey * vy);
     }
     __syncthreads();
-    bool ok;
-    if (structured_setup(S, c)) {
-      ok = structured_solve(S, c, 0.0, S.b);
-    } else if (Smem<NMAX>::WN >= n) {
-      assemble(S, c, S.th, 0.0, S.b);
-      ok = lu_solve_dense(S, n);
-    } else {
-      ok = false;
-    }
+    // more contact links than the structured solve holds: the term is left out
+    const bool ok = structured_setup(S, c) && structured_solve(S, c, 0.0, S.b);
     if (!ok) {
       st = 1;
       continue;
@@ -1093,23 +1402,29 @@ __global__ void zero3_kernel(double* a, double* b, double* c, int n) {
   }
 }
 
+hipError_t launch_zero3(double* a, double* b, double* c, int n, hipStream_t stream) {
+  if (n > 0)
+    hipLaunchKernelGGL(zero3_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, a, b, c, n);
+  return hipGetLastError();
+}
+
+// One launch per chain-length class: D.order[D.launch_first ...] lists the robots of
+// the class (longest expected work first), D.launch_count of them.
 hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
                        const double* weights, int T, double* dP, double* ds0, double* ds1,
                        double* loss, int* status, int nmax_class, hipStream_t stream) {
-  if (D.n_spam > 0)
-    hipLaunchKernelGGL(zero3_kernel, dim3((D.n_spam + 255) / 256), dim3(256), 0, stream, dP, ds0,
-                       ds1, D.n_spam);
-  dim3 grid(D.n_inst), block(kWave);
-  if (nmax_class <= 64)
+  if (D.launch_count <= 0) return hipSuccess;
+  dim3 grid(D.launch_count), block(kWave);
+  if (nmax_class == 64)
     hipLaunchKernelGGL((grad_kernel<64>), grid, block, 0, stream, P, D, goal, weights, T, dP, ds0,
                        ds1, loss, status);
-  else if (nmax_class <= 128)
+  else if (nmax_class == 128)
     hipLaunchKernelGGL((grad_kernel<128>), grid, block, 0, stream, P, D, goal, weights, T, dP,
                        ds0, ds1, loss, status);
-  else if (nmax_class <= 256)
+  else if (nmax_class == 256)
     hipLaunchKernelGGL((grad_kernel<256>), grid, block, 0, stream, P, D, goal, weights, T, dP,
                        ds0, ds1, loss, status);
-  else if (nmax_class <= 512)
+  else if (nmax_class == 512)
     hipLaunchKernelGGL((grad_kernel<512>), grid, block, 0, stream, P, D, goal, weights, T, dP,
                        ds0, ds1, loss, status);
   else
@@ -1117,24 +1432,87 @@ hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
   return hipGetLastError();
 }
 
+// Zero the state and records of every robot (a kernel rather than memsets, so that
+// a captured graph holds no memset nodes).
+__global__ void reset_kernel(KData D) {
+  const size_t B = D.n_inst, stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = i0; i < B * D.n_max; i += stride) D.theta[i] = 0.0;
+  for (size_t i = i0; i < B * D.t_max * 3; i += stride) D.tip[i] = 0.0;
+  for (size_t i = i0; i < B * D.t_max; i += stride) {
+    D.rho[i] = 0.0;
+    D.iters[i] = 0;
+    D.status[i] = 0;
+    D.ncont[i] = 0;
+    D.chash[i] = 0ull;
+    D.maxpen[i] = 0.0;
+  }
+  for (size_t i = i0; i < B; i += stride) {
+    D.ncur[i] = 0;
+    D.tcur[i] = 0;
+    D.jevals[i] = 0.0;
+    D.nsolves[i] = 0.0;
+  }
+}
+
+// Zero the state and records of the robots in slots[0..count) (one block per robot).
+__global__ void slot_reset_kernel(KData D, const int* slots, int count) {
+  if ((int)blockIdx.x >= count) return;
+  const size_t b = (size_t)slots[blockIdx.x];
+  for (int j = threadIdx.x; j < D.n_max; j += blockDim.x) D.theta[b * D.n_max + j] = 0.0;
+  for (int t = threadIdx.x; t < D.t_max; t += blockDim.x) {
+    const size_t bt = b * D.t_max + t;
+    D.tip[3 * bt] = 0.0;
+    D.tip[3 * bt + 1] = 0.0;
+    D.tip[3 * bt + 2] = 0.0;
+    D.rho[bt] = 0.0;
+    D.iters[bt] = 0;
+    D.status[bt] = 0;
+    D.ncont[bt] = 0;
+    D.chash[bt] = 0ull;
+    D.maxpen[bt] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    D.ncur[b] = 0;
+    D.tcur[b] = 0;
+    D.jevals[b] = 0.0;
+    D.nsolves[b] = 0.0;
+  }
+}
+
+hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slot_reset_kernel, dim3(count), dim3(256), 0, stream, D, slots, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(const KData& D, hipStream_t stream) {
+  const size_t work = (size_t)D.n_inst * (D.t_max * 3 > D.n_max ? D.t_max * 3 : D.n_max);
+  const size_t blocks = (work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096;
+  hipLaunchKernelGGL(reset_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
+                     stream, D);
+  return hipGetLastError();
+}
+
 // host-side launcher (instantiated for the supported chain lengths)
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
                           int nmax_class, hipStream_t stream) {
-  dim3 grid(D.n_inst), block(kWave);
+  if (D.launch_count <= 0) return hipSuccess;
+  dim3 grid(D.launch_count), block(kWave);
   if (P.dense_solver) {
-    if (nmax_class > 64) return hipErrorInvalidValue;
+    if (nmax_class != 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((rollout_kernel<64, true>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class <= 64) {
+  } else if (nmax_class == 64) {
     hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class <= 128) {
+  } else if (nmax_class == 128) {
     hipLaunchKernelGGL((rollout_kernel<128, false>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class <= 256) {
+  } else if (nmax_class == 256) {
     hipLaunchKernelGGL((rollout_kernel<256, false>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class <= 512) {
+  } else if (nmax_class == 512) {
     hipLaunchKernelGGL((rollout_kernel<512, false>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
   } else {

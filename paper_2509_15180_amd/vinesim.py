@@ -68,7 +68,10 @@ class Obstacle(C.Structure):
 EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
-           "vine_sim_trace_read", "vine_sim_grad")
+           "vine_sim_trace_read", "vine_sim_grad", "vine_sim_set_spams", "vine_server_create",
+           "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
+           "vine_server_release", "vine_server_stats", "vine_server_destroy",
+           "vine_server_last_error")
 
 _lib = None
 
@@ -113,6 +116,30 @@ def lib():
         L.vine_sim_trace_read.restype = C.c_int32
         L.vine_sim_grad.argtypes = [vp] * 9
         L.vine_sim_grad.restype = C.c_int32
+        L.vine_sim_set_spams.argtypes = [vp, C.POINTER(Spam), C.c_int32, vp]
+        L.vine_sim_set_spams.restype = C.c_int32
+        L.vine_server_create.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32,
+                                         C.c_int32, C.POINTER(vp)]
+        L.vine_server_create.restype = C.c_int32
+        L.vine_server_submit.argtypes = [vp, C.c_int64, C.POINTER(Instance), C.c_int32,
+                                         C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle),
+                                         C.c_int32]
+        L.vine_server_submit.restype = C.c_int32
+        L.vine_server_tick.argtypes = [vp, C.c_int32, vp]
+        L.vine_server_tick.restype = C.c_int32
+        L.vine_server_poll.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32]
+        L.vine_server_poll.restype = C.c_int32
+        L.vine_server_result.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]
+        L.vine_server_result.restype = C.c_int32
+        L.vine_server_release.argtypes = [vp, C.c_int64]
+        L.vine_server_release.restype = C.c_int32
+        L.vine_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.vine_server_stats.restype = None
+        L.vine_server_destroy.argtypes = [vp]
+        L.vine_server_destroy.restype = None
+        L.vine_server_last_error.argtypes = [vp]
+        L.vine_server_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -260,9 +287,87 @@ class VineSim:
         self._keep = (g, w)  # inputs stay alive until the caller synchronises
         return dP[:self.S], d0[:self.S], d1[:self.S], loss, st
 
+    def set_spams(self, spam, stream=None):
+        """vine_sim_set_spams: new sPAM records [S][4] (s_start, s_end, side, pressure)."""
+        spam = np.asarray(spam, np.float64).reshape(-1, 4)
+        arr = (Spam * max(1, len(spam)))()
+        for i, row in enumerate(spam):
+            arr[i] = Spam(*(float(x) for x in row))
+        self._check(lib().vine_sim_set_spams(self.h, arr, len(spam), _stream_ptr(stream)))
+
     def close(self):
         if getattr(self, "h", None):
             lib().vine_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class VineServer:
+    """vine_server_*: continuous batching of rollout requests (one handle)."""
+
+    def __init__(self, slots: int, max_links: int = MAX_LINKS, max_obstacles: int = MAX_OBSTACLES,
+                 max_spams: int = 8, params: Params | None = None, **over):
+        L = lib()
+        self._p = params if params is not None else default_params(**over)
+        h = C.c_void_p()
+        rc = L.vine_server_create(C.byref(self._p), int(slots), int(max_links),
+                                  int(max_obstacles), int(max_spams), C.byref(h))
+        if rc != VINE_OK:
+            raise VineError(rc, L.vine_server_last_error(None).decode())
+        self.h = h
+        self.n_links = {}
+
+    def _check(self, rc):
+        if rc < 0:
+            raise VineError(rc, lib().vine_server_last_error(self.h).decode())
+        return rc
+
+    def submit(self, request_id: int, work):
+        """Queue every instance of a Workload as one request."""
+        inst, B, spams, ns, obs, no = _pack(work)
+        self._check(lib().vine_server_submit(self.h, int(request_id), inst, B, spams, ns, obs, no))
+        self.n_links[int(request_id)] = [int(v) for v in work.inst_i[:, 0]]
+
+    def tick(self, steps: int = 16, stream=None) -> int:
+        return self._check(lib().vine_server_tick(self.h, int(steps), _stream_ptr(stream)))
+
+    def poll(self, cap: int = 4096):
+        ids = (C.c_int64 * cap)()
+        st = (C.c_int32 * cap)()
+        k = self._check(lib().vine_server_poll(self.h, ids, st, cap))
+        return [(int(ids[i]), int(st[i])) for i in range(k)]
+
+    def result(self, request_id: int, robot: int):
+        tip = (C.c_double * 3)()
+        n = self.n_links[int(request_id)][robot]
+        th = np.zeros(n)
+        self._check(lib().vine_server_result(self.h, int(request_id), int(robot), tip,
+                                             th.ctypes.data_as(C.POINTER(C.c_double))))
+        return np.array(tip[:]), th
+
+    def release(self, request_id: int):
+        self._check(lib().vine_server_release(self.h, int(request_id)))
+        self.n_links.pop(int(request_id), None)
+
+    def stats(self) -> dict:
+        out = (C.c_int64 * 4)()
+        lib().vine_server_stats(self.h, out)
+        return dict(queued=out[0], active=out[1], completed=out[2], joint_updates=out[3])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vine_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -73,3 +73,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(V, "_lib", None)
     with pytest.raises(ImportError):
         V.lib()
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = V.lib()
+    assert L.vine_sim_set_spams(None, None, 0, None) == V.VINE_EINVAL
+    assert L.vine_sim_grad(None, None, None, None, None, None, None, None, None) == V.VINE_EINVAL
+    assert L.vine_sim_reset(None, None) == V.VINE_EINVAL
+
+
+def test_server_rejects_bad_sizes_before_the_device():
+    import ctypes as C
+    L = V.lib()
+    h = C.c_void_p()
+    p = V.default_params()
+    assert L.vine_server_create(C.byref(p), 0, 64, 8, 4, C.byref(h)) == V.VINE_EINVAL
+    assert L.vine_server_create(C.byref(p), 8, V.MAX_LINKS + 1, 8, 4, C.byref(h)) == \
+        V.VINE_ECAPACITY
+    assert L.vine_server_tick(None, 4, None) == V.VINE_EINVAL
+    assert L.vine_server_poll(None, None, None, 0) == V.VINE_EINVAL

@@ -133,3 +133,59 @@ def test_grad_full_batch_sampled():
         assert abs(loss[b] - rloss[k]) <= 1e-9 * max(rloss[k], 1e-12)
         checked += 1
     assert checked >= 3
+
+
+def test_set_spams_equals_fresh_handle():
+    import torch
+    w = W.config4(16).subset([1, 2, 3])
+    w2 = W.pack([w.instance(i) for i in range(w.n_inst)], "moved")
+    w2.spam[:, 3] *= 0.7
+    w2.spam[:, 0] += 0.003
+    w2.spam[:, 1] = np.minimum(w2.spam[:, 1] + 0.001, 96 * 0.02)
+    with _sim(w) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, stream=s)
+        sim.set_spams(w2.spam, stream=s)
+        sim.reset(stream=s)
+        sim.rollout(-1, stream=s)
+        s.synchronize()
+        a = sim.read_all()
+    with _sim(w2) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, stream=s)
+        s.synchronize()
+        b = sim.read_all()
+    assert np.array_equal(a["theta"], b["theta"]) and np.array_equal(a["chash"], b["chash"])
+
+
+def test_autograd_function_and_descent():
+    """rollout_loss backward returns the adjoint; a few gradient steps on the
+    pressures lower the loss (a miniature of the design search)."""
+    import torch
+
+    from paper_2509_15180_amd.autograd import rollout_loss
+    w = W.config4(16).subset([1, 2, 3, 6])
+    with _sim(w) as sim:
+        P = torch.tensor(w.spam[:, 3], dtype=torch.float64, requires_grad=True)
+        s0 = torch.tensor(w.spam[:, 0], dtype=torch.float64, requires_grad=True)
+        s1 = torch.tensor(w.spam[:, 1], dtype=torch.float64, requires_grad=True)
+        side = w.spam[:, 2]
+        L0 = rollout_loss(sim, P, s0, s1, side, w.goal)
+        L0.backward()
+        _, (dP, d0, d1, loss, st) = _gpu(w, None, traj=False)
+        np.testing.assert_allclose(P.grad.numpy(), dP, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(s0.grad.numpy(), d0, rtol=1e-12, atol=0)
+        assert abs(L0.item() - loss.sum()) <= 1e-12 * loss.sum()
+        # one projected gradient step on the pressures, backtracking until the loss drops
+        g = P.grad.clone()
+        step = 0.05 * P.detach().abs().max().item() / max(g.abs().max().item(), 1e-30)
+        Ls = [L0.item()]
+        for _ in range(10):
+            with torch.no_grad():
+                Pt = (P.detach() - step * g).clamp(min=0.0)
+                Ls.append(rollout_loss(sim, Pt, s0.detach(), s1.detach(), side, w.goal).item())
+            if Ls[-1] < Ls[0]:
+                break
+            step *= 0.5
+        print("loss along the descent line search:", Ls, flush=True)
+        assert Ls[-1] < Ls[0]
