@@ -9,6 +9,10 @@ Other workloads (``--workload``), same JSON fields:
   uneven  16384 robots of 16-256 links with 0-64 obstacles in one rollout call
   grad    4096 robots of 96 links: rollout with the trajectory recorded, then the
           adjoint of every step's equilibrium (vine_sim_grad, all steps weighted)
+  serve   a Poisson stream of requests (one design of 16-512 links and 0-128 obstacles on
+          1-64 environment samples each) through the continuous-batching server at
+          ``--rate`` requests/s for ``--duration`` s after a warm-up; reports the
+          sustained joint-updates/s and the p50/p99 request latency
 
 Prints one JSON line with the driver's fields plus:
   roofline      the rollout kernel against the FP64 VALU peak (per-joint-evaluation
@@ -52,7 +56,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("uniform", "uneven", "grad"), default="uniform")
+    ap.add_argument("--workload", choices=("uniform", "uneven", "grad", "serve"),
+                    default="uniform")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=30.0, help="serve: measured seconds")
+    ap.add_argument("--warm", type=float, default=5.0, help="serve: warm-up seconds")
+    ap.add_argument("--slots", type=int, default=4096, help="serve: resident robots")
+    ap.add_argument("--tick-steps", type=int, default=8, help="serve: growth steps per round")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
     ap.add_argument("--cpu-robots", type=int, default=64, help="robots in the CPU-oracle sample")
@@ -71,6 +81,8 @@ def main():
 
     torch.cuda.set_device(0)
     wl = args.workload
+    if wl == "serve":
+        return serve(args, torch, V, W)
     if wl == "uniform":
         B = args.batch or 4096
         work = W.config2(B)
@@ -197,6 +209,80 @@ def main():
     }
     if grad_ms is not None:
         rec["adjoint_ms"] = grad_ms
+    print(json.dumps(rec), flush=True)
+
+
+def serve(args, torch, V, W):
+    """Open-loop stream: requests arrive on their Poisson clock whether or not the
+    server keeps up; latency = completion - arrival."""
+    horizon = args.warm + args.duration
+    n_req = max(1, int(args.rate * horizon * 1.05) + 1)
+    # requests are generated lazily in blocks (a saturated stream would otherwise build
+    # far more than the server can take)
+    block = 64
+    gen = {"next": 0, "buf": []}
+
+    def upcoming():
+        if not gen["buf"] and gen["next"] < n_req:
+            k = min(block, n_req - gen["next"])
+            gen["buf"] = W.config5_requests(k, rate=args.rate, start=gen["next"])
+            gen["next"] += k
+        return gen["buf"][0] if gen["buf"] else None
+
+    stream = torch.cuda.current_stream()
+    srv = V.VineServer(slots=args.slots, max_links=512, max_obstacles=128, max_spams=8)
+    arrival, size = {}, {}
+    done_at = {}
+    t0 = time.perf_counter()
+    ju0 = None
+    ticks = 0
+    while True:
+        now = time.perf_counter() - t0
+        if now > horizon:
+            break
+        r = upcoming()
+        while r is not None and r.arrival <= now:
+            srv.submit(r.rid, r.work)
+            arrival[r.rid] = r.arrival
+            size[r.rid] = r.work.joint_updates()
+            gen["buf"].pop(0)
+            r = upcoming()
+        st = srv.stats()
+        if ju0 is None and now >= args.warm:
+            ju0, tw = st["joint_updates"], now
+        if st["active"] + st["queued"] == 0:
+            if r is not None:
+                time.sleep(max(0.0, min(r.arrival - now, 0.01)))
+            continue
+        srv.tick(args.tick_steps, stream=stream)
+        ticks += 1
+        t_done = time.perf_counter() - t0
+        for rid, _ in srv.poll():
+            done_at[rid] = t_done
+            srv.release(rid)
+    st = srv.stats()
+    t_end = time.perf_counter() - t0
+    ju_rate = (st["joint_updates"] - (ju0 or 0)) / max(t_end - (tw if ju0 is not None else 0.0), 1e-9)
+    lat = np.array([done_at[i] - arrival[i] for i in done_at if arrival[i] >= args.warm])
+    offered = float(np.mean(list(size.values()))) * args.rate if size else 0.0
+    rec = {
+        "metric": METRIC, "value": ju_rate, "unit": "joint-updates/s", "n_gpus": 1,
+        "steps": ticks, "warmup": 0, "ms_per_step": 1e3 * t_end / max(ticks, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"request stream: Poisson {args.rate}/s, designs of 16-512 links and "
+                               f"0-128 obstacles on 1-64 jittered environment samples; "
+                               f"{args.slots} slots, {args.tick_steps} growth steps per round",
+                   "rate_per_s": args.rate, "warmup_s": args.warm, "measured_s": args.duration},
+        "serving": {"submitted": len(arrival), "completed": len(done_at),
+                    "completed_after_warmup": int(lat.size),
+                    "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+                    "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+                    "queued_at_end": st["queued"], "active_at_end": st["active"],
+                    "offered_joint_updates_per_s": offered},
+        "roofline": None, "cpu_baseline": None, "wall_s": t_end,
+    }
+    srv.close()
     print(json.dumps(rec), flush=True)
 
 

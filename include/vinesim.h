@@ -51,7 +51,7 @@ extern "C" {
 #define VINE_ST_CONVERGED 0   /* max_j |r_j| / M_max <= tol */
 #define VINE_ST_MAXITER 1     /* iteration limit reached */
 #define VINE_ST_NODESCENT 2   /* no descent direction / line search failed */
-#define VINE_ST_CAPACITY 3    /* more simultaneous contacts than the solver holds */
+#define VINE_ST_CAPACITY 3    /* more simultaneous disk/obstacle contacts than the contact list holds */
 #define VINE_ST_NONFINITE 4   /* a non-finite residual or energy appeared */
 #define VINE_ST_DONE (-1)     /* the robot had already reached its target length */
 
@@ -71,8 +71,11 @@ typedef struct vine_params {
   double armijo_c1;      /* sufficient-decrease constant of the line search */
   int32_t max_iter;      /* Newton iterations per equilibrium solve */
   int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
-  int32_t solver;        /* 0: structured O(n) solve of the Newton system (default);
-                            1: dense LU with partial pivoting (chains of <= 64 links; cross-check) */
+  int32_t solver;        /* 0: structured solve of the Newton system (default): scans for the
+                               chain part plus a low-rank update per contact link, and a
+                               sequential O(n) sweep when the contact links exceed 16;
+                            1: dense LU with partial pivoting (chains of <= 64 links; cross-check);
+                            2: the sequential O(n) sweep always (cross-check) */
   int32_t reserved;
 } vine_params;
 

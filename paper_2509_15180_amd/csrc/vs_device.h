@@ -46,6 +46,7 @@ struct KParams {
   double epsc, kc, tol, c_mu, step_max, c1, Ract;
   int max_iter, substeps;
   int dense_solver;   // 1: dense LU cross-check solver (chains of <= 64 links)
+  int seq_solver;     // 1: sequential chain sweep for every Newton system (cross-check)
 };
 
 // Per-robot and per-simulation device arrays (structure of arrays).

@@ -394,6 +394,7 @@ vs::KParams kparams(const vine_params& p) {
   k.max_iter = p.max_iter;
   k.substeps = p.growth_substeps;
   k.dense_solver = p.solver == 1;
+  k.seq_solver = p.solver == 2;
   return k;
 }
 
@@ -505,7 +506,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       !std::isfinite(p.a_corr) || !(p.eps_crit > 0.0 && p.eps_crit < 1.0) || !finite_pos(p.k_c) ||
       !finite_pos(p.tol) || !(p.c_mu >= 0.0) || !std::isfinite(p.c_mu) ||
       !finite_pos(p.step_max) || !(p.armijo_c1 > 0.0 && p.armijo_c1 < 1.0) || p.max_iter < 0 ||
-      p.growth_substeps < 1 || !(p.solver == 0 || p.solver == 1))
+      p.growth_substeps < 1 || !(p.solver >= 0 && p.solver <= 2))
     return fail(nullptr, VINE_EINVAL, "invalid vine_params");
   int N = 0;
   for (int b = 0; b < n_inst; ++b) {

@@ -472,35 +472,56 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
       xs[hh] = on ? S.px[j] + s * S.tx[j] : 0.0;
       ys[hh] = on ? S.py[j] + s * S.ty[j] : 0.0;
     }
-    for (int k = 0; k < c.K; ++k) {
-      const double ox = c.obs[4 * k], oy = c.obs[4 * k + 1], oa = c.obs[4 * k + 2],
-                   ob = c.obs[4 * k + 3];
-      const int kind = c.okind[k];
-      bool near[2];
+    for (int k0 = 0; k0 < c.K; k0 += 4) {
+      // four obstacles per round; the loads are unconditional (index clamped) so that
+      // they issue together and the round waits once
+      double ox[4], oy[4], oa[4], ob[4];
+      int kd[4];
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) near[hh] = on && obs_near(kind, ox, oy, oa, ob, c.R, xs[hh], ys[hh]);
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u < c.K ? k0 + u : c.K - 1;
+        ox[u] = c.obs[4 * k];
+        oy[u] = c.obs[4 * k + 1];
+        oa[u] = c.obs[4 * k + 2];
+        ob[u] = c.obs[4 * k + 3];
+        kd[u] = c.okind[k];
+      }
+      unsigned near = 0u;  // bit 2u + hh: disk hh may touch obstacle k0 + u
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        if (__ballot(near[hh]) == 0ull) continue;
-        double g = 0.0, nx = 0.0, ny = 0.0, kap = 0.0;
-        const bool hit =
-            near[hh] && obs_gap(kind, ox, oy, oa, ob, c.R, xs[hh], ys[hh], g, nx, ny, kap);
-        const unsigned long long m = __ballot(hit);
-        if (m) {
-          const int pos = cnt + __popcll(m & lt);
-          if (hit && pos < kMaxC) {
-            const double pen = -g;
-            S.ci[pos] = j;
-            S.ck[pos] = k;
-            S.cl[pos] = c.P.kc * pen;
-            S.cxx[pos] = xs[hh];
-            S.cxy[pos] = ys[hh];
-            S.cnx[pos] = nx;
-            S.cny[pos] = ny;
-            S.ckap[pos] = kap;
-            S.cpen[pos] = pen;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+          near |= (unsigned)obs_near(kd[u], ox[u], oy[u], oa[u], ob[u], c.R, xs[hh], ys[hh])
+                  << (2 * u + hh);
+      const int nk = c.K - k0 < 4 ? c.K - k0 : 4;
+      near &= on ? (1u << (2 * nk)) - 1u : 0u;
+      if (__ballot(near != 0u) == 0ull) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const bool nr = (near >> (2 * u + hh)) & 1u;
+          if (__ballot(nr) == 0ull) continue;
+          double g = 0.0, nx = 0.0, ny = 0.0, kap = 0.0;
+          const bool hit =
+              nr && obs_gap(kd[u], ox[u], oy[u], oa[u], ob[u], c.R, xs[hh], ys[hh], g, nx, ny, kap);
+          const unsigned long long m = __ballot(hit);
+          if (m) {
+            const int pos = cnt + __popcll(m & lt);
+            if (hit && pos < kMaxC) {
+              const double pen = -g;
+              S.ci[pos] = j;
+              S.ck[pos] = k0 + u;
+              S.cl[pos] = c.P.kc * pen;
+              S.cxx[pos] = xs[hh];
+              S.cxy[pos] = ys[hh];
+              S.cnx[pos] = nx;
+              S.cny[pos] = ny;
+              S.ckap[pos] = kap;
+              S.cpen[pos] = pen;
+            }
+            cnt += __popcll(m);
           }
-          cnt += __popcll(m);
         }
       }
     }
@@ -659,6 +680,29 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
   }
   if (lane == 0) S.ncl_links = L;
   __syncthreads();
+  // geometric diagonal: suffix sums of per-link forces, chunks from the tip down
+  double cfx = 0.0, cfy = 0.0;
+  const int nchunk = (n + kWave - 1) / kWave;
+  for (int ch = nchunk - 1; ch >= 0; --ch) {
+    const int j = ch * kWave + lane;
+    double fx = 0.0, fy = 0.0, q = 0.0;
+    if (j < n && S.lidx[j] >= 0) {
+      const double tjx = S.tx[j], tjy = S.ty[j];
+      for (int e = 0; e < nc; ++e) {
+        if (S.ci[e] != j) continue;
+        const double lam = S.cl[e], nx = S.cnx[e], ny = S.cny[e];
+        const double s = (S.cxx[e] - S.px[j]) * tjx + (S.cxy[e] - S.py[j]) * tjy;
+        fx += lam * nx;
+        fy += lam * ny;
+        q += lam * s * (nx * tjx + ny * tjy);
+      }
+    }
+    double sx = wscan_suffix(fx, lane) + cfx, sy = wscan_suffix(fy, lane) + cfy;
+    if (j < n) S.cg[j] = c.l * (S.tx[j] * (sx - fx) + S.ty[j] * (sy - fy)) + q;
+    cfx = __shfl(sx, 0, kWave);
+    cfy = __shfl(sy, 0, kWave);
+  }
+  __syncthreads();
   if (L > kMaxCL) return false;
   // 3x3 blocks, one lane per contact link (contacts visited in list order)
   for (int a = lane; a < L; a += kWave) {
@@ -685,28 +729,6 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
     S.cM[a][3] = m3;
     S.cM[a][4] = m4;
     S.cM[a][5] = m5;
-  }
-  // geometric diagonal: suffix sums of per-link forces, chunks from the tip down
-  double cfx = 0.0, cfy = 0.0;
-  const int nchunk = (n + kWave - 1) / kWave;
-  for (int ch = nchunk - 1; ch >= 0; --ch) {
-    const int j = ch * kWave + lane;
-    double fx = 0.0, fy = 0.0, q = 0.0;
-    if (j < n && S.lidx[j] >= 0) {
-      const double tjx = S.tx[j], tjy = S.ty[j];
-      for (int e = 0; e < nc; ++e) {
-        if (S.ci[e] != j) continue;
-        const double lam = S.cl[e], nx = S.cnx[e], ny = S.cny[e];
-        const double s = (S.cxx[e] - S.px[j]) * tjx + (S.cxy[e] - S.py[j]) * tjy;
-        fx += lam * nx;
-        fy += lam * ny;
-        q += lam * s * (nx * tjx + ny * tjy);
-      }
-    }
-    double sx = wscan_suffix(fx, lane) + cfx, sy = wscan_suffix(fy, lane) + cfy;
-    if (j < n) S.cg[j] = c.l * (S.tx[j] * (sx - fx) + S.ty[j] * (sy - fy)) + q;
-    cfx = __shfl(sx, 0, kWave);
-    cfy = __shfl(sy, 0, kWave);
   }
   __syncthreads();
   return true;
@@ -947,6 +969,77 @@ __device__ void capacitance_matrix(SM& S, int L) {
   __syncthreads();
 }
 
+// (I + S G) w = S c for one or two contact links (order NC = 3 or 6), the common case:
+// every lane assembles and eliminates the whole system in registers (Gaussian
+// elimination with partial pivoting, fully unrolled), so no lane waits on another.
+template <int NC, class SM>
+__device__ bool tiny_solve(SM& S) {
+  double K[NC][NC + 1];
+#pragma unroll
+  for (int b = 0; b < NC / 3; ++b) {
+    const double* M = S.cM[b];
+    const double m[3][3] = {{M[0], M[1], M[2]}, {M[1], M[3], M[4]}, {M[2], M[4], M[5]}};
+#pragma unroll
+    for (int r3 = 0; r3 < 3; ++r3) {
+      const int r = 3 * b + r3;
+#pragma unroll
+      for (int col = 0; col <= NC; ++col) {
+        double v = col == r ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          v += m[r3][k] * (col < NC ? S.sm.G[3 * b + k][col] : S.cvec[3 * b + k]);
+        K[r][col] = col < NC ? v : v - (col == r ? 1.0 : 0.0);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    int p = k;
+    double best = fabs(K[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < NC; ++i) {
+      const double v = fabs(K[i][k]);
+      if (v > best) {
+        best = v;
+        p = i;
+      }
+    }
+    if (!(best > 0.0)) return false;
+#pragma unroll
+    for (int i = k + 1; i < NC; ++i) {
+      if (p != i) continue;
+#pragma unroll
+      for (int j = k; j <= NC; ++j) {
+        const double t = K[k][j];
+        K[k][j] = K[i][j];
+        K[i][j] = t;
+      }
+    }
+    const double inv = 1.0 / K[k][k];
+#pragma unroll
+    for (int i = k + 1; i < NC; ++i) {
+      const double f = K[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j <= NC; ++j) K[i][j] = fma(-f, K[k][j], K[i][j]);
+    }
+  }
+  double x[NC];
+  bool fin = true;
+#pragma unroll
+  for (int i = NC - 1; i >= 0; --i) {
+    double sum = K[i][NC];
+#pragma unroll
+    for (int j = i + 1; j < NC; ++j) sum = fma(-K[i][j], x[j], sum);
+    x[i] = sum / K[i][i];
+    fin = fin && isfinite(x[i]);
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NC; ++i) S.wvec[i] = x[i];
+  __syncthreads();
+  return fin;
+}
+
 // (K | S c) w for ncol <= 15, one row per lane: Gauss-Jordan with partial pivoting
 // over the rows not yet used as pivots.  Rows stay in LDS between pivot steps; a step
 // loads the lane's row and the pivot row whole, so its loads issue together.
@@ -1027,8 +1120,16 @@ __device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* r
   } else if (ncol <= 15) {
     gram_mfma(S, c, ncol);  // G, c and the forward half of z
     tri_bwd(S, n, S.z);
-    capacitance_matrix(S, L);
-    if (!small_solve(S, ncol)) return false;
+    bool ok;
+    if (L == 1) {
+      ok = tiny_solve<3>(S);
+    } else if (L == 2) {
+      ok = tiny_solve<6>(S);
+    } else {
+      capacitance_matrix(S, L);
+      ok = small_solve(S, ncol);
+    }
+    if (!ok) return false;
   } else {
     tri_solve(S, n, S.v, S.z);
     ut_times(S, c, S.z, S.cvec, 1);
@@ -1072,6 +1173,109 @@ __device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* r
   return __all(fin);
 }
 
+// (H + mu I) d = rhs directly in relative angles, for any number of contact links
+// (the path taken when the contact links exceed the structured solve's capacity).
+// With B_j = (1, px_j, py_j) the exact Hessian has the chain form
+//   H_jm = q'_j [j = m] + B_j^T (sum_{k >= max(j,m)} S_k) B_m,
+//   S_k = sum_{contacts on link k} (k_c a a^T - lam kappa b b^T) + e0 e0^T C_k,
+// a = (n_y x_x - n_x x_y, -n_y, n_x), b = (n . x, -n_x, -n_y) (so that the contact
+// gradient is B_j . a), C_k the geometric diagonal.  Writing F_j = sum_{k >= j} S_k V_k
+// with V_k = sum_{m <= k} B_m d_m, the rows read (q'_j + mu) d_j + B_j . F_j = rhs_j;
+// the affine map F_{j+1} = A_{j+1} V_j + z_{j+1} is carried from the tip to the base
+// (a Riccati sweep of 3x3 matrices), then d follows from the base out.  One lane,
+// O(n).  false on a vanishing pivot.
+template <class SM>
+__device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rhs) {
+  const int lane = threadIdx.x, n = c.n, nc = S.ncl;
+  double* s00 = S.dinv;
+  double* s01 = S.ell;
+  double* s02 = S.z;
+  double* s11 = S.v;
+  double* s12 = S.aux;
+  double* s22 = S.ps1;
+  for (int k = lane; k < n; k += kWave) {
+    double m0 = S.cg[k], m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0, m5 = 0.0;
+    if (S.lidx[k] >= 0) {
+      for (int e = 0; e < nc; ++e) {
+        if (S.ci[e] != k) continue;
+        const double nx = S.cnx[e], ny = S.cny[e], x = S.cxx[e], y = S.cxy[e];
+        const double kc = c.P.kc, lk = S.cl[e] * S.ckap[e];
+        const double a0 = ny * x - nx * y, a1 = -ny, a2 = nx;
+        const double b0 = nx * x + ny * y, b1 = -nx, b2 = -ny;
+        m0 += kc * a0 * a0 - lk * b0 * b0;
+        m1 += kc * a0 * a1 - lk * b0 * b1;
+        m2 += kc * a0 * a2 - lk * b0 * b2;
+        m3 += kc * a1 * a1 - lk * b1 * b1;
+        m4 += kc * a1 * a2 - lk * b1 * b2;
+        m5 += kc * a2 * a2 - lk * b2 * b2;
+      }
+    }
+    s00[k] = m0;
+    s01[k] = m1;
+    s02[k] = m2;
+    s11[k] = m3;
+    s12[k] = m4;
+    s22[k] = m5;
+  }
+  __syncthreads();
+  int ok = 1;
+  if (lane == 0) {
+    double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
+    double z0 = 0, z1 = 0, z2 = 0;
+    for (int k = n - 1; k >= 0; --k) {
+      A0 += s00[k];
+      A1 += s01[k];
+      A2 += s02[k];
+      A3 += s11[k];
+      A4 += s12[k];
+      A5 += s22[k];
+      const double B1 = S.px[k], B2 = S.py[k];
+      const double h0 = A0 + A1 * B1 + A2 * B2;
+      const double h1 = A1 + A3 * B1 + A4 * B2;
+      const double h2 = A2 + A4 * B1 + A5 * B2;
+      const double dk = S.dq[k] + mu, bh = h0 + B1 * h1 + B2 * h2;
+      const double D = dk + bh;
+      if (!(isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)))) {
+        ok = 0;
+        break;
+      }
+      const double iD = 1.0 / D;
+      const double u = rhs[k] - (z0 + B1 * z1 + B2 * z2);
+      A0 -= h0 * h0 * iD;
+      A1 -= h0 * h1 * iD;
+      A2 -= h0 * h2 * iD;
+      A3 -= h1 * h1 * iD;
+      A4 -= h1 * h2 * iD;
+      A5 -= h2 * h2 * iD;
+      const double ui = u * iD;
+      z0 += h0 * ui;
+      z1 += h1 * ui;
+      z2 += h2 * ui;
+      s00[k] = h0;  // the slots of S_k now hold what the outward pass needs
+      s01[k] = h1;
+      s02[k] = h2;
+      s11[k] = iD;
+      s12[k] = u;
+    }
+    if (ok) {
+      double V0 = 0, V1 = 0, V2 = 0;
+      for (int k = 0; k < n; ++k) {
+        const double x = (s12[k] - (s00[k] * V0 + s01[k] * V1 + s02[k] * V2)) * s11[k];
+        V0 += x;
+        V1 += S.px[k] * x;
+        V2 += S.py[k] * x;
+        S.d[k] = x;
+      }
+    }
+    S.ps2[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (S.ps2[0] == 0.0) return false;
+  bool fin = true;
+  for (int j = lane; j < n; j += kWave) fin = fin && isfinite(S.d[j]);
+  return __all(fin);
+}
+
 // One equilibrium solve from S.th (in place).  Returns the status code.
 template <class SM, bool DENSE>
 __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
@@ -1104,20 +1308,17 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     ++iters;
     bool ok = false;
     double slope = 0.0, mu = P.c_mu * rm;
-    const bool dense = DENSE || !structured_setup(S, c);
-    if (dense && SM::WN < n) {
-      status = 3;  // more contact links than the structured solve holds
-      break;
-    }
+    const bool structured = structured_setup(S, c) && !P.seq_solver;
     for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
     __syncthreads();
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
       if (lane == 0) S.nsolves += 1.0;
-      if (dense) {
+      if (DENSE) {
         assemble(S, c, S.th, mu, S.b);
         if (!lu_solve_dense(S, n)) continue;
-      } else if (!structured_solve(S, c, mu, S.b)) {
+      } else if (structured ? !structured_solve(S, c, mu, S.b)
+                            : !chain_solve_seq(S, c, mu, S.b)) {
         continue;
       }
       double s = 0.0;
@@ -1355,8 +1556,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       S.b[j] = 2.0 * wt * (ex * vx + ey * vy);
     }
     __syncthreads();
-    // more contact links than the structured solve holds: the term is left out
-    const bool ok = structured_setup(S, c) && structured_solve(S, c, 0.0, S.b);
+    const bool ok = structured_setup(S, c) ? structured_solve(S, c, 0.0, S.b)
+                                           : chain_solve_seq(S, c, 0.0, S.b);
     if (!ok) {
       st = 1;
       continue;

@@ -113,9 +113,22 @@ def test_structured_solver_matches_dense_lu():
     work = W.config2(24)
     a = _gpu_rollout_p(work, solver=0)
     b = _gpu_rollout_p(work, solver=1)
-    dth = np.abs(a["theta"] - b["theta"]).max(1)
-    print(f"structured vs dense: max dtheta {dth.max():.2e}, iters {a['iters'].sum()} vs "
-          f"{b['iters'].sum()}", flush=True)
+    c = _gpu_rollout_p(work, solver=2)
+    for other, name in ((b, "dense LU"), (c, "sequential sweep")):
+        dth = np.abs(a["theta"] - other["theta"]).max(1)
+        print(f"structured vs {name}: max dtheta {dth.max():.2e}, iters {a['iters'].sum()} vs "
+              f"{other['iters'].sum()}", flush=True)
+        assert (dth <= 1e-8).sum() >= len(dth) - 1
+
+
+def test_sequential_sweep_matches_structured_on_long_chains():
+    full = W.config3(400)
+    idx = [i for i in range(400) if full.inst_i[i, 0] >= 150][:24]
+    work = full.subset(idx)
+    a = _gpu_rollout_p(work, solver=0)
+    c = _gpu_rollout_p(work, solver=2)
+    dth = np.abs(a["theta"] - c["theta"]).max(1)
+    print(f"long chains, structured vs sequential: max dtheta {dth.max():.2e}", flush=True)
     assert (dth <= 1e-8).sum() >= len(dth) - 1
 
 
@@ -144,9 +157,11 @@ def test_uneven_batch_full_size():
     n = full.inst_i[:, 0]
     K = full.inst_i[:, 4]
     assert np.array_equal(got["nlinks"], n)
-    conv = (got["status"] == 0) | (got["status"] == -1)
-    print(f"uneven batch: steps converged {conv.mean() * 100:.3f} %", flush=True)
-    assert conv.mean() > 0.999
+    st = got["status"]
+    vals, cnts = np.unique(st, return_counts=True)
+    print(f"uneven batch: step statuses {dict(zip(vals.tolist(), cnts.tolist()))}", flush=True)
+    assert not (st == 3).any() and not (st == 4).any()
+    assert ((st == 0) | (st == -1)).mean() > 0.999
     pick = []
     for lo, hi in ((16, 64), (65, 128), (129, 192), (193, 256)):
         for klo, khi in ((0, 16), (48, 64)):
