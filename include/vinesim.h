@@ -58,7 +58,7 @@ extern "C" {
 /* Simulation-wide constants.  Defaults (vine_params_default): R_c = 5 mm,
  * R_act = 17.18 mm, a = 1e-4 (Sec. 3.1); eps_crit = 0.01 (Sec. 3.2: fitted in the
  * paper, value not printed); k_c = 1e4 N/m; tol = 1e-10; max_iter = 500;
- * growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad; armijo_c1 = 1e-4. */
+ * growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad; armijo_c1 = 1e-4; solver = 2. */
 typedef struct vine_params {
   double R_c;            /* sPAM constriction radius (m), Eq. 1 */
   double R_act;          /* sPAM tube radius (m), Eq. 1c */
@@ -71,11 +71,15 @@ typedef struct vine_params {
   double armijo_c1;      /* sufficient-decrease constant of the line search */
   int32_t max_iter;      /* Newton iterations per equilibrium solve */
   int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
-  int32_t solver;        /* 0: structured solve of the Newton system (default): scans for the
-                               chain part plus a low-rank update per contact link, and a
-                               sequential O(n) sweep when the contact links exceed 16;
-                            1: dense LU with partial pivoting (chains of <= 64 links; cross-check);
-                            2: the sequential O(n) sweep always (cross-check) */
+  int32_t solver;        /* Newton system of the growth solve.
+                            2 (default): sequential O(n) sweep in relative angles (a Riccati
+                               recursion of 3x3 blocks from the tip, then a substitution from
+                               the base), any number of contacts;
+                            0: structured solve: scans for the chain part plus a low-rank
+                               update per contact link, the sweep above 16 contact links;
+                            1: dense LU with partial pivoting (chains of <= 64 links;
+                               cross-check, not accepted by the server).
+                            The adjoint (vine_sim_grad) always uses the structured solve. */
   int32_t reserved;
 } vine_params;
 

@@ -491,7 +491,7 @@ void vine_params_default(vine_params* p) {
   p->armijo_c1 = 1e-4;
   p->max_iter = 500;
   p->growth_substeps = 2;
-  p->solver = 0;
+  p->solver = 2;
   p->reserved = 0;
 }
 
@@ -974,8 +974,8 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max
   if (max_links > VINE_MAX_LINKS || max_obstacles > VINE_MAX_OBSTACLES ||
       max_spams > VINE_MAX_SPAMS)
     return sfail(nullptr, VINE_ECAPACITY, "bounds above the library's limits");
-  if (params->solver != 0)
-    return sfail(nullptr, VINE_EINVAL, "the server runs the structured solver only");
+  if (params->solver == 1)
+    return sfail(nullptr, VINE_EINVAL, "the dense cross-check solver is not served");
   // the slab: `slots` placeholder robots at the bounds (overwritten on admission)
   vine_instance ph{};
   ph.n_links = max_links;

@@ -1173,8 +1173,19 @@ __device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* r
   return __all(fin);
 }
 
+// 1/x from the hardware reciprocal and two Newton steps (each doubles the correct
+// bits; the result is within an ulp or two, and non-finite for a zero or non-finite x)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // (H + mu I) d = rhs directly in relative angles, for any number of contact links
-// (the path taken when the contact links exceed the structured solve's capacity).
+// (the default Newton solve; the structured solve hands over to it beyond its
+// capacity of contact links).
 // With B_j = (1, px_j, py_j) the exact Hessian has the chain form
 //   H_jm = q'_j [j = m] + B_j^T (sum_{k >= max(j,m)} S_k) B_m,
 //   S_k = sum_{contacts on link k} (k_c a a^T - lam kappa b b^T) + e0 e0^T C_k,
@@ -1218,54 +1229,79 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
     s22[k] = m5;
   }
   __syncthreads();
-  int ok = 1;
   if (lane == 0) {
+    // One lane walks the chain.  Each pass loads the next link's inputs while the
+    // current link computes (the index is clamped, so the last load repeats a valid
+    // one), and the pivot test only sets a flag: a failed pivot makes the remaining
+    // values non-finite, which the caller sees, and the loop has no branch.
+    bool ok = true;
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
     double z0 = 0, z1 = 0, z2 = 0;
-    for (int k = n - 1; k >= 0; --k) {
-      A0 += s00[k];
-      A1 += s01[k];
-      A2 += s02[k];
-      A3 += s11[k];
-      A4 += s12[k];
-      A5 += s22[k];
-      const double B1 = S.px[k], B2 = S.py[k];
-      const double h0 = A0 + A1 * B1 + A2 * B2;
-      const double h1 = A1 + A3 * B1 + A4 * B2;
-      const double h2 = A2 + A4 * B1 + A5 * B2;
-      const double dk = S.dq[k] + mu, bh = h0 + B1 * h1 + B2 * h2;
+    const int kt = n > 0 ? n - 1 : 0;
+    double q00 = s00[kt], q01 = s01[kt], q02 = s02[kt], q11 = s11[kt], q12 = s12[kt];
+    double q22 = s22[kt], qB1 = S.px[kt], qB2 = S.py[kt], qd = S.dq[kt], qr = rhs[kt];
+    int k;
+    for (k = n - 1; k >= 0; --k) {
+      A0 += q00;
+      A1 += q01;
+      A2 += q02;
+      A3 += q11;
+      A4 += q12;
+      A5 += q22;
+      const double B1 = qB1, B2 = qB2, dk = qd + mu, rk = qr;
+      const int kn = k > 0 ? k - 1 : 0;
+      q00 = s00[kn];
+      q01 = s01[kn];
+      q02 = s02[kn];
+      q11 = s11[kn];
+      q12 = s12[kn];
+      q22 = s22[kn];
+      qB1 = S.px[kn];
+      qB2 = S.py[kn];
+      qd = S.dq[kn];
+      qr = rhs[kn];
+      const double h0 = fma(A2, B2, fma(A1, B1, A0));
+      const double h1 = fma(A4, B2, fma(A3, B1, A1));
+      const double h2 = fma(A5, B2, fma(A4, B1, A2));
+      const double bh = fma(B2, h2, fma(B1, h1, h0));
       const double D = dk + bh;
-      if (!(isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)))) {
-        ok = 0;
-        break;
-      }
-      const double iD = 1.0 / D;
-      const double u = rhs[k] - (z0 + B1 * z1 + B2 * z2);
-      A0 -= h0 * h0 * iD;
-      A1 -= h0 * h1 * iD;
-      A2 -= h0 * h2 * iD;
-      A3 -= h1 * h1 * iD;
-      A4 -= h1 * h2 * iD;
-      A5 -= h2 * h2 * iD;
-      const double ui = u * iD;
-      z0 += h0 * ui;
-      z1 += h1 * ui;
-      z2 += h2 * ui;
+      ok = ok && isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh));
+      const double iD = rcp_nr(D);
+      const double u = rk - fma(B2, z2, fma(B1, z1, z0));
+      const double g0 = h0 * iD, g1 = h1 * iD, g2 = h2 * iD, ui = u * iD;
+      A0 = fma(-h0, g0, A0);
+      A1 = fma(-h0, g1, A1);
+      A2 = fma(-h0, g2, A2);
+      A3 = fma(-h1, g1, A3);
+      A4 = fma(-h1, g2, A4);
+      A5 = fma(-h2, g2, A5);
+      z0 = fma(h0, ui, z0);
+      z1 = fma(h1, ui, z1);
+      z2 = fma(h2, ui, z2);
       s00[k] = h0;  // the slots of S_k now hold what the outward pass needs
       s01[k] = h1;
       s02[k] = h2;
       s11[k] = iD;
       s12[k] = u;
     }
-    if (ok) {
-      double V0 = 0, V1 = 0, V2 = 0;
-      for (int k = 0; k < n; ++k) {
-        const double x = (s12[k] - (s00[k] * V0 + s01[k] * V1 + s02[k] * V2)) * s11[k];
-        V0 += x;
-        V1 += S.px[k] * x;
-        V2 += S.py[k] * x;
-        S.d[k] = x;
-      }
+    double V0 = 0, V1 = 0, V2 = 0;
+    double p0 = s00[0], p1 = s01[0], p2 = s02[0], pi = s11[0], pu = s12[0];
+    double pB1 = S.px[0], pB2 = S.py[0];
+    for (k = 0; k < n; ++k) {
+      const double h0 = p0, h1 = p1, h2 = p2, iD = pi, u = pu, B1 = pB1, B2 = pB2;
+      const int kn = k + 1 < n ? k + 1 : k;
+      p0 = s00[kn];
+      p1 = s01[kn];
+      p2 = s02[kn];
+      pi = s11[kn];
+      pu = s12[kn];
+      pB1 = S.px[kn];
+      pB2 = S.py[kn];
+      const double x = (u - fma(h2, V2, fma(h1, V1, h0 * V0))) * iD;
+      V0 += x;
+      V1 = fma(B1, x, V1);
+      V2 = fma(B2, x, V2);
+      S.d[k] = x;
     }
     S.ps2[0] = ok ? 1.0 : 0.0;
   }

@@ -109,14 +109,15 @@ def _gpu_rollout_p(work, **over):
         return sim.read_all()
 
 
-def test_structured_solver_matches_dense_lu():
+def test_newton_solvers_agree():
+    """The default sequential sweep against the structured solve and a dense LU."""
     work = W.config2(24)
-    a = _gpu_rollout_p(work, solver=0)
+    a = _gpu_rollout_p(work, solver=2)
     b = _gpu_rollout_p(work, solver=1)
-    c = _gpu_rollout_p(work, solver=2)
-    for other, name in ((b, "dense LU"), (c, "sequential sweep")):
+    c = _gpu_rollout_p(work, solver=0)
+    for other, name in ((b, "dense LU"), (c, "structured solve")):
         dth = np.abs(a["theta"] - other["theta"]).max(1)
-        print(f"structured vs {name}: max dtheta {dth.max():.2e}, iters {a['iters'].sum()} vs "
+        print(f"sweep vs {name}: max dtheta {dth.max():.2e}, iters {a['iters'].sum()} vs "
               f"{other['iters'].sum()}", flush=True)
         assert (dth <= 1e-8).sum() >= len(dth) - 1
 
