@@ -16,6 +16,8 @@
 #include "../../include/vinesim.h"
 #include "vs_device.h"
 
+static_assert(vs::kMaxObs == VINE_MAX_OBSTACLES, "obstacle capacity of the kernels");
+
 namespace vs {
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
                           int nmax_class, hipStream_t stream);

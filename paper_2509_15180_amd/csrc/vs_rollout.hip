@@ -14,9 +14,10 @@
 //       residual r_j = q_j - sum_{contacts on links >= j} lam (x - p_j) x n
 //       (suffix scans of per-link force and moment sums);
 //       stop when max_j |r_j| / M_max <= tol;
-//       exact Hessian in LDS; (H + mu I) d = -r by LU with partial pivoting,
-//       mu = c_mu |r|_inf raised tenfold until d descends; cap |d|_inf;
-//       Armijo backtracking on the energy.
+//       (H + mu I) d = -r with the exact Hessian: by default a sequential O(n)
+//       Riccati sweep along the chain (a structured solve and a dense LU are
+//       cross-checks), mu = c_mu |r|_inf raised tenfold until d descends;
+//       cap |d|_inf; Armijo backtracking on the energy.
 #include <hip/hip_runtime.h>
 
 #include "vs_device.h"
@@ -278,10 +279,9 @@ struct Ctx {
   double l, R, Mmax, arm, bx, by, bpsi, last_len;
   const SpamTable* tab;
   const WrTable* wr;
-  // this robot's obstacles, read through the constant address space (scalar loads:
-  // the obstacle index is the same for the whole wave)
-  const __attribute__((address_space(4))) double* obs;  // [K][4]
-  const __attribute__((address_space(4))) int* okind;   // [K]
+  // this robot's obstacles in global memory (read once into LDS, see stage_obstacles)
+  const double* obs;  // [K][4]: cx, cy, a, b
+  const int* okind;   // [K]
   KParams P;
 };
 
@@ -369,14 +369,14 @@ __device__ __forceinline__ bool obs_gap(int kind, double ox, double oy, double o
   return true;
 }
 
-// The pre-tests of obs_gap alone: false only for pairs obs_gap rejects.
+// The pre-tests of obs_gap alone: false only for pairs obs_gap rejects.  Both tests
+// are computed and one is selected, so that the wave does not branch on the kind.
 __device__ __forceinline__ bool obs_near(int kind, double ox, double oy, double oa, double ob,
                                          double R, double x, double y) {
-  if (kind == 0) {
-    const double vx = x - ox, vy = y - oy, rr = oa + R;
-    return vx * vx + vy * vy < rr * rr * (1.0 + 1e-12);
-  }
-  return (int)(fabs(x - ox) - oa < R) & (int)(fabs(y - oy) - ob < R);
+  const double vx = x - ox, vy = y - oy, rr = oa + R;
+  const bool circ = vx * vx + vy * vy < rr * rr * (1.0 + 1e-12);
+  const bool box = (int)(fabs(vx) - oa < R) & (int)(fabs(vy) - ob < R);
+  return kind == 0 ? circ : box;
 }
 
 // ---------------------------------------------------------------------------
@@ -394,7 +394,12 @@ struct Smem {
       double G[kMaxCols][kMaxCols + 1];  // U^T T^-1 U, then (I + S G | S c) and its LU in place
     } sm;
     double F[kWave][17];  // one chunk of forward-substituted columns (Gram by MFMA; padded)
+    struct {
+      double x[kMaxObs], y[kMaxObs], a[kMaxObs], b[kMaxObs];
+      int kind[kMaxObs];
+    } obst;  // the robot's obstacles while no solve holds this space (obs_ok set)
   };
+  int obs_ok;  // obst holds the robot's obstacles
   double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
   double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
   double pp[NMAX], pm[NMAX];
@@ -418,11 +423,27 @@ struct Smem {
   double jevals, nsolves;  // work counters (lane 0 updates)
 };
 
+// Copy the robot's obstacles into LDS (structure of arrays).  The space is shared with
+// the structured and dense solves, which clear obs_ok; evaluate() stages again then.
+template <class SM>
+__device__ void stage_obstacles(SM& S, const Ctx& c) {
+  for (int k = threadIdx.x; k < c.K; k += kWave) {
+    S.obst.x[k] = c.obs[4 * (size_t)k];
+    S.obst.y[k] = c.obs[4 * (size_t)k + 1];
+    S.obst.a[k] = c.obs[4 * (size_t)k + 2];
+    S.obst.b[k] = c.obs[4 * (size_t)k + 3];
+    S.obst.kind[k] = c.okind[k];
+  }
+  if (threadIdx.x == 0) S.obs_ok = 1;
+  __syncthreads();
+}
+
 // Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
 template <class SM>
 __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   const int lane = threadIdx.x;
   const int n = c.n;
+  if (__builtin_amdgcn_readfirstlane(S.obs_ok) == 0) stage_obstacles(S, c);
   if (lane == 0) S.jevals += n;
   double cphi = c.bpsi, cx = c.bx, cy = c.by;
   for (int base = 0; base < n; base += kWave) {
@@ -473,18 +494,18 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
       ys[hh] = on ? S.py[j] + s * S.ty[j] : 0.0;
     }
     for (int k0 = 0; k0 < c.K; k0 += 4) {
-      // four obstacles per round; the loads are unconditional (index clamped) so that
-      // they issue together and the round waits once
+      // four obstacles per round, read from LDS at addresses the whole wave shares
+      // (broadcast reads); the index is clamped so that the reads issue together
       double ox[4], oy[4], oa[4], ob[4];
       int kd[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = k0 + u < c.K ? k0 + u : c.K - 1;
-        ox[u] = c.obs[4 * k];
-        oy[u] = c.obs[4 * k + 1];
-        oa[u] = c.obs[4 * k + 2];
-        ob[u] = c.obs[4 * k + 3];
-        kd[u] = c.okind[k];
+        ox[u] = S.obst.x[k];
+        oy[u] = S.obst.y[k];
+        oa[u] = S.obst.a[k];
+        ob[u] = S.obst.b[k];
+        kd[u] = S.obst.kind[k];
       }
       unsigned near = 0u;  // bit 2u + hh: disk hh may touch obstacle k0 + u
 #pragma unroll
@@ -565,6 +586,7 @@ template <class SM>
 __device__ void assemble(SM& S, const Ctx& c, const double* th, double mu,
                          const double* rhs) {
   const int lane = threadIdx.x, n = c.n;
+  if (lane == 0) S.obs_ok = 0;  // W overwrites the staged obstacles
   for (int j = lane; j < n; j += kWave) {
     for (int m = 0; m < n; ++m) S.W[j][m] = 0.0;
     double dq;
@@ -1110,6 +1132,7 @@ __device__ bool small_solve(SM& S, int ncol) {
 template <class SM>
 __device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* rhs) {
   const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
+  if (lane == 0) S.obs_ok = 0;  // G and F overwrite the staged obstacles
   if (!tri_factor(S, n, mu)) return false;
   // right-hand side in absolute angles: b_m - b_{m+1}
   for (int m = lane; m < n; m += kWave) S.v[m] = rhs[m] - (m + 1 < n ? rhs[m + 1] : 0.0);
@@ -1425,7 +1448,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   const double* dd = D.dd + 6 * b;
   Ctx c;
   const int ntar = ii[0];
-  c.K = ii[2];
+  c.K = ii[2] < kMaxObs ? ii[2] : kMaxObs;  // the boundary rejects more
   c.l = dd[0];
   c.R = dd[1];
   c.Mmax = kPi * dd[2] * c.R * c.R * c.R;
@@ -1439,8 +1462,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   c.trace = (b == D.trace_robot) ? D.trace : nullptr;
   c.trace_n = D.trace_n;
   c.trace_cap = D.trace_cap;
-  c.obs = (const __attribute__((address_space(4))) double*)(D.obs + 4 * (size_t)ii[1]);
-  c.okind = (const __attribute__((address_space(4))) int*)(D.okind + ii[1]);
+  c.obs = D.obs + 4 * (size_t)ii[1];
+  c.okind = D.okind + ii[1];
+  if (lane == 0) S.obs_ok = 0;  // staged by the first evaluation
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
@@ -1542,7 +1566,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   const double* dd = D.dd + 6 * b;
   Ctx c;
   const int ntar = ii[0];
-  c.K = ii[2];
+  c.K = ii[2] < kMaxObs ? ii[2] : kMaxObs;  // the boundary rejects more
   c.l = dd[0];
   c.R = dd[1];
   c.Mmax = kPi * dd[2] * c.R * c.R * c.R;
@@ -1555,8 +1579,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   c.P = P;
   c.trace = nullptr;
   c.last_len = c.l;
-  c.obs = (const __attribute__((address_space(4))) double*)(D.obs + 4 * (size_t)ii[1]);
-  c.okind = (const __attribute__((address_space(4))) int*)(D.okind + ii[1]);
+  c.obs = D.obs + 4 * (size_t)ii[1];
+  c.okind = D.okind + ii[1];
+  if (lane == 0) S.obs_ok = 0;  // staged by the first evaluation
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
