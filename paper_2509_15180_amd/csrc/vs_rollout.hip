@@ -486,13 +486,18 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     const int j = base + lane;
     const bool on = j < n;
     const double L = (j == n - 1) ? c.last_len : c.l;
+    const double pxj = on ? S.px[j] : 0.0, pyj = on ? S.py[j] : 0.0;
+    const double txj = on ? S.tx[j] : 0.0, tyj = on ? S.ty[j] : 0.0;
     double xs[2], ys[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const double s = 0.5 * (hh + 1) * L;
-      xs[hh] = on ? S.px[j] + s * S.tx[j] : 0.0;
-      ys[hh] = on ? S.py[j] + s * S.ty[j] : 0.0;
+      xs[hh] = pxj + s * txj;
+      ys[hh] = pyj + s * tyj;
     }
+    // this link's contact sums, in the order the contacts are listed: moment and force
+    // (residual), and the force's moment along the link (geometric stiffness)
+    double a_s1 = 0.0, a_fx = 0.0, a_fy = 0.0, a_q = 0.0;
     for (int k0 = 0; k0 < c.K; k0 += 4) {
       // four obstacles per round, read from LDS at addresses the whole wave shares
       // (broadcast reads); the index is clamped so that the reads issue together
@@ -530,21 +535,32 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
           if (m) {
             const int pos = cnt + __popcll(m & lt);
             if (hit && pos < kMaxC) {
-              const double pen = -g;
+              const double pen = -g, lam = c.P.kc * pen;
               S.ci[pos] = j;
               S.ck[pos] = k0 + u;
-              S.cl[pos] = c.P.kc * pen;
+              S.cl[pos] = lam;
               S.cxx[pos] = xs[hh];
               S.cxy[pos] = ys[hh];
               S.cnx[pos] = nx;
               S.cny[pos] = ny;
               S.ckap[pos] = kap;
               S.cpen[pos] = pen;
+              a_s1 += lam * (xs[hh] * ny - ys[hh] * nx);
+              a_fx += lam * nx;
+              a_fy += lam * ny;
+              const double sd = (xs[hh] - pxj) * txj + (ys[hh] - pyj) * tyj;
+              a_q += lam * sd * (nx * txj + ny * tyj);
             }
             cnt += __popcll(m);
           }
         }
       }
+    }
+    if (on) {  // read by the suffix sums below and by structured_setup
+      S.ps1[j] = a_s1;
+      S.ps2[j] = a_fx;
+      S.aux[j] = a_fy;
+      S.v[j] = a_q;
     }
   }
   int nc = cnt < kMaxC ? cnt : kMaxC;
@@ -558,15 +574,8 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   int nchunk = (n + kWave - 1) / kWave;
   for (int ch = nchunk - 1; ch >= 0; --ch) {
     int j = ch * kWave + lane;
-    double s1 = 0.0, s2x = 0.0, s2y = 0.0;
-    for (int e = 0; e < nc; ++e) {
-      if (S.ci[e] == j) {
-        double lam = S.cl[e];
-        s1 += lam * (S.cxx[e] * S.cny[e] - S.cxy[e] * S.cnx[e]);
-        s2x += lam * S.cnx[e];
-        s2y += lam * S.cny[e];
-      }
-    }
+    double s1 = j < n ? S.ps1[j] : 0.0, s2x = j < n ? S.ps2[j] : 0.0;
+    double s2y = j < n ? S.aux[j] : 0.0;
     s1 = wscan_suffix(s1, lane) + c1;
     s2x = wscan_suffix(s2x, lane) + c2x;
     s2y = wscan_suffix(s2y, lane) + c2y;
@@ -673,8 +682,10 @@ __device__ bool lu_solve_dense(SM& S, int n) {
 //   C_m = l t_m . (sum of contact forces on links beyond m) + sum_{disks on m} lam s n.t_m,
 //   M_i = sum_{disks on i} k_c alpha alpha^T - lam kappa beta beta^T,
 //   alpha = (n_y, -n_x, s t_i x n), beta = (n_x, n_y, s t_i . n),
-// s the disk's distance from the link's proximal joint.  Returns false when more
-// than kMaxCL links are in contact.
+// s the disk's distance from the link's proximal joint.  C takes the per-link contact
+// sums that evaluate() leaves in S.ps2, S.aux and S.v, so this must follow the
+// evaluation of the same state.  Returns false when more than kMaxCL links are in
+// contact.
 template <class SM>
 __device__ bool structured_setup(SM& S, const Ctx& c) {
   const int lane = threadIdx.x, n = c.n, nc = S.ncl;
@@ -707,18 +718,9 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
   const int nchunk = (n + kWave - 1) / kWave;
   for (int ch = nchunk - 1; ch >= 0; --ch) {
     const int j = ch * kWave + lane;
-    double fx = 0.0, fy = 0.0, q = 0.0;
-    if (j < n && S.lidx[j] >= 0) {
-      const double tjx = S.tx[j], tjy = S.ty[j];
-      for (int e = 0; e < nc; ++e) {
-        if (S.ci[e] != j) continue;
-        const double lam = S.cl[e], nx = S.cnx[e], ny = S.cny[e];
-        const double s = (S.cxx[e] - S.px[j]) * tjx + (S.cxy[e] - S.py[j]) * tjy;
-        fx += lam * nx;
-        fy += lam * ny;
-        q += lam * s * (nx * tjx + ny * tjy);
-      }
-    }
+    // per-link contact force and its moment along the link, summed by evaluate()
+    const double fx = j < n ? S.ps2[j] : 0.0, fy = j < n ? S.aux[j] : 0.0;
+    const double q = j < n ? S.v[j] : 0.0;
     double sx = wscan_suffix(fx, lane) + cfx, sy = wscan_suffix(fy, lane) + cfy;
     if (j < n) S.cg[j] = c.l * (S.tx[j] * (sx - fx) + S.ty[j] * (sy - fy)) + q;
     cfx = __shfl(sx, 0, kWave);
