@@ -15,6 +15,7 @@ constexpr int kSpamPieces = 24;
 constexpr int kSpamDeg = 20;
 
 struct SpamTable {
+  static constexpr bool kHasSlope = true;
   double l0;                                 // actuator unit length (= link length)
   double emax;                               // slack strain eps(m = 1/2)
   double G0;                                 // G(0)

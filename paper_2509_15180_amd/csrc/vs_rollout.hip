@@ -239,10 +239,28 @@ __device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
   return fma(x, b1, c[0] - b2);
 }
 
+// LDS copies of the series that every evaluation sums: G and its integral (not the
+// slope, which only the Newton set-up needs) and the integral of the body moment.
+// Same member names as SpamTable / WrTable, so the laws below take either.
+struct SpamLds {
+  static constexpr bool kHasSlope = false;
+  double emax, G0;
+  double bnd[kSpamPieces + 1], cum[kSpamPieces + 1];
+  double c[kSpamPieces][kSpamDeg + 1];
+  double ic[kSpamPieces][kSpamDeg + 2];
+};
+
+struct WrLds {
+  double th_on, du, h_pi, ih_pi;
+  double cum[kIhPieces + 1];
+  double ic[kIhPieces][kIhDeg + 2];
+};
+
 // int_0^x wr_h (energy of the body moment per pi P R^3): above the onset, the exact
 // antiderivative of a piecewise Chebyshev fit of 2 u h(theta_on + u^2) in
 // u = sqrt(x - theta_on), so that its slope in x equals h to the fit's accuracy.
-__device__ double wr_int(double x, const WrTable& T) {
+template <class Tab>
+__device__ double wr_int(double x, const Tab& T) {
   if (x <= T.th_on) return x * x / (4.0 * T.th_on);
   if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
   const double u = sqrt(x - T.th_on);
@@ -253,8 +271,10 @@ __device__ double wr_int(double x, const WrTable& T) {
   return T.cum[k] + 0.5 * T.du * clenshaw(T.ic[k], kIhDeg + 1, t);
 }
 
-// sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral
-__device__ void spam_law(const SpamTable& T, double eps, double* G, double* dG, double* IG) {
+// sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral.  A
+// table without the slope series gives a NaN slope (never asked for).
+template <class Tab>
+__device__ void spam_law(const Tab& T, double eps, double* G, double* dG, double* IG) {
   if (eps >= T.emax) {
     if (G) *G = 0.0;
     if (dG) *dG = 0.0;
@@ -266,7 +286,11 @@ __device__ void spam_law(const SpamTable& T, double eps, double* G, double* dG, 
   double a = T.bnd[k], b = T.bnd[k + 1];
   double x = (2.0 * eps - a - b) / (b - a);
   if (G) *G = clenshaw(T.c[k], kSpamDeg, x);
-  if (dG) *dG = clenshaw(T.dc[k], kSpamDeg - 1, x) * 2.0 / (b - a);
+  if constexpr (Tab::kHasSlope) {
+    if (dG) *dG = clenshaw(T.dc[k], kSpamDeg - 1, x) * 2.0 / (b - a);
+  } else {
+    if (dG) *dG = __builtin_nan("");
+  }
   if (IG) *IG = T.cum[k] + 0.5 * (b - a) * clenshaw(T.ic[k], kSpamDeg + 1, x);
 }
 
@@ -279,7 +303,7 @@ struct Ctx {
   double l, R, Mmax, arm, bx, by, bpsi, last_len;
   const SpamTable* tab;
   const WrTable* wr;
-  // this robot's obstacles in global memory (read once into LDS, see stage_obstacles)
+  // this robot's obstacles in global memory (copied into LDS, see stage_resident)
   const double* obs;  // [K][4]: cx, cy, a, b
   const int* okind;   // [K]
   KParams P;
@@ -288,17 +312,18 @@ struct Ctx {
 // joint moment (Eq. 3b with Eq. 2), slope and energy for angle th and coverage pp/pm.
 // Only the actuator side the bend stretches needs the force law; the other side sits
 // at zero strain, G(0) = G0.
-__device__ void joint_law(const Ctx& c, double th, double pp, double pm, double* q, double* dq,
-                          double* E) {
-  const double epsc = c.P.epsc, th_on = c.wr->th_on;
+template <class TS, class TW>
+__device__ void joint_law(const Ctx& c, const TS& ts, const TW& tw, double th, double pp,
+                          double pm, double* q, double* dq, double* E) {
+  const double epsc = c.P.epsc, th_on = tw.th_on;
   const double ath = fabs(th);
-  const double G0 = c.tab->G0;
+  const double G0 = ts.G0;
   const double eps = c.arm * ath / c.l;
   double G = G0, dG = 0.0, IG = 0.0;
   if (th != 0.0)
-    spam_law(*c.tab, eps, q ? &G : nullptr, dq ? &dG : nullptr, E ? &IG : nullptr);
+    spam_law(ts, eps, q ? &G : nullptr, dq ? &dG : nullptr, E ? &IG : nullptr);
   else if (dq)
-    spam_law(*c.tab, 0.0, nullptr, &dG, nullptr);
+    spam_law(ts, 0.0, nullptr, &dG, nullptr);
   const double pstr = th >= 0.0 ? pp : pm;  // stretched side
   if (q) {
     const double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * wr_h(ath, epsc, th_on);
@@ -311,7 +336,7 @@ __device__ void joint_law(const Ctx& c, double th, double pp, double pm, double*
     *dq = d;
   }
   if (E) {
-    const double Eb = c.Mmax * wr_int(ath, *c.wr);
+    const double Eb = c.Mmax * wr_int(ath, tw);
     const double Ea = th >= 0.0 ? (-c.l * pp * IG + c.arm * pm * G0 * th)
                                 : (-c.arm * pp * G0 * th - c.l * pm * IG);
     *E = Eb + Ea;
@@ -395,11 +420,13 @@ struct Smem {
     } sm;
     double F[kWave][17];  // one chunk of forward-substituted columns (Gram by MFMA; padded)
     struct {
-      double x[kMaxObs], y[kMaxObs], a[kMaxObs], b[kMaxObs];
-      int kind[kMaxObs];
-    } obst;  // the robot's obstacles while no solve holds this space (obs_ok set)
+      double ox[kMaxObs], oy[kMaxObs], oa[kMaxObs], ob[kMaxObs];
+      int okind[kMaxObs];
+      SpamLds sp;
+      WrLds wr;
+    } res;  // the robot's obstacles and law tables while no solve holds this space
   };
-  int obs_ok;  // obst holds the robot's obstacles
+  int res_ok;  // res holds this robot's data
   double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
   double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
   double pp[NMAX], pm[NMAX];
@@ -423,18 +450,42 @@ struct Smem {
   double jevals, nsolves;  // work counters (lane 0 updates)
 };
 
-// Copy the robot's obstacles into LDS (structure of arrays).  The space is shared with
-// the structured and dense solves, which clear obs_ok; evaluate() stages again then.
+// Copy the robot's obstacles (structure of arrays) and the series of its law tables
+// into LDS.  The space is shared with the structured and dense solves, which clear
+// res_ok; evaluate() copies again then.
 template <class SM>
-__device__ void stage_obstacles(SM& S, const Ctx& c) {
-  for (int k = threadIdx.x; k < c.K; k += kWave) {
-    S.obst.x[k] = c.obs[4 * (size_t)k];
-    S.obst.y[k] = c.obs[4 * (size_t)k + 1];
-    S.obst.a[k] = c.obs[4 * (size_t)k + 2];
-    S.obst.b[k] = c.obs[4 * (size_t)k + 3];
-    S.obst.kind[k] = c.okind[k];
+__device__ void stage_resident(SM& S, const Ctx& c) {
+  const int lane = threadIdx.x;
+  static_assert(sizeof(S.res) <= sizeof(S.sm), "resident data must fit the solve space");
+  for (int k = lane; k < c.K; k += kWave) {
+    S.res.ox[k] = c.obs[4 * (size_t)k];
+    S.res.oy[k] = c.obs[4 * (size_t)k + 1];
+    S.res.oa[k] = c.obs[4 * (size_t)k + 2];
+    S.res.ob[k] = c.obs[4 * (size_t)k + 3];
+    S.res.okind[k] = c.okind[k];
   }
-  if (threadIdx.x == 0) S.obs_ok = 1;
+  const SpamTable& T = *c.tab;
+  for (int i = lane; i < kSpamPieces * (kSpamDeg + 1); i += kWave)
+    (&S.res.sp.c[0][0])[i] = (&T.c[0][0])[i];
+  for (int i = lane; i < kSpamPieces * (kSpamDeg + 2); i += kWave)
+    (&S.res.sp.ic[0][0])[i] = (&T.ic[0][0])[i];
+  for (int i = lane; i <= kSpamPieces; i += kWave) {
+    S.res.sp.bnd[i] = T.bnd[i];
+    S.res.sp.cum[i] = T.cum[i];
+  }
+  const WrTable& W = *c.wr;
+  for (int i = lane; i < kIhPieces * (kIhDeg + 2); i += kWave)
+    (&S.res.wr.ic[0][0])[i] = (&W.ic[0][0])[i];
+  for (int i = lane; i <= kIhPieces; i += kWave) S.res.wr.cum[i] = W.cum[i];
+  if (lane == 0) {
+    S.res.sp.emax = T.emax;
+    S.res.sp.G0 = T.G0;
+    S.res.wr.th_on = W.th_on;
+    S.res.wr.du = W.du;
+    S.res.wr.h_pi = W.h_pi;
+    S.res.wr.ih_pi = W.ih_pi;
+    S.res_ok = 1;
+  }
   __syncthreads();
 }
 
@@ -443,7 +494,7 @@ template <class SM>
 __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   const int lane = threadIdx.x;
   const int n = c.n;
-  if (__builtin_amdgcn_readfirstlane(S.obs_ok) == 0) stage_obstacles(S, c);
+  if (__builtin_amdgcn_readfirstlane(S.res_ok) == 0) stage_resident(S, c);
   if (lane == 0) S.jevals += n;
   double cphi = c.bpsi, cx = c.bx, cy = c.by;
   for (int base = 0; base < n; base += kWave) {
@@ -473,7 +524,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   double Esum = 0.0;
   for (int j = lane; j < n; j += kWave) {
     double q, E = 0.0;
-    joint_law(c, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
     S.r[j] = q;
     Esum += E;
   }
@@ -506,11 +557,11 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = k0 + u < c.K ? k0 + u : c.K - 1;
-        ox[u] = S.obst.x[k];
-        oy[u] = S.obst.y[k];
-        oa[u] = S.obst.a[k];
-        ob[u] = S.obst.b[k];
-        kd[u] = S.obst.kind[k];
+        ox[u] = S.res.ox[k];
+        oy[u] = S.res.oy[k];
+        oa[u] = S.res.oa[k];
+        ob[u] = S.res.ob[k];
+        kd[u] = S.res.okind[k];
       }
       unsigned near = 0u;  // bit 2u + hh: disk hh may touch obstacle k0 + u
 #pragma unroll
@@ -595,11 +646,11 @@ template <class SM>
 __device__ void assemble(SM& S, const Ctx& c, const double* th, double mu,
                          const double* rhs) {
   const int lane = threadIdx.x, n = c.n;
-  if (lane == 0) S.obs_ok = 0;  // W overwrites the staged obstacles
+  if (lane == 0) S.res_ok = 0;  // W overwrites the resident data
   for (int j = lane; j < n; j += kWave) {
     for (int m = 0; m < n; ++m) S.W[j][m] = 0.0;
     double dq;
-    joint_law(c, th[j], S.pp[j], S.pm[j], nullptr, &dq, nullptr);
+    joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], nullptr, &dq, nullptr);
     S.W[j][j] = dq + mu;
     S.W[j][n] = rhs[j];
   }
@@ -692,7 +743,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
   const unsigned long long lt = (1ull << lane) - 1ull;
   for (int j = lane; j < n; j += kWave) {
     double d;
-    joint_law(c, S.th[j], S.pp[j], S.pm[j], nullptr, &d, nullptr);
+    joint_law(c, *c.tab, *c.wr, S.th[j], S.pp[j], S.pm[j], nullptr, &d, nullptr);
     S.dq[j] = d;
     S.lidx[j] = -1;
   }
@@ -1134,7 +1185,7 @@ __device__ bool small_solve(SM& S, int ncol) {
 template <class SM>
 __device__ bool structured_solve(SM& S, const Ctx& c, double mu, const double* rhs) {
   const int lane = threadIdx.x, n = c.n, L = S.ncl_links;
-  if (lane == 0) S.obs_ok = 0;  // G and F overwrite the staged obstacles
+  if (lane == 0) S.res_ok = 0;  // G and F overwrite the resident data
   if (!tri_factor(S, n, mu)) return false;
   // right-hand side in absolute angles: b_m - b_{m+1}
   for (int m = lane; m < n; m += kWave) S.v[m] = rhs[m] - (m + 1 < n ? rhs[m + 1] : 0.0);
@@ -1259,7 +1310,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
     // current link computes (the index is clamped, so the last load repeats a valid
     // one), and the pivot test only sets a flag: a failed pivot makes the remaining
     // values non-finite, which the caller sees, and the loop has no branch.
-    bool ok = true;
+    int okf = 1;
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
     double z0 = 0, z1 = 0, z2 = 0;
     const int kt = n > 0 ? n - 1 : 0;
@@ -1290,7 +1341,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       const double h2 = fma(A5, B2, fma(A4, B1, A2));
       const double bh = fma(B2, h2, fma(B1, h1, h0));
       const double D = dk + bh;
-      ok = ok && isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh));
+      okf &= (int)isfinite(D) & (int)(fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)));
       const double iD = rcp_nr(D);
       const double u = rk - fma(B2, z2, fma(B1, z1, z0));
       const double g0 = h0 * iD, g1 = h1 * iD, g2 = h2 * iD, ui = u * iD;
@@ -1328,7 +1379,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       V2 = fma(B2, x, V2);
       S.d[k] = x;
     }
-    S.ps2[0] = ok ? 1.0 : 0.0;
+    S.ps2[0] = okf ? 1.0 : 0.0;
   }
   __syncthreads();
   if (S.ps2[0] == 0.0) return false;
@@ -1466,7 +1517,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   c.trace_cap = D.trace_cap;
   c.obs = D.obs + 4 * (size_t)ii[1];
   c.okind = D.okind + ii[1];
-  if (lane == 0) S.obs_ok = 0;  // staged by the first evaluation
+  if (lane == 0) S.res_ok = 0;  // staged by the first evaluation
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
@@ -1583,7 +1634,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   c.last_len = c.l;
   c.obs = D.obs + 4 * (size_t)ii[1];
   c.okind = D.okind + ii[1];
-  if (lane == 0) S.obs_ok = 0;  // staged by the first evaluation
+  if (lane == 0) S.res_ok = 0;  // staged by the first evaluation
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
