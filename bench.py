@@ -17,7 +17,9 @@ Other workloads (``--workload``), same JSON fields:
 Prints one JSON line with the driver's fields plus:
   roofline      the rollout kernel against the FP64 VALU peak (per-joint-evaluation
                 FLOP count below), timed with HIP events on the stream the kernel is
-                launched on;
+                launched on; traffic (HBM bytes per launch) and the executed FP64 VALU
+                work from the committed rocprofv3 counter summary, while the kernel
+                sources are unchanged since it was taken (else null);
   per_instance  the same kernel launched once per robot (batch of one), serial on one
                 stream, on a sample of the robots;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload on the host
@@ -47,6 +49,27 @@ def flops_per_joint_eval(K: float) -> float:
     return 325.0 + 17.0 * K
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "rollout_kernel_uniform_4096_counters.json")
+KERNEL_SOURCES = ("paper_2509_15180_amd/csrc/vs_rollout.hip", "paper_2509_15180_amd/csrc/vs_device.h")
+
+
+def measured_counters(workload: str, robots: int):
+    """HBM bytes and FP64 instruction counts of one rollout launch, taken with rocprofv3
+    PMC runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size; SQ_INSTS_*)
+    and committed under profiles/.  Returned only for the workload they were taken on and
+    while the kernel sources hash to what they were then; else None."""
+    if workload != "uniform" or robots != 4096 or not os.path.exists(COUNTERS):
+        return None
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    with open(COUNTERS) as fh:
+        rec = json.load(fh)
+    return rec if rec.get("kernel_source_sha256") == h.hexdigest() else None
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -65,7 +88,7 @@ def main():
     ap.add_argument("--tick-steps", type=int, default=8, help="serve: growth steps per round")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
-    ap.add_argument("--cpu-robots", type=int, default=64, help="robots in the CPU-oracle sample")
+    ap.add_argument("--cpu-robots", type=int, default=160, help="robots in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -186,6 +209,15 @@ def main():
                          f"{' (those of <= 128 links)' if wl == 'uneven' else ''}, full rollouts "
                          f"({sub.joint_updates()} joint-updates in {csec:.1f} s)"}
 
+    meas = measured_counters(wl, B)
+    traffic = meas["hbm_bytes_per_launch"] if meas else None
+    counters = None
+    if meas:  # executed FP64 VALU work (wave instructions x 64 lanes, FMA = 2)
+        cflop = meas["fp64_flop_per_launch_from_counters"]
+        counters = {"fp64_flop_per_launch": cflop,
+                    "achieved": cflop / (kern_ms * 1e-3) / 1e12,
+                    "frac": cflop / (kern_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                    "source": os.path.relpath(COUNTERS, ROOT)}
     rec = {
         "metric": METRIC, "value": value, "unit": "joint-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -194,8 +226,9 @@ def main():
         "config": {"workload": desc, "robots": B, "links_max": int(n.max()),
                    "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "rollout_kernel", "kernel_ms": kern_ms,
+                     "counters": counters,
                      "joint_evaluations": jevals,
                      "flop_per_joint_eval": flops_per_joint_eval(K_mean),
                      "linear_solves": nsolves},
