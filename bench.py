@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
     ap.add_argument("--cpu-robots", type=int, default=160, help="robots in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the captured reset + rollout (vine_sim_rollout_graph)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): robots are "
@@ -131,8 +133,11 @@ def main():
     goal = torch.as_tensor(work.goal, dtype=torch.float64).cuda()
 
     def one_step():
-        sim.reset(stream=stream)
-        sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
+        if args.graph:
+            sim.rollout_graph(record_traj=(wl == "grad"), stream=stream)
+        else:
+            sim.reset(stream=stream)
+            sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
         if wl == "grad":
             sim.grad(goal, weights, stream=stream)
 
@@ -223,7 +228,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "robots": B, "links_max": int(n.max()),
+        "config": {"workload": desc, "robots": B, "links_max": int(n.max()), "graph": bool(args.graph),
                    "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,

@@ -165,6 +165,16 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
  * n_steps steps.  Same semantics as vine_sim_step. */
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
 
+/* vine_sim_reset followed by vine_sim_rollout(h, -1, record_traj, stream) (every robot
+ * regrown from zero length to its target, Sec. 4 growth steps), as one HIP graph: the
+ * reset and the per-class launches (with their fork/join across the handle's streams)
+ * are captured on the first call for each value of record_traj (nonzero = 1) and
+ * replayed by later calls, so a repeated rollout costs one graph launch.  The graph
+ * holds no memset nodes.  Results are bitwise those of the two eager calls.  The
+ * capture is dropped by vine_sim_trace (it holds the trace buffer's address).  Errors:
+ * VINE_EINVAL (null handle), VINE_ENOMEM (trajectory), VINE_EDEVICE (capture, launch). */
+int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream);
+
 /* Gradient of a tip-reaching loss with respect to the actuation design, by the
  * adjoint of the equilibrium conditions (Sec. 5 searches sPAM placement and
  * pressure with the simulator in the loop; the adjoint differentiates each step's

@@ -351,6 +351,9 @@ struct vine_sim {
   int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
+  // vine_sim_rollout_graph: reset + full rollout captured once per record flag
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   int trace_robot = -1, trace_cap = 0;
   double* trace = nullptr;
   int* trace_n = nullptr;
@@ -366,7 +369,17 @@ int fail(vine_sim* h, int code, const std::string& msg) {
   return code;
 }
 
+void drop_graphs(vine_sim* h) {
+  for (auto& g : h->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 void free_all(vine_sim* h) {
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (int c = 0; c < vine_sim::kClasses; ++c) {
     if (h->cls_stream[c]) (void)hipStreamDestroy(h->cls_stream[c]);
     if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
@@ -694,17 +707,24 @@ int32_t vine_sim_reset(vine_sim* h, void* stream) {
   return VINE_OK;
 }
 
+static int32_t ensure_traj(vine_sim* h) {  // B * T * N doubles, allocated on first use
+  if (h->traj) return VINE_OK;
+  hipError_t e = dalloc(&h->traj, (size_t)h->B * h->T * h->N);
+  if (e != hipSuccess) {
+    h->traj = nullptr;
+    return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
+                std::string("trajectory allocation: ") + hipGetErrorString(e));
+  }
+  return VINE_OK;
+}
+
 static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   if (n_steps < 0) n_steps = h->T;
   if (n_steps == 0) return VINE_OK;
-  if (record_traj && !h->traj) {  // B * T * N doubles, allocated on first use
-    hipError_t e = dalloc(&h->traj, (size_t)h->B * h->T * h->N);
-    if (e != hipSuccess) {
-      h->traj = nullptr;
-      return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
-                  std::string("trajectory allocation: ") + hipGetErrorString(e));
-    }
+  if (record_traj) {
+    const int32_t r = ensure_traj(h);
+    if (r != VINE_OK) return r;
   }
   const vs::KParams kp = kparams(h->prm);
   hipError_t e = for_each_class(h, (hipStream_t)stream,
@@ -723,6 +743,44 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
 
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
   return advance(h, n_steps < 0 ? -1 : n_steps, record_traj, stream);
+}
+
+int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  const int g = record_traj ? 1 : 0;
+  if (g) {
+    const int32_t r = ensure_traj(h);
+    if (r != VINE_OK) return r;
+  }
+  if (!h->graph[g]) {
+    // capture on a stream of the handle's own (the caller's may be the null stream);
+    // the class streams join the capture through the fork/join events
+    hipError_t e = hipSuccess;
+    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const vs::KParams kp = kparams(h->prm);
+      hipError_t le = vs::launch_reset(kdata(h), h->cap_stream);
+      if (le == hipSuccess)
+        le = for_each_class(h, h->cap_stream, [&](int links, const vs::KData& D, hipStream_t s) {
+          return vs::launch_rollout(kp, D, h->T, g, links, s);
+        });
+      e = hipStreamEndCapture(h->cap_stream, &graph);  // ends the capture in every case
+      if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->graph[g], graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->graph[g] = nullptr;
+      return fail(h, VINE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+  }
+  const hipError_t e = hipGraphLaunch(h->graph[g], (hipStream_t)stream);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  h->traj_valid = g != 0;  // as after vine_sim_reset + vine_sim_rollout
+  h->traj_all = g != 0;
+  return VINE_OK;
 }
 
 int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,
@@ -848,6 +906,7 @@ const char* vine_sim_last_error(const vine_sim* h) {
 
 int32_t vine_sim_trace(vine_sim* h, int32_t robot, int32_t capacity) {
   if (!h || robot < -1 || robot >= h->B || capacity < 0) return fail(h, VINE_EINVAL, "bad arguments");
+  drop_graphs(h);  // captured launches hold the trace buffer's address
   if (h->trace) (void)hipFree(h->trace);
   if (h->trace_n) (void)hipFree(h->trace_n);
   h->trace = nullptr;

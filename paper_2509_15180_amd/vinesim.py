@@ -5,7 +5,8 @@ library.  The binding fails loudly when the library is missing; it never falls
 back to another implementation.
 
 Names follow the C ABI: ``create`` -> vine_sim_create, ``VineSim.step`` ->
-vine_sim_step, ``VineSim.rollout`` -> vine_sim_rollout, ``VineSim.read`` ->
+vine_sim_step, ``VineSim.rollout`` -> vine_sim_rollout, ``VineSim.rollout_graph`` ->
+vine_sim_rollout_graph, ``VineSim.read`` ->
 vine_sim_read, ``VineSim.grad`` -> vine_sim_grad, ``VineSim.close`` ->
 vine_sim_destroy.
 """
@@ -66,6 +67,7 @@ class Obstacle(C.Structure):
 
 
 EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
+           "vine_sim_rollout_graph",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_set_spams", "vine_server_create",
@@ -94,6 +96,8 @@ def lib():
         L.vine_sim_step.restype = C.c_int32
         L.vine_sim_rollout.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.vine_sim_rollout.restype = C.c_int32
+        L.vine_sim_rollout_graph.argtypes = [vp, C.c_int32, vp]
+        L.vine_sim_rollout_graph.restype = C.c_int32
         L.vine_sim_reset.argtypes = [vp, vp]
         L.vine_sim_reset.restype = C.c_int32
         L.vine_sim_read.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
@@ -206,6 +210,12 @@ class VineSim:
     def rollout(self, n_steps: int = -1, record_traj: bool = False, stream=None):
         self._check(lib().vine_sim_rollout(self.h, int(n_steps), int(bool(record_traj)),
                                            _stream_ptr(stream)))
+
+    def rollout_graph(self, record_traj: bool = False, stream=None):
+        """Reset and roll every robot out to full length as one captured HIP graph
+        (captured on the first call for each record_traj, replayed afterwards)."""
+        self._check(lib().vine_sim_rollout_graph(self.h, int(bool(record_traj)),
+                                                 _stream_ptr(stream)))
 
     def reset(self, stream=None):
         self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))
