@@ -276,6 +276,77 @@ def config5_requests(n_req: int, rate: float = 2000.0, start: int = 0,
     return out
 
 
+# ---------------------------------------------------------------------------
+# robustness and funnelling studies (Sec. 6 of the paper): one design in one
+# environment, rolled out many times under perturbation
+
+
+def study_rng(*keys: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 6, *keys])))
+
+
+def perturbed(work: Workload, i: int, trials: int, sigma_env: float = 0.0,
+              sigma_act: float = 0.0, tag: int = 0) -> Workload:
+    """``trials`` copies of instance ``i`` with Gaussian perturbations (trial t draws
+    from ``study_rng(i, tag, t)``):
+
+    * environment, relative level ``sigma_env``: each obstacle centre moves by
+      N(0, (sigma_env |c - base|)^2) per axis (an error proportional to its range from
+      the base) and each size (radius, half-sides) is scaled by 1 + N(0, sigma_env^2),
+      floored at 10 % of its nominal value; a draw that would meet the first link is
+      redrawn (up to 100 times, else the obstacle keeps its nominal placement);
+    * actuation, relative level ``sigma_act``: each sPAM's pressure and span length are
+      scaled by 1 + N(0, sigma_act^2) (floored at 0 and at one tenth of the span), the
+      start kept, the end clipped to the body.
+
+    Level 0 reproduces the instance exactly."""
+    base = work.instance(i)
+    l, R = float(base["d"][0]), float(base["d"][1])
+    bx, by, psi = (float(v) for v in base["d"][3:6])
+    L_body = base["n"] * l
+    items = []
+    for t in range(trials):
+        rng = study_rng(i, tag, t)
+        obs = base["obs"].copy()
+        for k in range(len(obs)):
+            cx, cy, a, b = base["obs"][k]
+            rng_k = np.hypot(cx - bx, cy - by)
+            for _attempt in range(100):
+                dc = rng.normal(0.0, 1.0, size=2) * sigma_env * rng_k
+                fa, fb = 1.0 + sigma_env * rng.normal(0.0, 1.0, size=2)
+                na = max(a * fa, 0.1 * a)
+                nb = max(b * fb, 0.1 * b) if base["kind"][k] == RECT else 0.0
+                if not _meets_first_link(int(base["kind"][k]), cx + dc[0] - bx, cy + dc[1] - by,
+                                         na, nb, l, R, psi):
+                    obs[k] = (cx + dc[0], cy + dc[1], na, nb)
+                    break
+        spam = base["spam"].copy()
+        for j in range(len(spam)):
+            s0, s1, side, p = base["spam"][j]
+            fp, fs = 1.0 + sigma_act * rng.normal(0.0, 1.0, size=2)
+            span = max((s1 - s0) * fs, 0.1 * (s1 - s0))
+            spam[j] = (s0, min(s0 + span, L_body), side, max(p * fp, 0.0))
+        items.append(dict(n=base["n"], d=base["d"].copy(), spam=spam, kind=base["kind"].copy(),
+                          obs=obs, goal=base["goal"].copy()))
+    return pack(items, f"{work.name}[{i}] perturbed", dict(instance=i, sigma_env=sigma_env,
+                                                          sigma_act=sigma_act, tag=tag))
+
+
+def start_angles(work: Workload, i: int, count: int, spread: float) -> Workload:
+    """``count`` copies of instance ``i`` whose base headings are evenly spaced over
+    [psi - spread/2, psi + spread/2] (psi the instance's own heading)."""
+    base = work.instance(i)
+    psi = float(base["d"][5])
+    heads = psi + spread * (np.arange(count) / max(count - 1, 1) - 0.5)
+    items = []
+    for h in heads:
+        d = base["d"].copy()
+        d[5] = h
+        items.append(dict(n=base["n"], d=d, spam=base["spam"].copy(), kind=base["kind"].copy(),
+                          obs=base["obs"].copy(), goal=base["goal"].copy()))
+    return pack(items, f"{work.name}[{i}] start angles", dict(instance=i, spread=spread))
+
+
 def by_name(name: str, B: int | None = None) -> Workload:
     if name == "cfg1":
         return config1(B or 64)
