@@ -356,9 +356,10 @@ __device__ __forceinline__ bool obs_gap(int kind, double ox, double oy, double o
     if (!(d2 < rr * rr * (1.0 + 1e-12))) return false;
     const double d = sqrt(d2);
     if (d > 0.0) {
-      nx = vx / d;
-      ny = vy / d;
-      kap = 1.0 / d;
+      const double id = 1.0 / d;
+      nx = vx * id;
+      ny = vy * id;
+      kap = id;
     } else {
       nx = 1.0;
       ny = 0.0;
@@ -375,10 +376,10 @@ __device__ __forceinline__ bool obs_gap(int kind, double ox, double oy, double o
     const double ox = fmax(dx, 0.0), oy = fmax(dy, 0.0);
     const double d2 = ox * ox + oy * oy;
     if (!(d2 < R * R * (1.0 + 1e-12))) return false;
-    const double d = sqrt(d2);
-    nx = sx * ox / d;
-    ny = sy * oy / d;
-    if (dx > 0.0 && dy > 0.0) kap = 1.0 / d;
+    const double d = sqrt(d2), id = 1.0 / d;
+    nx = sx * ox * id;
+    ny = sy * oy * id;
+    if (dx > 0.0 && dy > 0.0) kap = id;
     g = d - R;
     return g < 0.0;
   }
@@ -736,9 +737,10 @@ __device__ bool lu_solve_dense(SM& S, int n) {
 // s the disk's distance from the link's proximal joint.  C takes the per-link contact
 // sums that evaluate() leaves in S.ps2, S.aux and S.v, so this must follow the
 // evaluation of the same state.  Returns false when more than kMaxCL links are in
-// contact.
+// contact, and (after the slopes, the contact-link flags in lidx and C, all that the
+// chain sweep needs) when blocks is false.
 template <class SM>
-__device__ bool structured_setup(SM& S, const Ctx& c) {
+__device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
   const int lane = threadIdx.x, n = c.n, nc = S.ncl;
   const unsigned long long lt = (1ull << lane) - 1ull;
   for (int j = lane; j < n; j += kWave) {
@@ -751,7 +753,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
   for (int e = lane; e < nc; e += kWave) S.lidx[S.ci[e]] = 0;
   __syncthreads();
   int L = 0;
-  for (int base = 0; base < n; base += kWave) {
+  for (int base = 0; base < n && blocks; base += kWave) {
     int j = base + lane;
     bool f = j < n && S.lidx[j] == 0;
     unsigned long long m = __ballot(f);
@@ -778,7 +780,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c) {
     cfy = __shfl(sy, 0, kWave);
   }
   __syncthreads();
-  if (L > kMaxCL) return false;
+  if (!blocks || L > kMaxCL) return false;
   // 3x3 blocks, one lane per contact link (contacts visited in list order)
   for (int a = lane; a < L; a += kWave) {
     const int i = S.clink[a];
@@ -1420,7 +1422,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     ++iters;
     bool ok = false;
     double slope = 0.0, mu = P.c_mu * rm;
-    const bool structured = structured_setup(S, c) && !P.seq_solver;
+    const bool structured = structured_setup(S, c, !P.seq_solver);
     for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
     __syncthreads();
     for (int tries = 0; tries < 24; ++tries) {
