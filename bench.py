@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--tick-steps", type=int, default=8, help="serve: growth steps per round")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
-    ap.add_argument("--cpu-robots", type=int, default=160, help="robots in the CPU-oracle sample")
+    ap.add_argument("--cpu-robots", type=int, default=320, help="robots in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="time the captured reset + rollout (vine_sim_rollout_graph)")
