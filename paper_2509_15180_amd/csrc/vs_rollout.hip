@@ -1308,36 +1308,28 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
   }
   __syncthreads();
   if (lane == 0) {
-    // One lane walks the chain.  Each pass loads the next link's inputs while the
-    // current link computes (the index is clamped, so the last load repeats a valid
-    // one), and the pivot test only sets a flag: a failed pivot makes the remaining
-    // values non-finite, which the caller sees, and the loop has no branch.
+    // One lane walks the chain, two links per pass: while one link computes, the
+    // inputs of the link after the next are loading (indices are clamped, so the last
+    // loads repeat valid ones).  The pivot test only sets a flag: a failed pivot makes
+    // the remaining values non-finite, which the caller sees, and the loop has no branch.
     int okf = 1;
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
     double z0 = 0, z1 = 0, z2 = 0;
-    const int kt = n > 0 ? n - 1 : 0;
-    double q00 = s00[kt], q01 = s01[kt], q02 = s02[kt], q11 = s11[kt], q12 = s12[kt];
-    double q22 = s22[kt], qB1 = S.px[kt], qB2 = S.py[kt], qd = S.dq[kt], qr = rhs[kt];
-    int k;
-    for (k = n - 1; k >= 0; --k) {
-      A0 += q00;
-      A1 += q01;
-      A2 += q02;
-      A3 += q11;
-      A4 += q12;
-      A5 += q22;
-      const double B1 = qB1, B2 = qB2, dk = qd + mu, rk = qr;
-      const int kn = k > 0 ? k - 1 : 0;
-      q00 = s00[kn];
-      q01 = s01[kn];
-      q02 = s02[kn];
-      q11 = s11[kn];
-      q12 = s12[kn];
-      q22 = s22[kn];
-      qB1 = S.px[kn];
-      qB2 = S.py[kn];
-      qd = S.dq[kn];
-      qr = rhs[kn];
+    struct In {
+      double s0, s1, s2, s3, s4, s5, B1, B2, d, r;
+    };
+    auto load_in = [&](int k) {
+      k = k > 0 ? k : 0;
+      return In{s00[k], s01[k], s02[k], s11[k], s12[k], s22[k], S.px[k], S.py[k], S.dq[k], rhs[k]};
+    };
+    auto inward = [&](const In& q, int k) {
+      A0 += q.s0;
+      A1 += q.s1;
+      A2 += q.s2;
+      A3 += q.s3;
+      A4 += q.s4;
+      A5 += q.s5;
+      const double B1 = q.B1, B2 = q.B2, dk = q.d + mu;
       const double h0 = fma(A2, B2, fma(A1, B1, A0));
       const double h1 = fma(A4, B2, fma(A3, B1, A1));
       const double h2 = fma(A5, B2, fma(A4, B1, A2));
@@ -1345,42 +1337,55 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       const double D = dk + bh;
       okf &= (int)isfinite(D) & (int)(fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)));
       const double iD = rcp_nr(D);
-      const double u = rk - fma(B2, z2, fma(B1, z1, z0));
-      const double g0 = h0 * iD, g1 = h1 * iD, g2 = h2 * iD, ui = u * iD;
+      const double u = q.r - fma(B2, z2, fma(B1, z1, z0));
+      const double g0 = h0 * iD, g1 = h1 * iD, g2 = h2 * iD, w = u * iD;
       A0 = fma(-h0, g0, A0);
       A1 = fma(-h0, g1, A1);
       A2 = fma(-h0, g2, A2);
       A3 = fma(-h1, g1, A3);
       A4 = fma(-h1, g2, A4);
       A5 = fma(-h2, g2, A5);
-      z0 = fma(h0, ui, z0);
-      z1 = fma(h1, ui, z1);
-      z2 = fma(h2, ui, z2);
-      s00[k] = h0;  // the slots of S_k now hold what the outward pass needs
-      s01[k] = h1;
-      s02[k] = h2;
-      s11[k] = iD;
-      s12[k] = u;
+      z0 = fma(h0, w, z0);
+      z1 = fma(h1, w, z1);
+      z2 = fma(h2, w, z2);
+      s00[k] = g0;  // the slots of S_k now hold what the outward pass needs
+      s01[k] = g1;
+      s02[k] = g2;
+      s11[k] = w;
+    };
+    In qa = load_in(n - 1), qb = load_in(n - 2);
+    int k;
+    for (k = n - 1; k >= 1; k -= 2) {
+      inward(qa, k);
+      qa = load_in(k - 2);
+      inward(qb, k - 1);
+      qb = load_in(k - 3);
     }
+    if (k == 0) inward(qa, 0);
+    // outward: d_k = w_k - g_k . V_{k-1}, V_k = V_{k-1} + B_k d_k
+    struct Out {
+      double g0, g1, g2, w, B1, B2;
+    };
+    auto load_out = [&](int k) {
+      k = k < n ? k : 0;
+      return Out{s00[k], s01[k], s02[k], s11[k], S.px[k], S.py[k]};
+    };
     double V0 = 0, V1 = 0, V2 = 0;
-    double p0 = s00[0], p1 = s01[0], p2 = s02[0], pi = s11[0], pu = s12[0];
-    double pB1 = S.px[0], pB2 = S.py[0];
-    for (k = 0; k < n; ++k) {
-      const double h0 = p0, h1 = p1, h2 = p2, iD = pi, u = pu, B1 = pB1, B2 = pB2;
-      const int kn = k + 1 < n ? k + 1 : k;
-      p0 = s00[kn];
-      p1 = s01[kn];
-      p2 = s02[kn];
-      pi = s11[kn];
-      pu = s12[kn];
-      pB1 = S.px[kn];
-      pB2 = S.py[kn];
-      const double x = (u - fma(h2, V2, fma(h1, V1, h0 * V0))) * iD;
+    auto outward = [&](const Out& o, int k) {
+      const double x = o.w - fma(o.g2, V2, fma(o.g1, V1, o.g0 * V0));
       V0 += x;
-      V1 = fma(B1, x, V1);
-      V2 = fma(B2, x, V2);
+      V1 = fma(o.B1, x, V1);
+      V2 = fma(o.B2, x, V2);
       S.d[k] = x;
+    };
+    Out oa = load_out(0), ob = load_out(1);
+    for (k = 0; k + 1 < n; k += 2) {
+      outward(oa, k);
+      oa = load_out(k + 2);
+      outward(ob, k + 1);
+      ob = load_out(k + 3);
     }
+    if (k < n) outward(oa, k);
     S.ps2[0] = okf ? 1.0 : 0.0;
   }
   __syncthreads();
