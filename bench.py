@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="time the captured reset + rollout (vine_sim_rollout_graph)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the create-time launch order (no vine_sim_tune_order after the warm-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): robots are "
@@ -144,6 +146,9 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    tuned = bool(args.warmup > 0 and not args.no_tune)
+    if tuned:  # launch order from the cycles the warm-up rollout measured per robot
+        sim.tune_order(stream=stream)
     ev0, ev1 = _events(torch)
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -229,6 +234,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "robots": B, "links_max": int(n.max()), "graph": bool(args.graph),
+                   "schedule": "measured by the warm-up rollout" if tuned else "create-time estimate",
                    "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,

@@ -134,7 +134,9 @@ typedef enum vine_field {
   VINE_F_TRAJ = 9,     /* double [B][T][N] joint angles after each step (when recorded) */
   VINE_F_JEVALS = 10,  /* double [B]       work counter: sum over residual evaluations of the
                           link count (since create or the last reset) */
-  VINE_F_NSOLVES = 11  /* double [B]       work counter: linear solves of the Newton system */
+  VINE_F_NSOLVES = 11, /* double [B]       work counter: linear solves of the Newton system */
+  VINE_F_CYCLES = 12   /* double [B]       shader-clock cycles each robot's wave spent in rollout
+                          launches since the reset (what vine_sim_tune_order sorts by) */
 } vine_field;
 
 typedef struct vine_sim vine_sim;
@@ -164,6 +166,16 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
 /* Grow every robot to its target length in one launch (n_steps = -1) or by
  * n_steps steps.  Same semantics as vine_sim_step. */
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
+
+/* Launch-order autotuning.  A batched launch lasts as long as its last robot, and the
+ * robots of a chain-length class start in the handle's launch order as compute units
+ * free up, so a long robot that starts late lengthens the launch.  At create the order
+ * is a work estimate (links^2 x (4 + obstacles), longest first); this call replaces it,
+ * inside each class, by the cycles each robot measured in the rollouts since the last
+ * reset (VINE_F_CYCLES), longest first, for the launches that follow (repeated rollouts
+ * of the same batch, as in a design search).  Robots never interact, so results do not
+ * depend on the order.  Synchronises the stream.  Errors: VINE_EINVAL, VINE_EDEVICE. */
+int32_t vine_sim_tune_order(vine_sim* h, void* stream);
 
 /* vine_sim_reset followed by vine_sim_rollout(h, -1, record_traj, stream) (every robot
  * regrown from zero length to its target, Sec. 4 growth steps), as one HIP graph: the

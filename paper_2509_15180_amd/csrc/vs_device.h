@@ -86,6 +86,7 @@ struct KData {
   // work counters per robot (accumulated over calls)
   double* jevals;     // [B] sum over residual/energy evaluations of the link count
   double* nsolves;    // [B] dense (H + mu I) solves
+  double* cycles;     // [B] shader-clock cycles spent in rollout launches since the reset
   // solver trace of one robot (diagnostics): rows of kTraceCols doubles
   int trace_robot;    // -1: off
   int trace_cap;      // rows

@@ -344,10 +344,12 @@ struct vine_sim {
   double* traj = nullptr;
   double* jevals = nullptr;
   double* nsolves = nullptr;
+  double* cycles = nullptr;
   // robots grouped by chain-length class (64/128/256/512 links), longest expected work
   // first within a class; each class runs as its own launch on its own stream
   static constexpr int kClasses = 4;
   int* order = nullptr;
+  std::vector<int> order_h;  // host copy of the launch order
   int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
@@ -387,7 +389,7 @@ void free_all(vine_sim* h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   void* ptrs[] = {h->order, h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
-                  h->maxpen, h->traj, h->jevals, h->nsolves, h->trace, h->trace_n};
+                  h->maxpen, h->traj, h->jevals, h->nsolves, h->cycles, h->trace, h->trace_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -440,6 +442,7 @@ vs::KData kdata(vine_sim* h) {
   D.traj = h->traj;
   D.jevals = h->jevals;
   D.nsolves = h->nsolves;
+  D.cycles = h->cycles;
   D.trace_robot = h->trace ? h->trace_robot : -1;
   D.order = h->order;
   D.launch_first = 0;
@@ -650,6 +653,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->maxpen, B * TT));
   A(dalloc(&h->jevals, B));
   A(dalloc(&h->nsolves, B));
+  A(dalloc(&h->cycles, B));
   if (e != hipSuccess) {
     free_all(h);
     delete h;
@@ -657,6 +661,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
                 std::string("device allocation: ") + hipGetErrorString(e));
   }
   A(hipMemcpy(h->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  h->order_h = order;
   A(hipMemcpy(h->ii, ii.data(), sizeof(int) * ii.size(), hipMemcpyHostToDevice));
   A(hipMemcpy(h->dd, dd.data(), sizeof(double) * dd.size(), hipMemcpyHostToDevice));
   if (!cover.empty())
@@ -743,6 +748,26 @@ int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* s
 
 int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
   return advance(h, n_steps < 0 ? -1 : n_steps, record_traj, stream);
+}
+
+int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> cyc(h->B);
+  hipError_t e = hipMemcpyAsync(cyc.data(), h->cycles, sizeof(double) * h->B,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("read cycles: ") + hipGetErrorString(e));
+  for (int c = 0; c < vine_sim::kClasses; ++c) {
+    auto first = h->order_h.begin() + h->cls_first[c];
+    std::stable_sort(first, first + h->cls_count[c],
+                     [&](int a, int b) { return cyc[a] > cyc[b]; });
+  }
+  e = hipMemcpyAsync(h->order, h->order_h.data(), sizeof(int) * h->order_h.size(),
+                     hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("write order: ") + hipGetErrorString(e));
+  return VINE_OK;
 }
 
 int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream) {
@@ -851,6 +876,7 @@ int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {
     case VINE_F_TRAJ: return 8 * B * T * N;
     case VINE_F_JEVALS: return 8 * B;
     case VINE_F_NSOLVES: return 8 * B;
+    case VINE_F_CYCLES: return 8 * B;
     default: return 0;
   }
 }
@@ -876,6 +902,7 @@ int32_t vine_sim_read(const vine_sim* hc, int32_t field, void* dst, int32_t dst_
       break;
     case VINE_F_JEVALS: src = h->jevals; break;
     case VINE_F_NSOLVES: src = h->nsolves; break;
+    case VINE_F_CYCLES: src = h->cycles; break;
     default: return fail(h, VINE_EINVAL, "unknown field");
   }
   size_t bytes = (size_t)vine_sim_field_bytes(h, field);

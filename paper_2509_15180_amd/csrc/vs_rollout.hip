@@ -1529,6 +1529,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
   }
+  const long long t_begin = clock64();  // this robot's time in the launch (for scheduling)
   int n = D.ncur[b];
   int t = D.tcur[b];
   if (lane == 0) {
@@ -1604,6 +1605,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     D.tcur[b] = t;
     D.jevals[b] += S.jevals;
     D.nsolves[b] += S.nsolves;
+    D.cycles[b] += (double)(clock64() - t_begin);
   }
 }
 
@@ -1774,6 +1776,7 @@ __global__ void reset_kernel(KData D) {
     D.tcur[i] = 0;
     D.jevals[i] = 0.0;
     D.nsolves[i] = 0.0;
+    D.cycles[i] = 0.0;
   }
 }
 
@@ -1799,6 +1802,7 @@ __global__ void slot_reset_kernel(KData D, const int* slots, int count) {
     D.tcur[b] = 0;
     D.jevals[b] = 0.0;
     D.nsolves[b] = 0.0;
+    D.cycles[b] = 0.0;
   }
 }
 

@@ -27,7 +27,7 @@ FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np
               rho=(3, np.float64, "BT"), iters=(4, np.int32, "BT"), status=(5, np.int32, "BT"),
               ncont=(6, np.int32, "BT"), chash=(7, np.uint64, "BT"), maxpen=(8, np.float64, "BT"),
               traj=(9, np.float64, "BTN"), jevals=(10, np.float64, "B"),
-              nsolves=(11, np.float64, "B"))
+              nsolves=(11, np.float64, "B"), cycles=(12, np.float64, "B"))
 
 MAX_LINKS = 512
 MAX_OBSTACLES = 128
@@ -67,7 +67,7 @@ class Obstacle(C.Structure):
 
 
 EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_rollout",
-           "vine_sim_rollout_graph",
+           "vine_sim_rollout_graph", "vine_sim_tune_order",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_set_spams", "vine_server_create",
@@ -98,6 +98,8 @@ def lib():
         L.vine_sim_rollout.restype = C.c_int32
         L.vine_sim_rollout_graph.argtypes = [vp, C.c_int32, vp]
         L.vine_sim_rollout_graph.restype = C.c_int32
+        L.vine_sim_tune_order.argtypes = [vp, vp]
+        L.vine_sim_tune_order.restype = C.c_int32
         L.vine_sim_reset.argtypes = [vp, vp]
         L.vine_sim_reset.restype = C.c_int32
         L.vine_sim_read.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
@@ -216,6 +218,10 @@ class VineSim:
         (captured on the first call for each record_traj, replayed afterwards)."""
         self._check(lib().vine_sim_rollout_graph(self.h, int(bool(record_traj)),
                                                  _stream_ptr(stream)))
+
+    def tune_order(self, stream=None):
+        """Launch order by the cycles each robot measured since the last reset (longest first)."""
+        self._check(lib().vine_sim_tune_order(self.h, _stream_ptr(stream)))
 
     def reset(self, stream=None):
         self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))

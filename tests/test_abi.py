@@ -81,6 +81,7 @@ def test_null_handle_calls_fail_cleanly():
     assert L.vine_sim_grad(None, None, None, None, None, None, None, None, None) == V.VINE_EINVAL
     assert L.vine_sim_reset(None, None) == V.VINE_EINVAL
     assert L.vine_sim_rollout_graph(None, 0, None) == V.VINE_EINVAL
+    assert L.vine_sim_tune_order(None, None) == V.VINE_EINVAL
 
 
 def test_server_rejects_bad_sizes_before_the_device():

@@ -32,7 +32,8 @@ def _replays_match(work, record):
             assert float(total) == float(1 << 20)
             got = sim.read_all(traj=record)
             for k in ref:
-                assert np.array_equal(got[k], ref[k]), (rep, k)
+                if k != "cycles":  # timing, not a result
+                    assert np.array_equal(got[k], ref[k]), (rep, k)
 
 
 def test_graph_replays_one_class():
