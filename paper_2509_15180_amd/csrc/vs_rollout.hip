@@ -99,6 +99,24 @@ __device__ __forceinline__ double dpp_or(double v, double idv) {
   return __hiloint2double(hi, lo);
 }
 
+// Minimum and maximum over each 16-lane row (lanes 16r + 15 hold row r's result; lanes
+// outside the chain pass +/-1e300, which never wins)
+__device__ __forceinline__ double row_min(double v) {
+  v = fmin(v, dpp_or<0x111>(v, 1e300));  // row_shr:1
+  v = fmin(v, dpp_or<0x112>(v, 1e300));  // row_shr:2
+  v = fmin(v, dpp_or<0x114>(v, 1e300));  // row_shr:4
+  v = fmin(v, dpp_or<0x118>(v, 1e300));  // row_shr:8
+  return v;
+}
+
+__device__ __forceinline__ double row_max(double v) {
+  v = fmax(v, dpp_or<0x111>(v, -1e300));
+  v = fmax(v, dpp_or<0x112>(v, -1e300));
+  v = fmax(v, dpp_or<0x114>(v, -1e300));
+  v = fmax(v, dpp_or<0x118>(v, -1e300));
+  return v;
+}
+
 // Scans of affine maps y -> A y + B over the 64 lanes.  compose(later, earlier) =
 // (A_l A_e, A_l B_e + B_l); identity (1, 0).
 __device__ __forceinline__ void aff_compose(double& A, double& B, double Ae, double Be) {
@@ -550,28 +568,79 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     // this link's contact sums, in the order the contacts are listed: moment and force
     // (residual), and the force's moment along the link (geometric stiffness)
     double a_s1 = 0.0, a_fx = 0.0, a_fy = 0.0, a_q = 0.0;
-    for (int k0 = 0; k0 < c.K; k0 += 4) {
+    // Broad phase: the bounding box of each 16-lane row's disk centres, and per obstacle
+    // whether its box widened by the tube radius (and a relative 1e-9) meets any row's
+    // box.  An obstacle that meets none fails the pair pre-test for every disk of the
+    // chunk, so the rounds below visit only the others, in index order (the contact list
+    // keeps the order of a full sweep).
+    unsigned long long cand0 = 0ull, cand1 = 0ull;
+    {
+      const double bx0 = row_min(on ? fmin(xs[0], xs[1]) : 1e300);
+      const double bx1 = row_max(on ? fmax(xs[0], xs[1]) : -1e300);
+      const double by0 = row_min(on ? fmin(ys[0], ys[1]) : 1e300);
+      const double by1 = row_max(on ? fmax(ys[0], ys[1]) : -1e300);
+      double rx0[4], rx1[4], ry0[4], ry1[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        rx0[r] = lane_bcast(bx0, 16 * r + 15);
+        rx1[r] = lane_bcast(bx1, 16 * r + 15);
+        ry0[r] = lane_bcast(by0, 16 * r + 15);
+        ry1[r] = lane_bcast(by1, 16 * r + 15);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = lane + kWave * q;
+        bool meets = false;
+        if (k < c.K) {
+          const double cx = S.res.ox[k], cy = S.res.oy[k], oa = S.res.oa[k];
+          const double ob = S.res.okind[k] == 0 ? oa : S.res.ob[k];
+          const double ex = (oa + c.R) * (1.0 + 1e-9), ey = (ob + c.R) * (1.0 + 1e-9);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            meets = meets || ((cx + ex >= rx0[r]) && (cx - ex <= rx1[r]) &&
+                              (cy + ey >= ry0[r]) && (cy - ey <= ry1[r]));
+        }
+        const unsigned long long m = __ballot(meets);
+        if (q == 0) cand0 = m; else cand1 = m;
+      }
+    }
+    while (cand0 | cand1) {
+      // the next four candidates (repeating the last one when fewer are left)
+      int ks[4], nk = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (cand0) {
+          ks[u] = __builtin_ctzll(cand0);
+          cand0 &= cand0 - 1ull;
+          ++nk;
+        } else if (cand1) {
+          ks[u] = kWave + __builtin_ctzll(cand1);
+          cand1 &= cand1 - 1ull;
+          ++nk;
+        } else {
+          ks[u] = ks[u > 0 ? u - 1 : 0];
+        }
+      }
       // four obstacles per round, read from LDS at addresses the whole wave shares
-      // (broadcast reads); the index is clamped so that the reads issue together
+      // (broadcast reads), issued together
       double ox[4], oy[4], oa[4], ob[4];
       int kd[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int k = k0 + u < c.K ? k0 + u : c.K - 1;
+        const int k = ks[u];
         ox[u] = S.res.ox[k];
         oy[u] = S.res.oy[k];
         oa[u] = S.res.oa[k];
         ob[u] = S.res.ob[k];
         kd[u] = S.res.okind[k];
       }
-      unsigned near = 0u;  // bit 2u + hh: disk hh may touch obstacle k0 + u
+      unsigned near = 0u;  // bit 2u + hh: disk hh may touch obstacle ks[u]
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
           near |= (unsigned)obs_near(kd[u], ox[u], oy[u], oa[u], ob[u], c.R, xs[hh], ys[hh])
                   << (2 * u + hh);
-      const int nk = c.K - k0 < 4 ? c.K - k0 : 4;
       near &= on ? (1u << (2 * nk)) - 1u : 0u;
       if (__ballot(near != 0u) == 0ull) continue;
 #pragma unroll
@@ -589,7 +658,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
             if (hit && pos < kMaxC) {
               const double pen = -g, lam = c.P.kc * pen;
               S.ci[pos] = j;
-              S.ck[pos] = k0 + u;
+              S.ck[pos] = ks[u];
               S.cl[pos] = lam;
               S.cxx[pos] = xs[hh];
               S.cxy[pos] = ys[hh];
