@@ -1,7 +1,6 @@
 /*
  * vinesim.h -- C ABI of the MI355X (gfx950) vine-robot simulator: the batched
- * quasi-static growth step of a soft growing robot, arXiv 2509.15180
- * ("Parallel Simulation of Contact and Actuation for Soft Growing Robots").
+ * quasi-static growth step of a soft growing robot (arXiv 2509.15180).
  *
  * Model (paper section / equation):
  *   - a robot is a chain of rigid links of length l in minimal coordinates, the

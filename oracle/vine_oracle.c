@@ -1,7 +1,6 @@
 /*
  * vine_oracle.c -- plain FP64 CPU oracle for the quasi-static growth step of a
- * soft growing ("vine") robot, arXiv 2509.15180 ("Parallel Simulation of Contact
- * and Actuation for Soft Growing Robots").
+ * soft growing ("vine") robot (arXiv 2509.15180).
  *
  * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
  * of the benchmark load this library.  It shares no code, header, table or
