@@ -20,6 +20,8 @@
 //       cap |d|_inf; Armijo backtracking on the energy.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "vs_device.h"
 
 namespace vs {
@@ -429,27 +431,38 @@ __device__ __forceinline__ bool obs_near(int kind, double ox, double oy, double 
 constexpr int kMaxCL = 16;             // contact links the structured solve holds
 constexpr int kMaxCols = 3 * kMaxCL;   // columns of its low-rank term
 
-template <int NMAX, int WN_ = 1>
+// FULL_ = false is the layout of the chain-sweep launches of long chains: no space for
+// the structured and dense solves, the law tables read from global memory, and the
+// trial angles of the line search kept in b (free once the step is solved).  That
+// cuts the 256-link robot from 71 to 53 KB, three robots per compute unit instead of
+// two, and the 128-link robot to 33 KB, four instead of three.
+template <int NMAX, int WN_ = 1, bool FULL_ = true>
 struct Smem {
   static constexpr int WN = WN_;  // order of the dense cross-check system (64, else unused)
+  static constexpr bool kFull = FULL_;
+  static constexpr int NS = FULL_ ? kMaxCL : 1, NSC = FULL_ ? kMaxCols : 1;
+  struct ResObs {
+    double ox[kMaxObs], oy[kMaxObs], oa[kMaxObs], ob[kMaxObs];
+    int okind[kMaxObs];
+  };
+  struct ResFull : ResObs {
+    SpamLds sp;
+    WrLds wr;
+  };
   union {
     double W[WN][WN + 1];                           // (H + mu I | -r), LU in place
     struct {
-      double G[kMaxCols][kMaxCols + 1];  // U^T T^-1 U, then (I + S G | S c) and its LU in place
+      double G[NSC][kMaxCols + 1];  // U^T T^-1 U, then (I + S G | S c) and its LU in place
     } sm;
-    double F[kWave][17];  // one chunk of forward-substituted columns (Gram by MFMA; padded)
-    struct {
-      double ox[kMaxObs], oy[kMaxObs], oa[kMaxObs], ob[kMaxObs];
-      int okind[kMaxObs];
-      SpamLds sp;
-      WrLds wr;
-    } res;  // the robot's obstacles and law tables while no solve holds this space
+    double F[FULL_ ? kWave : 1][17];  // one chunk of forward-substituted columns (Gram by MFMA)
+    std::conditional_t<FULL_, ResFull, ResObs> res;  // the robot's obstacles (and law tables)
+                                                     // while no solve holds this space
   };
   int res_ok;  // res holds this robot's data
-  double th[NMAX], tt[NMAX], d[NMAX], r[NMAX];
+  double th[NMAX], tt[FULL_ ? NMAX : 1], d[NMAX], r[NMAX];
   double px[NMAX + 1], py[NMAX + 1], tx[NMAX], ty[NMAX];
   double pp[NMAX], pm[NMAX];
-  // structured solve
+  // Newton set-up and solves
   double dq[NMAX];     // joint stiffness q'_j
   double cg[NMAX];     // geometric stiffness, diagonal in absolute angles
   double dinv[NMAX];   // 1 / pivots of the tridiagonal part
@@ -457,10 +470,10 @@ struct Smem {
   double z[NMAX], v[NMAX], aux[NMAX], b[NMAX];
   double ps1[NMAX], ps2[NMAX];
   int lidx[NMAX];      // link -> contact-link slot (or -1)
-  int clink[kMaxCL];   // contact-link slot -> link
-  double cM[kMaxCL][6];  // 3x3 contact block per contact link (symmetric: 00 01 02 11 12 22)
-  double cvec[kMaxCols], wvec[kMaxCols];
-  double gcarry[16];   // forward-substitution carries between row chunks (Gram pass)
+  int clink[NS];       // contact-link slot -> link
+  double cM[NS][6];    // 3x3 contact block per contact link (symmetric: 00 01 02 11 12 22)
+  double cvec[NSC], wvec[NSC];
+  double gcarry[FULL_ ? 16 : 1];  // forward-substitution carries between row chunks (Gram pass)
   int ncl_links;
   int ci[kMaxC], ck[kMaxC];
   double cl[kMaxC], cxx[kMaxC], cxy[kMaxC], cnx[kMaxC], cny[kMaxC], ckap[kMaxC], cpen[kMaxC];
@@ -475,7 +488,6 @@ struct Smem {
 template <class SM>
 __device__ void stage_resident(SM& S, const Ctx& c) {
   const int lane = threadIdx.x;
-  static_assert(sizeof(S.res) <= sizeof(S.sm), "resident data must fit the solve space");
   for (int k = lane; k < c.K; k += kWave) {
     S.res.ox[k] = c.obs[4 * (size_t)k];
     S.res.oy[k] = c.obs[4 * (size_t)k + 1];
@@ -483,6 +495,8 @@ __device__ void stage_resident(SM& S, const Ctx& c) {
     S.res.ob[k] = c.obs[4 * (size_t)k + 3];
     S.res.okind[k] = c.okind[k];
   }
+  if constexpr (SM::kFull) {
+  static_assert(sizeof(S.res) <= sizeof(S.sm), "resident data must fit the solve space");
   const SpamTable& T = *c.tab;
   for (int i = lane; i < kSpamPieces * (kSpamDeg + 1); i += kWave)
     (&S.res.sp.c[0][0])[i] = (&T.c[0][0])[i];
@@ -503,8 +517,9 @@ __device__ void stage_resident(SM& S, const Ctx& c) {
     S.res.wr.du = W.du;
     S.res.wr.h_pi = W.h_pi;
     S.res.wr.ih_pi = W.ih_pi;
-    S.res_ok = 1;
   }
+  }
+  if (lane == 0) S.res_ok = 1;
   __syncthreads();
 }
 
@@ -543,7 +558,10 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   double Esum = 0.0;
   for (int j = lane; j < n; j += kWave) {
     double q, E = 0.0;
-    joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    if constexpr (SM::kFull)
+      joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    else
+      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
     S.r[j] = q;
     Esum += E;
   }
@@ -822,7 +840,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
   for (int e = lane; e < nc; e += kWave) S.lidx[S.ci[e]] = 0;
   __syncthreads();
   int L = 0;
-  for (int base = 0; base < n && blocks; base += kWave) {
+  for (int base = 0; base < n && blocks && SM::kFull; base += kWave) {
     int j = base + lane;
     bool f = j < n && S.lidx[j] == 0;
     unsigned long long m = __ballot(f);
@@ -849,7 +867,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
     cfy = __shfl(sy, 0, kWave);
   }
   __syncthreads();
-  if (!blocks || L > kMaxCL) return false;
+  if (!SM::kFull || !blocks || L > kMaxCL) return false;
   // 3x3 blocks, one lane per contact link (contacts visited in list order)
   for (int a = lane; a < L; a += kWave) {
     const int i = S.clink[a];
@@ -1496,18 +1514,20 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     ++iters;
     bool ok = false;
     double slope = 0.0, mu = P.c_mu * rm;
-    const bool structured = structured_setup(S, c, !P.seq_solver);
+    const bool structured = structured_setup(S, c, SM::kFull && !P.seq_solver);
     for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
     __syncthreads();
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
       if (lane == 0) S.nsolves += 1.0;
-      if (DENSE) {
+      if constexpr (DENSE) {
         assemble(S, c, S.th, mu, S.b);
         if (!lu_solve_dense(S, n)) continue;
-      } else if (structured ? !structured_solve(S, c, mu, S.b)
-                            : !chain_solve_seq(S, c, mu, S.b)) {
-        continue;
+      } else if constexpr (SM::kFull) {
+        if (structured ? !structured_solve(S, c, mu, S.b) : !chain_solve_seq(S, c, mu, S.b))
+          continue;
+      } else {
+        if (!chain_solve_seq(S, c, mu, S.b)) continue;
       }
       double s = 0.0;
       for (int j = lane; j < n; j += kWave) s += S.r[j] * S.d[j];
@@ -1531,12 +1551,13 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     }
     __syncthreads();
     const bool skip = -slope < 1e-12 * c.Mmax;
+    double* tt = SM::kFull ? S.tt : S.b;  // trial angles (b is free once the step is solved)
     double alpha = 1.0, Pn = 0.0;
     bool acc = false;
     for (int ls = 0; ls < 40; ++ls) {
-      for (int j = lane; j < n; j += kWave) S.tt[j] = S.th[j] + alpha * S.d[j];
+      for (int j = lane; j < n; j += kWave) tt[j] = S.th[j] + alpha * S.d[j];
       __syncthreads();
-      Pn = evaluate(S, c, S.tt, true);
+      Pn = evaluate(S, c, tt, true);
       if (skip || Pn <= Pi + P.c1 * alpha * slope) {
         acc = true;
         break;
@@ -1556,7 +1577,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
         c.trace_n[0] = row + 1;
       }
     }
-    for (int j = lane; j < n; j += kWave) S.th[j] = S.tt[j];
+    for (int j = lane; j < n; j += kWave) S.th[j] = tt[j];
     Pi = Pn;
     __syncthreads();
   }
@@ -1566,10 +1587,10 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
 
 // ---------------------------------------------------------------------------
 
-template <int NMAX, bool DENSE>
+template <int NMAX, bool DENSE, bool FULL = true>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(KParams P, KData D, int n_steps,
                                                         int record_traj) {
-  __shared__ Smem<NMAX, DENSE ? 64 : 1> S;
+  __shared__ Smem<NMAX, DENSE ? 64 : 1, FULL> S;
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x];
   const int lane = threadIdx.x;
@@ -1619,7 +1640,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         c.last_len = c.l * (double)s / (double)P.substeps;
         c.step = t;
         c.sub = s;
-        int st = solve<Smem<NMAX, DENSE ? 64 : 1>, DENSE>(S, c, its, rho);
+        int st = solve<Smem<NMAX, DENSE ? 64 : 1, FULL>, DENSE>(S, c, its, rho);
         st_worst = st > st_worst ? st : st_worst;
       }
     } else {
@@ -1898,18 +1919,30 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int rec
     if (nmax_class != 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((rollout_kernel<64, true>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class == 64) {
+  } else if (nmax_class == 64) {  // the full layout still fits four robots per CU
     hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
   } else if (nmax_class == 128) {
-    hipLaunchKernelGGL((rollout_kernel<128, false>), grid, block, 0, stream, P, D, n_steps,
-                       record_traj);
+    if (P.seq_solver)
+      hipLaunchKernelGGL((rollout_kernel<128, false, false>), grid, block, 0, stream, P, D,
+                         n_steps, record_traj);
+    else
+      hipLaunchKernelGGL((rollout_kernel<128, false>), grid, block, 0, stream, P, D, n_steps,
+                         record_traj);
   } else if (nmax_class == 256) {
-    hipLaunchKernelGGL((rollout_kernel<256, false>), grid, block, 0, stream, P, D, n_steps,
-                       record_traj);
+    if (P.seq_solver)
+      hipLaunchKernelGGL((rollout_kernel<256, false, false>), grid, block, 0, stream, P, D,
+                         n_steps, record_traj);
+    else
+      hipLaunchKernelGGL((rollout_kernel<256, false>), grid, block, 0, stream, P, D, n_steps,
+                         record_traj);
   } else if (nmax_class == 512) {
-    hipLaunchKernelGGL((rollout_kernel<512, false>), grid, block, 0, stream, P, D, n_steps,
-                       record_traj);
+    if (P.seq_solver)
+      hipLaunchKernelGGL((rollout_kernel<512, false, false>), grid, block, 0, stream, P, D,
+                         n_steps, record_traj);
+    else
+      hipLaunchKernelGGL((rollout_kernel<512, false>), grid, block, 0, stream, P, D, n_steps,
+                         record_traj);
   } else {
     return hipErrorInvalidValue;
   }
