@@ -1397,9 +1397,8 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
   if (lane == 0) {
     // One lane walks the chain, two links per pass: while one link computes, the
     // inputs of the link after the next are loading (indices are clamped, so the last
-    // loads repeat valid ones).  The pivot test only sets a flag: a failed pivot makes
-    // the remaining values non-finite, which the caller sees, and the loop has no branch.
-    int okf = 1;
+    // loads repeat valid ones).  Each link's B^T A B is stored, and all lanes test the
+    // pivots after the walk (a failed pivot makes the remaining values non-finite).
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
     double z0 = 0, z1 = 0, z2 = 0;
     struct In {
@@ -1422,7 +1421,6 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       const double h2 = fma(A5, B2, fma(A4, B1, A2));
       const double bh = fma(B2, h2, fma(B1, h1, h0));
       const double D = dk + bh;
-      okf &= (int)isfinite(D) & (int)(fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)));
       const double iD = rcp_nr(D);
       const double u = q.r - fma(B2, z2, fma(B1, z1, z0));
       const double g0 = h0 * iD, g1 = h1 * iD, g2 = h2 * iD, w = u * iD;
@@ -1439,6 +1437,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       s01[k] = g1;
       s02[k] = g2;
       s11[k] = w;
+      s12[k] = bh;
     };
     In qa = load_in(n - 1), qb = load_in(n - 2);
     int k;
@@ -1473,12 +1472,14 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
       ob = load_out(k + 3);
     }
     if (k < n) outward(oa, k);
-    S.ps2[0] = okf ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (S.ps2[0] == 0.0) return false;
+  // the pivots D = (q' + mu) + B^T A B, rounded as in the walk
   bool fin = true;
-  for (int j = lane; j < n; j += kWave) fin = fin && isfinite(S.d[j]);
+  for (int j = lane; j < n; j += kWave) {
+    const double dk = S.dq[j] + mu, bh = s12[j], D = dk + bh;
+    fin = fin && isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh)) && isfinite(S.d[j]);
+  }
   return __all(fin);
 }
 
