@@ -1920,9 +1920,13 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int rec
     if (nmax_class != 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((rollout_kernel<64, true>), grid, block, 0, stream, P, D, n_steps,
                        record_traj);
-  } else if (nmax_class == 64) {  // the full layout still fits four robots per CU
-    hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
-                       record_traj);
+  } else if (nmax_class == 64) {
+    if (P.seq_solver)
+      hipLaunchKernelGGL((rollout_kernel<64, false, false>), grid, block, 0, stream, P, D,
+                         n_steps, record_traj);
+    else
+      hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
+                         record_traj);
   } else if (nmax_class == 128) {
     if (P.seq_solver)
       hipLaunchKernelGGL((rollout_kernel<128, false, false>), grid, block, 0, stream, P, D,
