@@ -257,6 +257,21 @@ double wr_h_host(double x, double epsc) {
          (4.0 * (std::sin(gm) + (kPi - gm) * std::cos(gm)));
 }
 
+// the same law in long double: near pi the numerator and denominator of Eq. 2a both
+// cancel, which costs the double formula ~1e-13; the h series is fitted to these values
+double wr_h_host_ld(double x, double epsc) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double th_on = 2.0L * asinl((long double)epsc);
+  long double xl = x;
+  if (xl <= th_on) return (double)(xl / (2.0L * th_on));
+  if (xl > pi) xl = pi;
+  long double c = 2.0L * epsc / sinl(0.5L * xl) - 1.0L;
+  c = c > 1.0L ? 1.0L : (c < -1.0L ? -1.0L : c);
+  const long double gm = acosl(c);
+  return (double)((sinl(2.0L * gm) + 2.0L * pi - 2.0L * gm) /
+                  (4.0L * (sinl(gm) + (pi - gm) * cosl(gm))));
+}
+
 void build_wr_table(WrTable* T, double epsc) {
   std::memset(T, 0, sizeof(*T));
   constexpr int P = vs::kIhPieces, D = vs::kIhDeg;
@@ -264,15 +279,17 @@ void build_wr_table(WrTable* T, double epsc) {
   T->umax = std::sqrt(kPi - T->th_on);
   T->du = T->umax / P;
   T->cum[0] = T->th_on / 4.0;
-  std::vector<double> f(D + 1);
+  std::vector<double> f(D + 1), hv(D + 1);
   double c[D + 1], av[D + 3];
   for (int k = 0; k < P; ++k) {
     const double a = k * T->du, b = a + T->du;
     for (int q = 0; q <= D; ++q) {
       const double t = std::cos(kPi * (q + 0.5) / (D + 1));
       const double u = 0.5 * (a + b) + 0.5 * (b - a) * t;
+      hv[q] = wr_h_host_ld(T->th_on + u * u, epsc);
       f[q] = 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
     }
+    cheb_coeffs(hv, D, T->hc[k]);
     cheb_coeffs(f, D, c);
     for (int j = 0; j <= D + 2; ++j) av[j] = j <= D ? c[j] : 0.0;
     av[0] *= 2.0;

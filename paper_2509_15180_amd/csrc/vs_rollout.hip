@@ -219,23 +219,13 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
 // ---------------------------------------------------------------------------
 // model laws
 
-// fraction of pi P R^3 carried by the wrinkled body at bend |x| (Eq. 2a-b); linear
-// below the onset theta_on = 2 asin(eps_c); clamped beyond pi.  With s = sin(x/2),
-// cos(gamma0) = 2 eps_c / s - 1 and sin(gamma0) = sqrt(1 - cos^2), so
-// Eq. 2a needs one acos and one square root.
-__device__ double wr_h(double x, double epsc, double th_on) {
-  if (x <= th_on) return x / (2.0 * th_on);
-  if (x > kPi) x = kPi;
-  const double s = sin(0.5 * x);
-  const double c = fmin(1.0, 2.0 * epsc / s - 1.0);
-  const double sg = sqrt((1.0 - c) * (1.0 + c));  // sin(acos c), rounded as acos is
-  const double g = acos(c);
-  return (2.0 * sg * c + 2.0 * kPi - 2.0 * g) / (4.0 * (sg + (kPi - g) * c));
-}
-
-// d wr_h / dx = 4 eps_c cos(x/2) (N (pi - g) - sin(g) D) / (s^2 D^2) with N, D the
-// numerator and denominator of Eq. 2a (the 1/sin(gamma0) of dgamma0/dx cancels).
-// Slope of the linear branch at the onset itself; 0 from pi on.
+// Slope of the wrinkled body's moment fraction h(x) of Eq. 2a-b (bend x = |theta|;
+// h is linear below the onset theta_on = 2 asin(eps_c) and constant beyond pi).  With
+// s = sin(x/2), cos(g) = 2 eps_c / s - 1 for the wrinkle angle g = gamma0, and N, D the
+// numerator and denominator of Eq. 2a,
+//   dh/dx = 4 eps_c cos(x/2) (N (pi - g) - sin(g) D) / (s^2 D^2)
+// (the 1/sin(gamma0) of dgamma0/dx cancels).  Slope of the linear branch at the onset
+// itself; 0 from pi on.
 __device__ double wr_dh(double x, double epsc, double th_on) {
   if (x <= th_on) return 0.5 / th_on;
   if (x >= kPi) return 0.0;
@@ -276,19 +266,31 @@ struct WrLds {
   double ic[kIhPieces][kIhDeg + 2];
 };
 
-// int_0^x wr_h (energy of the body moment per pi P R^3): above the onset, the exact
-// antiderivative of a piecewise Chebyshev fit of 2 u h(theta_on + u^2) in
-// u = sqrt(x - theta_on), so that its slope in x equals h to the fit's accuracy.
+// The wrinkling moment fraction h (Eq. 2a) and its integral from 0 (the energy of the
+// body moment per pi P R^3).  Below the onset both are exact (h is linear); above it they
+// are piecewise Chebyshev series in u = sqrt(x - theta_on): h itself, and the exact
+// antiderivative of a fit of 2 u h(theta_on + u^2), so that the integral's slope in x
+// equals h to the fits' accuracy.  Beyond pi, h stays at h(pi).
 template <class Tab>
-__device__ double wr_int(double x, const Tab& T) {
-  if (x <= T.th_on) return x * x / (4.0 * T.th_on);
-  if (x >= kPi) return T.ih_pi + T.h_pi * (x - kPi);
+__device__ void wr_law(double x, const Tab& T, const WrTable& Th, bool want_h, bool want_ih,
+                       double& h, double& ih) {
+  if (x <= T.th_on) {
+    h = x / (2.0 * T.th_on);
+    ih = x * x / (4.0 * T.th_on);
+    return;
+  }
+  if (x >= kPi) {
+    h = T.h_pi;
+    ih = T.ih_pi + T.h_pi * (x - kPi);
+    return;
+  }
   const double u = sqrt(x - T.th_on);
   int k = (int)(u / T.du);
   k = k > kIhPieces - 1 ? kIhPieces - 1 : k;
   const double a = k * T.du;
   const double t = 2.0 * (u - a) / T.du - 1.0;
-  return T.cum[k] + 0.5 * T.du * clenshaw(T.ic[k], kIhDeg + 1, t);
+  if (want_h) h = clenshaw(Th.hc[k], kIhDeg, t);
+  if (want_ih) ih = T.cum[k] + 0.5 * T.du * clenshaw(T.ic[k], kIhDeg + 1, t);
 }
 
 // sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral.  A
@@ -345,8 +347,10 @@ __device__ void joint_law(const Ctx& c, const TS& ts, const TW& tw, double th, d
   else if (dq)
     spam_law(ts, 0.0, nullptr, &dG, nullptr);
   const double pstr = th >= 0.0 ? pp : pm;  // stretched side
+  double h = 0.0, ih = 0.0;
+  if (q || E) wr_law(ath, tw, *c.wr, q != nullptr, E != nullptr, h, ih);
   if (q) {
-    const double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * wr_h(ath, epsc, th_on);
+    const double Mb = (th >= 0.0 ? 1.0 : -1.0) * c.Mmax * h;
     *q = th >= 0.0 ? Mb - c.arm * (pp * G - pm * G0) : Mb - c.arm * (pp * G0 - pm * G);
   }
   if (dq) {
@@ -356,7 +360,7 @@ __device__ void joint_law(const Ctx& c, const TS& ts, const TW& tw, double th, d
     *dq = d;
   }
   if (E) {
-    const double Eb = c.Mmax * wr_int(ath, tw);
+    const double Eb = c.Mmax * ih;
     const double Ea = th >= 0.0 ? (-c.l * pp * IG + c.arm * pm * G0 * th)
                                 : (-c.arm * pp * G0 * th - c.l * pm * IG);
     *E = Eb + Ea;
