@@ -435,11 +435,11 @@ __device__ __forceinline__ bool obs_near(int kind, double ox, double oy, double 
 constexpr int kMaxCL = 16;             // contact links the structured solve holds
 constexpr int kMaxCols = 3 * kMaxCL;   // columns of its low-rank term
 
-// FULL_ = false is the layout of the chain-sweep launches of long chains: no space for
-// the structured and dense solves, the law tables read from global memory, and the
-// trial angles of the line search kept in b (free once the step is solved).  That
-// cuts the 256-link robot from 71 to 53 KB, three robots per compute unit instead of
-// two, and the 128-link robot to 33 KB, four instead of three.
+// FULL_ = false is the layout of the chain-sweep launches (every class when the sweep
+// solves the Newton systems): no space for the structured and dense solves, the law
+// tables read from global memory, and the trial angles of the line search kept in b
+// (free once the step is solved).  That cuts the 256-link robot from 71 to 53 KB (three
+// robots per compute unit instead of two) and lets the kernel compile without spills.
 template <int NMAX, int WN_ = 1, bool FULL_ = true>
 struct Smem {
   static constexpr int WN = WN_;  // order of the dense cross-check system (64, else unused)
