@@ -29,8 +29,9 @@ struct SpamTable {
 // The wrinkling moment fraction h (Eq. 2) above the onset and its integral: in
 // u = sqrt(x - theta_on) on [0, sqrt(pi - theta_on)], pieces of equal width du; on piece
 // k the integrand 2 u h(theta_on + u^2) is a Chebyshev series whose antiderivative (zero
-// at the piece's left end, variable t in [-1, 1]) is stored, and h(theta_on + u^2) is a
-// second series (h is analytic in u: the bend angle gamma_0 grows like u at the onset).
+// at the piece's left end, variable t in [-1, 1]) is stored, and h(theta_on + u^2) and
+// its slope dh/dx are two more series.  Both are analytic in u: the bend angle gamma_0
+// grows like u at the onset, and h - h(theta_on) starts at u^2.
 constexpr int kIhPieces = 32;
 constexpr int kIhDeg = 16;
 
@@ -43,6 +44,7 @@ struct WrTable {
   double cum[kIhPieces + 1];          // int_0^{x(u_k)} h at piece boundaries
   double ic[kIhPieces][kIhDeg + 2];   // per piece: antiderivative series in t
   double hc[kIhPieces][kIhDeg + 1];   // per piece: h(th_on + u^2) itself, series in t
+  double dhc[kIhPieces][kIhDeg + 1];  // per piece: dh/dx at th_on + u^2, series in t
 };
 
 // Solver and model constants passed by value to the kernels.

@@ -272,6 +272,21 @@ double wr_h_host_ld(double x, double epsc) {
                   (4.0L * (sinl(gm) + (pi - gm) * cosl(gm))));
 }
 
+// its slope above the onset, in long double.  With s = sin(x/2), cos(g) = 2 eps_c / s - 1
+// for the wrinkle angle g = gamma0, and N, D the numerator and denominator of Eq. 2a,
+//   dh/dx = 4 eps_c cos(x/2) (N (pi - g) - sin(g) D) / (s^2 D^2)
+// (the 1/sin(gamma0) of dgamma0/dx cancels); acos near 1 loses half the digits in double
+double wr_dh_host_ld(double x, double epsc) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double xl = x, s = sinl(0.5L * xl), co = cosl(0.5L * xl);
+  long double c = 2.0L * epsc / s - 1.0L;
+  c = c > 1.0L ? 1.0L : c;
+  const long double g = acosl(c), sg = sqrtl((1.0L - c) * (1.0L + c));
+  const long double N = 2.0L * sg * c + 2.0L * pi - 2.0L * g;
+  const long double D = 4.0L * (sg + (pi - g) * c);
+  return (double)(4.0L * epsc * co * (N * (pi - g) - sg * D) / (s * s * D * D));
+}
+
 void build_wr_table(WrTable* T, double epsc) {
   std::memset(T, 0, sizeof(*T));
   constexpr int P = vs::kIhPieces, D = vs::kIhDeg;
@@ -279,7 +294,7 @@ void build_wr_table(WrTable* T, double epsc) {
   T->umax = std::sqrt(kPi - T->th_on);
   T->du = T->umax / P;
   T->cum[0] = T->th_on / 4.0;
-  std::vector<double> f(D + 1), hv(D + 1);
+  std::vector<double> f(D + 1), hv(D + 1), dv(D + 1);
   double c[D + 1], av[D + 3];
   for (int k = 0; k < P; ++k) {
     const double a = k * T->du, b = a + T->du;
@@ -287,9 +302,11 @@ void build_wr_table(WrTable* T, double epsc) {
       const double t = std::cos(kPi * (q + 0.5) / (D + 1));
       const double u = 0.5 * (a + b) + 0.5 * (b - a) * t;
       hv[q] = wr_h_host_ld(T->th_on + u * u, epsc);
+      dv[q] = wr_dh_host_ld(T->th_on + u * u, epsc);
       f[q] = 2.0 * u * wr_h_host(T->th_on + u * u, epsc);
     }
     cheb_coeffs(hv, D, T->hc[k]);
+    cheb_coeffs(dv, D, T->dhc[k]);
     cheb_coeffs(f, D, c);
     for (int j = 0; j <= D + 2; ++j) av[j] = j <= D ? c[j] : 0.0;
     av[0] *= 2.0;

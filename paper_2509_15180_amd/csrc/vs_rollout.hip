@@ -219,25 +219,6 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
 // ---------------------------------------------------------------------------
 // model laws
 
-// Slope of the wrinkled body's moment fraction h(x) of Eq. 2a-b (bend x = |theta|;
-// h is linear below the onset theta_on = 2 asin(eps_c) and constant beyond pi).  With
-// s = sin(x/2), cos(g) = 2 eps_c / s - 1 for the wrinkle angle g = gamma0, and N, D the
-// numerator and denominator of Eq. 2a,
-//   dh/dx = 4 eps_c cos(x/2) (N (pi - g) - sin(g) D) / (s^2 D^2)
-// (the 1/sin(gamma0) of dgamma0/dx cancels).  Slope of the linear branch at the onset
-// itself; 0 from pi on.
-__device__ double wr_dh(double x, double epsc, double th_on) {
-  if (x <= th_on) return 0.5 / th_on;
-  if (x >= kPi) return 0.0;
-  double s, co;
-  sincos(0.5 * x, &s, &co);
-  const double c = fmin(1.0, 2.0 * epsc / s - 1.0);
-  const double sg = sqrt((1.0 - c) * (1.0 + c));  // sin(acos c), rounded as acos is
-  const double g = acos(c);
-  const double N = 2.0 * sg * c + 2.0 * kPi - 2.0 * g;
-  const double D = 4.0 * (sg + (kPi - g) * c);
-  return 4.0 * epsc * co * (N * (kPi - g) - sg * D) / (s * s * D * D);
-}
 
 __device__ __forceinline__ double clenshaw(const double* c, int deg, double x) {
   double b1 = 0.0, b2 = 0.0;
@@ -293,6 +274,20 @@ __device__ void wr_law(double x, const Tab& T, const WrTable& Th, bool want_h, b
   if (want_ih) ih = T.cum[k] + 0.5 * T.du * clenshaw(T.ic[k], kIhDeg + 1, t);
 }
 
+// Slope dh/dx: 1/(2 theta_on) on the linear branch (also at the onset itself), a series in
+// the same u above it (the series was fitted to a long-double closed form, which in double
+// loses digits to the arccosine near the onset and to cancellation near pi), 0 from pi on.
+__device__ double wr_slope(double x, const WrTable& T) {
+  if (x <= T.th_on) return 0.5 / T.th_on;
+  if (x >= kPi) return 0.0;
+  const double u = sqrt(x - T.th_on);
+  int k = (int)(u / T.du);
+  k = k > kIhPieces - 1 ? kIhPieces - 1 : k;
+  const double a = k * T.du;
+  const double t = 2.0 * (u - a) / T.du - 1.0;
+  return clenshaw(T.dhc[k], kIhDeg, t);
+}
+
 // sPAM force per unit pressure G(eps) (Eq. 1d / P_act), its slope and integral.  A
 // table without the slope series gives a NaN slope (never asked for).
 template <class Tab>
@@ -337,7 +332,6 @@ struct Ctx {
 template <class TS, class TW>
 __device__ void joint_law(const Ctx& c, const TS& ts, const TW& tw, double th, double pp,
                           double pm, double* q, double* dq, double* E) {
-  const double epsc = c.P.epsc, th_on = tw.th_on;
   const double ath = fabs(th);
   const double G0 = ts.G0;
   const double eps = c.arm * ath / c.l;
@@ -355,7 +349,7 @@ __device__ void joint_law(const Ctx& c, const TS& ts, const TW& tw, double th, d
   }
   if (dq) {
     const double k = c.arm * c.arm / c.l;
-    double d = c.Mmax * wr_dh(ath, epsc, th_on);
+    double d = c.Mmax * wr_slope(ath, *c.wr);
     d -= th != 0.0 ? k * pstr * dG : 0.5 * k * (pp + pm) * dG;
     *dq = d;
   }
