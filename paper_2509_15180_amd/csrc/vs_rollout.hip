@@ -434,10 +434,11 @@ constexpr int kMaxCols = 3 * kMaxCL;   // columns of its low-rank term
 // tables read from global memory, and the trial angles of the line search kept in b
 // (free once the step is solved).  That cuts the 256-link robot from 71 to 53 KB (three
 // robots per compute unit instead of two) and lets the kernel compile without spills.
-template <int NMAX, int WN_ = 1, bool FULL_ = true>
+template <int NMAX, int WN_ = 1, bool FULL_ = true, bool HELP_ = false>
 struct Smem {
   static constexpr int WN = WN_;  // order of the dense cross-check system (64, else unused)
   static constexpr bool kFull = FULL_;
+  static constexpr bool kHelper = HELP_;  // a second wave takes each evaluation's obstacle phase
   static constexpr int NS = FULL_ ? kMaxCL : 1, NSC = FULL_ ? kMaxCols : 1;
   struct ResObs {
     double ox[kMaxObs], oy[kMaxObs], oa[kMaxObs], ob[kMaxObs];
@@ -478,7 +479,24 @@ struct Smem {
   int ncl;
   int overflow;
   double jevals, nsolves;  // work counters (lane 0 updates)
+  int cmd, cmd_seq, eval_n;  // solver wave -> helper wave: 1 = obstacle phase, 2 = end
+  double eval_last;
 };
+
+// Barrier of the solver's own wave.  A wave's LDS operations complete in the order it
+// issues them, so ordering the accesses of its lanes needs only a compiler fence.  In the
+// two-wave launches the solver wave meets its helper wave only at the barriers of
+// evaluate() and at its end, so every other barrier must be this one.
+template <class SM>
+__device__ __forceinline__ void bsync() {
+  if constexpr (SM::kHelper) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // Copy the robot's obstacles (structure of arrays) and the series of its law tables
 // into LDS.  The space is shared with the structured and dense solves, which clear
@@ -518,51 +536,15 @@ __device__ void stage_resident(SM& S, const Ctx& c) {
   }
   }
   if (lane == 0) S.res_ok = 1;
-  __syncthreads();
+  bsync<SM>();
 }
 
-// Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
+// The contact part of an evaluation at the poses in S (n links, the last of length
+// last_len), on one wave whose lane index is lane: penetrating (disk, obstacle) pairs
+// into the contact list, each link's contact sums into ps1, ps2, aux and v, and ncl and
+// overflow.
 template <class SM>
-__device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
-  const int lane = threadIdx.x;
-  const int n = c.n;
-  if (__builtin_amdgcn_readfirstlane(S.res_ok) == 0) stage_resident(S, c);
-  if (lane == 0) S.jevals += n;
-  double cphi = c.bpsi, cx = c.bx, cy = c.by;
-  for (int base = 0; base < n; base += kWave) {
-    int j = base + lane;
-    bool on = j < n;
-    double phi = wscan_incl(on ? th[j] : 0.0, lane) + cphi;
-    double sj, cj;
-    sincos(phi, &sj, &cj);
-    double L = (j == n - 1) ? c.last_len : c.l;
-    double ex = on ? L * cj : 0.0, ey = on ? L * sj : 0.0;
-    double sx = wscan_incl(ex, lane) + cx, sy = wscan_incl(ey, lane) + cy;
-    if (on) {
-      S.tx[j] = cj;
-      S.ty[j] = sj;
-      S.px[j + 1] = sx;
-      S.py[j + 1] = sy;
-    }
-    cphi = __shfl(phi, kWave - 1, kWave);
-    cx = __shfl(sx, kWave - 1, kWave);
-    cy = __shfl(sy, kWave - 1, kWave);
-  }
-  if (lane == 0) {
-    S.px[0] = c.bx;
-    S.py[0] = c.by;
-  }
-  __syncthreads();
-  double Esum = 0.0;
-  for (int j = lane; j < n; j += kWave) {
-    double q, E = 0.0;
-    if constexpr (SM::kFull)
-      joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
-    else
-      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
-    S.r[j] = q;
-    Esum += E;
-  }
+__device__ void obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int lane) {
   // penetrating (disk, obstacle) pairs, compacted in (obstacle, disk, link) order per
   // chunk.  The exact gap (square root, divisions) is taken only for pairs whose
   // cheap pre-test some lane of the wave passes.
@@ -571,7 +553,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   for (int base = 0; base < n; base += kWave) {
     const int j = base + lane;
     const bool on = j < n;
-    const double L = (j == n - 1) ? c.last_len : c.l;
+    const double L = (j == n - 1) ? last_len : c.l;
     const double pxj = on ? S.px[j] : 0.0, pyj = on ? S.py[j] : 0.0;
     const double txj = on ? S.tx[j] : 0.0, tyj = on ? S.ty[j] : 0.0;
     double xs[2], ys[2];
@@ -700,12 +682,72 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
       S.v[j] = a_q;
     }
   }
-  int nc = cnt < kMaxC ? cnt : kMaxC;
+  const int nc = cnt < kMaxC ? cnt : kMaxC;
   if (lane == 0) {
     S.ncl = nc;
     S.overflow = cnt > kMaxC;
   }
-  __syncthreads();
+}
+
+// Poses, joint moments, contacts, residual (into S.r) and energy at angles th.
+template <class SM>
+__device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
+  const int lane = threadIdx.x;
+  const int n = c.n;
+  if (__builtin_amdgcn_readfirstlane(S.res_ok) == 0) stage_resident(S, c);
+  if (lane == 0) S.jevals += n;
+  double cphi = c.bpsi, cx = c.bx, cy = c.by;
+  for (int base = 0; base < n; base += kWave) {
+    int j = base + lane;
+    bool on = j < n;
+    double phi = wscan_incl(on ? th[j] : 0.0, lane) + cphi;
+    double sj, cj;
+    sincos(phi, &sj, &cj);
+    double L = (j == n - 1) ? c.last_len : c.l;
+    double ex = on ? L * cj : 0.0, ey = on ? L * sj : 0.0;
+    double sx = wscan_incl(ex, lane) + cx, sy = wscan_incl(ey, lane) + cy;
+    if (on) {
+      S.tx[j] = cj;
+      S.ty[j] = sj;
+      S.px[j + 1] = sx;
+      S.py[j + 1] = sy;
+    }
+    cphi = __shfl(phi, kWave - 1, kWave);
+    cx = __shfl(sx, kWave - 1, kWave);
+    cy = __shfl(sy, kWave - 1, kWave);
+  }
+  if (lane == 0) {
+    S.px[0] = c.bx;
+    S.py[0] = c.by;
+  }
+  if constexpr (SM::kHelper) {
+    if (lane == 0) {
+      S.eval_n = n;
+      S.eval_last = c.last_len;
+      S.cmd = 1;
+      S.cmd_seq += 1;
+    }
+    __syncthreads();  // the poses are in LDS: the helper wave starts the obstacle phase
+  } else {
+    bsync<SM>();
+  }
+  double Esum = 0.0;
+  for (int j = lane; j < n; j += kWave) {
+    double q, E = 0.0;
+    if constexpr (SM::kFull)
+      joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    else
+      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    S.r[j] = q;
+    Esum += E;
+  }
+  if constexpr (SM::kHelper) {
+    __syncthreads();  // the helper wave's contacts and contact sums are in LDS
+  } else {
+    obstacle_phase(S, c, n, c.last_len, lane);
+    bsync<SM>();
+  }
+  const int nc = S.ncl;
   // per-link force and moment sums, then suffix sums from the tip toward the base
   double c1 = 0.0, c2x = 0.0, c2y = 0.0;
   int nchunk = (n + kWave - 1) / kWave;
@@ -723,7 +765,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   }
   double pen2 = 0.0;
   for (int e = lane; e < nc; e += kWave) pen2 += 0.5 * c.P.kc * S.cpen[e] * S.cpen[e];
-  __syncthreads();
+  bsync<SM>();
   return wsum(Esum) + wsum(pen2);
 }
 
@@ -834,9 +876,9 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
     S.dq[j] = d;
     S.lidx[j] = -1;
   }
-  __syncthreads();
+  bsync<SM>();
   for (int e = lane; e < nc; e += kWave) S.lidx[S.ci[e]] = 0;
-  __syncthreads();
+  bsync<SM>();
   int L = 0;
   for (int base = 0; base < n && blocks && SM::kFull; base += kWave) {
     int j = base + lane;
@@ -850,7 +892,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
     L += __popcll(m);
   }
   if (lane == 0) S.ncl_links = L;
-  __syncthreads();
+  bsync<SM>();
   // geometric diagonal: suffix sums of per-link forces, chunks from the tip down
   double cfx = 0.0, cfy = 0.0;
   const int nchunk = (n + kWave - 1) / kWave;
@@ -864,7 +906,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
     cfx = __shfl(sx, 0, kWave);
     cfy = __shfl(sy, 0, kWave);
   }
-  __syncthreads();
+  bsync<SM>();
   if (!SM::kFull || !blocks || L > kMaxCL) return false;
   // 3x3 blocks, one lane per contact link (contacts visited in list order)
   for (int a = lane; a < L; a += kWave) {
@@ -892,7 +934,7 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
     S.cM[a][4] = m4;
     S.cM[a][5] = m5;
   }
-  __syncthreads();
+  bsync<SM>();
   return true;
 }
 
@@ -1391,7 +1433,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
     s12[k] = m4;
     s22[k] = m5;
   }
-  __syncthreads();
+  bsync<SM>();
   if (lane == 0) {
     // One lane walks the chain, two links per pass: while one link computes, the
     // inputs of the link after the next are loading (indices are clamped, so the last
@@ -1471,7 +1513,7 @@ __device__ bool chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rh
     }
     if (k < n) outward(oa, k);
   }
-  __syncthreads();
+  bsync<SM>();
   // the pivots D = (q' + mu) + B^T A B, rounded as in the walk
   bool fin = true;
   for (int j = lane; j < n; j += kWave) {
@@ -1515,7 +1557,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     double slope = 0.0, mu = P.c_mu * rm;
     const bool structured = structured_setup(S, c, SM::kFull && !P.seq_solver);
     for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
-    __syncthreads();
+    bsync<SM>();
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) mu = fmax(10.0 * mu, 1e-8 * c.Mmax);
       if (lane == 0) S.nsolves += 1.0;
@@ -1548,14 +1590,14 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
       for (int j = lane; j < n; j += kWave) S.d[j] *= f;
       slope *= f;
     }
-    __syncthreads();
+    bsync<SM>();
     const bool skip = -slope < 1e-12 * c.Mmax;
     double* tt = SM::kFull ? S.tt : S.b;  // trial angles (b is free once the step is solved)
     double alpha = 1.0, Pn = 0.0;
     bool acc = false;
     for (int ls = 0; ls < 40; ++ls) {
       for (int j = lane; j < n; j += kWave) tt[j] = S.th[j] + alpha * S.d[j];
-      __syncthreads();
+      bsync<SM>();
       Pn = evaluate(S, c, tt, true);
       if (skip || Pn <= Pi + P.c1 * alpha * slope) {
         acc = true;
@@ -1578,7 +1620,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     }
     for (int j = lane; j < n; j += kWave) S.th[j] = tt[j];
     Pi = Pn;
-    __syncthreads();
+    bsync<SM>();
   }
   if (status != 0) evaluate(S, c, S.th, false);  // poses/contacts of the kept state
   return status;
@@ -1586,10 +1628,31 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
 
 // ---------------------------------------------------------------------------
 
-template <int NMAX, bool DENSE, bool FULL = true>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(KParams P, KData D, int n_steps,
+// The helper wave of a two-wave launch: the obstacle phase of each evaluation the solver
+// wave posts (between the two barriers of evaluate()), until the solver wave posts its
+// end.  A barrier with no new command also ends the loop: a barrier completes without
+// waves that have ended, so the helper never waits on a solver wave that is gone.
+template <class SM>
+__device__ void obstacle_helper(SM& S, const Ctx& c) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int seen = 0;
+  for (;;) {
+    __syncthreads();
+    const int seq = S.cmd_seq, cmd = S.cmd;
+    if (seq == seen || cmd != 1) break;
+    seen = seq;
+    obstacle_phase(S, c, S.eval_n, S.eval_last, lane);
+    __syncthreads();
+  }
+}
+
+// One robot per workgroup: one wave (HELP = false) or two, the second taking the
+// obstacle phase of every evaluation while the first sums the joint law.
+template <int NMAX, bool DENSE, bool FULL = true, bool HELP = false>
+__global__ __launch_bounds__(HELP ? 2 * kWave : kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(KParams P, KData D, int n_steps,
                                                         int record_traj) {
-  __shared__ Smem<NMAX, DENSE ? 64 : 1, FULL> S;
+  using SMT = Smem<NMAX, DENSE ? 64 : 1, FULL, HELP>;
+  __shared__ SMT S;
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x];
   const int lane = threadIdx.x;
@@ -1613,7 +1676,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   c.trace_cap = D.trace_cap;
   c.obs = D.obs + 4 * (size_t)ii[1];
   c.okind = D.okind + ii[1];
-  if (lane == 0) S.res_ok = 0;  // staged by the first evaluation
+  if constexpr (HELP) {
+    if (threadIdx.x >= kWave) {
+      obstacle_helper(S, c);
+      return;
+    }
+  }
+  if (lane == 0) {
+    S.res_ok = 0;  // staged by the first evaluation
+    S.cmd = 0;
+    S.cmd_seq = 0;
+  }
   for (int j = lane; j < ntar; j += kWave) {
     S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
@@ -1626,20 +1699,20 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     S.nsolves = 0.0;
   }
   for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
-  __syncthreads();
+  bsync<SMT>();
   for (int step = 0; step < n_steps && t < D.t_max; ++step, ++t) {
     int st_worst = 0, its = 0;
     double rho = 0.0;
     if (n < ntar) {
       ++n;
       if (lane == 0) S.th[n - 1] = 0.0;
-      __syncthreads();
+      bsync<SMT>();
       c.n = n;
       for (int s = 1; s <= P.substeps; ++s) {
         c.last_len = c.l * (double)s / (double)P.substeps;
         c.step = t;
         c.sub = s;
-        int st = solve<Smem<NMAX, DENSE ? 64 : 1, FULL>, DENSE>(S, c, its, rho);
+        int st = solve<SMT, DENSE>(S, c, its, rho);
         st_worst = st > st_worst ? st : st_worst;
       }
     } else {
@@ -1686,7 +1759,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     if (record_traj && D.traj)
       for (int j = lane; j < D.n_max; j += kWave)
         D.traj[bt * D.n_max + j] = j < n ? S.th[j] : 0.0;
-    __syncthreads();
+    bsync<SMT>();
   }
   for (int j = lane; j < n; j += kWave) D.theta[(size_t)b * D.n_max + j] = S.th[j];
   if (lane == 0) {
@@ -1695,6 +1768,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     D.jevals[b] += S.jevals;
     D.nsolves[b] += S.nsolves;
     D.cycles[b] += (double)(clock64() - t_begin);
+  }
+  if constexpr (HELP) {
+    if (lane == 0) {
+      S.cmd = 2;
+      S.cmd_seq += 1;
+    }
+    __syncthreads();  // releases the helper wave, which then ends
   }
 }
 
@@ -1920,8 +2000,8 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int rec
                        record_traj);
   } else if (nmax_class == 64) {
     if (P.seq_solver)
-      hipLaunchKernelGGL((rollout_kernel<64, false, false>), grid, block, 0, stream, P, D,
-                         n_steps, record_traj);
+      hipLaunchKernelGGL((rollout_kernel<64, false, false, true>), grid, dim3(2 * kWave), 0,
+                         stream, P, D, n_steps, record_traj);
     else
       hipLaunchKernelGGL((rollout_kernel<64, false>), grid, block, 0, stream, P, D, n_steps,
                          record_traj);
