@@ -2007,22 +2007,22 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int rec
                          record_traj);
   } else if (nmax_class == 128) {
     if (P.seq_solver)
-      hipLaunchKernelGGL((rollout_kernel<128, false, false>), grid, block, 0, stream, P, D,
-                         n_steps, record_traj);
+      hipLaunchKernelGGL((rollout_kernel<128, false, false, true>), grid, dim3(2 * kWave), 0,
+                         stream, P, D, n_steps, record_traj);
     else
       hipLaunchKernelGGL((rollout_kernel<128, false>), grid, block, 0, stream, P, D, n_steps,
                          record_traj);
   } else if (nmax_class == 256) {
     if (P.seq_solver)
-      hipLaunchKernelGGL((rollout_kernel<256, false, false>), grid, block, 0, stream, P, D,
-                         n_steps, record_traj);
+      hipLaunchKernelGGL((rollout_kernel<256, false, false, true>), grid, dim3(2 * kWave), 0,
+                         stream, P, D, n_steps, record_traj);
     else
       hipLaunchKernelGGL((rollout_kernel<256, false>), grid, block, 0, stream, P, D, n_steps,
                          record_traj);
   } else if (nmax_class == 512) {
     if (P.seq_solver)
-      hipLaunchKernelGGL((rollout_kernel<512, false, false>), grid, block, 0, stream, P, D,
-                         n_steps, record_traj);
+      hipLaunchKernelGGL((rollout_kernel<512, false, false, true>), grid, dim3(2 * kWave), 0,
+                         stream, P, D, n_steps, record_traj);
     else
       hipLaunchKernelGGL((rollout_kernel<512, false>), grid, block, 0, stream, P, D, n_steps,
                          record_traj);
