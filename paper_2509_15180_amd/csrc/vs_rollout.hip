@@ -734,10 +734,17 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   double Esum = 0.0;
   for (int j = lane; j < n; j += kWave) {
     double q, E = 0.0;
-    if constexpr (SM::kFull)
+    if constexpr (SM::kFull) {
       joint_law(c, S.res.sp, S.res.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
-    else
+    } else if constexpr (SM::kHelper) {
+      // the joint slopes too, while the helper wave is busy with the contacts: the Newton
+      // set-up that follows an evaluation is always at the angles last evaluated
+      double dqj;
+      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, &dqj, want_E ? &E : nullptr);
+      S.dq[j] = dqj;
+    } else {
       joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+    }
     S.r[j] = q;
     Esum += E;
   }
@@ -871,9 +878,11 @@ __device__ bool structured_setup(SM& S, const Ctx& c, bool blocks = true) {
   const int lane = threadIdx.x, n = c.n, nc = S.ncl;
   const unsigned long long lt = (1ull << lane) - 1ull;
   for (int j = lane; j < n; j += kWave) {
-    double d;
-    joint_law(c, *c.tab, *c.wr, S.th[j], S.pp[j], S.pm[j], nullptr, &d, nullptr);
-    S.dq[j] = d;
+    if constexpr (!SM::kHelper) {  // two-wave launches: evaluate() left them in dq
+      double d;
+      joint_law(c, *c.tab, *c.wr, S.th[j], S.pp[j], S.pm[j], nullptr, &d, nullptr);
+      S.dq[j] = d;
+    }
     S.lidx[j] = -1;
   }
   bsync<SM>();
