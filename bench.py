@@ -136,10 +136,10 @@ def main():
 
     def one_step():
         if args.graph:
-            sim.rollout_graph(record_traj=(wl == "grad"), stream=stream)
+            sim.rollout_graph(ckpt_every=32 if wl == "grad" else 0, stream=stream)
         else:
             sim.reset(stream=stream)
-            sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
+            sim.rollout(-1, ckpt_every=32 if wl == "grad" else 0, stream=stream)
         if wl == "grad":
             sim.grad(goal, weights, stream=stream)
 
@@ -166,7 +166,7 @@ def main():
     sim.reset(stream=stream)
     k0, k1 = _events(torch)
     k0.record(stream)
-    sim.rollout(-1, record_traj=(wl == "grad"), stream=stream)
+    sim.rollout(-1, ckpt_every=32 if wl == "grad" else 0, stream=stream)
     k1.record(stream)
     torch.cuda.synchronize()
     kern_ms = k0.elapsed_time(k1)

@@ -8,9 +8,13 @@
  *   - each joint carries the wrinkling-based restoring moment of the inflated body
  *     (Sec. 3.2, Eq. 2) and the moment of the sPAM actuators that cover it
  *     (Sec. 3.1, Eq. 1; Sec. 3.3, Eq. 3: strain eps = (2R + R_act) theta / l);
- *   - one growth step appends a link and brings the chain to the minimum-energy
- *     state of Eq. 4 read as a potential energy: joint energies plus a penalty
- *     k_c/2 pen^2 on every penetration of the body into an obstacle (Alg. 1).
+ *   - one growth step appends a link and brings the chain to a minimum-energy state
+ *     of Eq. 4 (an argmin) read as a potential energy: joint energies plus a penalty
+ *     k_c/2 pen^2 on every penetration of the body into an obstacle (Alg. 1).  The
+ *     state reached is the local minimum that a damped descent from the previous
+ *     state (new link straight) finds; stationary points that are not minima
+ *     (saddles, such as a straight body pushed head-on into an obstacle) are left
+ *     along their negative curvature.
  *
  * Units are SI throughout: metres, pascals, radians, newtons.
  *
@@ -47,7 +51,7 @@ extern "C" {
 #define VINE_ECAPACITY (-5) /* more links, obstacles or sPAMs per robot than supported */
 
 /* per-step status codes in the STATUS field */
-#define VINE_ST_CONVERGED 0   /* max_j |r_j| / M_max <= tol */
+#define VINE_ST_CONVERGED 0   /* max_j |r_j| / M_max <= tol and H + pd_shift M_max I positive definite */
 #define VINE_ST_MAXITER 1     /* iteration limit reached */
 #define VINE_ST_NODESCENT 2   /* no descent direction / line search failed */
 #define VINE_ST_CAPACITY 3    /* more simultaneous disk/obstacle contacts than the contact list holds */
@@ -56,8 +60,18 @@ extern "C" {
 
 /* Simulation-wide constants.  Defaults (vine_params_default): R_c = 5 mm,
  * R_act = 17.18 mm, a = 1e-4 (Sec. 3.1); eps_crit = 0.01 (Sec. 3.2: fitted in the
- * paper, value not printed); k_c = 1e4 N/m; tol = 1e-10; max_iter = 500;
- * growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad; armijo_c1 = 1e-4; solver = 2. */
+ * paper, value not printed); k_c = 1e4 N/m; tol = 1e-10; pd_shift = 1e-8 /rad;
+ * max_iter = 500; growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad;
+ * armijo_c1 = 1e-4.
+ *
+ * The descent (one growth sub-step): at each iterate the exact Hessian H of the energy
+ * is factorised as H + mu I = U D U^T by a Riccati sweep that eliminates the joints from
+ * the tip (O(n) for any number of contacts; its pivots D give the inertia), with
+ * mu = max(c_mu max_j |r_j|, pd_shift M_max) raised tenfold while a pivot vanishes.
+ * Converged: max_j |r_j| / M_max <= tol and every pivot at mu = pd_shift M_max positive.
+ * Positive definite: the step (H + mu I) d = -r, |d|_inf capped at step_max.  Otherwise a
+ * step of length step_max along v with U^T v = e_k, k the most negative pivot.  Armijo
+ * backtracking on the energy. */
 typedef struct vine_params {
   double R_c;            /* sPAM constriction radius (m), Eq. 1 */
   double R_act;          /* sPAM tube radius (m), Eq. 1c */
@@ -68,17 +82,10 @@ typedef struct vine_params {
   double c_mu;           /* damping per unit residual, mu = c_mu max_j |r_j| (1/rad) */
   double step_max;       /* cap on the joint-space step per iteration (rad) */
   double armijo_c1;      /* sufficient-decrease constant of the line search */
-  int32_t max_iter;      /* Newton iterations per equilibrium solve */
+  double pd_shift;       /* delta / M_max (1/rad): a stationary state is accepted when
+                            H + delta I is positive definite */
+  int32_t max_iter;      /* iterations per equilibrium solve */
   int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
-  int32_t solver;        /* Newton system of the growth solve.
-                            2 (default): sequential O(n) sweep in relative angles (a Riccati
-                               recursion of 3x3 blocks from the tip, then a substitution from
-                               the base), any number of contacts;
-                            0: structured solve: scans for the chain part plus a low-rank
-                               update per contact link, the sweep above 16 contact links;
-                            1: dense LU with partial pivoting (chains of <= 64 links;
-                               cross-check, not accepted by the server).
-                            The adjoint (vine_sim_grad) always uses the structured solve. */
   int32_t reserved;
 } vine_params;
 
@@ -130,12 +137,18 @@ typedef enum vine_field {
   VINE_F_NCONTACT = 6, /* int32  [B][T]    (link, obstacle) pairs in contact after each step */
   VINE_F_CHASH = 7,    /* uint64 [B][T]    order-free hash of that contact set */
   VINE_F_MAXPEN = 8,   /* double [B][T]    deepest penetration after each step (m) */
-  VINE_F_TRAJ = 9,     /* double [B][T][N] joint angles after each step (when recorded) */
+  VINE_F_TRAJ = 9,     /* double [B][R][N] joint angles after every record_every-th step (row
+                          t / record_every after step t) and after the last step T - 1,
+                          R = ceil(T / record_every), as last recorded */
   VINE_F_JEVALS = 10,  /* double [B]       work counter: sum over residual evaluations of the
                           link count (since create or the last reset) */
   VINE_F_NSOLVES = 11, /* double [B]       work counter: linear solves of the Newton system */
-  VINE_F_CYCLES = 12   /* double [B]       shader-clock cycles each robot's wave spent in rollout
+  VINE_F_CYCLES = 12,  /* double [B]       shader-clock cycles each robot's wave spent in rollout
                           launches since the reset (what vine_sim_tune_order sorts by) */
+  VINE_F_NEGSTEPS = 13, /* double [B]      work counter: steps along negative curvature */
+  VINE_F_CKPT = 14     /* double [B][C][N] checkpoints: row q is the state before step
+                          q ckpt_every (joint angles, 0 beyond the link count then),
+                          C = ceil(T / ckpt_every) */
 } vine_field;
 
 typedef struct vine_sim vine_sim;
@@ -158,13 +171,24 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
 /* Advance every robot that is shorter than its target by n_steps growth steps
  * (Alg. 1 repeated): append a link at zero angle, then, for each growth sub-step,
  * solve the equilibrium.  Robots at their target length are left unchanged and
- * record VINE_ST_DONE.  n_steps <= 0 is a no-op.  When record_traj is non-zero the
- * joint angles after every step are kept for VINE_F_TRAJ.  Asynchronous on stream. */
-int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
+ * record VINE_ST_DONE.  n_steps = 0 is a no-op (n_steps < 0: VINE_EINVAL).
+ *   record_every  0: no trajectory; r >= 1: the joint angles after every r-th step
+ *                 (and after step T - 1) go to VINE_F_TRAJ.  The buffer
+ *                 (B x ceil(T / r) x N doubles) is allocated on the first call that
+ *                 records with this r; a call with another r reallocates it.
+ *   ckpt_every    0: no checkpoints; c >= 1: the state before every c-th step goes to
+ *                 VINE_F_CKPT (B x ceil(T / c) x N doubles, allocated likewise).  With
+ *                 checkpoints on every call since the reset, vine_sim_grad recomputes
+ *                 the weighted steps from them instead of needing the trajectory
+ *                 (32 keeps 1/32 of the states).
+ * Asynchronous on stream.  Errors: VINE_EINVAL, VINE_ENOMEM, VINE_EDEVICE. */
+int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_every, int32_t ckpt_every,
+                      void* stream);
 
 /* Grow every robot to its target length in one launch (n_steps = -1) or by
  * n_steps steps.  Same semantics as vine_sim_step. */
-int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream);
+int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_every, int32_t ckpt_every,
+                         void* stream);
 
 /* Launch-order autotuning.  A batched launch lasts as long as its last robot, and the
  * robots of a chain-length class start in the handle's launch order as compute units
@@ -176,15 +200,17 @@ int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void
  * depend on the order.  Synchronises the stream.  Errors: VINE_EINVAL, VINE_EDEVICE. */
 int32_t vine_sim_tune_order(vine_sim* h, void* stream);
 
-/* vine_sim_reset followed by vine_sim_rollout(h, -1, record_traj, stream) (every robot
- * regrown from zero length to its target, Sec. 4 growth steps), as one HIP graph: the
- * reset and the per-class launches (with their fork/join across the handle's streams)
- * are captured on the first call for each value of record_traj (nonzero = 1) and
- * replayed by later calls, so a repeated rollout costs one graph launch.  The graph
- * holds no memset nodes.  Results are bitwise those of the two eager calls.  The
- * capture is dropped by vine_sim_trace (it holds the trace buffer's address).  Errors:
- * VINE_EINVAL (null handle), VINE_ENOMEM (trajectory), VINE_EDEVICE (capture, launch). */
-int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream);
+/* vine_sim_reset followed by vine_sim_rollout(h, -1, record_every, ckpt_every, stream)
+ * (every robot regrown from zero length to its target, Sec. 4 growth steps), as one HIP
+ * graph: the reset and the per-class launches (with their fork/join across the
+ * handle's streams) are captured on the first call for each (record_every, ckpt_every)
+ * (up to four kept) and replayed by later calls, so a repeated rollout costs one graph
+ * launch.  The graph holds no memset nodes.  Results are bitwise those of the two eager
+ * calls.  Captures are dropped by vine_sim_trace and when a trajectory or checkpoint
+ * buffer is reallocated (they hold the buffers' addresses).  Errors: VINE_EINVAL,
+ * VINE_ENOMEM (trajectory, checkpoints), VINE_EDEVICE (capture, launch). */
+int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_every,
+                               void* stream);
 
 /* Gradient of a tip-reaching loss with respect to the actuation design, by the
  * adjoint of the equilibrium conditions (Sec. 5 searches sPAM placement and
@@ -195,23 +221,29 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream);
  * at create:  dL/dP_s, dL/ds_start_s, dL/ds_end_s of L = sum_b L_b (records shared
  * by several robots collect the sum).  Each equilibrium contributes
  *     -lam^T dr/dp with H lam = w_t dL_t/dtheta,
- * H the exact Hessian of the energy at theta_b(t) (the one the growth solver uses,
- * undamped).  Equilibria are taken as they were computed: the derivative of a
- * step whose status is not VINE_ST_CONVERGED, or across a change of the contact
- * set, is that of the smooth branch the state sits on.
+ * H the exact Hessian of the energy at theta_b(t) (factorised by the sweep the growth
+ * solver uses, undamped).  Equilibria are taken as they were computed: the derivative
+ * of a step whose status is not VINE_ST_CONVERGED, or across a change of the contact
+ * set, is that of the smooth branch the state sits on (flagged in adj_status).
  *   goal          device, double [B][2]
  *   step_weights  device, double [T] (T from vine_sim_dims), or NULL: the loss
  *                 is then w = 1 on the current state alone.  With weights, steps
  *                 not yet taken by a robot are skipped, and every step/rollout call
- *                 since the last reset must have recorded the trajectory
- *                 (record_traj), else VINE_ESTATE.
+ *                 since the last reset must have recorded every step
+ *                 (record_every = 1) or written checkpoints (ckpt_every > 0, the
+ *                 same on every call), else VINE_ESTATE.  Without the full
+ *                 trajectory the states are recomputed segment by segment from the
+ *                 checkpoints (bitwise the states of the rollout; one more rollout's
+ *                 work, and B x ckpt_every x N doubles of segment buffers allocated
+ *                 on first use).
  *   dL_dP, dL_ds_start, dL_ds_end   device, double [n_spams] (overwritten)
  *   loss          device, double [B] (overwritten with L_b)
- *   adj_status    device, int32 [B] or NULL: 0, or 1 when an adjoint system was
- *                 singular or had more contacts than the solver holds (that
- *                 step's term is then left out).
+ *   adj_status    device, int32 [B] or NULL: bit 0 set when an adjoint system was
+ *                 singular or had more contacts than the contact list holds (that
+ *                 step's term is then left out); bit 1 set when a weighted step had
+ *                 not converged in the rollout (VINE_ST_* > 0).
  * Asynchronous on stream.  Errors: VINE_EINVAL (null pointers), VINE_ESTATE,
- * VINE_EDEVICE. */
+ * VINE_ENOMEM, VINE_EDEVICE. */
 int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,
                       double* dL_dP, double* dL_ds_start, double* dL_ds_end, double* loss,
                       int32_t* adj_status, void* stream);

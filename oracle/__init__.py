@@ -17,10 +17,10 @@ _lib = None
 
 # parameter vector layout (see prm_from in vine_oracle.c)
 PARAM_NAMES = ("Rc", "Ract", "acorr", "epsc", "kc", "tol", "max_iter", "substeps", "fd_h", "c1",
-               "c_mu", "cheb_n", "step_max", "mu_up")
+               "c_mu", "cheb_n", "step_max", "mu_up", "pd_shift")
 DEFAULTS = dict(Rc=0.005, Ract=0.01718, acorr=1e-4, epsc=0.01, kc=1e4, tol=1e-10, max_iter=500,
                 substeps=2, fd_h=0.0, c1=1e-4, c_mu=1.0, cheb_n=128,
-                step_max=0.05, mu_up=10.0)
+                step_max=0.05, mu_up=10.0, pd_shift=1e-8)
 
 
 def params(**over) -> np.ndarray:
@@ -213,11 +213,12 @@ def chain_hessian(inst: dict, th, prm=None, last_len=0.0):
 
 
 def chain_solve(inst: dict, th0, prm=None, last_len=0.0):
-    """Equilibrium from th0: (theta, status, info[iters, backtracks, mu raises, rho])."""
+    """Equilibrium from th0: (theta, status, info[iters, backtracks, mu raises, rho,
+    steps along negative curvature])."""
     prm = params() if prm is None else prm
     d, spam, kind, obs = _chain_args(inst)
     th = _f64(th0).copy()
-    info = np.zeros(4)
+    info = np.zeros(5)
     st = lib().vo_chain_solve(len(th), _d(d), _d(spam), len(spam), len(kind), _i(kind), _d(obs),
                               _d(prm), last_len, _d(th), _d(info))
     return th, st, info
@@ -238,7 +239,7 @@ def rollout(work, n_steps: int | None = None, prm=None, threads: int = 0, traj: 
         theta=np.zeros((B, n_max)), tip=np.zeros((B, T, 3)), rho=np.zeros((B, T)),
         iters=np.zeros((B, T), np.int32), status=np.zeros((B, T), np.int32),
         ncont=np.zeros((B, T), np.int32), chash=np.zeros((B, T), np.uint64),
-        maxpen=np.zeros((B, T)), stats=np.zeros((B, 4)))
+        maxpen=np.zeros((B, T)), stats=np.zeros((B, 6)))
     tr = np.zeros((B, T, n_max)) if traj else None
     inst_i, inst_d = _i32(work.inst_i), _f64(work.inst_d)
     spam, kind, obs = _f64(work.spam.reshape(-1, 4)), _i32(work.obs_kind), _f64(work.obs_d.reshape(-1, 4))

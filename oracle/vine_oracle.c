@@ -57,6 +57,8 @@ typedef struct {
   double step_max;          /* cap on max_j |step_j| (rad) */
   double mu_up;             /* factor by which mu is raised when a step does not descend */
   int cheb_n;               /* Chebyshev degree of the G fit */
+  double pd_shift;          /* delta / M_max: a state is a minimum when H + delta I is
+                               positive definite (1/rad) */
 } vo_prm;
 
 static void prm_from(const double* p, vo_prm* P) {
@@ -74,6 +76,7 @@ static void prm_from(const double* p, vo_prm* P) {
   P->cheb_n = (int)p[11];
   P->step_max = p[12];
   P->mu_up = p[13];
+  P->pd_shift = p[14];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -694,29 +697,76 @@ static int dense_solve(int n, const double* H, double mu, const double* b, doubl
   return 0;
 }
 
+/* LDL^T factorisation of the symmetric matrix H + mu I (dense, row-major n x n),
+ * eliminating the joints from the tip (index n-1) down to the base:
+ *   H + mu I = U diag(D) U^T,  U unit upper triangular.
+ * A (n x n) receives U above its diagonal; D the pivots.  By Sylvester's law of
+ * inertia the number of negative pivots is the number of negative eigenvalues, so
+ * H + mu I is positive definite exactly when every pivot is.  Returns the number of
+ * negative pivots, or -1 on a zero or non-finite pivot. */
+static int ldlt_tip(int n, const double* H, double mu, double* A, double* D) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[i * n + j] = H[i * n + j] + (i == j ? mu : 0.0);
+  int neg = 0;
+  for (int k = n - 1; k >= 0; --k) {
+    double dk = A[k * n + k];
+    if (!isfinite(dk) || dk == 0.0) return -1;
+    D[k] = dk;
+    if (dk < 0.0) ++neg;
+    for (int i = 0; i < k; ++i) A[i * n + k] /= dk; /* U_ik */
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j <= i; ++j) {
+        A[i * n + j] -= A[i * n + k] * dk * A[j * n + k];
+        A[j * n + i] = A[i * n + j];
+      }
+  }
+  return neg;
+}
+
+/* Direction of negative curvature from the factorisation above: v with U^T v = e_k, so
+ * that v^T (H + mu I) v = D_k.  v vanishes below joint k and v_k = 1. */
+static void neg_curv_dir(int n, const double* A, int k, double* v) {
+  for (int m = 0; m < n; ++m) v[m] = 0.0;
+  v[k] = 1.0;
+  for (int m = k + 1; m < n; ++m) {
+    double s = 0.0;
+    for (int i = k; i < m; ++i) s += A[i * n + m] * v[i];
+    v[m] = -s;
+  }
+}
+
 typedef struct {
-  int iters, backtracks, mu_raises, status;
+  int iters, backtracks, mu_raises, status, neg_steps, tie_steps;
   double rho;
 } vo_solve_stats;
 
-/* Damped Newton descent of Pi from th (in place).
- *  - H: exact Hessian of Pi (analytic; by central differences of r when fd_h > 0);
- *  - step (H + mu I) d = -r with mu = c_mu max_j |r_j|: an implicit Euler step of the
- *    overdamped motion (gradient flow) that the quasi-static model stands for, which
- *    becomes Newton's step as the residual vanishes; mu is raised tenfold until the
- *    step descends (r.d < 0);
- *  - Armijo backtracking on Pi (halving, constant c1), skipped once the predicted
- *    decrease -r.d is below 1e-12 M_max (round-off level of Pi);
- *  - stop when rho = max_j |r_j| / M_max <= tol.
+/* Descent of Pi from th (in place) to a local minimum (Eq. 4 is an argmin).
+ * At each iterate, with the exact Hessian H (analytic; by central differences of r when
+ * fd_h > 0) and delta = pd_shift M_max:
+ *  - factorise H + mu I by LDL^T from the tip to the base (ldlt_tip), mu starting at
+ *    max(c_mu max_j |r_j|, delta) and raised tenfold only when a pivot vanishes;
+ *  - converged (status 0) when rho = max_j |r_j| / M_max <= tol and H + delta I is
+ *    positive definite: a stationary point that is not a saddle;
+ *  - H + mu I positive definite: the step (H + mu I) d = -r (Gaussian elimination), an
+ *    implicit Euler step of the overdamped motion (gradient flow) that the quasi-static
+ *    model stands for, which becomes Newton's step as the residual vanishes;
+ *  - otherwise a step along negative curvature: d = s v with v from neg_curv_dir at the
+ *    most negative pivot (ties: the joint nearest the base), its sign chosen so that
+ *    r.d <= 0 (d_k > 0 when r.v = 0, e.g. at an exactly symmetric saddle);
+ *  - cap max_j |d_j| at step_max (curvature steps are scaled to it);
+ *  - Armijo backtracking on Pi (halving, constant c1) against the predicted change
+ *    alpha r.d (+ alpha^2 d.H d / 2 for a curvature step), skipped once the predicted
+ *    decrease of the full step is below 1e-12 M_max (round-off level of Pi).
  * status: 0 converged, 1 iteration limit, 2 no descent / line search failure,
  * 4 non-finite state. */
 static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_pose* w) {
   const vo_prm* P = c->P;
   int n = c->n;
   size_t nn = (size_t)n;
-  double* buf = (double*)malloc(sizeof(double) * (nn * nn + nn * (nn + 1) + 9 * nn + 16));
+  double* buf = (double*)malloc(sizeof(double) * (2 * nn * nn + nn * (nn + 1) + 11 * nn + 16));
   double* H = buf;
-  double* W = H + nn * nn;
+  double* A = H + nn * nn;
+  double* W = A + nn * nn;
   double* r = W + nn * (nn + 1);
   double* rp = r + nn;
   double* rm = rp + nn;
@@ -725,8 +775,11 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
   double* ha = tt + nn;
   double* hb = ha + nn;
   double* hu = hb + nn;
+  double* piv = hu + nn;
+  double* Hd = piv + nn;
   int capc = 2 * n * (c->K > 0 ? c->K : 1) + 1, ncl = 0;
   vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
+  const double delta = P->pd_shift * c->Mmax;
   memset(st, 0, sizeof(*st));
   st->status = 1;
   double Pi = chain_eval(c, th, r, 1, cl, capc, &ncl, w);
@@ -738,12 +791,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       st->status = 4;
       break;
     }
-    if (st->rho <= P->tol) {
-      st->status = 0;
-      break;
-    }
-    if (it == P->max_iter) break;
-    st->iters++;
+    const int small = st->rho <= P->tol;
     if (P->fd_h > 0.0) {
       /* Hessian by central differences of r (cross-check mode) */
       double h = P->fd_h;
@@ -764,44 +812,84 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
     } else {
       chain_hessian(c, th, cl, ncl < capc ? ncl : capc, w, H, ha, hb, hu);
     }
-    for (int i = 0; i < n; ++i) rp[i] = -r[i];
-    /* implicit Euler step of the gradient flow with mu = 1/h = c_mu |r|_inf; raise mu
-     * tenfold (floor 1e-8 M_max) until the step descends */
-    int ok = 0;
-    double slope = 0.0;
-    double mu = P->c_mu * rmax;
+    /* mu: the implicit-Euler damping 1/h = c_mu |r|_inf, at least delta; raised tenfold
+     * while a pivot vanishes or the step does not descend */
+    double mu = fmax(P->c_mu * rmax, delta);
+    int mode = 0; /* 1: Newton step in d, 2: curvature step in d, 3: converged */
+    double slope = 0.0, curv = 0.0;
     for (int tries = 0; tries < 24; ++tries) {
       if (tries > 0) {
-        mu = fmax(P->mu_up * mu, 1e-8 * c->Mmax);
+        mu = fmax(P->mu_up * mu, delta);
         st->mu_raises++;
       }
-      if (dense_solve(n, H, mu, rp, d, W) != 0) continue;
-      slope = 0.0;
-      for (int i = 0; i < n; ++i) slope += r[i] * d[i];
-      if (slope < 0.0) {
-        ok = 1;
-        break;
+      int neg = ldlt_tip(n, H, mu, A, piv);
+      if (neg < 0) continue;
+      if (neg == 0) {
+        if (small) {
+          mode = 3;
+          break;
+        }
+        for (int i = 0; i < n; ++i) rp[i] = -r[i];
+        if (dense_solve(n, H, mu, rp, d, W) != 0) continue;
+        slope = 0.0;
+        for (int i = 0; i < n; ++i) slope += r[i] * d[i];
+        if (slope < 0.0) {
+          mode = 1;
+          break;
+        }
+        continue;
       }
+      int k = 0;
+      for (int j = 1; j < n; ++j)
+        if (piv[j] < piv[k]) k = j;
+      neg_curv_dir(n, A, k, d);
+      double vmax = 0.0, rv = 0.0;
+      for (int i = 0; i < n; ++i) {
+        vmax = fmax(vmax, fabs(d[i]));
+        rv += r[i] * d[i];
+      }
+      double s = (rv > 0.0 ? -1.0 : 1.0) * P->step_max / vmax;
+      for (int i = 0; i < n; ++i) d[i] *= s;
+      slope = s * rv;
+      curv = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double a = 0.0;
+        for (int j = 0; j < n; ++j) a += H[i * n + j] * d[j];
+        Hd[i] = a;
+        curv += d[i] * a;
+      }
+      mode = 2;
+      st->neg_steps++;
+      if (rv == 0.0) st->tie_steps++; /* the sign came from the tie rule */
+      break;
     }
-    if (!ok) {
+    if (mode == 3) {
+      st->status = 0;
+      break;
+    }
+    if (it == P->max_iter) break;
+    st->iters++;
+    if (mode == 0) {
       st->status = 2;
       break;
     }
-    /* cap the joint-space step length so that the iterates follow the flow */
-    double dmax = 0.0;
-    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(d[i]));
-    if (dmax > P->step_max) {
-      double f = P->step_max / dmax;
-      for (int i = 0; i < n; ++i) d[i] *= f;
-      slope *= f;
+    if (mode == 1) {
+      /* cap the joint-space step length so that the iterates follow the flow */
+      double dmax = 0.0;
+      for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(d[i]));
+      if (dmax > P->step_max) {
+        double f = P->step_max / dmax;
+        for (int i = 0; i < n; ++i) d[i] *= f;
+        slope *= f;
+      }
     }
     double alpha = 1.0, Pn = 0.0;
     int accepted = 0;
-    int skip = (-slope < 1e-12 * c->Mmax);
+    int skip = (-(slope + 0.5 * curv) < 1e-12 * c->Mmax);
     for (int ls = 0; ls < 40; ++ls) {
       for (int i = 0; i < n; ++i) tt[i] = th[i] + alpha * d[i];
       Pn = chain_eval(c, tt, rm, 1, cl, capc, &ncl, w);
-      if (skip || Pn <= Pi + P->c1 * alpha * slope) {
+      if (skip || Pn <= Pi + P->c1 * (alpha * slope + 0.5 * alpha * alpha * curv)) {
         accepted = 1;
         break;
       }
@@ -813,8 +901,8 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       break;
     }
     if (vo_verbose)
-      fprintf(stderr, "it %d rho %.3e mu %.3e slope %.3e alpha %.3e Pi %.12e\n", it, st->rho, mu,
-              slope, alpha, Pn);
+      fprintf(stderr, "it %d rho %.3e mu %.3e mode %d slope %.3e curv %.3e alpha %.3e Pi %.12e\n",
+              it, st->rho, mu, mode, slope, curv, alpha, Pn);
     memcpy(th, tt, sizeof(double) * nn);
     memcpy(r, rm, sizeof(double) * nn);
     Pi = Pn;
@@ -874,7 +962,9 @@ static void chain_init(vo_chain* c, const vo_prm* P, const double* prm, const do
  *  rho    [B][T], iters [B][T], status [B][T] (-1 once the instance is full grown),
  *  ncont  [B][T], chash [B][T] (order-free hash of the contact set), maxpen [B][T]
  *  traj   [B][T][n_max]     joint angles after each step
- *  stats  [B][4]            total Newton iterations, backtracks, damping raises, max contacts */
+ *  stats  [B][6]            total iterations, backtracks, damping raises, max contacts,
+ *                           steps along negative curvature, those of them whose sign
+ *                           the tie rule chose (r.v = 0) */
 int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spam,
                const int* obs_kind, const double* obs_d, const double* prm, int n_steps,
                int n_threads, int n_max, double* theta, double* tip, double* rho, int* iters,
@@ -904,7 +994,7 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
     pose_alloc(&w, nalloc);
     int capc = 2 * nalloc * (c.K > 0 ? c.K : 1) + 1;
     vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
-    double tot_it = 0, tot_bt = 0, tot_mu = 0, max_c = 0;
+    double tot_it = 0, tot_bt = 0, tot_mu = 0, max_c = 0, tot_neg = 0, tot_tie = 0;
     c.n = 0;
     for (int t = 0; t < n_steps; ++t) {
       int st_worst = 0, it_sum = 0;
@@ -919,6 +1009,8 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
           it_sum += st.iters;
           tot_bt += st.backtracks;
           tot_mu += st.mu_raises;
+          tot_neg += st.neg_steps;
+          tot_tie += st.tie_steps;
           if (st.status > st_worst) st_worst = st.status;
           rho_last = st.rho;
         }
@@ -965,10 +1057,12 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
     }
     for (int i = 0; i < n_max; ++i) theta[(size_t)b * n_max + i] = (i < ntar) ? th[i] : 0.0;
     if (stats) {
-      stats[4 * b + 0] = tot_it;
-      stats[4 * b + 1] = tot_bt;
-      stats[4 * b + 2] = tot_mu;
-      stats[4 * b + 3] = max_c;
+      stats[6 * b + 0] = tot_it;
+      stats[6 * b + 1] = tot_bt;
+      stats[6 * b + 2] = tot_mu;
+      stats[6 * b + 3] = max_c;
+      stats[6 * b + 4] = tot_neg;
+      stats[6 * b + 5] = tot_tie;
     }
     free(Pp);
     free(th);
@@ -1023,7 +1117,7 @@ double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, 
 }
 
 /* Solve one equilibrium from th (in place); returns status; info = iters, backtracks,
- * damping raises, rho */
+ * damping raises, rho, steps along negative curvature */
 int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, const int* kind,
                    const double* obs, const double* prm, double last_len, double* th,
                    double* info) {
@@ -1047,6 +1141,7 @@ int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, co
     info[1] = st.backtracks;
     info[2] = st.mu_raises;
     info[3] = st.rho;
+    info[4] = st.neg_steps;
   }
   free(w.px);
   free(Pp);

@@ -50,9 +50,8 @@ struct WrTable {
 // Solver and model constants passed by value to the kernels.
 struct KParams {
   double epsc, kc, tol, c_mu, step_max, c1, Ract;
+  double pd_shift;    // delta / M_max: converged states have H + delta I positive definite
   int max_iter, substeps;
-  int dense_solver;   // 1: dense LU cross-check solver (chains of <= 64 links)
-  int seq_solver;     // 1: sequential chain sweep for every Newton system (cross-check)
 };
 
 // Per-robot and per-simulation device arrays (structure of arrays).
@@ -86,10 +85,14 @@ struct KData {
   int* ncont;
   unsigned long long* chash;
   double* maxpen;
-  double* traj;       // [B][T][N] or null
+  double* traj;       // [B][n_rec][N] or null: joint angles after every rec_every-th step
+  int rec_every, n_rec;  // (row t / rec_every after step t; the last step always)
+  double* ckpt;       // [B][n_ckpt][N] or null: the state before every ckpt_every-th step
+  int ckpt_every, n_ckpt;
   // work counters per robot (accumulated over calls)
   double* jevals;     // [B] sum over residual/energy evaluations of the link count
-  double* nsolves;    // [B] dense (H + mu I) solves
+  double* nsolves;    // [B] factorisations of H + mu I
+  double* negsteps;   // [B] steps along negative curvature
   double* cycles;     // [B] shader-clock cycles spent in rollout launches since the reset
   // solver trace of one robot (diagnostics): rows of kTraceCols doubles
   int trace_robot;    // -1: off
@@ -97,6 +100,15 @@ struct KData {
   double* trace;      // [cap][kTraceCols]; trace_n[0] counts rows written
   int* trace_n;
 };
-constexpr int kTraceCols = 10;  // step, substep, iter, rho, mu, slope, alpha, Pi, tries, ncontacts
+// Running sums of the adjoint between the launches of a segmented (checkpointed)
+// gradient: per robot and lane its sPAM's three derivatives, and the loss and status.
+struct GradPart {
+  double* sums;   // [B][kWave][3] or null (single launch)
+  double* loss;   // [B]
+  int* status;    // [B]
+  int first, last;  // start from zero; commit to the outputs
+};
+
+constexpr int kTraceCols = 10;  // step, substep, iter, rho, mu, slope, alpha, Pi, mode, ncontacts
 
 }  // namespace vs

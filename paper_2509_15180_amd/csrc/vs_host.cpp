@@ -19,13 +19,16 @@
 static_assert(vs::kMaxObs == VINE_MAX_OBSTACLES, "obstacle capacity of the kernels");
 
 namespace vs {
-hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int record_traj,
-                          int nmax_class, hipStream_t stream);
+hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
+                          hipStream_t stream);
 hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
-                       const double* weights, int T, double* dP, double* ds0, double* ds1,
-                       double* loss, int* status, int nmax_class, hipStream_t stream);
+                       const double* weights, int T, int t0, const double* traj, int traj_rows,
+                       const GradPart& part, double* dP, double* ds0, double* ds1, double* loss,
+                       int* status, int nmax_class, hipStream_t stream);
 hipError_t launch_zero3(double* a, double* b, double* c, int n, hipStream_t stream);
 hipError_t launch_reset(const KData& D, hipStream_t stream);
+hipError_t launch_seg_load(const KData& Dseg, const double* ckpt, const int* tcur, int n_ckpt,
+                           int q, int ce, hipStream_t stream);
 }
 
 using vs::SpamTable;
@@ -375,10 +378,25 @@ struct vine_sim {
   int* ncont = nullptr;
   unsigned long long* chash = nullptr;
   double* maxpen = nullptr;
-  double* traj = nullptr;
+  double* traj = nullptr;    // [B][n_rec][N], allocated for rec_every on first use
+  int rec_every = 0, n_rec = 0;
+  double* ckpt = nullptr;    // [B][n_ckpt][N], allocated for ckpt_every on first use
+  int ckpt_every = 0, n_ckpt = 0;
   double* jevals = nullptr;
   double* nsolves = nullptr;
+  double* negsteps = nullptr;
   double* cycles = nullptr;
+  // recomputation of a checkpoint segment for the adjoint (allocated on first use):
+  // state, records and trajectory of ckpt_every steps
+  struct Seg {
+    double *theta = nullptr, *tip = nullptr, *rho = nullptr, *maxpen = nullptr,
+           *traj = nullptr, *jevals = nullptr, *nsolves = nullptr, *negsteps = nullptr,
+           *cycles = nullptr, *gsums = nullptr, *gloss = nullptr;
+    int *ncur = nullptr, *tcur = nullptr, *iters = nullptr, *status = nullptr, *ncont = nullptr,
+        *gstat = nullptr;
+    unsigned long long* chash = nullptr;
+    int steps = 0;  // ckpt_every the buffers were sized for
+  } seg;
   // robots grouped by chain-length class (64/128/256/512 links), longest expected work
   // first within a class; each class runs as its own launch on its own stream
   static constexpr int kClasses = 4;
@@ -387,14 +405,18 @@ struct vine_sim {
   int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
-  // vine_sim_rollout_graph: reset + full rollout captured once per record flag
+  // vine_sim_rollout_graph: reset + full rollout captured once per (rec_every, ckpt_every)
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  static constexpr int kGraphs = 4;
+  hipGraphExec_t graph[kGraphs] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_key[kGraphs][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   int trace_robot = -1, trace_cap = 0;
   double* trace = nullptr;
   int* trace_n = nullptr;
   bool traj_valid = false;  // some step since the reset recorded its joint angles
-  bool traj_all = true;     // every step since the reset did
+  bool traj_all = true;     // every step since the reset did, with the same rec_every
+  bool ckpt_all = true;     // every step since the reset wrote checkpoints (same ckpt_every)
+  bool ckpt_any = false;
   std::string err;
 };
 
@@ -406,11 +428,21 @@ int fail(vine_sim* h, int code, const std::string& msg) {
 }
 
 void drop_graphs(vine_sim* h) {
-  for (auto& g : h->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (int k = 0; k < vine_sim::kGraphs; ++k) {
+    if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+    h->graph[k] = nullptr;
+    h->graph_key[k][0] = h->graph_key[k][1] = -1;
+  }
+}
+
+void free_seg(vine_sim* h) {
+  vine_sim::Seg& g = h->seg;
+  void* ptrs[] = {g.theta, g.tip, g.rho, g.maxpen, g.traj, g.jevals, g.nsolves, g.negsteps,
+                  g.cycles, g.gsums, g.gloss, g.ncur, g.tcur, g.iters, g.status, g.ncont,
+                  g.gstat, g.chash};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  g = vine_sim::Seg();
 }
 
 void free_all(vine_sim* h) {
@@ -421,9 +453,11 @@ void free_all(vine_sim* h) {
     if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
   }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  free_seg(h);
   void* ptrs[] = {h->order, h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
-                  h->maxpen, h->traj, h->jevals, h->nsolves, h->cycles, h->trace, h->trace_n};
+                  h->maxpen, h->traj, h->ckpt, h->jevals, h->nsolves, h->negsteps, h->cycles,
+                  h->trace, h->trace_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -442,10 +476,9 @@ vs::KParams kparams(const vine_params& p) {
   k.step_max = p.step_max;
   k.c1 = p.armijo_c1;
   k.Ract = p.R_act;
+  k.pd_shift = p.pd_shift;
   k.max_iter = p.max_iter;
   k.substeps = p.growth_substeps;
-  k.dense_solver = p.solver == 1;
-  k.seq_solver = p.solver == 2;
   return k;
 }
 
@@ -473,9 +506,15 @@ vs::KData kdata(vine_sim* h) {
   D.ncont = h->ncont;
   D.chash = h->chash;
   D.maxpen = h->maxpen;
-  D.traj = h->traj;
+  D.traj = nullptr;  // set by the calls that record (advance)
+  D.rec_every = h->rec_every;
+  D.n_rec = h->n_rec;
+  D.ckpt = nullptr;
+  D.ckpt_every = h->ckpt_every;
+  D.n_ckpt = h->n_ckpt;
   D.jevals = h->jevals;
   D.nsolves = h->nsolves;
+  D.negsteps = h->negsteps;
   D.cycles = h->cycles;
   D.trace_robot = h->trace ? h->trace_robot : -1;
   D.order = h->order;
@@ -499,14 +538,13 @@ int link_class(int n) {
 // caller's stream; several fork onto the handle's class streams and join back, so
 // that short and long chains share the device.
 template <typename F>
-hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
+hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch) {
   int used = 0, only = -1;
   for (int c = 0; c < vine_sim::kClasses; ++c)
     if (h->cls_count[c] > 0) {
       ++used;
       only = c;
     }
-  vs::KData D = kdata(h);
   if (used <= 1) {
     if (only < 0) return hipSuccess;
     D.launch_first = h->cls_first[only];
@@ -526,6 +564,11 @@ hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
   return e;
 }
 
+template <typename F>
+hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
+  return for_each_class(h, stream, kdata(h), launch);
+}
+
 }  // namespace
 
 extern "C" {
@@ -541,9 +584,9 @@ void vine_params_default(vine_params* p) {
   p->c_mu = 1.0;
   p->step_max = 0.05;
   p->armijo_c1 = 1e-4;
+  p->pd_shift = 1e-8;
   p->max_iter = 500;
   p->growth_substeps = 2;
-  p->solver = 2;
   p->reserved = 0;
 }
 
@@ -557,8 +600,8 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   if (!finite_pos(p.R_c) || !finite_pos(p.R_act) || !(p.R_act > p.R_c) || !(p.a_corr >= 0.0) ||
       !std::isfinite(p.a_corr) || !(p.eps_crit > 0.0 && p.eps_crit < 1.0) || !finite_pos(p.k_c) ||
       !finite_pos(p.tol) || !(p.c_mu >= 0.0) || !std::isfinite(p.c_mu) ||
-      !finite_pos(p.step_max) || !(p.armijo_c1 > 0.0 && p.armijo_c1 < 1.0) || p.max_iter < 0 ||
-      p.growth_substeps < 1 || !(p.solver >= 0 && p.solver <= 2))
+      !finite_pos(p.step_max) || !(p.armijo_c1 > 0.0 && p.armijo_c1 < 1.0) ||
+      !finite_pos(p.pd_shift) || p.max_iter < 0 || p.growth_substeps < 1)
     return fail(nullptr, VINE_EINVAL, "invalid vine_params");
   int N = 0;
   for (int b = 0; b < n_inst; ++b) {
@@ -588,8 +631,6 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     }
     if (I.n_links > N) N = I.n_links;
   }
-  if (p.solver == 1 && N > 64)
-    return fail(nullptr, VINE_ECAPACITY, "the dense cross-check solver holds at most 64 links");
   vine_sim* h = new (std::nothrow) vine_sim();
   if (!h) return fail(nullptr, VINE_ENOMEM, "host allocation failed");
   h->prm = p;
@@ -687,6 +728,7 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->maxpen, B * TT));
   A(dalloc(&h->jevals, B));
   A(dalloc(&h->nsolves, B));
+  A(dalloc(&h->negsteps, B));
   A(dalloc(&h->cycles, B));
   if (e != hipSuccess) {
     free_all(h);
@@ -742,46 +784,107 @@ int32_t vine_sim_reset(vine_sim* h, void* stream) {
   const hipError_t e = vs::launch_reset(kdata(h), (hipStream_t)stream);
   h->traj_valid = false;
   h->traj_all = true;
+  h->ckpt_any = false;
+  h->ckpt_all = true;
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("reset: ") + hipGetErrorString(e));
   return VINE_OK;
 }
 
-static int32_t ensure_traj(vine_sim* h) {  // B * T * N doubles, allocated on first use
-  if (h->traj) return VINE_OK;
-  hipError_t e = dalloc(&h->traj, (size_t)h->B * h->T * h->N);
+// The trajectory buffer for rec_every (B x ceil(T / rec_every) x N doubles), allocated
+// on first use and again when rec_every changes (the recorded rows are then invalid).
+static int32_t ensure_traj(vine_sim* h, int rec_every) {
+  if (h->traj && h->rec_every == rec_every) return VINE_OK;
+  if (h->traj) (void)hipFree(h->traj);
+  h->traj = nullptr;
+  h->traj_valid = false;
+  drop_graphs(h);  // captured launches hold the buffer's address
+  const int rows = (h->T + rec_every - 1) / rec_every;
+  hipError_t e = dalloc(&h->traj, (size_t)h->B * rows * h->N);
   if (e != hipSuccess) {
     h->traj = nullptr;
+    h->rec_every = h->n_rec = 0;
     return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
                 std::string("trajectory allocation: ") + hipGetErrorString(e));
   }
+  h->rec_every = rec_every;
+  h->n_rec = rows;
   return VINE_OK;
 }
 
-static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
-  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
-  if (n_steps < 0) n_steps = h->T;
-  if (n_steps == 0) return VINE_OK;
-  if (record_traj) {
-    const int32_t r = ensure_traj(h);
+// The checkpoint buffer for ckpt_every (B x ceil(T / ckpt_every) x N doubles).
+static int32_t ensure_ckpt(vine_sim* h, int ckpt_every) {
+  if (h->ckpt && h->ckpt_every == ckpt_every) return VINE_OK;
+  if (h->ckpt) (void)hipFree(h->ckpt);
+  h->ckpt = nullptr;
+  h->ckpt_any = false;
+  drop_graphs(h);
+  const int rows = (h->T + ckpt_every - 1) / ckpt_every;
+  hipError_t e = dalloc(&h->ckpt, (size_t)h->B * rows * h->N);
+  if (e != hipSuccess) {
+    h->ckpt = nullptr;
+    h->ckpt_every = h->n_ckpt = 0;
+    return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
+                std::string("checkpoint allocation: ") + hipGetErrorString(e));
+  }
+  h->ckpt_every = ckpt_every;
+  h->n_ckpt = rows;
+  return VINE_OK;
+}
+
+// KData of a launch that records every rec_every-th step (0: none) and checkpoints
+// every ckpt_every-th (0: none); the buffers must exist.
+static vs::KData kdata_rec(vine_sim* h, int rec_every, int ckpt_every) {
+  vs::KData D = kdata(h);
+  if (rec_every > 0) D.traj = h->traj;
+  if (ckpt_every > 0) D.ckpt = h->ckpt;
+  return D;
+}
+
+static int32_t check_rec(vine_sim* h, int32_t record_every, int32_t ckpt_every) {
+  if (record_every < 0 || ckpt_every < 0)
+    return fail(h, VINE_EINVAL, "record_every and ckpt_every must be >= 0");
+  if (record_every > 0) {
+    const int32_t r = ensure_traj(h, record_every);
     if (r != VINE_OK) return r;
   }
-  const vs::KParams kp = kparams(h->prm);
-  hipError_t e = for_each_class(h, (hipStream_t)stream,
-                                [&](int links, const vs::KData& D, hipStream_t s) {
-                                  return vs::launch_rollout(kp, D, n_steps, record_traj, links, s);
-                                });
-  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
-  if (record_traj) h->traj_valid = true; else h->traj_all = false;
+  if (ckpt_every > 0) {
+    const int32_t r = ensure_ckpt(h, ckpt_every);
+    if (r != VINE_OK) return r;
+  }
   return VINE_OK;
 }
 
-int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
-  if (n_steps < 0) return fail(h, VINE_EINVAL, "n_steps < 0");
-  return advance(h, n_steps, record_traj, stream);
+static void note_rec(vine_sim* h, int32_t record_every, int32_t ckpt_every) {
+  if (record_every > 0) h->traj_valid = true; else h->traj_all = false;
+  if (ckpt_every > 0) h->ckpt_any = true; else h->ckpt_all = false;
 }
 
-int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_traj, void* stream) {
-  return advance(h, n_steps < 0 ? -1 : n_steps, record_traj, stream);
+static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_every, int32_t ckpt_every,
+                       void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  if (n_steps < 0) n_steps = h->T;
+  int32_t r = check_rec(h, record_every, ckpt_every);
+  if (r != VINE_OK) return r;
+  if (n_steps == 0) return VINE_OK;
+  const vs::KParams kp = kparams(h->prm);
+  hipError_t e = for_each_class(h, (hipStream_t)stream, kdata_rec(h, record_every, ckpt_every),
+                                [&](int links, const vs::KData& D, hipStream_t s) {
+                                  return vs::launch_rollout(kp, D, n_steps, links, s);
+                                });
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+  note_rec(h, record_every, ckpt_every);
+  return VINE_OK;
+}
+
+int32_t vine_sim_step(vine_sim* h, int32_t n_steps, int32_t record_every, int32_t ckpt_every,
+                      void* stream) {
+  if (n_steps < 0) return fail(h, VINE_EINVAL, "n_steps < 0");
+  return advance(h, n_steps, record_every, ckpt_every, stream);
+}
+
+int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_every, int32_t ckpt_every,
+                         void* stream) {
+  return advance(h, n_steps < 0 ? -1 : n_steps, record_every, ckpt_every, stream);
 }
 
 int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
@@ -804,14 +907,28 @@ int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
   return VINE_OK;
 }
 
-int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream) {
+int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_every,
+                               void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
-  const int g = record_traj ? 1 : 0;
-  if (g) {
-    const int32_t r = ensure_traj(h);
-    if (r != VINE_OK) return r;
-  }
-  if (!h->graph[g]) {
+  int32_t r = check_rec(h, record_every, ckpt_every);
+  if (r != VINE_OK) return r;
+  int g = -1;
+  for (int k = 0; k < vine_sim::kGraphs; ++k)
+    if (h->graph[k] && h->graph_key[k][0] == record_every && h->graph_key[k][1] == ckpt_every)
+      g = k;
+  if (g < 0) {
+    for (int k = 0; k < vine_sim::kGraphs && g < 0; ++k)
+      if (!h->graph[k]) g = k;
+    if (g < 0) {  // all slots taken: drop the oldest capture
+      (void)hipGraphExecDestroy(h->graph[0]);
+      for (int k = 1; k < vine_sim::kGraphs; ++k) {
+        h->graph[k - 1] = h->graph[k];
+        h->graph_key[k - 1][0] = h->graph_key[k][0];
+        h->graph_key[k - 1][1] = h->graph_key[k][1];
+      }
+      g = vine_sim::kGraphs - 1;
+      h->graph[g] = nullptr;
+    }
     // capture on a stream of the handle's own (the caller's may be the null stream);
     // the class streams join the capture through the fork/join events
     hipError_t e = hipSuccess;
@@ -822,9 +939,10 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream) {
       const vs::KParams kp = kparams(h->prm);
       hipError_t le = vs::launch_reset(kdata(h), h->cap_stream);
       if (le == hipSuccess)
-        le = for_each_class(h, h->cap_stream, [&](int links, const vs::KData& D, hipStream_t s) {
-          return vs::launch_rollout(kp, D, h->T, g, links, s);
-        });
+        le = for_each_class(h, h->cap_stream, kdata_rec(h, record_every, ckpt_every),
+                            [&](int links, const vs::KData& D, hipStream_t s) {
+                              return vs::launch_rollout(kp, D, h->T, links, s);
+                            });
       e = hipStreamEndCapture(h->cap_stream, &graph);  // ends the capture in every case
       if (e == hipSuccess) e = le;
     }
@@ -834,12 +952,53 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_traj, void* stream) {
       h->graph[g] = nullptr;
       return fail(h, VINE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     }
+    h->graph_key[g][0] = record_every;
+    h->graph_key[g][1] = ckpt_every;
   }
   const hipError_t e = hipGraphLaunch(h->graph[g], (hipStream_t)stream);
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-  h->traj_valid = g != 0;  // as after vine_sim_reset + vine_sim_rollout
-  h->traj_all = g != 0;
+  // as after vine_sim_reset + vine_sim_rollout
+  h->traj_valid = record_every > 0;
+  h->traj_all = record_every > 0;
+  h->ckpt_any = ckpt_every > 0;
+  h->ckpt_all = ckpt_every > 0;
   return VINE_OK;
+}
+
+// Segment buffers for recomputing ckpt_every steps from a checkpoint.
+static hipError_t ensure_seg(vine_sim* h) {
+  vine_sim::Seg& g = h->seg;
+  if (g.theta && g.steps == h->ckpt_every) return hipSuccess;
+  free_seg(h);
+  const size_t B = h->B, N = h->N, C = h->ckpt_every;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  A(dalloc(&g.theta, B * N));
+  A(dalloc(&g.ncur, B));
+  A(dalloc(&g.tcur, B));
+  A(dalloc(&g.tip, B * C * 3));
+  A(dalloc(&g.rho, B * C));
+  A(dalloc(&g.iters, B * C));
+  A(dalloc(&g.status, B * C));
+  A(dalloc(&g.ncont, B * C));
+  A(dalloc(&g.chash, B * C));
+  A(dalloc(&g.maxpen, B * C));
+  A(dalloc(&g.traj, B * C * N));
+  A(dalloc(&g.jevals, B));
+  A(dalloc(&g.nsolves, B));
+  A(dalloc(&g.negsteps, B));
+  A(dalloc(&g.cycles, B));
+  A(dalloc(&g.gsums, B * vs::kWave * 3));
+  A(dalloc(&g.gloss, B));
+  A(dalloc(&g.gstat, B));
+  if (e != hipSuccess) {
+    free_seg(h);
+    return e;
+  }
+  g.steps = h->ckpt_every;
+  return hipSuccess;
 }
 
 int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,
@@ -848,17 +1007,67 @@ int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weight
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   if (!goal || !loss || (h->S > 0 && (!dL_dP || !dL_ds_start || !dL_ds_end)))
     return fail(h, VINE_EINVAL, "null goal, loss or gradient pointer");
-  if (step_weights && !(h->traj_valid && h->traj_all))
+  const bool full_traj = h->traj_valid && h->traj_all && h->rec_every == 1;
+  const bool from_ckpt = h->ckpt && h->ckpt_any && h->ckpt_all;
+  if (step_weights && !full_traj && !from_ckpt)
     return fail(h, VINE_ESTATE,
-                "step weights need the joint angles of every step since the reset "
-                "(record_traj on every step/rollout call)");
+                "step weights need the joint angles of every step since the reset: record "
+                "every step (record_every = 1) or checkpoints (ckpt_every > 0) on every "
+                "step/rollout call");
+  hipStream_t s = (hipStream_t)stream;
   const vs::KParams kp = kparams(h->prm);
-  hipError_t e = vs::launch_zero3(dL_dP, dL_ds_start, dL_ds_end, h->S, (hipStream_t)stream);
-  if (e == hipSuccess)
-    e = for_each_class(h, (hipStream_t)stream, [&](int links, const vs::KData& D, hipStream_t s) {
-      return vs::launch_grad(kp, D, goal, step_weights, h->T, dL_dP, dL_ds_start, dL_ds_end,
-                             loss, adj_status, links, s);
+  hipError_t e = vs::launch_zero3(dL_dP, dL_ds_start, dL_ds_end, h->S, s);
+  if (e == hipSuccess && (!step_weights || full_traj)) {
+    const vs::GradPart one{nullptr, nullptr, nullptr, 1, 1};
+    e = for_each_class(h, s, [&](int links, const vs::KData& D, hipStream_t cs) {
+      return vs::launch_grad(kp, D, goal, step_weights, h->T, 0, h->traj, h->n_rec, one, dL_dP,
+                             dL_ds_start, dL_ds_end, loss, adj_status, links, cs);
     });
+  } else if (e == hipSuccess) {
+    // recompute the states of each checkpoint segment (the same kernel from the same
+    // state, so bitwise the states of the rollout), then its terms of the adjoint
+    e = ensure_seg(h);
+    if (e != hipSuccess)
+      return fail(h, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
+                  std::string("segment allocation: ") + hipGetErrorString(e));
+    const vine_sim::Seg& g = h->seg;
+    vs::KData Dseg = kdata(h);
+    Dseg.t_max = h->ckpt_every;
+    Dseg.theta = g.theta;
+    Dseg.ncur = g.ncur;
+    Dseg.tcur = g.tcur;
+    Dseg.tip = g.tip;
+    Dseg.rho = g.rho;
+    Dseg.iters = g.iters;
+    Dseg.status = g.status;
+    Dseg.ncont = g.ncont;
+    Dseg.chash = g.chash;
+    Dseg.maxpen = g.maxpen;
+    Dseg.traj = g.traj;
+    Dseg.rec_every = 1;
+    Dseg.n_rec = h->ckpt_every;
+    Dseg.ckpt = nullptr;
+    Dseg.jevals = g.jevals;
+    Dseg.nsolves = g.nsolves;
+    Dseg.negsteps = g.negsteps;
+    Dseg.cycles = g.cycles;
+    Dseg.trace_robot = -1;
+    const int ce = h->ckpt_every;
+    for (int q = 0; q < h->n_ckpt && e == hipSuccess; ++q) {
+      const int t0 = q * ce, len = std::min(ce, h->T - t0);
+      e = vs::launch_seg_load(Dseg, h->ckpt, h->tcur, h->n_ckpt, q, ce, s);
+      if (e == hipSuccess)
+        e = for_each_class(h, s, Dseg, [&](int links, const vs::KData& D, hipStream_t cs) {
+          return vs::launch_rollout(kp, D, len, links, cs);
+        });
+      const vs::GradPart part{g.gsums, g.gloss, g.gstat, q == 0, q == h->n_ckpt - 1};
+      if (e == hipSuccess)
+        e = for_each_class(h, s, [&](int links, const vs::KData& D, hipStream_t cs) {
+          return vs::launch_grad(kp, D, goal, step_weights + t0, len, t0, g.traj, ce, part,
+                                 dL_dP, dL_ds_start, dL_ds_end, loss, adj_status, links, cs);
+        });
+    }
+  }
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   return VINE_OK;
 }
@@ -907,10 +1116,12 @@ int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {
     case VINE_F_NCONTACT: return 4 * B * T;
     case VINE_F_CHASH: return 8 * B * T;
     case VINE_F_MAXPEN: return 8 * B * T;
-    case VINE_F_TRAJ: return 8 * B * T * N;
+    case VINE_F_TRAJ: return 8 * B * h->n_rec * N;
     case VINE_F_JEVALS: return 8 * B;
     case VINE_F_NSOLVES: return 8 * B;
     case VINE_F_CYCLES: return 8 * B;
+    case VINE_F_NEGSTEPS: return 8 * B;
+    case VINE_F_CKPT: return 8 * B * h->n_ckpt * N;
     default: return 0;
   }
 }
@@ -937,6 +1148,11 @@ int32_t vine_sim_read(const vine_sim* hc, int32_t field, void* dst, int32_t dst_
     case VINE_F_JEVALS: src = h->jevals; break;
     case VINE_F_NSOLVES: src = h->nsolves; break;
     case VINE_F_CYCLES: src = h->cycles; break;
+    case VINE_F_NEGSTEPS: src = h->negsteps; break;
+    case VINE_F_CKPT:
+      if (!h->ckpt_any) return fail(h, VINE_ESTATE, "no checkpoints were written");
+      src = h->ckpt;
+      break;
     default: return fail(h, VINE_EINVAL, "unknown field");
   }
   size_t bytes = (size_t)vine_sim_field_bytes(h, field);
@@ -1096,8 +1312,6 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max
   if (max_links > VINE_MAX_LINKS || max_obstacles > VINE_MAX_OBSTACLES ||
       max_spams > VINE_MAX_SPAMS)
     return sfail(nullptr, VINE_ECAPACITY, "bounds above the library's limits");
-  if (params->solver == 1)
-    return sfail(nullptr, VINE_EINVAL, "the dense cross-check solver is not served");
   // the slab: `slots` placeholder robots at the bounds (overwritten on admission)
   vine_instance ph{};
   ph.n_links = max_links;
@@ -1284,7 +1498,7 @@ int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
   if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch set-up: ") + hipGetErrorString(e));
   const vs::KParams kp = kparams(h->prm);
   e = for_each_class(h, st, [&](int links, const vs::KData& D, hipStream_t ss) {
-    return vs::launch_rollout(kp, D, steps, 0, links, ss);
+    return vs::launch_rollout(kp, D, steps, links, ss);
   });
   std::vector<int> ncur(s->slots);
   A(hipMemcpyAsync(ncur.data(), h->ncur, sizeof(int) * s->slots, hipMemcpyDeviceToHost, st));

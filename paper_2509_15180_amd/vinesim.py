@@ -26,8 +26,9 @@ ST_DONE, ST_CONVERGED, ST_MAXITER, ST_NODESCENT, ST_CAPACITY, ST_NONFINITE = -1,
 FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np.float64, "BT3"),
               rho=(3, np.float64, "BT"), iters=(4, np.int32, "BT"), status=(5, np.int32, "BT"),
               ncont=(6, np.int32, "BT"), chash=(7, np.uint64, "BT"), maxpen=(8, np.float64, "BT"),
-              traj=(9, np.float64, "BTN"), jevals=(10, np.float64, "B"),
-              nsolves=(11, np.float64, "B"), cycles=(12, np.float64, "B"))
+              traj=(9, np.float64, "BRN"), jevals=(10, np.float64, "B"),
+              nsolves=(11, np.float64, "B"), cycles=(12, np.float64, "B"),
+              negsteps=(13, np.float64, "B"), ckpt=(14, np.float64, "BCN"))
 
 MAX_LINKS = 512
 MAX_OBSTACLES = 128
@@ -44,8 +45,8 @@ class Params(C.Structure):
     _fields_ = [("R_c", C.c_double), ("R_act", C.c_double), ("a_corr", C.c_double),
                 ("eps_crit", C.c_double), ("k_c", C.c_double), ("tol", C.c_double),
                 ("c_mu", C.c_double), ("step_max", C.c_double), ("armijo_c1", C.c_double),
-                ("max_iter", C.c_int32), ("growth_substeps", C.c_int32), ("solver", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("pd_shift", C.c_double), ("max_iter", C.c_int32),
+                ("growth_substeps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Instance(C.Structure):
@@ -92,11 +93,11 @@ def lib():
                                       C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle), C.c_int32,
                                       C.POINTER(vp)]
         L.vine_sim_create.restype = C.c_int32
-        L.vine_sim_step.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.vine_sim_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
         L.vine_sim_step.restype = C.c_int32
-        L.vine_sim_rollout.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.vine_sim_rollout.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
         L.vine_sim_rollout.restype = C.c_int32
-        L.vine_sim_rollout_graph.argtypes = [vp, C.c_int32, vp]
+        L.vine_sim_rollout_graph.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.vine_sim_rollout_graph.restype = C.c_int32
         L.vine_sim_tune_order.argtypes = [vp, vp]
         L.vine_sim_tune_order.restype = C.c_int32
@@ -200,24 +201,37 @@ class VineSim:
         L.vine_sim_dims(h, dims)
         self.B, self.T, self.N = int(dims[0]), int(dims[1]), int(dims[2])
         self.S = int(len(work.spam))
+        self.rec_every = 0   # as last passed with a nonzero value (shape of "traj")
+        self.ckpt_every = 0  # likewise for "ckpt"
 
     def _check(self, rc):
         if rc != VINE_OK:
             raise VineError(rc, lib().vine_sim_last_error(self.h).decode())
 
-    def step(self, n_steps: int, record_traj: bool = False, stream=None):
-        self._check(lib().vine_sim_step(self.h, int(n_steps), int(bool(record_traj)),
+    def _note(self, record_every, ckpt_every):
+        if record_every:
+            self.rec_every = int(record_every)
+        if ckpt_every:
+            self.ckpt_every = int(ckpt_every)
+
+    def step(self, n_steps: int, record_every: int = 0, ckpt_every: int = 0, stream=None):
+        self._check(lib().vine_sim_step(self.h, int(n_steps), int(record_every), int(ckpt_every),
                                         _stream_ptr(stream)))
+        self._note(record_every, ckpt_every)
 
-    def rollout(self, n_steps: int = -1, record_traj: bool = False, stream=None):
-        self._check(lib().vine_sim_rollout(self.h, int(n_steps), int(bool(record_traj)),
-                                           _stream_ptr(stream)))
+    def rollout(self, n_steps: int = -1, record_every: int = 0, ckpt_every: int = 0,
+                stream=None):
+        self._check(lib().vine_sim_rollout(self.h, int(n_steps), int(record_every),
+                                           int(ckpt_every), _stream_ptr(stream)))
+        self._note(record_every, ckpt_every)
 
-    def rollout_graph(self, record_traj: bool = False, stream=None):
+    def rollout_graph(self, record_every: int = 0, ckpt_every: int = 0, stream=None):
         """Reset and roll every robot out to full length as one captured HIP graph
-        (captured on the first call for each record_traj, replayed afterwards)."""
-        self._check(lib().vine_sim_rollout_graph(self.h, int(bool(record_traj)),
+        (captured on the first call for each (record_every, ckpt_every), replayed
+        afterwards)."""
+        self._check(lib().vine_sim_rollout_graph(self.h, int(record_every), int(ckpt_every),
                                                  _stream_ptr(stream)))
+        self._note(record_every, ckpt_every)
 
     def tune_order(self, stream=None):
         """Launch order by the cycles each robot measured since the last reset (longest first)."""
@@ -228,7 +242,9 @@ class VineSim:
 
     def field_shape(self, name: str):
         code, dt, shp = FIELDS[name]
-        dims = dict(B=self.B, T=self.T, N=self.N, **{"3": 3})
+        ceil = lambda a, b: -(-a // b) if b else 0
+        dims = dict(B=self.B, T=self.T, N=self.N, R=ceil(self.T, self.rec_every),
+                    C=ceil(self.T, self.ckpt_every), **{"3": 3})
         return tuple(dims[c] for c in shp), dt, code
 
     def read(self, name: str, out=None, stream=None):
@@ -250,7 +266,7 @@ class VineSim:
         return out
 
     def read_all(self, traj: bool = False) -> dict:
-        names = [k for k in FIELDS if k != "traj"] + (["traj"] if traj else [])
+        names = [k for k in FIELDS if k not in ("traj", "ckpt")] + (["traj"] if traj else [])
         return {k: self.read(k) for k in names}
 
     def spam_law(self, l: float, eps):

@@ -8,12 +8,11 @@ Every instance ``i`` of workload ``cfg`` draws from its own generator
 ``PCG64(SeedSequence([250915180, cfg, i]))``, so the first ``B`` instances of
 a large batch are the same robots as a batch of size ``B``.
 
-Units are SI (m, Pa, rad).  The robot base sits at the origin.  The one-robot
-workload (circles only) heads along +x.  The rectangle workloads draw the base
-heading from U[-10, 10] degrees: with a heading of exactly +x the straight
-initial body is exactly parallel or perpendicular to every axis-aligned
-rectangle side, and head-on contact becomes an exactly symmetric buckling
-point that no descent can resolve.
+Units are SI (m, Pa, rad).  The robot base sits at the origin and heads along
++x in every workload, so the straight initial body is exactly parallel or
+perpendicular to every axis-aligned rectangle side; head-on contacts are then
+exactly symmetric buckling points, which the solvers resolve by their
+negative-curvature rule.
 
 Layout of a :class:`Workload` (structure of arrays, host memory):
 
@@ -34,7 +33,6 @@ SEED_ROOT = 250915180
 
 CIRCLE = 0
 RECT = 1
-HEADING_SPREAD = np.deg2rad(10.0)
 
 
 def instance_rng(cfg: int, i: int) -> np.random.Generator:
@@ -186,7 +184,7 @@ def config2(B: int = 4096, start: int = 0) -> Workload:
     l, R = 0.02, 0.025
     for i in range(start, start + B):
         rng = instance_rng(2, i)
-        psi = rng.uniform(-HEADING_SPREAD, HEADING_SPREAD)
+        psi = 0.0
         pv = rng.uniform(2000.0, 6000.0)
         spam = _sample_spams_links(rng, 64, int(rng.integers(0, 5)), l, (0.0, 20000.0))
         kind, obs = _sample_obstacles(rng, 10, 10, ((0.0, 1.5), (-0.75, 0.75)), (0.02, 0.10),
@@ -202,7 +200,7 @@ def config3(B: int = 16384, start: int = 0) -> Workload:
     l, R = 0.02, 0.025
     for i in range(start, start + B):
         rng = instance_rng(3, i)
-        psi = rng.uniform(-HEADING_SPREAD, HEADING_SPREAD)
+        psi = 0.0
         n = int(rng.integers(16, 257))
         K = int(rng.integers(0, 65))
         pv = rng.uniform(2000.0, 6000.0)
@@ -220,7 +218,7 @@ def config4(B: int = 4096, start: int = 0) -> Workload:
     l, R, n = 0.02, 0.025, 96
     for i in range(start, start + B):
         rng = instance_rng(4, i)
-        psi = rng.uniform(-HEADING_SPREAD, HEADING_SPREAD)
+        psi = 0.0
         pv = rng.uniform(2000.0, 6000.0)
         rows = []
         for _ in range(int(rng.integers(1, 5))):
@@ -258,7 +256,7 @@ def config5_requests(n_req: int, rate: float = 2000.0, start: int = 0,
     for j in range(start, start + n_req):
         t += float(gaps[j])
         rng = instance_rng(5, j)
-        psi = rng.uniform(-HEADING_SPREAD, HEADING_SPREAD)
+        psi = 0.0
         n = int(rng.integers(16, n_max + 1))
         K = int(rng.integers(0, k_max + 1))
         S = int(rng.integers(1, s_max + 1))

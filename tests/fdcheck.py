@@ -69,10 +69,17 @@ def fd_values(cases: list[Case], Lpm: np.ndarray) -> np.ndarray:
     return np.array([(Lpm[2 * i] - Lpm[2 * i + 1]) / (2 * c.h) for i, c in enumerate(cases)])
 
 
-def smooth(cases: list[Case], chash_pm: np.ndarray, chash_base: np.ndarray) -> np.ndarray:
-    """True where neither perturbed rollout changed the contact set at any step."""
+def smooth(cases: list[Case], chash_pm: np.ndarray, chash_base: np.ndarray,
+           neg_pm=None, neg_base=None) -> np.ndarray:
+    """True where neither perturbed rollout changed the contact set at any step and (when
+    the counts are given) neither took a different number of steps along negative
+    curvature than the base rollout: a changed count means the descent passed a
+    bifurcation of the equilibrium within +-h, where the loss is not differentiable."""
     ok = []
     for i, c in enumerate(cases):
-        ok.append(bool((chash_pm[2 * i] == chash_base[c.robot]).all()
-                       and (chash_pm[2 * i + 1] == chash_base[c.robot]).all()))
+        same = bool((chash_pm[2 * i] == chash_base[c.robot]).all()
+                    and (chash_pm[2 * i + 1] == chash_base[c.robot]).all())
+        if neg_pm is not None:
+            same = same and neg_pm[2 * i] == neg_base[c.robot] == neg_pm[2 * i + 1]
+        ok.append(same)
     return np.array(ok)

@@ -80,7 +80,7 @@ def test_null_handle_calls_fail_cleanly():
     assert L.vine_sim_set_spams(None, None, 0, None) == V.VINE_EINVAL
     assert L.vine_sim_grad(None, None, None, None, None, None, None, None, None) == V.VINE_EINVAL
     assert L.vine_sim_reset(None, None) == V.VINE_EINVAL
-    assert L.vine_sim_rollout_graph(None, 0, None) == V.VINE_EINVAL
+    assert L.vine_sim_rollout_graph(None, 0, 0, None) == V.VINE_EINVAL
     assert L.vine_sim_tune_order(None, None) == V.VINE_EINVAL
 
 

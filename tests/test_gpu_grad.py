@@ -27,11 +27,11 @@ def _sim(work):
     return V.VineSim(work)
 
 
-def _gpu(work, weights=None, traj=True):
+def _gpu(work, weights=None, traj=True, ckpt=0):
     import torch
     with _sim(work) as sim:
         s = torch.cuda.current_stream()
-        sim.rollout(-1, record_traj=traj, stream=s)
+        sim.rollout(-1, record_every=1 if traj else 0, ckpt_every=ckpt, stream=s)
         g = sim.grad(work.goal, weights, stream=s)
         s.synchronize()
         out = sim.read_all()
@@ -81,7 +81,7 @@ def test_grad_matches_fd_of_gpu_rollouts():
         s.synchronize()
         o = sim.read_all()
     fd = fd_values(cases, losses(o["tip"], wp.goal))
-    ok = smooth(cases, o["chash"], base["chash"])
+    ok = smooth(cases, o["chash"], base["chash"], o["negsteps"], base["negsteps"])
     g = {"P": dP, "s0": d0, "s1": d1}
     adj = np.array([g[c.name][c.spam] for c in cases])
     assert ok.sum() >= 10
@@ -96,8 +96,8 @@ def test_grad_needs_recorded_trajectory():
     w = W.config4(16).subset([1])
     with _sim(w) as sim:
         s = torch.cuda.current_stream()
-        sim.rollout(10, record_traj=True, stream=s)
-        sim.rollout(-1, record_traj=False, stream=s)
+        sim.rollout(10, record_every=1, stream=s)
+        sim.rollout(-1, record_every=0, stream=s)
         with pytest.raises(V.VineError) as ei:
             sim.grad(w.goal, np.ones(sim.T), stream=s)
         assert ei.value.code == V.VINE_ESTATE
@@ -105,6 +105,53 @@ def test_grad_needs_recorded_trajectory():
         g = sim.grad(w.goal, None, stream=s)
         s.synchronize()
         assert np.isfinite(g[0].cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("ce", [32, 7])
+def test_grad_from_checkpoints_is_bitwise_the_full_trajectory(ce):
+    """A trajectory loss from checkpoints every ce steps (the states recomputed segment
+    by segment) equals, bit for bit, the one from the recorded trajectory; also when the
+    rollout is taken in several calls."""
+    import torch
+    w = W.config4(16).subset(ROBOTS)
+    weights = np.zeros(96)
+    weights[3::5] = 0.3
+    weights[-1] = 1.0
+    _, full = _gpu(w, weights, traj=True)
+    _, ck = _gpu(w, weights, traj=False, ckpt=ce)
+    with _sim(w) as sim:
+        s = torch.cuda.current_stream()
+        for _ in range(5):
+            sim.step(20, ckpt_every=ce, stream=s)
+        parts = tuple(x.cpu().numpy() for x in sim.grad(w.goal, weights, stream=s))
+        ck_rows = sim.read("ckpt")
+    assert ck_rows.shape == (w.n_inst, -(-96 // ce), 96)
+    print(f"ckpt_every={ce}: checkpoint rows {ck_rows.shape[1]}, "
+          f"loss {full[3].sum():.6e}", flush=True)
+    for a, b, c in zip(full, ck, parts):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_adjoint_flags_unconverged_steps():
+    """A rollout cut off by the iteration limit (max_iter = 1) is flagged (bit 1) by the
+    adjoint of its weighted steps, and the autograd bridge refuses it."""
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    from paper_2509_15180_amd.autograd import rollout_loss
+    w = W.config4(16).subset([1, 2])
+    with V.VineSim(w, V.default_params(max_iter=1)) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, record_every=1, stream=s)
+        dP, d0, d1, loss, st = sim.grad(w.goal, np.ones(96), stream=s)
+        s.synchronize()
+        status = sim.read("status")
+        assert (status == 1).any()
+        assert np.all((st.cpu().numpy() & 2) == 2)
+        P = torch.tensor(w.spam[:, 3], dtype=torch.float64, requires_grad=True)
+        with pytest.raises(V.VineError):
+            rollout_loss(sim, P, torch.tensor(w.spam[:, 0]), torch.tensor(w.spam[:, 1]),
+                         w.spam[:, 2], w.goal, np.ones(96))
 
 
 def test_grad_full_batch_sampled():

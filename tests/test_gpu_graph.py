@@ -18,12 +18,15 @@ def _replays_match(work, record):
     s = torch.cuda.current_stream()
     with V.VineSim(work) as sim, V.VineSim(work.subset([0])) as other:
         sim.reset(stream=s)
-        sim.rollout(-1, record_traj=record, stream=s)
+        sim.rollout(-1, record_every=1 if record else 0, ckpt_every=32 if record else 0, stream=s)
         s.synchronize()
         ref = sim.read_all(traj=record)
+        if record:
+            ref["ckpt"] = sim.read("ckpt")
         for rep in range(3):
-            print(f"replay {rep} (record_traj={record}, {work.n_inst} robots)", flush=True)
-            sim.rollout_graph(record_traj=record, stream=s)
+            print(f"replay {rep} (record={record}, {work.n_inst} robots)", flush=True)
+            sim.rollout_graph(record_every=1 if record else 0, ckpt_every=32 if record else 0,
+                              stream=s)
             # eager work between replays: another handle's launches and a torch reduction
             other.reset(stream=s)
             other.rollout(-1, stream=s)
@@ -31,6 +34,8 @@ def _replays_match(work, record):
             s.synchronize()
             assert float(total) == float(1 << 20)
             got = sim.read_all(traj=record)
+            if record:
+                got["ckpt"] = sim.read("ckpt")
             for k in ref:
                 if k != "cycles":  # timing, not a result
                     assert np.array_equal(got[k], ref[k]), (rep, k)
