@@ -360,8 +360,163 @@ def test_symmetries():
     assert np.allclose(rt["theta"], base["theta"], atol=1e-7)
 
 
-def test_config2_converges_without_tunnelling():
-    out = O.rollout(W.config2(8), threads=8)
+# --- equilibria are minima; contact behaviours of Sec. 4.1 and Sec. 6 ------------
+
+def _headon(kind, obs, n=40, l=0.02):
+    return dict(n=n, d=(l, 0.025, 3000.0, 0.0, 0.0, 0.0), spam=[], kind=[kind], obs=[obs])
+
+
+@pytest.mark.parametrize("kind,obs", [(0, (0.3, 0.0, 0.05, 0.0)), (1, (0.3, 0.0, 0.05, 0.05)),
+                                      (1, (0.45, 0.0, 0.1, 0.4))])
+def test_head_on_contact_buckles_near_the_base(kind, obs):
+    """Heading +x into an obstacle centred on the axis: the straight chain pushed head-on is
+    a stationary point of the energy but a saddle (Eq. 4 asks for a minimum), so the
+    descent leaves it along its buckling mode; no link passes into the obstacle, and the
+    chain bends most at a joint near its base (Sec. 6: the head-on robot buckles at a point
+    near its base)."""
+    out = O.rollout(W.pack([_headon(kind, obs)], "h"), threads=1)
     assert np.all(out["status"] == 0)
-    assert np.all(out["rho"] <= 1e-10)
-    assert out["maxpen"].max() < 0.01  # no link passes into an obstacle
+    assert out["maxpen"].max() <= 1e-3
+    assert out["stats"][0, 4] > 0 and out["stats"][0, 5] > 0  # left the saddle by the tie rule
+    th = out["theta"][0]
+    assert np.argmax(np.abs(th)) <= 2
+    assert abs(out["tip"][0, -1, 1]) > 0.05  # off the axis: buckled, not pushed through
+
+
+def test_stuck_tip_coils():
+    """A tip stuck in a corner (a cup of three walls): growth goes on, so the body turns
+    back on itself (Sec. 4.1: a tip stuck in a corner or head-on lets growth dominate and
+    the vine coils), without passing through a wall."""
+    obs = [(0.8, 0.0, 0.5, 1.0), (0.175, 0.37, 0.125, 0.25), (0.175, -0.37, 0.125, 0.25)]
+    it = dict(n=50, d=(0.02, 0.025, 3000.0, 0, 0, 0), spam=[], kind=[1, 1, 1], obs=obs)
+    out = O.rollout(W.pack([it], "cup"), traj=True, threads=1)
+    assert np.all(out["status"] == 0) and out["maxpen"].max() <= 1e-3
+    heading = np.cumsum(out["traj"][0], 1)
+    assert np.abs(heading[-1]).max() > 2.5  # turned back on itself
+    assert np.all(out["tip"][0, :, 0] <= 0.3 + 1e-3)
+
+
+def test_acute_and_obtuse_contact_change_curvature_in_opposite_senses():
+    """An sPAM curves the body toward +y; an obstacle met on the outer side of the curve
+    pushes along the curvature (bend into the contact normal: curvature increases), one on
+    the inner side pushes against it (curvature decreases) -- the acute and obtuse
+    single-obstacle cases of Sec. 6."""
+    l, R, n = 0.02, 0.025, 60
+    spam = [(5 * l, 40 * l, 1.0, 6000.0)]
+    free = dict(n=n, d=(l, R, 3000.0, 0, 0, 0), spam=spam, kind=[], obs=[])
+    f = O.rollout(W.pack([free], "f"), threads=1)
+    p, hd = f["tip"][0, 35, :2], f["tip"][0, 35, 2]
+    left = np.array([-np.sin(hd), np.cos(hd)])
+    r = 0.08
+    items = [dict(free, kind=[0], obs=[(*(p + side * left * (r + R - 0.015)), r, 0.0)])
+             for side in (-1.0, 1.0)]
+    out = O.rollout(W.pack(items, "s"), threads=2)
+    assert np.all(out["status"] == 0) and out["ncont"].max(1).min() >= 1
+    turn_free = f["theta"][0].sum()
+    assert out["theta"][0].sum() > turn_free + 1e-3   # outer side: curvature increases
+    assert out["theta"][1].sum() < turn_free - 1e-3   # inner side: curvature decreases
+
+
+@pytest.fixture(scope="module")
+def cfg2_256():
+    w = W.config2(256)
+    return w, O.rollout(w, traj=True, threads=8)
+
+
+def test_accepted_states_are_minima(cfg2_256):
+    """Every converged growth step of 256 uniform-batch robots is a local minimum: the
+    smallest eigenvalue of the exact Hessian (numpy's symmetric eigensolver, independent of
+    the solver's LDL^T) exceeds -delta, delta = 1e-8 M_max."""
+    w, out = cfg2_256
+    assert np.all(out["status"] == 0)
+    lam_min = np.inf
+    for b in range(w.n_inst):
+        inst = w.instance(b)
+        d = inst["d"]
+        Mmax = np.pi * d[2] * d[1] ** 3
+        for t in range(64):
+            H = O.chain_hessian(inst, out["traj"][b, t, :t + 1])
+            lam = np.linalg.eigvalsh(H)[0] / Mmax
+            lam_min = min(lam_min, lam)
+            assert lam > -1e-8, (b, t, lam)
+    print(f"smallest Hessian eigenvalue over 16384 accepted states: {lam_min:.3e} M_max/rad")
+
+
+def _wedged(inst, th, prm=None):
+    """(wedged, deepest penetration, deepest penetration on the opposite side): the deepest
+    disk is pressed between obstacles whose outward normals oppose (n1 . n2 < -0.5)."""
+    Pi, r, cont = O.chain_eval(inst, th, prm=prm)
+    e = int(np.argmax(cont[:, 7]))
+    x, n0 = cont[e, 3:5], cont[e, 5:7]
+    at = np.nonzero(np.all(np.abs(cont[:, 3:5] - x) < 1e-12, axis=1))[0]
+    opp = [f for f in at if np.dot(cont[f, 5:7], n0) < -0.5]
+    return bool(opp), cont[e, 7], max([cont[f, 7] for f in opp], default=0.0)
+
+
+def test_penetration_within_tolerance(cfg2_256):
+    """Zero penetration beyond tol_pen = 1 mm on >= 99.9 % of the converged contact states
+    of 256 uniform-batch robots (the penalty stiffness k_c = 1e4 N/m), not counting states
+    whose deepest disk is wedged between obstacles closer than the tube's diameter: there
+    the overlap is set by geometry, not by the stiffness (a disk squeezed equally from both
+    sides overlaps each by half the shortfall of the gap), and the pin bounds instead the
+    deepest penetration's excess over that equal share, (p1 - p2) / 2, by 1 mm."""
+    w, out = cfg2_256
+    conv = (out["status"] == 0) & (out["ncont"] > 0)
+    deep = np.argwhere(conv & (out["maxpen"] > 1e-3))
+    free_over, wedged = 0, 0
+    for b, t in deep:
+        wd, p1, p2 = _wedged(w.instance(int(b)), out["traj"][b, t, :t + 1])
+        if wd:
+            wedged += 1
+            assert 0.5 * (p1 - p2) <= 1e-3, (b, t, p1, p2)
+        else:
+            free_over += 1
+    n_states = int(conv.sum())
+    pens = out["maxpen"][conv]
+    print(f"contact states {n_states}: p50 {np.percentile(pens, 50) * 1e3:.3f} mm, p99.9 "
+          f"{np.percentile(pens, 99.9) * 1e3:.3f} mm, max {pens.max() * 1e3:.3f} mm; above 1 mm: "
+          f"{free_over} free, {wedged} wedged")
+    assert free_over <= 1e-3 * (n_states - wedged)
+
+
+def test_tiny_chain_symmetric_saddle_is_left_for_a_grid_minimum():
+    """n = 2 growing head-on into a circle on the axis: the straight state is a saddle;
+    the solver must end at one of the local minima that a brute-force grid of the energy
+    over [-pi/2, pi/2]^2 finds (polished), with a positive definite Hessian."""
+    inst = _inst(n=2, obs=[(0.07, 0.0, 0.02, 0.0)], kind=[0], pv=3000.0, l=0.025)
+    Pi0, r0, c0 = O.chain_eval(inst, np.zeros(2))
+    assert len(c0) > 0 and np.all(np.abs(r0) < 1e-15)  # stationary and in contact
+    assert np.linalg.eigvalsh(O.chain_hessian(inst, np.zeros(2)))[0] < 0  # a saddle
+    th, st, info = O.chain_solve(inst, np.zeros(2))
+    assert st == 0 and info[4] > 0
+    g = np.linspace(-np.pi / 2, np.pi / 2, 181)
+    Pi = np.array([[O.chain_eval(inst, [a, b])[0] for b in g] for a in g])
+    mins = []
+    for i in range(1, 180):
+        for j in range(1, 180):
+            if Pi[i, j] <= Pi[i - 1:i + 2, j - 1:j + 2].min():
+                res = optimize.minimize(lambda t: O.chain_eval(inst, t)[0], [g[i], g[j]],
+                                        jac=lambda t: O.chain_eval(inst, t)[1], method="BFGS",
+                                        options=dict(gtol=1e-12))
+                mins.append(res.x)
+    assert any(np.allclose(th, m, atol=1e-6) for m in mins)
+    assert np.linalg.eigvalsh(O.chain_hessian(inst, th))[0] > 0
+    assert O.chain_eval(inst, th)[0] < Pi0
+
+
+def test_ideal_ppam_at_zero_correction():
+    """Eq. 1 with a = 0 and l_a = l0 is the ideal PPAM: dividing Eq. 1a by Eq. 1b leaves
+    eps = 2 - 2 E(phi|m) / F(phi|m), with phi the root of F(phi|m) / (sqrt(m) cos phi) =
+    l0 / R_c; checked with scipy's elliptic integrals at the oracle's phi."""
+    prm0 = O.params(acorr=0.0)
+    for l0 in (0.02, 0.025):
+        for m in (0.05, 0.12, 0.3, 0.45):
+            eps, G, phi, sat = O.spam_state(m, l0, prm0)
+            assert not sat
+            F, E = special.ellipkinc(phi, m), special.ellipeinc(phi, m)
+            assert abs(F / (np.sqrt(m) * np.cos(phi)) - l0 / 0.005) < 1e-9 * l0 / 0.005
+            assert abs(eps - (2.0 - 2.0 * E / F)) < 1e-12
+            assert abs(G - np.pi * 0.005 ** 2 * (1 - 2 * m) / (2 * m * np.cos(phi) ** 2)) < 1e-15
+            # a = 1e-4 is a small correction of the same state
+            e1 = O.spam_state(m, l0)[0]
+            assert abs(e1 - eps) < 0.01
