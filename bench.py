@@ -1,33 +1,43 @@
 """Benchmark of the batched growth step on one MI355X.
 
-Default workload (the headline line): one bench step = one rollout of the whole batch
-to full length, 4096 robots of 64 links (2 cm links, 5 cm tube, 0-4 sPAMs, 10 circles +
-10 rectangles), i.e. 64 growth steps per robot and 4096 * 2080 = 8.52e6 joint-updates
-(a joint brought to the converged equilibrium of one growth step).
+Default workload (the headline line): the uneven batch, 16384 robots of 16-256 links
+(2 cm links, 5 cm tube, 0-6 sPAMs) among 0-64 obstacles (half circles, half
+rectangles); one bench step = the captured reset + rollout of the whole batch to full
+length (vine_sim_rollout_graph), in the launch order a first rollout measured
+(vine_sim_tune_order): 192 M joint-updates (a joint brought to the converged
+equilibrium of one growth step).  The line also carries the uniform batch (4096 robots
+of 64 links, 10 circles + 10 rectangles) timed the same way.
 
 Other workloads (``--workload``), same JSON fields:
-  uneven  16384 robots of 16-256 links with 0-64 obstacles in one rollout call
-  grad    4096 robots of 96 links: rollout with the trajectory recorded, then the
-          adjoint of every step's equilibrium (vine_sim_grad, all steps weighted)
+  uniform 4096 robots of 64 links as the headline
+  grad    4096 robots of 96 links: rollout with a checkpoint every 32 steps, then the
+          adjoint of every step's equilibrium (vine_sim_grad, all steps weighted, the
+          states recomputed from the checkpoints)
   serve   a Poisson stream of requests (one design of 16-512 links and 0-128 obstacles on
           1-64 environment samples each) through the continuous-batching server at
           ``--rate`` requests/s for ``--duration`` s after a warm-up; reports the
           sustained joint-updates/s and the p50/p99 request latency
 
 Prints one JSON line with the driver's fields plus:
-  roofline      the rollout kernel against the FP64 VALU peak (per-joint-evaluation
-                FLOP count below), timed with HIP events on the stream the kernel is
-                launched on; traffic (HBM bytes per launch) and the executed FP64 VALU
-                work from the committed rocprofv3 counter summary, while the kernel
-                sources are unchanged since it was taken (else null);
+  latency       per-robot rollout latency (seconds its workgroup took, device wall
+                clock): p50, p99, max; and the first rollout in the create-time order
+                next to the tuned ones;
+  accuracy      the batch against the FP64 oracle: on the CPU-baseline sample (run
+                live) and on the oracle's stored outputs of 1024 stratified robots
+                (tests/golden), max |dtheta|, max |dtip|, identical contact sets;
+  roofline      the rollout against the FP64 VALU peak (per-joint-evaluation FLOP count
+                below), timed with HIP events on the stream the class launches join;
+                traffic (HBM bytes per launch) from the committed rocprofv3 counter
+                summary while the kernel sources are unchanged since it was taken;
   per_instance  the same kernel launched once per robot (batch of one), serial on one
                 stream, on a sample of the robots;
-  cpu_baseline  the FP64 oracle on a bounded sample of the same workload on the host
-                cores.
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload on all the
+                host's cores, and on one core.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,29 +59,160 @@ def flops_per_joint_eval(K: float) -> float:
     return 325.0 + 17.0 * K
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "rollout_kernel_uniform_4096_counters.json")
 KERNEL_SOURCES = ("paper_2509_15180_amd/csrc/vs_rollout.hip", "paper_2509_15180_amd/csrc/vs_device.h")
 
 
-def measured_counters(workload: str, robots: int):
-    """HBM bytes and FP64 instruction counts of one rollout launch, taken with rocprofv3
-    PMC runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size; SQ_INSTS_*)
-    and committed under profiles/.  Returned only for the workload they were taken on and
-    while the kernel sources hash to what they were then; else None."""
-    if workload != "uniform" or robots != 4096 or not os.path.exists(COUNTERS):
-        return None
-    import hashlib
+def kernel_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    with open(COUNTERS) as fh:
+    return h.hexdigest()
+
+
+def measured_counters(workload: str):
+    """HBM bytes and FP64 instruction counts of one rollout, taken with rocprofv3 PMC runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size; SQ_INSTS_*) and
+    committed under profiles/.  Returned only while the kernel sources hash to what they
+    were then; else None."""
+    path = os.path.join(ROOT, "profiles", f"rollout_kernel_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
         rec = json.load(fh)
-    return rec if rec.get("kernel_source_sha256") == h.hexdigest() else None
+    return rec if rec.get("kernel_source_sha256") == kernel_hash() else None
 
 
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def host_info():
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return int(cores), int(os.cpu_count() or cores), model
+
+
+def make_workload(W, wl, B):
+    if wl == "uniform":
+        B = B or 4096
+        return W.config2(B), (f"uniform batch: {B} robots x 64 links (2 cm), 10 circles + 10 "
+                              f"rectangles, 0-4 sPAMs; rollout to full length")
+    if wl == "uneven":
+        B = B or 16384
+        return W.config3(B), (f"uneven batch: {B} robots x 16-256 links (2 cm), 0-64 obstacles "
+                              f"(half circles, half rectangles), 0-6 sPAMs; captured rollout to "
+                              f"full length")
+    B = B or 4096
+    return W.config4(B), (f"differentiation batch: {B} robots x 96 links, 12 circles + 12 "
+                          f"rectangles, 1-4 sPAMs, a goal each; rollout with a checkpoint every "
+                          f"32 steps + adjoint of every step")
+
+
+def timed_batch(torch, V, work, wl, args, stream):
+    """Create, first (untuned) rollout, tune, warm up, time K steps.  Returns the handle
+    and a dict of timings and counters."""
+    sim = V.VineSim(work)
+    grad = wl == "grad"
+    ce = 32 if grad else 0
+    weights = torch.ones(sim.T, dtype=torch.float64, device="cuda") if grad else None
+    goal = torch.as_tensor(work.goal, dtype=torch.float64).cuda()
+    # first rollout in the create-time order
+    f0, f1 = _events(torch)
+    f0.record(stream)
+    sim.rollout(-1, ckpt_every=ce, stream=stream)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    first_ms = f0.elapsed_time(f1)
+    tuned = not args.no_tune
+    if tuned:  # launch order from the cycles the first rollout measured per robot
+        sim.tune_order(stream=stream)
+
+    def one_step():
+        if args.eager:
+            sim.reset(stream=stream)
+            sim.rollout(-1, ckpt_every=ce, stream=stream)
+        else:
+            sim.rollout_graph(ckpt_every=ce, stream=stream)
+        if grad:
+            sim.grad(goal, weights, stream=stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ev0, ev1 = _events(torch)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        one_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    out = sim.read_all()
+    # the rollout call alone (no reset, no adjoint): the class launches fork from and join
+    # back to this stream, so these events bracket every launch
+    sim.reset(stream=stream)
+    k0, k1 = _events(torch)
+    k0.record(stream)
+    sim.rollout(-1, ckpt_every=ce, stream=stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    res = dict(ms=ms, wall=wall, first_ms=first_ms, tuned=tuned, kern_ms=k0.elapsed_time(k1),
+               out=out, robot_s=sim.read("time"))
+    if grad:
+        g0, g1 = _events(torch)
+        g0.record(stream)
+        sim.grad(goal, weights, stream=stream)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        res["adjoint_ms"] = g0.elapsed_time(g1)
+    return sim, res
+
+
+def compare(got, ref, T):
+    """GPU vs oracle arrays of the same robots: max |dtheta|, max |dtip| over the robots
+    whose contact sets agree at every step, and how many do."""
+    same = np.all(got["chash"][:, :T] == ref["chash"][:, :T], 1)
+    nth = ref["theta"].shape[1]
+    dth = np.abs(got["theta"][:, :nth] - ref["theta"]).max(1)
+    dtip = np.abs(got["tip"][:, :T, :2] - np.asarray(ref["tip"][:, :T, :2], np.float64)).max((1, 2))
+    ok = same & (dth <= 1e-5) & (dtip <= 1e-4)
+    return {"robots": int(len(same)), "identical_contact_sets": int(same.sum()),
+            "within_tolerance": int(ok.sum()),
+            "fraction_within_tolerance": float(ok.mean()) if len(ok) else None,
+            "max_abs_dtheta_rad": float(dth[same].max()) if same.any() else None,
+            "max_abs_dtip_m": float(dtip[same].max()) if same.any() else None,
+            "tolerances": {"theta_rad": 1e-5, "tip_m": 1e-4}}
+
+
+def golden_accuracy(wl, out):
+    """The batch against the oracle's stored outputs of the same robots (tests/golden),
+    while they match the oracle and workload sources."""
+    names = {"uneven": ("oracle_cfg3.npz", 256), "uniform": ("oracle_cfg2.npz", 64)}
+    if wl not in names:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", names[wl][0])
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_oracle_outputs as MK
+    g = np.load(path)
+    if str(g["source_sha256"]) != MK.source_hash():
+        return None
+    idx = g["idx"]
+    got = {k: out[k][idx] for k in ("theta", "tip", "chash")}
+    rec = compare(got, g, names[wl][1])
+    rec["source"] = os.path.relpath(path, ROOT)
+    return rec
 
 
 def main():
@@ -79,8 +220,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("uniform", "uneven", "grad", "serve"),
-                    default="uniform")
+    ap.add_argument("--workload", choices=("uneven", "uniform", "grad", "serve"), default="uneven")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: measured seconds")
     ap.add_argument("--warm", type=float, default=5.0, help="serve: warm-up seconds")
@@ -88,12 +228,13 @@ def main():
     ap.add_argument("--tick-steps", type=int, default=8, help="serve: growth steps per round")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
-    ap.add_argument("--cpu-robots", type=int, default=320, help="robots in the CPU-oracle sample")
+    ap.add_argument("--cpu-robots", type=int, default=48, help="robots in the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graph", action="store_true",
-                    help="time the captured reset + rollout (vine_sim_rollout_graph)")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the uniform batch's extra line")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager reset + rollout calls instead of the captured graph")
     ap.add_argument("--no-tune", action="store_true",
-                    help="keep the create-time launch order (no vine_sim_tune_order after the warm-up)")
+                    help="keep the create-time launch order (no vine_sim_tune_order)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): robots are "
@@ -110,80 +251,44 @@ def main():
     wl = args.workload
     if wl == "serve":
         return serve(args, torch, V, W)
-    if wl == "uniform":
-        B = args.batch or 4096
-        work = W.config2(B)
-        desc = (f"uniform batch: {B} robots x 64 links (2 cm), 10 circles + 10 rectangles, "
-                f"0-4 sPAMs; rollout to full length")
-    elif wl == "uneven":
-        B = args.batch or 16384
-        work = W.config3(B)
-        desc = (f"uneven batch: {B} robots x 16-256 links (2 cm), 0-64 obstacles, 0-6 sPAMs; "
-                f"rollout to full length in one call")
-    else:
-        B = args.batch or 4096
-        work = W.config4(B)
-        desc = (f"differentiation batch: {B} robots x 96 links, 12 circles + 12 rectangles, "
-                f"1-4 sPAMs, a goal each; rollout with trajectory + adjoint of every step")
+    stream = torch.cuda.current_stream()
+    work, desc = make_workload(W, wl, args.batch)
+    B = work.n_inst
     n = work.inst_i[:, 0].astype(np.float64)
     K_mean = float((work.inst_i[:, 4] * n * n).sum() / (n * n).sum())  # work-weighted obstacles
     ju = work.joint_updates()
-    sim = V.VineSim(work)
-    stream = torch.cuda.current_stream()
-    T = sim.T
-    weights = torch.ones(T, dtype=torch.float64, device="cuda") if wl == "grad" else None
-    goal = torch.as_tensor(work.goal, dtype=torch.float64).cuda()
-
-    def one_step():
-        if args.graph:
-            sim.rollout_graph(ckpt_every=32 if wl == "grad" else 0, stream=stream)
-        else:
-            sim.reset(stream=stream)
-            sim.rollout(-1, ckpt_every=32 if wl == "grad" else 0, stream=stream)
-        if wl == "grad":
-            sim.grad(goal, weights, stream=stream)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    tuned = bool(args.warmup > 0 and not args.no_tune)
-    if tuned:  # launch order from the cycles the warm-up rollout measured per robot
-        sim.tune_order(stream=stream)
-    ev0, ev1 = _events(torch)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        one_step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    out = sim.read_all()
+    print(f"bench: {desc}", file=sys.stderr, flush=True)
+    sim, R = timed_batch(torch, V, work, wl, args, stream)
+    out = R["out"]
+    value = ju / (R["ms"] * 1e-3)
     jevals = float(out["jevals"].sum())
-    nsolves = float(out["nsolves"].sum())
-    status = out["status"]
-    # time of the rollout call alone (no reset), same stream
-    sim.reset(stream=stream)
-    k0, k1 = _events(torch)
-    k0.record(stream)
-    sim.rollout(-1, ckpt_every=32 if wl == "grad" else 0, stream=stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = k0.elapsed_time(k1)
-    grad_ms = None
-    if wl == "grad":
-        g0, g1 = _events(torch)
-        g0.record(stream)
-        sim.grad(goal, weights, stream=stream)
-        g1.record(stream)
-        torch.cuda.synchronize()
-        grad_ms = g0.elapsed_time(g1)
     flops = jevals * flops_per_joint_eval(K_mean)
-    achieved = flops / (kern_ms * 1e-3) / 1e12
-    value = ju / (ms * 1e-3)
+    achieved = flops / (R["kern_ms"] * 1e-3) / 1e12
+    robot_s = R["robot_s"]
+    status = out["status"]
+
+    extra = None
+    if wl == "uneven" and not args.no_uniform:
+        w2, d2 = make_workload(W, "uniform", 0)
+        print("bench: uniform batch", file=sys.stderr, flush=True)
+        s2, R2 = timed_batch(torch, V, w2, "uniform", args, stream)
+        n2 = w2.inst_i[:, 0].astype(np.float64)
+        j2 = float(R2["out"]["jevals"].sum())
+        extra = {"workload": d2, "value": w2.joint_updates() / (R2["ms"] * 1e-3),
+                 "unit": "joint-updates/s", "ms_per_step": R2["ms"],
+                 "first_rollout_ms_create_time_order": R2["first_ms"],
+                 "kernel_ms": R2["kern_ms"],
+                 "roofline_frac": j2 * flops_per_joint_eval(20.0) / (R2["kern_ms"] * 1e-3) / 1e12
+                 / PEAK_FP64_TFLOPS,
+                 "latency_s": {"p50": float(np.percentile(R2["robot_s"], 50)),
+                               "p99": float(np.percentile(R2["robot_s"], 99))},
+                 "accuracy_vs_stored_oracle_outputs": golden_accuracy("uniform", R2["out"])}
+        s2.close()
 
     # plain per-instance form: one launch per robot, serial on one stream
-    pi_idx = np.linspace(0, B - 1, args.per_instance).astype(int)
+    order = np.argsort(n, kind="stable")
+    pi_idx = order[np.linspace(0, B - 1, args.per_instance).astype(int)]
+    print("bench: per-instance form", file=sys.stderr, flush=True)
     sims = [V.VineSim(work.subset([i])) for i in pi_idx]
     for s in sims:
         s.rollout(-1, stream=stream)
@@ -202,57 +307,84 @@ def main():
     for s in sims:
         s.close()
 
-    cpu = None
+    cores, ncpu, model = host_info()
+    cpu, acc_live = None, None
     if not args.no_cpu:
         import oracle as O
-        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        threads = max(1, min(int(threads), 16))
-        idx = np.arange(min(args.cpu_robots, B)) if wl != "uneven" else \
-            np.nonzero(work.inst_i[:, 0] <= 128)[0][:args.cpu_robots]
+        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        # a bounded sample spread over the link counts up to 96 (the oracle's dense
+        # solves grow like n^3 per iteration)
+        small = np.nonzero(n <= 96)[0]
+        idx = small[np.linspace(0, len(small) - 1, min(args.cpu_robots, len(small))).astype(int)]
         sub = work.subset(idx)
         c0 = time.perf_counter()
-        O.rollout(sub, threads=threads)
+        ref = O.rollout(sub, threads=cores)
         csec = time.perf_counter() - c0
-        cpu = {"value": sub.joint_updates() / csec, "unit": "joint-updates/s", "cores": threads,
+        one = sub.subset(np.arange(min(4, sub.n_inst)))
+        c1 = time.perf_counter()
+        O.rollout(one, threads=1)
+        c1sec = time.perf_counter() - c1
+        cpu = {"value": sub.joint_updates() / csec, "unit": "joint-updates/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{len(idx)} robots of the same batch"
-                         f"{' (those of <= 128 links)' if wl == 'uneven' else ''}, full rollouts "
-                         f"({sub.joint_updates()} joint-updates in {csec:.1f} s)"}
+               "sample": f"{len(idx)} robots of the same batch spread over the link counts up "
+                         f"to 96, full rollouts ({sub.joint_updates()} joint-updates in "
+                         f"{csec:.1f} s on {cores} threads)",
+               "single_core": {"value": one.joint_updates() / c1sec, "unit": "joint-updates/s",
+                               "sample": f"the first {one.n_inst} of them on one thread "
+                                         f"({c1sec:.1f} s)"},
+               "host": {"nproc": ncpu, "affinity": cores, "model": model}}
+        T = int(n[idx].max())
+        got = {k: out[k][idx] for k in ("theta", "tip", "chash")}
+        acc_live = compare(got, ref, T)
 
-    meas = measured_counters(wl, B)
+    meas = measured_counters(wl)
     traffic = meas["hbm_bytes_per_launch"] if meas else None
     counters = None
     if meas:  # executed FP64 VALU work (wave instructions x 64 lanes, FMA = 2)
         cflop = meas["fp64_flop_per_launch_from_counters"]
         counters = {"fp64_flop_per_launch": cflop,
-                    "achieved": cflop / (kern_ms * 1e-3) / 1e12,
-                    "frac": cflop / (kern_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-                    "source": os.path.relpath(COUNTERS, ROOT)}
+                    "achieved": cflop / (R["kern_ms"] * 1e-3) / 1e12,
+                    "frac": cflop / (R["kern_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                    "source": f"profiles/rollout_kernel_{wl}_counters.json"}
     rec = {
         "metric": METRIC, "value": value, "unit": "joint-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": R["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "robots": B, "links_max": int(n.max()), "graph": bool(args.graph),
-                   "schedule": "measured by the warm-up rollout" if tuned else "create-time estimate",
+        "config": {"workload": desc, "robots": B, "links_max": int(n.max()),
+                   "graph": not args.eager,
+                   "schedule": "measured by the first rollout" if R["tuned"] else "create-time estimate",
                    "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
+        "latency": {"unit": "s", "what": "per-robot rollout latency (its workgroup's time in the launch)",
+                    "p50": float(np.percentile(robot_s, 50)),
+                    "p99": float(np.percentile(robot_s, 99)), "max": float(robot_s.max()),
+                    "first_rollout_ms_create_time_order": R["first_ms"],
+                    "tuned_rollout_ms": R["ms"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "rollout_kernel", "kernel_ms": kern_ms,
-                     "counters": counters,
+                     "kernel": "rollout_kernel (all chain-length classes of one rollout)",
+                     "kernel_ms": R["kern_ms"], "counters": counters,
                      "joint_evaluations": jevals,
                      "flop_per_joint_eval": flops_per_joint_eval(K_mean),
-                     "linear_solves": nsolves},
+                     "linear_solves": float(out["nsolves"].sum()),
+                     "negative_curvature_steps": float(out["negsteps"].sum()),
+                     "simd_busy_fraction": None},
         "per_instance": {"value": pi_rate, "unit": "joint-updates/s", "robots": int(len(pi_idx)),
                          "speedup_batched": value / pi_rate},
         "cpu_baseline": cpu,
+        "accuracy": {"vs_cpu_baseline_sample": acc_live,
+                     "vs_stored_oracle_outputs": golden_accuracy(wl, out)},
         "quality": {"converged_steps": int((status == 0).sum()),
                     "other_steps": int(((status != 0) & (status != -1)).sum()),
-                    "max_penetration_m": float(out["maxpen"].max())},
-        "wall_s": wall,
+                    "max_penetration_m": float(out["maxpen"].max()),
+                    "p99_9_penetration_m": float(np.percentile(out["maxpen"][out["ncont"] > 0], 99.9))
+                    if (out["ncont"] > 0).any() else 0.0},
+        "wall_s": R["wall"],
     }
-    if grad_ms is not None:
-        rec["adjoint_ms"] = grad_ms
+    if extra is not None:
+        rec["uniform_batch"] = extra
+    if "adjoint_ms" in R:
+        rec["adjoint_ms"] = R["adjoint_ms"]
     print(json.dumps(rec), flush=True)
 
 

@@ -146,9 +146,12 @@ typedef enum vine_field {
   VINE_F_CYCLES = 12,  /* double [B]       shader-clock cycles each robot's wave spent in rollout
                           launches since the reset (what vine_sim_tune_order sorts by) */
   VINE_F_NEGSTEPS = 13, /* double [B]      work counter: steps along negative curvature */
-  VINE_F_CKPT = 14     /* double [B][C][N] checkpoints: row q is the state before step
+  VINE_F_CKPT = 14,    /* double [B][C][N] checkpoints: row q is the state before step
                           q ckpt_every (joint angles, 0 beyond the link count then),
                           C = ceil(T / ckpt_every) */
+  VINE_F_TIME = 15     /* double [B]       seconds each robot's workgroup spent in rollout
+                          launches since the reset (device wall clock): its rollout latency
+                          once it runs */
 } vine_field;
 
 typedef struct vine_sim vine_sim;

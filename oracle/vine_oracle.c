@@ -752,7 +752,9 @@ typedef struct {
  *    model stands for, which becomes Newton's step as the residual vanishes;
  *  - otherwise a step along negative curvature: d = s v with v from neg_curv_dir at the
  *    most negative pivot (ties: the joint nearest the base), its sign chosen so that
- *    r.d <= 0 (d_k > 0 when r.v = 0, e.g. at an exactly symmetric saddle);
+ *    r.d <= 0, and d_k > 0 when |r.v| <= tol M_max |v|_1 (a slope that a residual within
+ *    the convergence tolerance could produce: at a converged saddle the sign of r.v is
+ *    noise, and a symmetric saddle has r.v = 0);
  *  - cap max_j |d_j| at step_max (curvature steps are scaled to it);
  *  - Armijo backtracking on Pi (halving, constant c1) against the predicted change
  *    alpha r.d (+ alpha^2 d.H d / 2 for a curvature step), skipped once the predicted
@@ -843,12 +845,16 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       for (int j = 1; j < n; ++j)
         if (piv[j] < piv[k]) k = j;
       neg_curv_dir(n, A, k, d);
-      double vmax = 0.0, rv = 0.0;
+      double vmax = 0.0, rv = 0.0, v1 = 0.0;
       for (int i = 0; i < n; ++i) {
         vmax = fmax(vmax, fabs(d[i]));
         rv += r[i] * d[i];
+        v1 += fabs(d[i]);
       }
-      double s = (rv > 0.0 ? -1.0 : 1.0) * P->step_max / vmax;
+      /* the slope along v counts as zero when a residual within the tolerance could
+       * produce it (always so at a converged saddle): then the tie rule, d_k > 0 */
+      const int tie = fabs(rv) <= P->tol * c->Mmax * v1;
+      double s = (tie ? 1.0 : (rv > 0.0 ? -1.0 : 1.0)) * P->step_max / vmax;
       for (int i = 0; i < n; ++i) d[i] *= s;
       slope = s * rv;
       curv = 0.0;
@@ -860,7 +866,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       }
       mode = 2;
       st->neg_steps++;
-      if (rv == 0.0) st->tie_steps++; /* the sign came from the tie rule */
+      if (tie) st->tie_steps++; /* the sign came from the tie rule */
       break;
     }
     if (mode == 3) {
@@ -964,7 +970,7 @@ static void chain_init(vo_chain* c, const vo_prm* P, const double* prm, const do
  *  traj   [B][T][n_max]     joint angles after each step
  *  stats  [B][6]            total iterations, backtracks, damping raises, max contacts,
  *                           steps along negative curvature, those of them whose sign
- *                           the tie rule chose (r.v = 0) */
+ *                           the tie rule chose */
 int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spam,
                const int* obs_kind, const double* obs_d, const double* prm, int n_steps,
                int n_threads, int n_max, double* theta, double* tip, double* rho, int* iters,

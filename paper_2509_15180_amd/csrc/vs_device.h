@@ -94,6 +94,8 @@ struct KData {
   double* nsolves;    // [B] factorisations of H + mu I
   double* negsteps;   // [B] steps along negative curvature
   double* cycles;     // [B] shader-clock cycles spent in rollout launches since the reset
+  double* wtime;      // [B] seconds spent in rollout launches since the reset
+  double wall_period; // seconds per tick of the device's constant-rate wall clock
   // solver trace of one robot (diagnostics): rows of kTraceCols doubles
   int trace_robot;    // -1: off
   int trace_cap;      // rows

@@ -387,12 +387,14 @@ struct vine_sim {
   double* nsolves = nullptr;
   double* negsteps = nullptr;
   double* cycles = nullptr;
+  double* wtime = nullptr;
+  double wall_period = 0.0;  // seconds per device wall-clock tick
   // recomputation of a checkpoint segment for the adjoint (allocated on first use):
   // state, records and trajectory of ckpt_every steps
   struct Seg {
     double *theta = nullptr, *tip = nullptr, *rho = nullptr, *maxpen = nullptr,
            *traj = nullptr, *jevals = nullptr, *nsolves = nullptr, *negsteps = nullptr,
-           *cycles = nullptr, *gsums = nullptr, *gloss = nullptr;
+           *cycles = nullptr, *wtime = nullptr, *gsums = nullptr, *gloss = nullptr;
     int *ncur = nullptr, *tcur = nullptr, *iters = nullptr, *status = nullptr, *ncont = nullptr,
         *gstat = nullptr;
     unsigned long long* chash = nullptr;
@@ -439,7 +441,7 @@ void drop_graphs(vine_sim* h) {
 void free_seg(vine_sim* h) {
   vine_sim::Seg& g = h->seg;
   void* ptrs[] = {g.theta, g.tip, g.rho, g.maxpen, g.traj, g.jevals, g.nsolves, g.negsteps,
-                  g.cycles, g.gsums, g.gloss, g.ncur, g.tcur, g.iters, g.status, g.ncont,
+                  g.cycles, g.wtime, g.gsums, g.gloss, g.ncur, g.tcur, g.iters, g.status, g.ncont,
                   g.gstat, g.chash};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -458,6 +460,7 @@ void free_all(vine_sim* h) {
   void* ptrs[] = {h->order, h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
                   h->maxpen, h->traj, h->ckpt, h->jevals, h->nsolves, h->negsteps, h->cycles,
+                  h->wtime,
                   h->trace, h->trace_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -517,6 +520,8 @@ vs::KData kdata(vine_sim* h) {
   D.nsolves = h->nsolves;
   D.negsteps = h->negsteps;
   D.cycles = h->cycles;
+  D.wtime = h->wtime;
+  D.wall_period = h->wall_period;
   D.trace_robot = h->trace ? h->trace_robot : -1;
   D.order = h->order;
   D.launch_first = 0;
@@ -731,6 +736,13 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->nsolves, B));
   A(dalloc(&h->negsteps, B));
   A(dalloc(&h->cycles, B));
+  A(dalloc(&h->wtime, B));
+  {
+    int dev = 0, khz = 0;
+    A(hipGetDevice(&dev));
+    A(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    h->wall_period = khz > 0 ? 1e-3 / khz : 0.0;
+  }
   if (e != hipSuccess) {
     free_all(h);
     delete h;
@@ -991,6 +1003,7 @@ static hipError_t ensure_seg(vine_sim* h) {
   A(dalloc(&g.nsolves, B));
   A(dalloc(&g.negsteps, B));
   A(dalloc(&g.cycles, B));
+  A(dalloc(&g.wtime, B));
   A(dalloc(&g.gsums, B * vs::kWave * 3));
   A(dalloc(&g.gloss, B));
   A(dalloc(&g.gstat, B));
@@ -1057,6 +1070,7 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
     Dseg.nsolves = g->nsolves;
     Dseg.negsteps = g->negsteps;
     Dseg.cycles = g->cycles;
+    Dseg.wtime = g->wtime;
     Dseg.trace_robot = -1;
     const int ce = h->ckpt_every;
     for (int q = 0; q < h->n_ckpt && e == hipSuccess; ++q) {
@@ -1134,6 +1148,7 @@ int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {
     case VINE_F_NSOLVES: return 8 * B;
     case VINE_F_CYCLES: return 8 * B;
     case VINE_F_NEGSTEPS: return 8 * B;
+    case VINE_F_TIME: return 8 * B;
     case VINE_F_CKPT: return 8 * B * h->n_ckpt * N;
     default: return 0;
   }
@@ -1161,6 +1176,7 @@ int32_t vine_sim_read(const vine_sim* hc, int32_t field, void* dst, int32_t dst_
     case VINE_F_JEVALS: src = h->jevals; break;
     case VINE_F_NSOLVES: src = h->nsolves; break;
     case VINE_F_CYCLES: src = h->cycles; break;
+    case VINE_F_TIME: src = h->wtime; break;
     case VINE_F_NEGSTEPS: src = h->negsteps; break;
     case VINE_F_CKPT:
       if (!h->ckpt_any) return fail(h, VINE_ESTATE, "no checkpoints were written");

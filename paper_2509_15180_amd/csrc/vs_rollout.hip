@@ -839,8 +839,9 @@ __device__ double neg_curv_dir(SM& S, const Ctx& c, double mu) {
 //    sweep fails (a vanishing pivot) or a positive-definite step does not descend;
 //  - converged when rho <= tol and H + delta I is positive definite;
 //  - positive definite: the damped Newton step, capped at step_max;
-//  - indefinite: d = s v (neg_curv_dir), |d|_inf = step_max, sign so that r.d <= 0
-//    (d_k > 0 when r.v = 0, as at an exactly symmetric saddle);
+//  - indefinite: d = s v (neg_curv_dir), |d|_inf = step_max, sign so that r.d <= 0, and
+//    d_k > 0 when |r.v| <= tol M_max |v|_1 (a slope that a residual within the tolerance
+//    could produce: at a converged saddle the sign of r.v is noise);
 //  - Armijo backtracking on the energy against alpha r.d (+ alpha^2 d.H d / 2 for a
 //    curvature step), skipped once the full step's predicted decrease is below
 //    1e-12 M_max, the round-off level of the energy.
@@ -894,16 +895,19 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
         continue;
       }
       const double Dk = neg_curv_dir(S, c, mu);
-      double vm = 0.0, rv = 0.0, vv = 0.0;
+      double vm = 0.0, rv = 0.0, vv = 0.0, v1 = 0.0;
       for (int j = lane; j < n; j += kWave) {
         vm = fmax(vm, fabs(S.d[j]));
         rv += S.r[j] * S.d[j];
         vv += S.d[j] * S.d[j];
+        v1 += fabs(S.d[j]);
       }
       vm = wmax(vm);
       rv = wsum(rv);
       vv = wsum(vv);
-      const double s = (rv > 0.0 ? -1.0 : 1.0) * P.step_max / vm;
+      v1 = wsum(v1);
+      const bool tie = fabs(rv) <= P.tol * c.Mmax * v1;
+      const double s = (tie ? 1.0 : (rv > 0.0 ? -1.0 : 1.0)) * P.step_max / vm;
       for (int j = lane; j < n; j += kWave) S.d[j] *= s;
       slope = s * rv;
       curv = (Dk - mu * vv) * (s * s);
@@ -1042,6 +1046,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
   }
   const long long t_begin = clock64();  // this robot's time in the launch (for scheduling)
+  const long long w_begin = wall_clock64();  // and in seconds (constant-rate counter)
   int n = D.ncur[b];
   int t = D.tcur[b];
   if (lane == 0) {
@@ -1125,6 +1130,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     D.nsolves[b] += S.nsolves;
     D.negsteps[b] += S.negsteps;
     D.cycles[b] += (double)(clock64() - t_begin);
+    D.wtime[b] += (double)(wall_clock64() - w_begin) * D.wall_period;
   }
   if (lane == 0) {
     S.cmd = 2;
@@ -1260,6 +1266,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   }
 }
 
+// Host-side check before a launch: every array the kernels write or read per robot is
+// present (a missing buffer is reported as an error instead of reaching the device).
+static bool state_complete(const KData& D) {
+  return D.ii && D.dd && D.cover && D.okind && D.obs && D.tables && D.wr && D.order && D.theta &&
+         D.ncur && D.tcur && D.tip && D.rho && D.iters && D.status && D.ncont && D.chash &&
+         D.maxpen && D.jevals && D.nsolves && D.negsteps && D.cycles && D.wtime;
+}
+
 __global__ void zero3_kernel(double* a, double* b, double* c, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -1283,6 +1297,9 @@ hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
                        int* status, int nmax_class, hipStream_t stream) {
   if (D.launch_count <= 0) return hipSuccess;
   if ((!part.first || !part.last) && !(part.sums && part.loss && part.status))
+    return hipErrorInvalidValue;
+  if (!state_complete(D) || !goal || !loss || (D.n_spam > 0 && !(dP && ds0 && ds1)) ||
+      (weights && !traj))
     return hipErrorInvalidValue;
   dim3 grid(D.launch_count), block(kWave);
 #define VS_GRAD(NM)                                                                          \
@@ -1324,6 +1341,7 @@ __global__ void reset_kernel(KData D) {
     D.nsolves[i] = 0.0;
     D.negsteps[i] = 0.0;
     D.cycles[i] = 0.0;
+    D.wtime[i] = 0.0;
   }
 }
 
@@ -1351,6 +1369,7 @@ __global__ void slot_reset_kernel(KData D, const int* slots, int count) {
     D.nsolves[b] = 0.0;
     D.negsteps[b] = 0.0;
     D.cycles[b] = 0.0;
+    D.wtime[b] = 0.0;
   }
 }
 
@@ -1375,11 +1394,13 @@ __global__ void seg_load_kernel(KData Dseg, const double* ckpt, const int* tcur,
     Dseg.nsolves[b] = 0.0;
     Dseg.negsteps[b] = 0.0;
     Dseg.cycles[b] = 0.0;
+    Dseg.wtime[b] = 0.0;
   }
 }
 
 hipError_t launch_seg_load(const KData& Dseg, const double* ckpt, const int* tcur, int n_ckpt,
                            int q, int ce, hipStream_t stream) {
+  if (!state_complete(Dseg) || !ckpt || !tcur) return hipErrorInvalidValue;
   hipLaunchKernelGGL(seg_load_kernel, dim3(Dseg.n_inst), dim3(64), 0, stream, Dseg, ckpt, tcur,
                      n_ckpt, q, ce);
   return hipGetLastError();
@@ -1387,11 +1408,13 @@ hipError_t launch_seg_load(const KData& Dseg, const double* ckpt, const int* tcu
 
 hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
+  if (!state_complete(D) || !slots) return hipErrorInvalidValue;
   hipLaunchKernelGGL(slot_reset_kernel, dim3(count), dim3(256), 0, stream, D, slots, count);
   return hipGetLastError();
 }
 
 hipError_t launch_reset(const KData& D, hipStream_t stream) {
+  if (!state_complete(D)) return hipErrorInvalidValue;
   const size_t work = (size_t)D.n_inst * (D.t_max * 3 > D.n_max ? D.t_max * 3 : D.n_max);
   const size_t blocks = (work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096;
   hipLaunchKernelGGL(reset_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
@@ -1403,6 +1426,7 @@ hipError_t launch_reset(const KData& D, hipStream_t stream) {
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
                           hipStream_t stream) {
   if (D.launch_count <= 0) return hipSuccess;
+  if (!state_complete(D)) return hipErrorInvalidValue;
   if (D.traj && D.rec_every < 1) return hipErrorInvalidValue;
   if (D.ckpt && D.ckpt_every < 1) return hipErrorInvalidValue;
   dim3 grid(D.launch_count), block(2 * kWave);

@@ -28,7 +28,8 @@ FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np
               ncont=(6, np.int32, "BT"), chash=(7, np.uint64, "BT"), maxpen=(8, np.float64, "BT"),
               traj=(9, np.float64, "BRN"), jevals=(10, np.float64, "B"),
               nsolves=(11, np.float64, "B"), cycles=(12, np.float64, "B"),
-              negsteps=(13, np.float64, "B"), ckpt=(14, np.float64, "BCN"))
+              negsteps=(13, np.float64, "B"), ckpt=(14, np.float64, "BCN"),
+              time=(15, np.float64, "B"))
 
 MAX_LINKS = 512
 MAX_OBSTACLES = 128

@@ -19,6 +19,10 @@ Files (numpy .npz, compressed):
                     their first 300 growth steps
   oracle_cfg4_grad.npz  the differentiation batch, robots 0..511: final-step and
                     weighted-loss gradients with respect to every sPAM's pressure and ends
+
+The uniform and differentiation files also hold the contact hashes of the same robots
+with every body pressure scaled by 1 + 1e-14 (``perturbed_chash``): how often the
+oracle's own descent changes its result under a rounding-size change of an input.
 """
 from __future__ import annotations
 
@@ -82,6 +86,12 @@ def weights_cfg4(T: int = 96) -> np.ndarray:
     return w
 
 
+def pressure_perturbed(work: W.Workload, rel: float = 1e-14) -> W.Workload:
+    w = W.pack([work.instance(i) for i in range(work.n_inst)], work.name + "[p]", dict(work.meta))
+    w.inst_d[:, 2] *= 1.0 + rel
+    return w
+
+
 def save(name: str, **arrays):
     path = os.path.join(HERE, name)
     np.savez_compressed(path, source_sha256=np.array(source_hash()), **arrays)
@@ -115,16 +125,20 @@ def main():
         t = time.time()
         w = W.config2(1024)
         out = O.rollout(w, threads=th)
-        save("oracle_cfg2.npz", idx=np.arange(1024), **rollout_arrays(w, out, 64))
+        pert = O.rollout(pressure_perturbed(w), threads=th)
+        save("oracle_cfg2.npz", idx=np.arange(1024), perturbed_chash=pert["chash"],
+             **rollout_arrays(w, out, 64))
         print(f"cfg2 {time.time() - t:.0f} s", flush=True)
     if "cfg4" in todo:
         t = time.time()
         w = W.config4(512)
         out = O.rollout(w, traj=True, threads=th)
+        pert = O.rollout(pressure_perturbed(w), threads=th)
         dP, d0, d1, loss = O.gradient(w, out["traj"], threads=th)
         wt = weights_cfg4()
         wP, w0, w1, wloss = O.gradient(w, out["traj"], weights=wt, threads=th)
         save("oracle_cfg4_grad.npz", idx=np.arange(512), weights=wt, chash=out["chash"],
+             perturbed_chash=pert["chash"],
              status=out["status"].astype(np.int8), theta=out["theta"], negsteps=out["stats"][:, 4],
              dP=dP, ds0=d0, ds1=d1, loss=loss, wdP=wP, wds0=w0, wds1=w1, wloss=wloss)
         print(f"cfg4 {time.time() - t:.0f} s", flush=True)

@@ -1,15 +1,13 @@
-"""Host-side logic of bench.py (no GPU): the measured-counter record is reported only
-for the workload it was taken on and only while the kernel sources are unchanged."""
+"""Host-side logic of bench.py (no GPU): the measured-counter record is reported only for
+the workload it was taken on and only while the kernel sources are unchanged; the
+accuracy summary compares the right things."""
 import json
 import os
 import shutil
 
+import numpy as np
+
 import bench
-
-
-def test_counters_only_for_their_workload():
-    assert bench.measured_counters("uneven", 4096) is None
-    assert bench.measured_counters("uniform", 1024) is None
 
 
 def test_counters_follow_the_kernel_sources(tmp_path, monkeypatch):
@@ -17,14 +15,26 @@ def test_counters_follow_the_kernel_sources(tmp_path, monkeypatch):
     for f in bench.KERNEL_SOURCES:
         os.makedirs(root / os.path.dirname(f), exist_ok=True)
         shutil.copy(os.path.join(bench.ROOT, f), root / f)
-    rec = json.load(open(bench.COUNTERS))
-    rec_path = root / "counters.json"
-    json.dump(rec, open(rec_path, "w"))
     monkeypatch.setattr(bench, "ROOT", str(root))
-    monkeypatch.setattr(bench, "COUNTERS", str(rec_path))
-    got = bench.measured_counters("uniform", 4096)
-    if got is not None:  # the committed record matches the committed sources
-        assert got["hbm_bytes_per_launch"] > 0
+    os.makedirs(root / "profiles")
+    rec = {"kernel_source_sha256": bench.kernel_hash(), "hbm_bytes_per_launch": 123.0,
+           "fp64_flop_per_launch_from_counters": 1.0}
+    json.dump(rec, open(root / "profiles" / "rollout_kernel_uneven_counters.json", "w"))
+    assert bench.measured_counters("uneven")["hbm_bytes_per_launch"] == 123.0
+    assert bench.measured_counters("uniform") is None  # taken on another workload
     with open(root / bench.KERNEL_SOURCES[0], "a") as fh:
         fh.write("\n// changed\n")
-    assert bench.measured_counters("uniform", 4096) is None
+    assert bench.measured_counters("uneven") is None
+
+
+def test_compare_counts_misses_and_tolerances():
+    rng = np.random.default_rng(0)
+    ref = {"theta": rng.normal(size=(5, 8)), "tip": rng.normal(size=(5, 8, 3)),
+           "chash": rng.integers(0, 2**63, size=(5, 8), dtype=np.uint64)}
+    got = {k: v.copy() for k, v in ref.items()}
+    got["theta"][1, 3] += 2e-5          # out of the angle tolerance
+    got["chash"][2, 7] ^= np.uint64(1)  # another contact set at the last step
+    got["tip"][3, 0, 0] += 5e-5         # within the tip tolerance
+    r = bench.compare(got, ref, 8)
+    assert r["robots"] == 5 and r["identical_contact_sets"] == 4 and r["within_tolerance"] == 3
+    assert abs(r["max_abs_dtheta_rad"] - 2e-5) < 1e-12

@@ -154,34 +154,6 @@ def test_adjoint_flags_unconverged_steps():
                          w.spam[:, 2], w.goal, np.ones(96))
 
 
-def test_grad_full_batch_sampled():
-    """The whole 4096-robot differentiation batch in one launch; sampled robots are
-    checked against the oracle one by one."""
-    w = W.config4(4096)
-    out, (dP, d0, d1, loss, st) = _gpu(w, None, traj=False)
-    assert np.isfinite(dP).all() and np.isfinite(d0).all() and np.isfinite(d1).all()
-    conv = np.all(out["status"] == 0, 1)
-    print(f"full batch: {conv.sum()} robots converged on every step, adjoint status ok on "
-          f"{(st == 0).sum()}", flush=True)
-    assert (st == 0).sum() >= 4096 - 8
-    pick = [5, 1000, 2047, 3333]
-    sub = w.subset(pick)
-    ref = O.rollout(sub, traj=True, threads=16)
-    rP, r0, r1, rloss = O.gradient(sub, ref["traj"], threads=16)
-    checked = 0
-    for k, b in enumerate(pick):
-        if not np.all(out["chash"][b] == ref["chash"][k]):
-            continue
-        so, sc = int(w.inst_i[b, 1]), int(w.inst_i[b, 2])
-        ro = int(sub.inst_i[k, 1])
-        for got, want in ((dP, rP), (d0, r0), (d1, r1)):
-            g, x = got[so:so + sc], want[ro:ro + sc]
-            assert _rel(g, x, 1e-6 * max(np.abs(x).max(), 1e-30)).max() < 1e-6
-        assert abs(loss[b] - rloss[k]) <= 1e-9 * max(rloss[k], 1e-12)
-        checked += 1
-    assert checked >= 3
-
-
 def test_set_spams_equals_fresh_handle():
     import torch
     w = W.config4(16).subset([1, 2, 3])
