@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("uneven", "uniform", "grad", "serve"), default="uneven")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
+    ap.add_argument("--rates", default="", help="serve: several rates, comma-separated")
+    ap.add_argument("--hbm-mb", type=float, default=512.0, help="serve: device memory of the robot pools")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: measured seconds")
     ap.add_argument("--warm", type=float, default=5.0, help="serve: warm-up seconds")
     ap.add_argument("--slots", type=int, default=4096, help="serve: resident robots")
@@ -235,6 +237,9 @@ def main():
                     help="time eager reset + rollout calls instead of the captured graph")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the create-time launch order (no vine_sim_tune_order)")
+    ap.add_argument("--calibrate-copy-mb", type=float, default=0.0,
+                    help="first run one plain device copy of this many MB (read + write), the "
+                         "reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): robots are "
@@ -248,6 +253,14 @@ def main():
     from paper_2509_15180_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mb > 0:  # one copy kernel of known size
+        n = int(args.calibrate_copy_mb * 1e6 / 8)
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = args.workload
     if wl == "serve":
         return serve(args, torch, V, W)
@@ -388,11 +401,11 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def serve(args, torch, V, W):
+def serve_once(args, torch, V, W, rate):
     """Open-loop stream: requests arrive on their Poisson clock whether or not the
-    server keeps up; latency = completion - arrival."""
+    server keeps up; latency = completion (results read back) - arrival."""
     horizon = args.warm + args.duration
-    n_req = max(1, int(args.rate * horizon * 1.05) + 1)
+    n_req = max(1, int(rate * horizon * 1.05) + 1)
     # requests are generated lazily in blocks (a saturated stream would otherwise build
     # far more than the server can take)
     block = 64
@@ -401,17 +414,19 @@ def serve(args, torch, V, W):
     def upcoming():
         if not gen["buf"] and gen["next"] < n_req:
             k = min(block, n_req - gen["next"])
-            gen["buf"] = W.config5_requests(k, rate=args.rate, start=gen["next"])
+            gen["buf"] = W.config5_requests(k, rate=rate, start=gen["next"])
             gen["next"] += k
         return gen["buf"][0] if gen["buf"] else None
 
     stream = torch.cuda.current_stream()
-    srv = V.VineServer(slots=args.slots, max_links=512, max_obstacles=128, max_spams=8)
+    srv = V.VineServer(slots=args.slots, max_links=512, max_obstacles=128, max_spams=8,
+                       hbm_bytes=int(args.hbm_mb * 1e6))
     arrival, size = {}, {}
     done_at = {}
     t0 = time.perf_counter()
-    ju0 = None
+    ju0, tw = None, 0.0
     ticks = 0
+    peak_rows = 0
     while True:
         now = time.perf_counter() - t0
         if now > horizon:
@@ -424,6 +439,7 @@ def serve(args, torch, V, W):
             gen["buf"].pop(0)
             r = upcoming()
         st = srv.stats()
+        peak_rows = max(peak_rows, st["rows_used"])
         if ju0 is None and now >= args.warm:
             ju0, tw = st["joint_updates"], now
         if st["active"] + st["queued"] == 0:
@@ -438,27 +454,47 @@ def serve(args, torch, V, W):
             srv.release(rid)
     st = srv.stats()
     t_end = time.perf_counter() - t0
-    ju_rate = (st["joint_updates"] - (ju0 or 0)) / max(t_end - (tw if ju0 is not None else 0.0), 1e-9)
+    ju_rate = (st["joint_updates"] - (ju0 or 0)) / max(t_end - tw, 1e-9)
     lat = np.array([done_at[i] - arrival[i] for i in done_at if arrival[i] >= args.warm])
-    offered = float(np.mean(list(size.values()))) * args.rate if size else 0.0
+    offered = float(np.mean(list(size.values()))) * rate if size else 0.0
+    rec = {"rate_per_s": rate, "submitted": len(arrival), "completed": len(done_at),
+           "completed_after_warmup": int(lat.size), "joint_updates_per_s": ju_rate,
+           "offered_joint_updates_per_s": offered,
+           "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+           "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+           "queued_at_end": st["queued"], "resident_at_end": st["active"],
+           "peak_rows": peak_rows, "rows": st["rows"], "hbm_bytes": st["hbm_bytes"],
+           "ticks": ticks, "wall_s": t_end}
+    srv.close()
+    return rec
+
+
+def serve(args, torch, V, W):
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    runs = []
+    for rate in rates:
+        print(f"bench: serving at {rate}/s", file=sys.stderr, flush=True)
+        runs.append(serve_once(args, torch, V, W, rate))
+    # the highest rate whose p99 stays bounded: the queue drained and p99 within three
+    # times that of the lowest rate measured
+    base = runs[0]["p99_latency_s"]
+    bounded = [r for r in runs if r["p99_latency_s"] is not None and r["queued_at_end"] == 0
+               and base is not None and r["p99_latency_s"] <= 3.0 * base]
+    best = max(bounded, key=lambda r: r["rate_per_s"]) if bounded else runs[0]
     rec = {
-        "metric": METRIC, "value": ju_rate, "unit": "joint-updates/s", "n_gpus": 1,
-        "steps": ticks, "warmup": 0, "ms_per_step": 1e3 * t_end / max(ticks, 1),
+        "metric": METRIC, "value": best["joint_updates_per_s"], "unit": "joint-updates/s",
+        "n_gpus": 1, "steps": best["ticks"], "warmup": 0,
+        "ms_per_step": 1e3 * best["wall_s"] / max(best["ticks"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"request stream: Poisson {args.rate}/s, designs of 16-512 links and "
-                               f"0-128 obstacles on 1-64 jittered environment samples; "
-                               f"{args.slots} slots, {args.tick_steps} growth steps per round",
-                   "rate_per_s": args.rate, "warmup_s": args.warm, "measured_s": args.duration},
-        "serving": {"submitted": len(arrival), "completed": len(done_at),
-                    "completed_after_warmup": int(lat.size),
-                    "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
-                    "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
-                    "queued_at_end": st["queued"], "active_at_end": st["active"],
-                    "offered_joint_updates_per_s": offered},
-        "roofline": None, "cpu_baseline": None, "wall_s": t_end,
+        "config": {"workload": "request stream: Poisson arrivals, designs of 16-512 links and "
+                               "0-128 obstacles on 1-64 jittered environment samples; "
+                               f"{args.slots} slots, {args.hbm_mb:.0f} MB of robot pools, "
+                               f"{args.tick_steps} growth steps per round",
+                   "warmup_s": args.warm, "measured_s": args.duration},
+        "serving": {"highest_rate_with_bounded_p99": best["rate_per_s"], "runs": runs},
+        "roofline": None, "cpu_baseline": None,
     }
-    srv.close()
     print(json.dumps(rec), flush=True)
 
 

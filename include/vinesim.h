@@ -305,25 +305,41 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
 /* Serving: continuous batching of rollout requests on one device.
  *
  * The paper's planner (Sec. 5) issues many short simulation jobs whose sizes vary
- * (designs of different length, several environment samples each).  A server keeps a
- * fixed set of robot slots resident on the device; queued robots are admitted into
- * free slots at each tick, every active robot advances by a fixed number of growth
- * steps, and finished robots free their slots at once, so long and short jobs share
- * the device without waiting for each other's batch to drain.
+ * (designs of different length, several environment samples each).  A server keeps the
+ * robots it has admitted resident on the device and advances them together; queued
+ * robots are admitted as soon as a slot and device memory free up, so long and short
+ * jobs share the device without waiting for each other's batch to drain.
  *
- * A request is a set of robots (e.g. one design on S environment samples); it
- * completes when all of its robots have reached their target length.  Results are
- * bitwise those of the same robots run through vine_sim_create / vine_sim_rollout
- * (robots never interact, and the kernels are the same). */
+ * Device memory is a budget, not a worst case: a robot of n links and K obstacles takes
+ * n rows of a row pool (joint angle, sPAM coverage and one growth step's records per
+ * row, 84 bytes) and K entries of an obstacle pool (36 bytes), allocated first-fit on
+ * admission and freed when it retires.  Admission is first come, first served: the
+ * robot at the head of the queue waits until a slot and room in both pools are free.
+ *
+ * A tick enqueues its work on the stream and returns without waiting for it: the
+ * admitted robots' rows are copied in from pinned host staging (asynchronously), every
+ * resident robot advances by `steps` growth steps (one launch per chain-length class;
+ * robots already at full length do nothing), and the link counts are copied out
+ * asynchronously.  The host reads a tick's link counts two ticks later (waiting on an
+ * event of that tick, by then normally complete, so the device always has the next
+ * tick queued); a robot seen at full length has its results copied out then and read,
+ * with its memory freed, two ticks after that.  A request is a set of robots (e.g. one
+ * design on S environment samples) and completes when all of its robots are read back.
+ * Results are bitwise those of the same robots run through vine_sim_create /
+ * vine_sim_rollout (robots never interact, and the kernels are the same). */
 typedef struct vine_server vine_server;
 
-/* slots: robots resident at once; max_links / max_obstacles / max_spams bound each
- * robot (<= VINE_MAX_LINKS / VINE_MAX_OBSTACLES / VINE_MAX_SPAMS).  Device memory is
- * allocated here, once.  Up to 8 distinct link lengths are supported over the
- * server's life (the force-law table is built on first use of a length).  Errors:
- * VINE_EINVAL, VINE_ECAPACITY, VINE_ENOMEM, VINE_EDEVICE. */
-int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max_links,
-                           int32_t max_obstacles, int32_t max_spams, vine_server** out);
+/* slots: robots resident at once; hbm_bytes: device memory for the pools and per-slot
+ * rows, split so that the pools hold floor((hbm_bytes - 148 slots) / (84 max_links +
+ * 36 max_obstacles)) robots at the bounds (more of smaller ones); max_links /
+ * max_obstacles / max_spams bound each robot (<= VINE_MAX_LINKS / VINE_MAX_OBSTACLES /
+ * VINE_MAX_SPAMS).  Device and pinned host memory are allocated here, once.  Up to 8
+ * distinct link lengths are supported over the server's life (the force-law table is
+ * built on first use of a length).  Errors: VINE_EINVAL (also a budget below one robot
+ * at the bounds), VINE_ECAPACITY, VINE_ENOMEM, VINE_EDEVICE. */
+int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm_bytes,
+                           int32_t max_links, int32_t max_obstacles, int32_t max_spams,
+                           vine_server** out);
 
 /* Queue one request (FIFO).  Host arrays as for vine_sim_create (offsets relative to
  * these arrays); copied.  request_id is the caller's and must not be queued twice at
@@ -333,10 +349,11 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
                            int32_t n_inst, const vine_spam* spams, int32_t n_spams,
                            const vine_obstacle* obstacles, int32_t n_obstacles);
 
-/* One scheduling round: admit queued robots into free slots, advance every active
- * robot by `steps` growth steps (one launch per chain-length class), and retire the
- * robots that reached their length.  Synchronises `stream` before returning.  Returns
- * the number of requests completed in this round, or a negative VINE_E* code. */
+/* One scheduling round, enqueued on `stream` (see above): read back the round two
+ * ticks earlier, admit queued robots, advance every resident robot by `steps` growth
+ * steps.  Returns the number of requests completed by this call (their results read
+ * back), or a negative VINE_E* code.  Call it while requests are queued or resident
+ * (vine_server_stats) to drain the server. */
 int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream);
 
 /* Completed requests not yet polled, oldest first: their ids into ids[] (host, up to
@@ -354,9 +371,11 @@ int32_t vine_server_result(const vine_server* s, int64_t request_id, int32_t rob
 /* Forget a completed request's results. */
 int32_t vine_server_release(vine_server* s, int64_t request_id);
 
-/* Counters: [0] robots queued, [1] robots active, [2] requests completed,
- * [3] joint-updates done (sum over growth steps of the link count). */
-void vine_server_stats(const vine_server* s, int64_t out[4]);
+/* Counters: [0] robots queued, [1] robots resident (advancing or being read back),
+ * [2] requests completed, [3] joint-updates done (sum over growth steps of the link
+ * count, as of the last snapshot read), [4] rows in use, [5] row capacity, [6] device
+ * bytes of the pools and slot rows, [7] robots being read back. */
+void vine_server_stats(const vine_server* s, int64_t out[8]);
 
 void vine_server_destroy(vine_server* s);
 const char* vine_server_last_error(const vine_server* s);

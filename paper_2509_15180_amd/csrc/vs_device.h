@@ -54,14 +54,30 @@ struct KParams {
   int max_iter, substeps;
 };
 
+// Fields of the per-robot integer row ii[b][kII].
+constexpr int kII = 10;
+enum : int {
+  kNTarget = 0,   // target link count
+  kObsOff = 1,    // first obstacle (rows of obs, okind)
+  kObsCnt = 2,
+  kTableId = 3,   // sPAM force-law table
+  kCoverOff = 4,  // first joint row of cover
+  kSpamOff = 5,   // first sPAM record
+  kSpamCnt = 6,
+  kThetaOff = 7,  // first element of the robot's joint angles in theta
+  kRecOff = 8,    // first element of its per-step records (tip row = 3 x that)
+  kRecCap = 9     // per-step records it holds (steps it can take)
+};
+
 // Per-robot and per-simulation device arrays (structure of arrays).
 struct KData {
   int n_inst;
-  int n_max;          // largest target link count (row length of theta)
-  int t_max;          // recorded steps per robot
+  int n_max;          // largest target link count (row length of traj, ckpt)
+  int t_max;          // recorded steps per robot (rows of traj)
+  long long theta_len, rec_len;  // elements of theta and of each per-step record array
+  int skip_done;      // robots at their target length do nothing (serving)
   // inputs
-  const int* ii;      // [B][8]: n_target, obs_off, obs_cnt, table_id, cover_off, spam_off,
-                      //         spam_cnt, 0
+  const int* ii;      // [B][kII], fields above
   const double* dd;   // [B][6]: l, R, P_vine, base_x, base_y, base_heading
   const double* cover;// [sum n][2]: P+_j, P-_j
   const int* okind;   // [O]
@@ -74,11 +90,11 @@ struct KData {
   const int* order;
   int launch_first, launch_count;
   // state
-  double* theta;      // [B][N]
+  double* theta;      // robot b: [ii[b][kThetaOff], + n_target)
   int* ncur;          // [B]
   int* tcur;          // [B] steps recorded so far
-  // records [B][T]...
-  double* tip;        // [B][T][3]
+  // per-step records, robot b at [ii[b][kRecOff], + ii[b][kRecCap])...
+  double* tip;        // ...times 3 (x, y, heading)
   double* rho;
   int* iters;
   int* status;

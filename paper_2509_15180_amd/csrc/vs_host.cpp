@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <type_traits>
@@ -28,8 +29,8 @@ hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
                        int* status, int nmax_class, hipStream_t stream);
 hipError_t launch_zero3(double* a, double* b, double* c, int n, hipStream_t stream);
 hipError_t launch_reset(const KData& D, hipStream_t stream);
-hipError_t launch_seg_load(const KData& Dseg, const double* ckpt, const int* tcur, int n_ckpt,
-                           int q, int ce, hipStream_t stream);
+hipError_t launch_seg_load(const KData& Dseg, const int* ii_handle, const double* ckpt,
+                           const int* tcur, int n_ckpt, int q, int ce, hipStream_t stream);
 }
 
 using vs::SpamTable;
@@ -357,6 +358,8 @@ void append_cover(const vine_instance& I, const vine_spam* spams, std::vector<do
 struct vine_sim {
   vine_params prm;
   int B = 0, N = 0, T = 0, S = 0;
+  long long theta_len = 0, rec_len = 0;  // elements of theta and of each record array
+  int skip_done = 0;                     // serving slabs: robots at full length do nothing
   std::vector<double> link_lens;      // distinct link lengths (table ids)
   std::vector<SpamTable> tables_h;
   std::vector<vine_instance> inst_h;  // as given at create (sPAM ranges, lengths)
@@ -396,7 +399,7 @@ struct vine_sim {
            *traj = nullptr, *jevals = nullptr, *nsolves = nullptr, *negsteps = nullptr,
            *cycles = nullptr, *wtime = nullptr, *gsums = nullptr, *gloss = nullptr;
     int *ncur = nullptr, *tcur = nullptr, *iters = nullptr, *status = nullptr, *ncont = nullptr,
-        *gstat = nullptr;
+        *gstat = nullptr, *ii = nullptr;
     unsigned long long* chash = nullptr;
     int steps = 0;  // ckpt_every the buffers were sized for
   } seg;
@@ -442,7 +445,7 @@ void free_seg(vine_sim* h) {
   vine_sim::Seg& g = h->seg;
   void* ptrs[] = {g.theta, g.tip, g.rho, g.maxpen, g.traj, g.jevals, g.nsolves, g.negsteps,
                   g.cycles, g.wtime, g.gsums, g.gloss, g.ncur, g.tcur, g.iters, g.status, g.ncont,
-                  g.gstat, g.chash};
+                  g.gstat, g.ii, g.chash};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   g = vine_sim::Seg();
@@ -491,6 +494,9 @@ vs::KData kdata(vine_sim* h) {
   D.n_inst = h->B;
   D.n_max = h->N;
   D.t_max = h->T;
+  D.theta_len = h->theta_len;
+  D.rec_len = h->rec_len;
+  D.skip_done = h->skip_done;
   D.ii = h->ii;
   D.dd = h->dd;
   D.cover = h->cover;
@@ -644,8 +650,10 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   h->N = N;
   h->T = N;
   h->S = n_spams;
+  h->theta_len = (long long)n_inst * N;
+  h->rec_len = (long long)n_inst * N;
   // host-side derived inputs
-  std::vector<int> ii(8 * (size_t)n_inst);
+  std::vector<int> ii(vs::kII * (size_t)n_inst);
   std::vector<double> dd(6 * (size_t)n_inst);
   std::vector<int> okind;
   std::vector<double> obs;
@@ -659,14 +667,17 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       tid = (int)h->link_lens.size();
       h->link_lens.push_back(I.link_len);
     }
-    ii[8 * b + 0] = I.n_links;
-    ii[8 * b + 1] = (int)okind.size();
-    ii[8 * b + 2] = I.obs_count;
-    ii[8 * b + 3] = tid;
-    ii[8 * b + 4] = (int)(cover.size() / 2);
-    ii[8 * b + 5] = I.spam_offset;
-    ii[8 * b + 6] = I.spam_count;
-    ii[8 * b + 7] = 0;
+    int* row = ii.data() + vs::kII * (size_t)b;
+    row[vs::kNTarget] = I.n_links;
+    row[vs::kObsOff] = (int)okind.size();
+    row[vs::kObsCnt] = I.obs_count;
+    row[vs::kTableId] = tid;
+    row[vs::kCoverOff] = (int)(cover.size() / 2);
+    row[vs::kSpamOff] = I.spam_offset;
+    row[vs::kSpamCnt] = I.spam_count;
+    row[vs::kThetaOff] = b * N;  // N = T: every robot gets a row of each
+    row[vs::kRecOff] = b * N;
+    row[vs::kRecCap] = N;
     dd[6 * b + 0] = I.link_len;
     dd[6 * b + 1] = I.tube_radius;
     dd[6 * b + 2] = I.body_pressure;
@@ -1007,6 +1018,7 @@ static hipError_t ensure_seg(vine_sim* h) {
   A(dalloc(&g.gsums, B * vs::kWave * 3));
   A(dalloc(&g.gloss, B));
   A(dalloc(&g.gstat, B));
+  A(dalloc(&g.ii, B * vs::kII));
   if (e != hipSuccess) {
     free_seg(h);
     return e;
@@ -1052,6 +1064,7 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
     // state, so bitwise the states of the rollout), then its terms of the adjoint
     vs::KData Dseg = kdata(h);
     Dseg.t_max = h->ckpt_every;
+    Dseg.ii = g->ii;  // the handle's robot rows with the segment's record fields
     Dseg.theta = g->theta;
     Dseg.ncur = g->ncur;
     Dseg.tcur = g->tcur;
@@ -1075,7 +1088,7 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
     const int ce = h->ckpt_every;
     for (int q = 0; q < h->n_ckpt && e == hipSuccess; ++q) {
       const int t0 = q * ce, len = std::min(ce, h->T - t0);
-      e = vs::launch_seg_load(Dseg, h->ckpt, h->tcur, h->n_ckpt, q, ce, s);
+      e = vs::launch_seg_load(Dseg, h->ii, h->ckpt, h->tcur, h->n_ckpt, q, ce, s);
       if (e == hipSuccess)
         e = for_each_class(h, s, Dseg, [&](int links, const vs::KData& D, hipStream_t cs) {
           return vs::launch_rollout(kp, D, len, links, cs);
@@ -1273,17 +1286,77 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Serving: continuous batching over a slab of resident robot slots.  The slab is an
-// ordinary handle whose per-robot rows are rewritten when a robot is admitted; the
-// kernels are the batch kernels, launched over the list of active slots.
+// Serving: continuous batching over a slab of resident robots.  The slab's per-robot
+// arrays live in pools: a row pool (one row per link: joint angle, sPAM coverage and
+// one step's records; a robot of n links holds n consecutive rows) and an obstacle
+// pool, each with a first-fit free list, so the device memory a robot takes follows its
+// size and admission is by a byte budget.  A tick enqueues its work without waiting for
+// it: the copies in (from pinned staging), the launches, and an asynchronous snapshot of
+// the link counts; the host acts on a tick's snapshot two ticks later, so the device
+// always has the next tick queued while the host does its bookkeeping.
 
 namespace vs {
 hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream);
 }
 
+namespace {
+
+// first-fit free list over [0, cap)
+struct FreeList {
+  std::map<int64_t, int64_t> free;  // offset -> length
+  int64_t cap = 0, used = 0;
+  void init(int64_t c) {
+    cap = c;
+    used = 0;
+    free.clear();
+    if (c > 0) free[0] = c;
+  }
+  int64_t take(int64_t len) {
+    if (len <= 0) return 0;
+    for (auto it = free.begin(); it != free.end(); ++it)
+      if (it->second >= len) {
+        const int64_t off = it->first, rest = it->second - len;
+        free.erase(it);
+        if (rest > 0) free[off + len] = rest;
+        used += len;
+        return off;
+      }
+    return -1;
+  }
+  void give(int64_t off, int64_t len) {
+    if (len <= 0) return;
+    used -= len;
+    auto it = free.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free.erase(nx);
+    }
+    if (it != free.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free.erase(it);
+      }
+    }
+  }
+};
+
+template <typename T>
+hipError_t halloc(T** p, size_t count) {  // pinned host staging
+  return hipHostMalloc((void**)p, sizeof(T) * (count > 0 ? count : 1), hipHostMallocDefault);
+}
+
+constexpr int64_t kRowBytes = 8 + 24 + 8 + 4 + 4 + 4 + 8 + 8 + 16;  // theta, records, coverage
+constexpr int64_t kObsBytes = 4 + 32;
+constexpr int64_t kSlotBytes = 4 * vs::kII + 48 + 8 + 40 + 4 + 8;  // ii, dd, counts, counters, lists
+
+}  // namespace
+
 struct vine_server {
-  vine_sim* h = nullptr;  // slab: B = slots, N = T = max_links
+  vine_sim* h = nullptr;  // the slab
   int slots = 0, max_links = 0, max_obs = 0, max_spams = 0;
+  int64_t hbm_bytes = 0;
   static constexpr int kMaxTables = 8;
   struct Robot {
     int64_t req = 0;
@@ -1291,20 +1364,39 @@ struct vine_server {
     vine_instance inst{};
     std::vector<vine_spam> spams;
     std::vector<vine_obstacle> obs;
+    int64_t row = -1, obs_off = -1;
+    int n_known = 0;  // link count at the last snapshot read
   };
   struct Request {
     int n_robots = 0, n_done = 0, worst = 0;
     std::vector<double> tips;                 // 3 per robot
     std::vector<std::vector<double>> theta;   // per robot
   };
+  enum SlotState : int { kFree = 0, kActive = 1, kRetiring = 2 };
   std::deque<Robot> queue;
-  std::vector<int> slot_robot;                // index into live, or -1
   std::vector<Robot> live;                    // by slot
-  std::vector<int> ncur_before;               // host copy of the link counts
+  std::vector<int> state;                     // SlotState by slot
+  FreeList rows, obst;
   std::unordered_map<int64_t, Request> reqs;
   std::deque<int64_t> completed;
-  int* d_slots = nullptr;                     // admitted slots of a round
-  int64_t joint_updates = 0, n_completed = 0;
+  int64_t joint_updates = 0, n_completed = 0, tick = 0;
+  // pinned staging: inputs at the pools' offsets, per-tick slot lists, snapshots, results
+  int* st_ii = nullptr;
+  double* st_dd = nullptr;
+  double* st_cover = nullptr;
+  int* st_okind = nullptr;
+  double* st_obs = nullptr;
+  int* st_adm[2] = {nullptr, nullptr};
+  int* st_order[2] = {nullptr, nullptr};
+  int* st_snap[2] = {nullptr, nullptr};
+  double* st_theta = nullptr;
+  double* st_tip = nullptr;
+  int* st_status = nullptr;
+  int* d_adm[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_live[2] = {false, false};
+  std::vector<int> snap_slots[2];   // slots whose link counts the snapshot of that tick holds
+  std::vector<int> gather[2];       // slots whose results that tick copied out
   std::string err;
 };
 
@@ -1330,37 +1422,44 @@ int table_for(vine_server* sv, double l) {
   return t;
 }
 
+void free_server(vine_server* s) {
+  void* pinned[] = {s->st_ii, s->st_dd, s->st_cover, s->st_okind, s->st_obs, s->st_adm[0],
+                    s->st_adm[1], s->st_order[0], s->st_order[1], s->st_snap[0], s->st_snap[1],
+                    s->st_theta, s->st_tip, s->st_status};
+  for (void* p : pinned)
+    if (p) (void)hipHostFree(p);
+  for (int k = 0; k < 2; ++k) {
+    if (s->d_adm[k]) (void)hipFree(s->d_adm[k]);
+    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  }
+  if (s->h) vine_sim_destroy(s->h);
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max_links,
-                           int32_t max_obstacles, int32_t max_spams, vine_server** out) {
+int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm_bytes,
+                           int32_t max_links, int32_t max_obstacles, int32_t max_spams,
+                           vine_server** out) {
   if (!params || !out || slots < 1 || max_links < 1 || max_obstacles < 0 || max_spams < 0)
     return sfail(nullptr, VINE_EINVAL, "null pointer or non-positive size");
   if (max_links > VINE_MAX_LINKS || max_obstacles > VINE_MAX_OBSTACLES ||
       max_spams > VINE_MAX_SPAMS)
     return sfail(nullptr, VINE_ECAPACITY, "bounds above the library's limits");
-  // the slab: `slots` placeholder robots at the bounds (overwritten on admission)
+  // the budget buys whole robots at the bounds: max_links rows + max_obstacles obstacles
+  const int64_t per_robot = kRowBytes * max_links + kObsBytes * max_obstacles;
+  const int64_t units = (hbm_bytes - kSlotBytes * (int64_t)slots) / per_robot;
+  if (units < 1)
+    return sfail(nullptr, VINE_EINVAL, "the byte budget does not hold one robot at the bounds");
+  // a slab of `slots` robots at zero size, pools sized from the budget
   vine_instance ph{};
   ph.n_links = max_links;
   ph.link_len = 0.02;
   ph.tube_radius = 0.025;
   ph.body_pressure = 1000.0;
-  std::vector<vine_instance> inst(slots, ph);
-  std::vector<vine_spam> sp((size_t)slots * (max_spams > 0 ? max_spams : 1),
-                            vine_spam{0.0, 0.0, 1.0, 0.0});
-  std::vector<vine_obstacle> ob((size_t)slots * (max_obstacles > 0 ? max_obstacles : 1),
-                                vine_obstacle{0, 0, 1e6, 1e6, 1.0, 1.0});
-  for (int b = 0; b < slots; ++b) {
-    inst[b].spam_offset = b * max_spams;
-    inst[b].spam_count = max_spams;
-    inst[b].obs_offset = b * max_obstacles;
-    inst[b].obs_count = max_obstacles;
-  }
   vine_sim* h = nullptr;
-  int rc = vine_sim_create(params, inst.data(), slots, sp.data(), (int)sp.size(), ob.data(),
-                           (int)ob.size(), &h);
+  int rc = vine_sim_create(params, &ph, 1, nullptr, 0, nullptr, 0, &h);
   if (rc != VINE_OK) return rc;
   vine_server* s = new (std::nothrow) vine_server();
   if (!s) {
@@ -1372,23 +1471,88 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int32_t max
   s->max_links = max_links;
   s->max_obs = max_obstacles;
   s->max_spams = max_spams;
-  s->slot_robot.assign(slots, -1);
+  const int64_t R = units * max_links, Ko = std::max<int64_t>(1, units * max_obstacles);
+  s->rows.init(R);
+  s->obst.init(units * max_obstacles);
   s->live.resize(slots);
-  s->ncur_before.assign(slots, 0);
-  // room for every link-length table the server may need
+  s->state.assign(slots, vine_server::kFree);
+  // replace the slab's per-robot arrays by pools of the budget's size
+  void* old[] = {h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->theta, h->ncur, h->tcur,
+                 h->tip, h->rho, h->iters, h->status, h->ncont, h->chash, h->maxpen, h->jevals,
+                 h->nsolves, h->negsteps, h->cycles, h->wtime, h->order};
+  for (void* p : old) (void)hipFree(p);
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  const size_t B = slots;
+  A(dalloc(&h->ii, B * vs::kII));
+  A(dalloc(&h->dd, B * 6));
+  A(dalloc(&h->cover, (size_t)R * 2));
+  A(dalloc(&h->spam, 1));
+  A(dalloc(&h->okind, (size_t)Ko));
+  A(dalloc(&h->obs, (size_t)Ko * 4));
+  A(dalloc(&h->theta, (size_t)R));
+  A(dalloc(&h->ncur, B));
+  A(dalloc(&h->tcur, B));
+  A(dalloc(&h->tip, (size_t)R * 3));
+  A(dalloc(&h->rho, (size_t)R));
+  A(dalloc(&h->iters, (size_t)R));
+  A(dalloc(&h->status, (size_t)R));
+  A(dalloc(&h->ncont, (size_t)R));
+  A(dalloc(&h->chash, (size_t)R));
+  A(dalloc(&h->maxpen, (size_t)R));
+  A(dalloc(&h->jevals, B));
+  A(dalloc(&h->nsolves, B));
+  A(dalloc(&h->negsteps, B));
+  A(dalloc(&h->cycles, B));
+  A(dalloc(&h->wtime, B));
+  A(dalloc(&h->order, B));
   SpamTable* t8 = nullptr;
-  hipError_t e = dalloc(&t8, vine_server::kMaxTables);
+  A(dalloc(&t8, vine_server::kMaxTables));
   if (e == hipSuccess)
     e = hipMemcpy(t8, h->tables_h.data(), sizeof(SpamTable) * h->tables_h.size(),
                   hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = dalloc(&s->d_slots, slots);
-  if (e != hipSuccess) {
-    if (t8) (void)hipFree(t8);
-    vine_server_destroy(s);
-    return sfail(nullptr, VINE_EDEVICE, std::string("server allocation: ") + hipGetErrorString(e));
-  }
   (void)hipFree(h->tables);
   h->tables = t8;
+  for (int k = 0; k < 2; ++k) {
+    A(dalloc(&s->d_adm[k], B));
+    A(halloc(&s->st_adm[k], B));
+    A(halloc(&s->st_order[k], B));
+    A(halloc(&s->st_snap[k], B));
+    A(hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming));
+  }
+  A(halloc(&s->st_ii, B * vs::kII));
+  A(halloc(&s->st_dd, B * 6));
+  A(halloc(&s->st_cover, (size_t)R * 2));
+  A(halloc(&s->st_okind, (size_t)Ko));
+  A(halloc(&s->st_obs, (size_t)Ko * 4));
+  A(halloc(&s->st_theta, (size_t)R));
+  A(halloc(&s->st_tip, (size_t)R * 3));
+  A(halloc(&s->st_status, (size_t)R));
+  h->B = slots;
+  h->N = max_links;
+  h->T = max_links;
+  h->S = 0;
+  h->theta_len = R;
+  h->rec_len = R;
+  h->skip_done = 1;
+  h->inst_h.clear();
+  h->order_h.assign(B, 0);
+  for (int c = 0; c < vine_sim::kClasses; ++c) h->cls_first[c] = h->cls_count[c] = 0;
+  if (e == hipSuccess) {
+    // every slot empty: zero rows (target 0 links), zero state
+    std::vector<int> ii(B * vs::kII, 0);
+    e = hipMemcpy(h->ii, ii.data(), sizeof(int) * ii.size(), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = vs::launch_reset(kdata(h), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    vine_server_destroy(s);
+    return sfail(nullptr, e == hipErrorOutOfMemory ? VINE_ENOMEM : VINE_EDEVICE,
+                 std::string("server allocation: ") + hipGetErrorString(e));
+  }
+  s->hbm_bytes = kRowBytes * R + kObsBytes * Ko + kSlotBytes * (int64_t)slots;
   *out = s;
   return VINE_OK;
 }
@@ -1443,123 +1607,169 @@ int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
   if (!s || steps < 1) return sfail(s, VINE_EINVAL, "null server or steps < 1");
   vine_sim* h = s->h;
   hipStream_t st = (hipStream_t)stream;
+  const int par = (int)(s->tick & 1);
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
   };
-  // admission: write the robot's rows into a free slot
-  std::vector<int> admitted;
-  std::vector<double> cover;
-  std::vector<double> obs_rows;
-  std::vector<int> kinds;
-  std::vector<double> spam_rows;
-  for (int slot = 0; slot < s->slots && !s->queue.empty(); ++slot) {
-    if (s->slot_robot[slot] >= 0) continue;
-    vine_server::Robot r = std::move(s->queue.front());
-    s->queue.pop_front();
-    const int tid = table_for(s, r.inst.link_len);
+  int done_now = 0;
+  // 1. the tick two back: its results and its snapshot (copies complete with its event)
+  if (s->ev_live[par]) {
+    A(hipEventSynchronize(s->ev[par]));
+    if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("wait: ") + hipGetErrorString(e));
+    s->ev_live[par] = false;
+    for (int slot : s->gather[par]) {  // results copied out by that tick: the robot is done
+      vine_server::Robot& r = s->live[slot];
+      vine_server::Request& R = s->reqs[r.req];
+      const int n = r.inst.n_links;
+      const int64_t row = r.row;
+      R.theta[r.index].assign(s->st_theta + row, s->st_theta + row + n);
+      std::copy(s->st_tip + 3 * (row + n - 1), s->st_tip + 3 * (row + n), R.tips.begin() + 3 * (size_t)r.index);
+      for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, s->st_status[row + t]);
+      if (++R.n_done == R.n_robots) {
+        s->completed.push_back(r.req);
+        ++s->n_completed;
+        ++done_now;
+      }
+      s->rows.give(r.row, n);
+      s->obst.give(r.obs_off, (int64_t)r.obs.size());
+      s->state[slot] = vine_server::kFree;
+      r = vine_server::Robot();
+    }
+    s->gather[par].clear();
+    for (const int slot : s->snap_slots[par]) {  // link counts after that tick
+      vine_server::Robot& r = s->live[slot];
+      const int n0 = r.n_known, n1 = s->st_snap[par][slot];
+      s->joint_updates += (int64_t)n1 * (n1 + 1) / 2 - (int64_t)n0 * (n0 + 1) / 2;
+      r.n_known = n1;
+      if (n1 >= r.inst.n_links && s->state[slot] == vine_server::kActive) {
+        // finished: copy its angles, last tip and statuses out (read two ticks on)
+        const int n = r.inst.n_links;
+        const int64_t row = r.row;
+        A(hipMemcpyAsync(s->st_theta + row, h->theta + row, sizeof(double) * n,
+                         hipMemcpyDeviceToHost, st));
+        A(hipMemcpyAsync(s->st_tip + 3 * (row + n - 1), h->tip + 3 * (row + n - 1),
+                         sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        A(hipMemcpyAsync(s->st_status + row, h->status + row, sizeof(int) * n,
+                         hipMemcpyDeviceToHost, st));
+        s->state[slot] = vine_server::kRetiring;
+        s->gather[par].push_back(slot);
+      }
+    }
+    s->snap_slots[par].clear();
+  }
+  // 2. admission: queued robots (first come, first served) into a free slot and free rows
+  int nadm = 0;
+  for (int slot = 0; slot < s->slots && !s->queue.empty() && e == hipSuccess; ++slot) {
+    if (s->state[slot] != vine_server::kFree) continue;
+    vine_server::Robot& q = s->queue.front();
+    const int n = q.inst.n_links, K = (int)q.obs.size();
+    const int64_t row = s->rows.take(n);
+    if (row < 0) break;
+    const int64_t oo = s->obst.take(K);
+    if (oo < 0) {
+      s->rows.give(row, n);
+      break;
+    }
+    const int tid = table_for(s, q.inst.link_len);
     if (tid < 0) {
-      s->queue.push_front(std::move(r));
+      s->rows.give(row, n);
+      s->obst.give(oo, K);
       return sfail(s, tid == -1 ? VINE_ECAPACITY : VINE_EDEVICE,
                    tid == -1 ? "more than 8 distinct link lengths" : "table upload failed");
     }
+    vine_server::Robot r = std::move(q);
+    s->queue.pop_front();
+    r.row = row;
+    r.obs_off = oo;
+    r.n_known = 0;
     const vine_instance& I = r.inst;
-    const int ii[8] = {I.n_links, slot * s->max_obs, I.obs_count, tid, slot * s->max_links,
-                       slot * s->max_spams, I.spam_count, 0};
-    const double dd[6] = {I.link_len, I.tube_radius, I.body_pressure, I.base_x, I.base_y,
-                          I.base_heading};
-    cover.clear();
+    int* ii = s->st_ii + vs::kII * (size_t)slot;
+    ii[vs::kNTarget] = n;
+    ii[vs::kObsOff] = (int)oo;
+    ii[vs::kObsCnt] = K;
+    ii[vs::kTableId] = tid;
+    ii[vs::kCoverOff] = (int)row;
+    ii[vs::kSpamOff] = 0;
+    ii[vs::kSpamCnt] = 0;
+    ii[vs::kThetaOff] = (int)row;
+    ii[vs::kRecOff] = (int)row;
+    ii[vs::kRecCap] = n;
+    double* dd = s->st_dd + 6 * (size_t)slot;
+    dd[0] = I.link_len;
+    dd[1] = I.tube_radius;
+    dd[2] = I.body_pressure;
+    dd[3] = I.base_x;
+    dd[4] = I.base_y;
+    dd[5] = I.base_heading;
+    std::vector<double> cover;
     append_cover(I, r.spams.data(), cover);
-    obs_rows.clear();
-    kinds.clear();
-    for (const vine_obstacle& O : r.obs) {
-      kinds.push_back(O.kind);
-      obs_rows.insert(obs_rows.end(), {O.cx, O.cy, O.a, O.kind == 1 ? O.b : 0.0});
+    std::copy(cover.begin(), cover.end(), s->st_cover + 2 * row);
+    for (int k = 0; k < K; ++k) {
+      const vine_obstacle& O = r.obs[k];
+      s->st_okind[oo + k] = O.kind;
+      double* o = s->st_obs + 4 * (oo + k);
+      o[0] = O.cx;
+      o[1] = O.cy;
+      o[2] = O.a;
+      o[3] = O.kind == 1 ? O.b : 0.0;
     }
-    spam_rows.clear();
-    for (const vine_spam& S : r.spams)
-      spam_rows.insert(spam_rows.end(), {S.s_start, S.s_end, S.side, S.pressure});
-    // synchronous copies: the host rows are reused for the next robot
-    A(hipMemcpy(h->ii + 8 * (size_t)slot, ii, sizeof ii, hipMemcpyHostToDevice));
-    A(hipMemcpy(h->dd + 6 * (size_t)slot, dd, sizeof dd, hipMemcpyHostToDevice));
-    A(hipMemcpy(h->cover + 2 * (size_t)slot * s->max_links, cover.data(),
-                sizeof(double) * cover.size(), hipMemcpyHostToDevice));
-    if (!kinds.empty()) {
-      A(hipMemcpy(h->okind + (size_t)slot * s->max_obs, kinds.data(), sizeof(int) * kinds.size(),
-                  hipMemcpyHostToDevice));
-      A(hipMemcpy(h->obs + 4 * (size_t)slot * s->max_obs, obs_rows.data(),
-                  sizeof(double) * obs_rows.size(), hipMemcpyHostToDevice));
+    // asynchronous copies from pinned staging; a staging row is rewritten only after its
+    // robot has retired, long after these copies ran
+    A(hipMemcpyAsync(h->ii + vs::kII * (size_t)slot, ii, sizeof(int) * vs::kII,
+                     hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(h->cover + 2 * row, s->st_cover + 2 * row, sizeof(double) * 2 * n,
+                     hipMemcpyHostToDevice, st));
+    if (K > 0) {
+      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, st));
+      A(hipMemcpyAsync(h->obs + 4 * oo, s->st_obs + 4 * oo, sizeof(double) * 4 * K,
+                       hipMemcpyHostToDevice, st));
     }
-    if (!spam_rows.empty())
-      A(hipMemcpy(h->spam + 4 * (size_t)slot * s->max_spams, spam_rows.data(),
-                  sizeof(double) * spam_rows.size(), hipMemcpyHostToDevice));
     s->live[slot] = std::move(r);
-    s->slot_robot[slot] = slot;
-    s->ncur_before[slot] = 0;
-    admitted.push_back(slot);
+    s->state[slot] = vine_server::kActive;
+    s->st_adm[par][nadm++] = slot;
   }
   if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("admission: ") + hipGetErrorString(e));
-  if (!admitted.empty()) {
-    A(hipMemcpyAsync(s->d_slots, admitted.data(), sizeof(int) * admitted.size(),
-                     hipMemcpyHostToDevice, st));
-    A(vs::launch_slot_reset(kdata(h), s->d_slots, (int)admitted.size(), st));
+  if (nadm > 0) {
+    A(hipMemcpyAsync(s->d_adm[par], s->st_adm[par], sizeof(int) * nadm, hipMemcpyHostToDevice, st));
+    A(vs::launch_slot_reset(kdata(h), s->d_adm[par], nadm, st));
   }
-  // launch order: active slots by class, longest expected work first
+  // 3. launches: active robots by class, longest expected work first
   std::vector<int> order;
   for (int slot = 0; slot < s->slots; ++slot)
-    if (s->slot_robot[slot] >= 0) order.push_back(slot);
-  if (order.empty()) return 0;
-  auto cost = [&](int b) {
-    const vine_instance& I = s->live[b].inst;
-    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
-  };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
-    if (ca != cb) return ca < cb;
-    return cost(a) > cost(b);
-  });
-  for (int c = 0; c < vine_sim::kClasses; ++c) h->cls_count[c] = 0;
-  for (int b : order) h->cls_count[link_class(s->live[b].inst.n_links)]++;
-  h->cls_first[0] = 0;
-  for (int c = 1; c < vine_sim::kClasses; ++c)
-    h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
-  A(hipMemcpyAsync(h->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch set-up: ") + hipGetErrorString(e));
-  const vs::KParams kp = kparams(h->prm);
-  e = for_each_class(h, st, [&](int links, const vs::KData& D, hipStream_t ss) {
-    return vs::launch_rollout(kp, D, steps, links, ss);
-  });
-  std::vector<int> ncur(s->slots);
-  A(hipMemcpyAsync(ncur.data(), h->ncur, sizeof(int) * s->slots, hipMemcpyDeviceToHost, st));
-  A(hipStreamSynchronize(st));
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("round: ") + hipGetErrorString(e));
-  // bookkeeping and retirement
-  int done_now = 0;
-  for (int b : order) {
-    const int n0 = s->ncur_before[b], n1 = ncur[b];
-    s->joint_updates += (int64_t)n1 * (n1 + 1) / 2 - (int64_t)n0 * (n0 + 1) / 2;
-    s->ncur_before[b] = n1;
-    vine_server::Robot& r = s->live[b];
-    if (n1 < r.inst.n_links) continue;
-    vine_server::Request& R = s->reqs[r.req];
-    const int n = r.inst.n_links;
-    std::vector<double> th(n);
-    std::vector<int> stat(n);
-    double tip[3];
-    A(hipMemcpy(th.data(), h->theta + (size_t)b * h->N, sizeof(double) * n, hipMemcpyDeviceToHost));
-    A(hipMemcpy(stat.data(), h->status + (size_t)b * h->T, sizeof(int) * n, hipMemcpyDeviceToHost));
-    A(hipMemcpy(tip, h->tip + 3 * ((size_t)b * h->T + n - 1), sizeof tip, hipMemcpyDeviceToHost));
-    for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, stat[t]);
-    std::copy(tip, tip + 3, R.tips.begin() + 3 * (size_t)r.index);
-    R.theta[r.index] = std::move(th);
-    if (++R.n_done == R.n_robots) {
-      s->completed.push_back(r.req);
-      ++s->n_completed;
-      ++done_now;
-    }
-    s->slot_robot[b] = -1;
+    if (s->state[slot] == vine_server::kActive) order.push_back(slot);
+  if (!order.empty()) {
+    auto cost = [&](int b) {
+      const vine_instance& I = s->live[b].inst;
+      return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
+      if (ca != cb) return ca < cb;
+      return cost(a) > cost(b);
+    });
+    for (int c = 0; c < vine_sim::kClasses; ++c) h->cls_count[c] = 0;
+    for (int b : order) h->cls_count[link_class(s->live[b].inst.n_links)]++;
+    h->cls_first[0] = 0;
+    for (int c = 1; c < vine_sim::kClasses; ++c)
+      h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
+    std::copy(order.begin(), order.end(), s->st_order[par]);
+    A(hipMemcpyAsync(h->order, s->st_order[par], sizeof(int) * order.size(),
+                     hipMemcpyHostToDevice, st));
+    const vs::KParams kp = kparams(h->prm);
+    if (e == hipSuccess)
+      e = for_each_class(h, st, [&](int links, const vs::KData& D, hipStream_t ss) {
+        return vs::launch_rollout(kp, D, steps, links, ss);
+      });
+    // 4. snapshot of the link counts of the robots launched, for two ticks on
+    s->snap_slots[par] = order;
+    A(hipMemcpyAsync(s->st_snap[par], h->ncur, sizeof(int) * s->slots, hipMemcpyDeviceToHost, st));
   }
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("retire: ") + hipGetErrorString(e));
+  A(hipEventRecord(s->ev[par], st));
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("tick: ") + hipGetErrorString(e));
+  s->ev_live[par] = true;
+  ++s->tick;
   return done_now;
 }
 
@@ -1599,20 +1809,26 @@ int32_t vine_server_release(vine_server* s, int64_t request_id) {
   return VINE_OK;
 }
 
-void vine_server_stats(const vine_server* s, int64_t out[4]) {
+void vine_server_stats(const vine_server* s, int64_t out[8]) {
   if (!s || !out) return;
-  int64_t active = 0;
-  for (int b : s->slot_robot) active += b >= 0;
+  int64_t active = 0, retiring = 0;
+  for (int st : s->state) {
+    active += st == vine_server::kActive;
+    retiring += st == vine_server::kRetiring;
+  }
   out[0] = (int64_t)s->queue.size();
-  out[1] = active;
+  out[1] = active + retiring;
   out[2] = s->n_completed;
   out[3] = s->joint_updates;
+  out[4] = s->rows.used;
+  out[5] = s->rows.cap;
+  out[6] = s->hbm_bytes;
+  out[7] = retiring;
 }
 
 void vine_server_destroy(vine_server* s) {
   if (!s) return;
-  if (s->d_slots) (void)hipFree(s->d_slots);
-  vine_sim_destroy(s->h);
+  free_server(s);
   delete s;
 }
 

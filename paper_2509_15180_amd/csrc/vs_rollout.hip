@@ -993,9 +993,9 @@ __device__ void obstacle_helper(SM& S, const Ctx& c) {
 
 // Robot b's constants into c.
 __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData& D, int b) {
-  const int* ii = D.ii + 8 * b;
+  const int* ii = D.ii + kII * b;
   const double* dd = D.dd + 6 * b;
-  c.K = ii[2] < kMaxObs ? ii[2] : kMaxObs;  // the boundary rejects more
+  c.K = ii[kObsCnt] < kMaxObs ? ii[kObsCnt] : kMaxObs;  // the boundary rejects more
   c.l = dd[0];
   c.R = dd[1];
   c.Mmax = kPi * dd[2] * c.R * c.R * c.R;
@@ -1003,15 +1003,15 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
   c.bx = dd[3];
   c.by = dd[4];
   c.bpsi = dd[5];
-  c.tab = D.tables + ii[3];
+  c.tab = D.tables + ii[kTableId];
   c.wr = D.wr;
   c.P = P;
   c.trace = nullptr;
   c.trace_n = D.trace_n;
   c.trace_cap = D.trace_cap;
   c.last_len = c.l;
-  c.obs = D.obs + 4 * (size_t)ii[1];
-  c.okind = D.okind + ii[1];
+  c.obs = D.obs + 4 * (size_t)ii[kObsOff];
+  c.okind = D.okind + ii[kObsOff];
 }
 
 // One robot per workgroup of two waves: the solver wave runs the growth steps, the
@@ -1027,11 +1027,15 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x];
   const int lane = threadIdx.x;
+  const int* ii = D.ii + kII * b;
+  const int ntar = ii[kNTarget];
+  if (D.skip_done && D.ncur[b] >= ntar) return;  // both waves: nothing to grow
   Ctx c;
   robot_ctx(c, P, D, b);
-  const int* ii = D.ii + 8 * b;
-  const int ntar = ii[0];
   c.trace = (b == D.trace_robot) ? D.trace : nullptr;
+  double* theta = D.theta + ii[kThetaOff];
+  const size_t rec0 = (size_t)ii[kRecOff];
+  const int rec_cap = ii[kRecCap];
   if (threadIdx.x >= kWave) {
     obstacle_helper(S, c);
     return;
@@ -1042,8 +1046,8 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     S.cmd_seq = 0;
   }
   for (int j = lane; j < ntar; j += kWave) {
-    S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
-    S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
+    S.pp[j] = D.cover[2 * (size_t)(ii[kCoverOff] + j)];
+    S.pm[j] = D.cover[2 * (size_t)(ii[kCoverOff] + j) + 1];
   }
   const long long t_begin = clock64();  // this robot's time in the launch (for scheduling)
   const long long w_begin = wall_clock64();  // and in seconds (constant-rate counter)
@@ -1054,9 +1058,9 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     S.nsolves = 0.0;
     S.negsteps = 0.0;
   }
-  for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
+  for (int j = lane; j < n; j += kWave) S.th[j] = theta[j];
   bsync<SMT>();
-  for (int step = 0; step < n_steps && t < D.t_max; ++step, ++t) {
+  for (int step = 0; step < n_steps && t < rec_cap; ++step, ++t) {
     if (D.ckpt && t % D.ckpt_every == 0) {
       double* row = D.ckpt + ((size_t)b * D.n_ckpt + t / D.ckpt_every) * D.n_max;
       for (int j = lane; j < D.n_max; j += kWave) row[j] = j < n ? S.th[j] : 0.0;
@@ -1082,7 +1086,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
       if (n > 0) evaluate(S, c, S.th, false);
     }
     // record the state after this step
-    const size_t bt = (size_t)b * D.t_max + t;
+    const size_t bt = rec0 + t;
     double hsum = 0.0;
     for (int j = lane; j < n; j += kWave) hsum += S.th[j];
     hsum = wsum(hsum);
@@ -1116,13 +1120,13 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
       D.chash[bt] = hv;
       D.maxpen[bt] = mp;
     }
-    if (D.traj && ((t + 1) % D.rec_every == 0 || t == D.t_max - 1)) {
+    if (D.traj && ((t + 1) % D.rec_every == 0 || t == rec_cap - 1)) {
       double* row = D.traj + ((size_t)b * D.n_rec + t / D.rec_every) * D.n_max;
       for (int j = lane; j < D.n_max; j += kWave) row[j] = j < n ? S.th[j] : 0.0;
     }
     bsync<SMT>();
   }
-  for (int j = lane; j < n; j += kWave) D.theta[(size_t)b * D.n_max + j] = S.th[j];
+  for (int j = lane; j < n; j += kWave) theta[j] = S.th[j];
   if (lane == 0) {
     D.ncur[b] = n;
     D.tcur[b] = t;
@@ -1164,16 +1168,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   __shared__ Smem<NMAX, false> S;
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x], lane = threadIdx.x;
-  const int* ii = D.ii + 8 * b;
+  const int* ii = D.ii + kII * b;
   Ctx c;
   robot_ctx(c, P, D, b);
-  const int ntar = ii[0];
+  const int ntar = ii[kNTarget];
   if (lane == 0) S.res_ok = 0;  // staged by the first evaluation
   for (int j = lane; j < ntar; j += kWave) {
-    S.pp[j] = D.cover[2 * (size_t)(ii[4] + j)];
-    S.pm[j] = D.cover[2 * (size_t)(ii[4] + j) + 1];
+    S.pp[j] = D.cover[2 * (size_t)(ii[kCoverOff] + j)];
+    S.pm[j] = D.cover[2 * (size_t)(ii[kCoverOff] + j) + 1];
   }
-  const int soff = ii[5], ns = ii[6];
+  const int soff = ii[kSpamOff], ns = ii[kSpamCnt];
   const double gx = goal[2 * b], gy = goal[2 * b + 1];
   double aP = 0.0, a0 = 0.0, a1 = 0.0, Lsum = 0.0;  // this lane's sPAM (lane < ns)
   int st = 0;
@@ -1199,11 +1203,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     } else {
       tg = D.tcur[b] - 1;
       n = D.ncur[b];
-      for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[(size_t)b * D.n_max + j];
+      for (int j = lane; j < n; j += kWave) S.th[j] = D.theta[ii[kThetaOff] + j];
     }
     if (n == 0) continue;
     if (tg >= 0) {
-      const int fs = D.status[(size_t)b * D.t_max + tg];
+      const int fs = D.status[(size_t)ii[kRecOff] + tg];
       if (fs > 0) st |= 2;
     }
     c.n = n;
@@ -1324,9 +1328,9 @@ hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
 __global__ void reset_kernel(KData D) {
   const size_t B = D.n_inst, stride = (size_t)gridDim.x * blockDim.x;
   const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (size_t i = i0; i < B * D.n_max; i += stride) D.theta[i] = 0.0;
-  for (size_t i = i0; i < B * D.t_max * 3; i += stride) D.tip[i] = 0.0;
-  for (size_t i = i0; i < B * D.t_max; i += stride) {
+  for (size_t i = i0; i < (size_t)D.theta_len; i += stride) D.theta[i] = 0.0;
+  for (size_t i = i0; i < (size_t)D.rec_len * 3; i += stride) D.tip[i] = 0.0;
+  for (size_t i = i0; i < (size_t)D.rec_len; i += stride) {
     D.rho[i] = 0.0;
     D.iters[i] = 0;
     D.status[i] = 0;
@@ -1349,9 +1353,10 @@ __global__ void reset_kernel(KData D) {
 __global__ void slot_reset_kernel(KData D, const int* slots, int count) {
   if ((int)blockIdx.x >= count) return;
   const size_t b = (size_t)slots[blockIdx.x];
-  for (int j = threadIdx.x; j < D.n_max; j += blockDim.x) D.theta[b * D.n_max + j] = 0.0;
-  for (int t = threadIdx.x; t < D.t_max; t += blockDim.x) {
-    const size_t bt = b * D.t_max + t;
+  const int* ii = D.ii + kII * b;
+  for (int j = threadIdx.x; j < ii[kNTarget]; j += blockDim.x) D.theta[ii[kThetaOff] + j] = 0.0;
+  for (int t = threadIdx.x; t < ii[kRecCap]; t += blockDim.x) {
+    const size_t bt = (size_t)ii[kRecOff] + t;
     D.tip[3 * bt] = 0.0;
     D.tip[3 * bt + 1] = 0.0;
     D.tip[3 * bt + 2] = 0.0;
@@ -1377,16 +1382,26 @@ __global__ void slot_reset_kernel(KData D, const int* slots, int count) {
 // step q ce) into the segment state of Dseg (one block per robot); the segment's records
 // start at 0.  A robot whose rollout had not reached step q ce (tcur) has no such
 // checkpoint and is marked as having taken the whole segment, so that it does nothing.
-__global__ void seg_load_kernel(KData Dseg, const double* ckpt, const int* tcur, int n_ckpt,
-                                int q, int ce) {
+// Dseg.ii is the handle's robot rows with the record fields of the segment buffers.
+__global__ void seg_load_kernel(KData Dseg, const int* ii_handle, const double* ckpt,
+                                const int* tcur, int n_ckpt, int q, int ce) {
   const int b = blockIdx.x;
   if (b >= Dseg.n_inst) return;
-  const int ntar = Dseg.ii[8 * b];
+  int* iis = const_cast<int*>(Dseg.ii) + kII * (size_t)b;
+  const int* iih = ii_handle + kII * (size_t)b;
+  const int ntar = iih[kNTarget];
   const bool have = tcur[b] > q * ce;
   const int n = !have ? 0 : (q * ce < ntar ? q * ce : ntar);
   const double* src = ckpt + ((size_t)b * n_ckpt + q) * Dseg.n_max;
-  for (int j = threadIdx.x; j < Dseg.n_max; j += blockDim.x)
-    Dseg.theta[(size_t)b * Dseg.n_max + j] = j < n ? src[j] : 0.0;
+  double* th = Dseg.theta + (size_t)b * Dseg.n_max;
+  for (int j = threadIdx.x; j < Dseg.n_max; j += blockDim.x) th[j] = j < n ? src[j] : 0.0;
+  if (threadIdx.x < kII) {
+    const int f = threadIdx.x;
+    iis[f] = f == kThetaOff ? b * Dseg.n_max
+           : f == kRecOff   ? b * ce
+           : f == kRecCap   ? ce
+                            : iih[f];
+  }
   if (threadIdx.x == 0) {
     Dseg.ncur[b] = n;
     Dseg.tcur[b] = have ? 0 : ce;
@@ -1398,11 +1413,11 @@ __global__ void seg_load_kernel(KData Dseg, const double* ckpt, const int* tcur,
   }
 }
 
-hipError_t launch_seg_load(const KData& Dseg, const double* ckpt, const int* tcur, int n_ckpt,
-                           int q, int ce, hipStream_t stream) {
-  if (!state_complete(Dseg) || !ckpt || !tcur) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(seg_load_kernel, dim3(Dseg.n_inst), dim3(64), 0, stream, Dseg, ckpt, tcur,
-                     n_ckpt, q, ce);
+hipError_t launch_seg_load(const KData& Dseg, const int* ii_handle, const double* ckpt,
+                           const int* tcur, int n_ckpt, int q, int ce, hipStream_t stream) {
+  if (!state_complete(Dseg) || !ii_handle || !ckpt || !tcur) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(seg_load_kernel, dim3(Dseg.n_inst), dim3(64), 0, stream, Dseg, ii_handle,
+                     ckpt, tcur, n_ckpt, q, ce);
   return hipGetLastError();
 }
 
@@ -1415,7 +1430,7 @@ hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStr
 
 hipError_t launch_reset(const KData& D, hipStream_t stream) {
   if (!state_complete(D)) return hipErrorInvalidValue;
-  const size_t work = (size_t)D.n_inst * (D.t_max * 3 > D.n_max ? D.t_max * 3 : D.n_max);
+  const size_t work = (size_t)(D.rec_len * 3 > D.theta_len ? D.rec_len * 3 : D.theta_len);
   const size_t blocks = (work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096;
   hipLaunchKernelGGL(reset_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
                      stream, D);

@@ -126,8 +126,8 @@ def lib():
         L.vine_sim_grad.restype = C.c_int32
         L.vine_sim_set_spams.argtypes = [vp, C.POINTER(Spam), C.c_int32, vp]
         L.vine_sim_set_spams.restype = C.c_int32
-        L.vine_server_create.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32,
-                                         C.c_int32, C.POINTER(vp)]
+        L.vine_server_create.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
+                                         C.c_int32, C.c_int32, C.POINTER(vp)]
         L.vine_server_create.restype = C.c_int32
         L.vine_server_submit.argtypes = [vp, C.c_int64, C.POINTER(Instance), C.c_int32,
                                          C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle),
@@ -347,14 +347,19 @@ class VineSim:
 
 
 class VineServer:
-    """vine_server_*: continuous batching of rollout requests (one handle)."""
+    """vine_server_*: continuous batching of rollout requests (one handle).  hbm_bytes:
+    the device-memory budget of the robot pools (default: room for ``slots`` robots at
+    the bounds)."""
 
     def __init__(self, slots: int, max_links: int = MAX_LINKS, max_obstacles: int = MAX_OBSTACLES,
-                 max_spams: int = 8, params: Params | None = None, **over):
+                 max_spams: int = 8, hbm_bytes: int | None = None, params: Params | None = None,
+                 **over):
         L = lib()
         self._p = params if params is not None else default_params(**over)
+        if hbm_bytes is None:
+            hbm_bytes = int(slots) * (84 * int(max_links) + 36 * int(max_obstacles) + 148)
         h = C.c_void_p()
-        rc = L.vine_server_create(C.byref(self._p), int(slots), int(max_links),
+        rc = L.vine_server_create(C.byref(self._p), int(slots), int(hbm_bytes), int(max_links),
                                   int(max_obstacles), int(max_spams), C.byref(h))
         if rc != VINE_OK:
             raise VineError(rc, L.vine_server_last_error(None).decode())
@@ -394,9 +399,10 @@ class VineServer:
         self.n_links.pop(int(request_id), None)
 
     def stats(self) -> dict:
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * 8)()
         lib().vine_server_stats(self.h, out)
-        return dict(queued=out[0], active=out[1], completed=out[2], joint_updates=out[3])
+        return dict(queued=out[0], active=out[1], completed=out[2], joint_updates=out[3],
+                    rows_used=out[4], rows=out[5], hbm_bytes=out[6], retiring=out[7])
 
     def close(self):
         if getattr(self, "h", None):

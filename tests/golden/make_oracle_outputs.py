@@ -17,6 +17,8 @@ Files (numpy .npz, compressed):
   oracle_cfg5.npz   16 robots of the request stream with 257-512 links and 65-128
                     obstacles (the first environment sample of the first such requests),
                     their first 300 growth steps
+  oracle_cfg5_full.npz  the first environment sample of requests 31 and 32 of the stream
+                    (481 and 453 links among 125 and 126 obstacles) at full length
   oracle_cfg4_grad.npz  the differentiation batch, robots 0..511: final-step and
                     weighted-loss gradients with respect to every sPAM's pressure and ends
 
@@ -110,7 +112,7 @@ def rollout_arrays(work, out, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=7)
-    ap.add_argument("--only", default="cfg1,cfg2,cfg4,cfg5,cfg3")
+    ap.add_argument("--only", default="cfg1,cfg2,cfg4,cfg5,cfg3,cfg5full")
     args = ap.parse_args()
     todo = args.only.split(",")
     th = args.threads
@@ -148,6 +150,14 @@ def main():
         out = O.rollout(w, n_steps=300, threads=th)
         save("oracle_cfg5.npz", rid=rids, **rollout_arrays(w, out, 300))
         print(f"cfg5 {time.time() - t:.0f} s", flush=True)
+    if "cfg5full" in todo:
+        t = time.time()
+        rids = np.array([31, 32])
+        reqs = {r.rid: r for r in W.config5_requests(33)}
+        w = W.pack([reqs[int(i)].work.instance(0) for i in rids], "cfg5-full")
+        out = O.rollout(w, threads=th)
+        save("oracle_cfg5_full.npz", rid=rids, **rollout_arrays(w, out, int(w.n_max)))
+        print(f"cfg5full {time.time() - t:.0f} s", flush=True)
     if "cfg3" in todo:
         t = time.time()
         full = W.config3(16384)

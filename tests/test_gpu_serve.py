@@ -1,12 +1,59 @@
 """Serving (continuous batching) through the C ABI: requests of mixed size streamed
-through a server with few slots give bitwise the results of the same robots rolled
-out alone with the batch entry points, and every request completes."""
+through a server give bitwise the results of the same robots rolled out alone with the
+batch entry points, and every request completes -- also at the full request size (up to
+512 links among up to 128 obstacles) under a device-memory budget that holds only a few
+such robots at once, where admission waits for rows to free up; and a full-size robot
+served in the mix matches the oracle's stored full-length rollout."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 from paper_2509_15180_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _alone(work, stream):
+    from paper_2509_15180_amd import vinesim as V
+    with V.VineSim(work) as sim:
+        sim.rollout(-1, stream=stream)
+        stream.synchronize()
+        return sim.read_all()
+
+
+def _drive(srv, reqs, stream, per_round=2, steps=8):
+    pending = list(reqs)
+    done = {}
+    rounds = 0
+    peak_rows = 0
+    while len(done) < len(reqs):
+        for _ in range(per_round):
+            if pending:
+                r = pending.pop(0)
+                srv.submit(r.rid, r.work)
+        srv.tick(steps, stream=stream)
+        for rid, worst in srv.poll():
+            done[rid] = worst
+        st = srv.stats()
+        peak_rows = max(peak_rows, st["rows_used"])
+        assert st["rows_used"] <= st["rows"]
+        rounds += 1
+        assert rounds < 20000
+    return done, rounds, peak_rows
+
+
+def _check_alone(srv, reqs, stream):
+    for r in reqs:
+        out = _alone(r.work, stream)
+        for k in range(r.work.n_inst):
+            tip, th = srv.result(r.rid, k)
+            n = int(r.work.inst_i[k, 0])
+            assert np.array_equal(th, out["theta"][k, :n]), (r.rid, k)
+            assert np.array_equal(tip, out["tip"][k, n - 1]), (r.rid, k)
 
 
 def test_mixed_stream_equals_alone():
@@ -17,33 +64,73 @@ def test_mixed_stream_equals_alone():
     reqs = W.config5_requests(10, n_max=160, k_max=48, s_max=6)
     stream = torch.cuda.current_stream()
     with V.VineServer(slots=24, max_links=160, max_obstacles=48, max_spams=8) as srv:
-        pending = list(reqs)
-        done = {}
-        rounds = 0
-        while len(done) < len(reqs):
-            # two new requests per round while any remain
-            for _ in range(2):
-                if pending:
-                    r = pending.pop(0)
-                    srv.submit(r.rid, r.work)
-            srv.tick(8, stream=stream)
-            for rid, worst in srv.poll():
-                done[rid] = worst
-            rounds += 1
-            assert rounds < 10000
+        done, rounds, peak = _drive(srv, reqs, stream)
         st = srv.stats()
         print(f"server: {rounds} rounds, {st['joint_updates']} joint-updates, "
               f"worst statuses {sorted(set(done.values()))}", flush=True)
         assert st["completed"] == len(reqs) and st["queued"] == 0 and st["active"] == 0
         assert st["joint_updates"] == sum(r.work.joint_updates() for r in reqs)
+        _check_alone(srv, reqs, stream)
         for r in reqs:
-            with V.VineSim(r.work) as sim:
-                sim.rollout(-1, stream=stream)
-                stream.synchronize()
-                out = sim.read_all()
-            for k in range(r.work.n_inst):
-                tip, th = srv.result(r.rid, k)
-                n = int(r.work.inst_i[k, 0])
-                assert np.array_equal(th, out["theta"][k, :n]), (r.rid, k)
-                assert np.array_equal(tip, out["tip"][k, n - 1]), (r.rid, k)
+            srv.release(r.rid)
+
+
+def _full_size_requests():
+    picked = []
+    for r in W.config5_requests(40):
+        n, K = int(r.work.inst_i[0, 0]), int(r.work.inst_i[0, 4])
+        big = n >= 400 and K >= 100
+        if big or len(picked) < 4:
+            r.work = r.work.subset(list(range(min(2 if big else 3, r.work.n_inst))))
+            picked.append(r)
+    return picked
+
+
+def test_full_size_requests_under_a_tight_budget():
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    reqs = _full_size_requests()
+    assert any(int(r.work.inst_i[0, 0]) >= 450 and int(r.work.inst_i[0, 4]) >= 120 for r in reqs)
+    # pools for three robots at the bounds: the rest wait for rows to free up
+    budget = 3 * (84 * 512 + 36 * 128) + 148 * 8
+    with V.VineServer(slots=8, max_links=512, max_obstacles=128, max_spams=8,
+                      hbm_bytes=budget) as srv:
+        done, rounds, peak = _drive(srv, reqs, stream, per_round=len(reqs), steps=16)
+        st = srv.stats()
+        print(f"full-size stream: {len(reqs)} requests, {sum(r.work.n_inst for r in reqs)} robots, "
+              f"{rounds} rounds, peak rows {peak} of {st['rows']} ({st['hbm_bytes']} bytes); worst "
+              f"statuses {sorted(set(done.values()))}", flush=True)
+        assert st["completed"] == len(reqs) and st["rows_used"] == 0
+        assert st["joint_updates"] == sum(r.work.joint_updates() for r in reqs)
+        _check_alone(srv, reqs, stream)
+        # the full-length oracle rollouts of two of these robots
+        path = os.path.join(HERE, "golden", "oracle_cfg5_full.npz")
+        if os.path.exists(path):
+            sys.path.insert(0, os.path.join(HERE, "golden"))
+            import make_oracle_outputs as MK
+            g = np.load(path)
+            assert str(g["source_sha256"]) == MK.source_hash(), "regenerate oracle_cfg5_full.npz"
+            import oracle as O
+            full = {r.rid: r for r in reqs}
+            for k, rid in enumerate(g["rid"]):
+                tip, th = srv.result(int(rid), 0)
+                dth = np.abs(th - g["theta"][k, :len(th)]).max()
+                dtip = np.abs(tip[:2] - g["tip_final"][k][:2]).max()
+                print(f"  request {rid} robot 0 vs the oracle at full length: max |dtheta| "
+                      f"{dth:.2e} rad, |dtip| {dtip:.2e} m", flush=True)
+                if dth <= 1e-5 and dtip <= 1e-4:
+                    continue
+                # another minimum: it must be a valid one by the oracle's arithmetic
+                inst = full[int(rid)].work.instance(0)
+                d = inst["d"]
+                Mmax = np.pi * d[2] * d[1] ** 3
+                Pi, r, cont = O.chain_eval(inst, th)
+                lam = np.linalg.eigvalsh(O.chain_hessian(inst, th))[0] / Mmax
+                print(f"    another minimum: oracle residual {np.abs(r).max() / Mmax:.1e} M_max, "
+                      f"smallest Hessian eigenvalue {lam:.2e} M_max", flush=True)
+                assert np.abs(r).max() / Mmax <= 1e-8 and lam > -1e-6
+        for r in reqs:
             srv.release(r.rid)
