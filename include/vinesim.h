@@ -251,6 +251,25 @@ int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weight
                       double* dL_dP, double* dL_ds_start, double* dL_ds_end, double* loss,
                       int32_t* adj_status, void* stream);
 
+/* Bytes of the per-device scratch of vine_sim_grad_noalloc (128 MiB). */
+#define VINE_GRAD_SCRATCH_BYTES (128ull << 20)
+
+/* vine_sim_grad for callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  Same arguments, results
+ * and errors as vine_sim_grad (bitwise the same outputs), but it allocates nothing:
+ * the segment buffers of the checkpoint path (the recomputed states, records and
+ * trajectory of ckpt_every steps, the robot rows and the adjoint's running sums; about
+ * 8 B x (N + ckpt_every (N + 10) + 210) per robot) live in a static device array of
+ * VINE_GRAD_SCRATCH_BYTES per device, held until the process ends.  Paths that need no
+ * segment buffers (the final-state loss, a recorded trajectory) behave exactly as
+ * vine_sim_grad.  Needs beyond the array give VINE_ECAPACITY (use vine_sim_grad).
+ * Every call on a device shares that device's array and overwrites what the last call
+ * left (every value is written before it is read); calls that overlap on one device
+ * race, so serialise them (e.g. issue them on one stream). */
+int32_t vine_sim_grad_noalloc(vine_sim* h, const double* goal, const double* step_weights,
+                              double* dL_dP, double* dL_ds_start, double* dL_ds_end,
+                              double* loss, int32_t* adj_status, void* stream);
+
 /* Replace the sPAM records (placement and pressure; Sec. 3.1 and Sec. 5: the design
  * variables of the search) without rebuilding the handle.  spams: host, n_spams
  * records laid out as at create (each robot keeps its offset and count), which must

@@ -7,6 +7,8 @@ namespace vs {
 
 constexpr int kWave = 64;
 constexpr int kMaxObs = 128;  // obstacles per robot (the boundary's VINE_MAX_OBSTACLES)
+// bytes of the static device scratch of the allocation-free adjoint (per device)
+constexpr unsigned long long kScratchBytes = 128ull << 20;
 
 // sPAM force law G(eps) = F_t / P_act (Sec. 3.1, Eq. 1d) on [0, eps_max] as a
 // piecewise Chebyshev series: pieces [b_k, b_{k+1}] with b_k = eps_max (k/P)^2

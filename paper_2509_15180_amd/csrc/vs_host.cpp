@@ -19,6 +19,7 @@
 #include "vs_device.h"
 
 static_assert(vs::kMaxObs == VINE_MAX_OBSTACLES, "obstacle capacity of the kernels");
+static_assert(vs::kScratchBytes == VINE_GRAD_SCRATCH_BYTES, "scratch size of the kernels");
 
 namespace vs {
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
@@ -31,6 +32,7 @@ hipError_t launch_zero3(double* a, double* b, double* c, int n, hipStream_t stre
 hipError_t launch_reset(const KData& D, hipStream_t stream);
 hipError_t launch_seg_load(const KData& Dseg, const int* ii_handle, const double* ckpt,
                            const int* tcur, int n_ckpt, int q, int ce, hipStream_t stream);
+hipError_t scratch_address(void** out);
 }
 
 using vs::SpamTable;
@@ -423,6 +425,7 @@ struct vine_sim {
   bool traj_all = true;     // every step since the reset did, with the same rec_every
   bool ckpt_all = true;     // every step since the reset wrote checkpoints (same ckpt_every)
   bool ckpt_any = false;
+  void* scratch = nullptr;  // this device's static scratch (vine_sim_grad_noalloc)
   std::string err;
 };
 
@@ -799,6 +802,12 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     delete h;
     return fail(nullptr, VINE_EDEVICE, "synchronise after reset");
   }
+  // this device's static scratch for vine_sim_grad_noalloc (looked up once per device)
+  if (vs::scratch_address(&h->scratch) != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(nullptr, VINE_EDEVICE, "device scratch address");
+  }
   *out = h;
   return VINE_OK;
 }
@@ -1027,6 +1036,39 @@ static hipError_t ensure_seg(vine_sim* h) {
   return hipSuccess;
 }
 
+// Views of the segment buffers inside one block of device memory of `bytes` bytes (each
+// array 256-byte aligned); false when they do not fit.
+static bool seg_view(void* base, size_t bytes, size_t B, size_t N, size_t C, vine_sim::Seg* g) {
+  size_t off = 0;
+  auto take = [&](auto** p, size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    *p = reinterpret_cast<std::remove_reference_t<decltype(**p)>*>((char*)base + off);
+    off += sizeof(**p) * (count > 0 ? count : 1);
+  };
+  take(&g->theta, B * N);
+  take(&g->ncur, B);
+  take(&g->tcur, B);
+  take(&g->tip, B * C * 3);
+  take(&g->rho, B * C);
+  take(&g->iters, B * C);
+  take(&g->status, B * C);
+  take(&g->ncont, B * C);
+  take(&g->chash, B * C);
+  take(&g->maxpen, B * C);
+  take(&g->traj, B * C * N);
+  take(&g->jevals, B);
+  take(&g->nsolves, B);
+  take(&g->negsteps, B);
+  take(&g->cycles, B);
+  take(&g->wtime, B);
+  take(&g->gsums, B * vs::kWave * 3);
+  take(&g->gloss, B);
+  take(&g->gstat, B);
+  take(&g->ii, B * vs::kII);
+  g->steps = (int)C;
+  return off <= bytes;
+}
+
 // vine_sim_grad with the segment buffers of the checkpoint path in g (null: allocated in
 // the handle on first use).
 static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_weights,
@@ -1110,6 +1152,28 @@ int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weight
                       int32_t* adj_status, void* stream) {
   return grad_impl(h, goal, step_weights, dL_dP, dL_ds_start, dL_ds_end, loss, adj_status,
                    stream, nullptr);
+}
+
+int32_t vine_sim_grad_noalloc(vine_sim* h, const double* goal, const double* step_weights,
+                              double* dL_dP, double* dL_ds_start, double* dL_ds_end,
+                              double* loss, int32_t* adj_status, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  const bool full_traj = h->traj_valid && h->traj_all && h->rec_every == 1;
+  if (!step_weights || full_traj || !(h->ckpt && h->ckpt_any && h->ckpt_all))
+    return grad_impl(h, goal, step_weights, dL_dP, dL_ds_start, dL_ds_end, loss, adj_status,
+                     stream, nullptr);  // no segment buffers needed (or the state error)
+  if (!h->scratch) return fail(h, VINE_EDEVICE, "no device scratch for this handle's device");
+  vine_sim::Seg view;
+  if (!seg_view(h->scratch, VINE_GRAD_SCRATCH_BYTES, h->B, h->N, h->ckpt_every, &view)) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "the segment buffers of %d robots x %d links x %d steps per checkpoint exceed "
+                  "the %llu-byte device scratch (use vine_sim_grad)",
+                  h->B, h->N, h->ckpt_every, (unsigned long long)VINE_GRAD_SCRATCH_BYTES);
+    return fail(h, VINE_ECAPACITY, msg);
+  }
+  return grad_impl(h, goal, step_weights, dL_dP, dL_ds_start, dL_ds_end, loss, adj_status,
+                   stream, &view);
 }
 
 int32_t vine_sim_set_spams(vine_sim* h, const vine_spam* spams, int32_t n_spams, void* stream) {

@@ -24,6 +24,8 @@
 //       Armijo backtracking on the energy.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "vs_device.h"
 
 namespace vs {
@@ -1456,6 +1458,36 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nma
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free adjoint (vine_sim_grad_noalloc): one static
+// array per device, held until the process ends.  In host code the array's name is a
+// host-side stand-in, not a device address, so its address on each device is looked up
+// once (with that device current) and kept; launches and copies use that address only.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Address of the current device's scratch (looked up on the first call for a device).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace vs

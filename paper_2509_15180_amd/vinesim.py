@@ -72,7 +72,8 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_rollout_graph", "vine_sim_tune_order",
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
-           "vine_sim_trace_read", "vine_sim_grad", "vine_sim_set_spams", "vine_server_create",
+           "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
+           "vine_server_create",
            "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
            "vine_server_release", "vine_server_stats", "vine_server_destroy",
            "vine_server_last_error")
@@ -124,6 +125,8 @@ def lib():
         L.vine_sim_trace_read.restype = C.c_int32
         L.vine_sim_grad.argtypes = [vp] * 9
         L.vine_sim_grad.restype = C.c_int32
+        L.vine_sim_grad_noalloc.argtypes = [vp] * 9
+        L.vine_sim_grad_noalloc.restype = C.c_int32
         L.vine_sim_set_spams.argtypes = [vp, C.POINTER(Spam), C.c_int32, vp]
         L.vine_sim_set_spams.restype = C.c_int32
         L.vine_server_create.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
@@ -292,11 +295,12 @@ class VineSim:
             self._check(n)
         return buf[:n]
 
-    def grad(self, goal, weights=None, stream=None):
-        """vine_sim_grad on device tensors.  ``goal`` [B][2] and ``weights`` [T] (or None:
-        the current state alone) may be numpy arrays or torch tensors; they are staged as
-        float64 device tensors.  Returns device tensors (dL_dP, dL_ds_start, dL_ds_end,
-        loss[B], adj_status[B]), valid once ``stream`` has been synchronised."""
+    def grad(self, goal, weights=None, stream=None, noalloc: bool = False):
+        """vine_sim_grad (vine_sim_grad_noalloc with ``noalloc``) on device tensors.
+        ``goal`` [B][2] and ``weights`` [T] (or None: the current state alone) may be numpy
+        arrays or torch tensors; they are staged as float64 device tensors.  Returns device
+        tensors (dL_dP, dL_ds_start, dL_ds_end, loss[B], adj_status[B]), valid once
+        ``stream`` has been synchronised."""
         import torch
 
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -315,8 +319,9 @@ class VineSim:
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
         if stream is None:
             stream = torch.cuda.current_stream()
-        self._check(lib().vine_sim_grad(self.h, ptr(g), ptr(w), ptr(dP), ptr(d0), ptr(d1),
-                                        ptr(loss), ptr(st), _stream_ptr(stream)))
+        fn = lib().vine_sim_grad_noalloc if noalloc else lib().vine_sim_grad
+        self._check(fn(self.h, ptr(g), ptr(w), ptr(dP), ptr(d0), ptr(d1), ptr(loss), ptr(st),
+                       _stream_ptr(stream)))
         self._keep = (g, w)  # inputs stay alive until the caller synchronises
         return dP[:self.S], d0[:self.S], d1[:self.S], loss, st
 
