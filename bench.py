@@ -227,7 +227,6 @@ def main():
     ap.add_argument("--duration", type=float, default=30.0, help="serve: measured seconds")
     ap.add_argument("--warm", type=float, default=5.0, help="serve: warm-up seconds")
     ap.add_argument("--slots", type=int, default=4096, help="serve: resident robots")
-    ap.add_argument("--tick-steps", type=int, default=8, help="serve: growth steps per round")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
     ap.add_argument("--cpu-robots", type=int, default=48, help="robots in the CPU-oracle sample")
@@ -279,6 +278,16 @@ def main():
     achieved = flops / (R["kern_ms"] * 1e-3) / 1e12
     robot_s = R["robot_s"]
     status = out["status"]
+    # how busy the rollout keeps the device: robot-seconds over the launch's robot slots
+    # (compute units x robots resident per compute unit of the most resident class)
+    per_cu, cus = V.occupancy()
+    classes = [c for c, lim in enumerate((64, 128, 256, 512)) if ((n <= lim) & (n > (0, 64, 128, 256)[c])).any()]
+    slots_dev = cus * max(per_cu[c] for c in classes)
+    busy = float(robot_s.sum()) / (R["kern_ms"] * 1e-3 * slots_dev)
+    slow = np.argsort(-robot_s)[:5]
+    slowest = [{"robot": int(b), "links": int(n[b]), "obstacles": int(work.inst_i[b, 4]),
+                "seconds": float(robot_s[b]), "iterations": int(out["iters"][b].sum()),
+                "negative_curvature_steps": float(out["negsteps"][b])} for b in slow]
 
     extra = None
     if wl == "uneven" and not args.no_uniform:
@@ -372,7 +381,7 @@ def main():
                     "p50": float(np.percentile(robot_s, 50)),
                     "p99": float(np.percentile(robot_s, 99)), "max": float(robot_s.max()),
                     "first_rollout_ms_create_time_order": R["first_ms"],
-                    "tuned_rollout_ms": R["ms"]},
+                    "tuned_rollout_ms": R["ms"], "slowest_robots": slowest},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "rollout_kernel (all chain-length classes of one rollout)",
@@ -381,7 +390,9 @@ def main():
                      "flop_per_joint_eval": flops_per_joint_eval(K_mean),
                      "linear_solves": float(out["nsolves"].sum()),
                      "negative_curvature_steps": float(out["negsteps"].sum()),
-                     "simd_busy_fraction": None},
+                     "simd_busy_fraction": busy,
+                     "occupancy": {"robots_per_cu": per_cu, "compute_units": cus,
+                                   "robot_slots": slots_dev}},
         "per_instance": {"value": pi_rate, "unit": "joint-updates/s", "robots": int(len(pi_idx)),
                          "speedup_batched": value / pi_rate},
         "cpu_baseline": cpu,
@@ -418,7 +429,6 @@ def serve_once(args, torch, V, W, rate):
             gen["next"] += k
         return gen["buf"][0] if gen["buf"] else None
 
-    stream = torch.cuda.current_stream()
     srv = V.VineServer(slots=args.slots, max_links=512, max_obstacles=128, max_spams=8,
                        hbm_bytes=int(args.hbm_mb * 1e6))
     arrival, size = {}, {}
@@ -446,12 +456,15 @@ def serve_once(args, torch, V, W, rate):
             if r is not None:
                 time.sleep(max(0.0, min(r.arrival - now, 0.01)))
             continue
-        srv.tick(args.tick_steps, stream=stream)
+        srv.tick()
         ticks += 1
         t_done = time.perf_counter() - t0
-        for rid, _ in srv.poll():
+        got = srv.poll()
+        for rid, _ in got:
             done_at[rid] = t_done
             srv.release(rid)
+        if not got:
+            time.sleep(0.0005)
     st = srv.stats()
     t_end = time.perf_counter() - t0
     ju_rate = (st["joint_updates"] - (ju0 or 0)) / max(t_end - tw, 1e-9)
@@ -489,8 +502,8 @@ def serve(args, torch, V, W):
         "data": "synthetic",
         "config": {"workload": "request stream: Poisson arrivals, designs of 16-512 links and "
                                "0-128 obstacles on 1-64 jittered environment samples; "
-                               f"{args.slots} slots, {args.hbm_mb:.0f} MB of robot pools, "
-                               f"{args.tick_steps} growth steps per round",
+                               f"{args.slots} slots, {args.hbm_mb:.0f} MB of robot pools; "
+                               f"each admitted group grown to full length in its own launches",
                    "warmup_s": args.warm, "measured_s": args.duration},
         "serving": {"highest_rate_with_bounded_p99": best["rate_per_s"], "runs": runs},
         "roofline": None, "cpu_baseline": None,

@@ -310,6 +310,12 @@ const char* vine_sim_last_error(const vine_sim* h);
 int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* eps, double* G,
                           double* dG, double* IG);
 
+/* Occupancy of the current device: robots of each chain-length class (up to 64, 128,
+ * 256 and 512 links) resident per compute unit in a rollout launch (each robot is one
+ * workgroup of two 64-lane waves), and the number of compute units.  For reports of
+ * how busy a launch keeps the device.  Errors: VINE_EDEVICE. */
+int32_t vine_sim_occupancy(int32_t per_cu[4], int32_t* compute_units);
+
 /* Diagnostics: record one row per accepted Newton iteration of robot `robot`
  * (step, sub-step, iteration, rho, mu, slope, step factor alpha, energy, 0,
  * contacts) into a device buffer of `capacity` rows on later step/rollout calls.
@@ -325,31 +331,30 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
  *
  * The paper's planner (Sec. 5) issues many short simulation jobs whose sizes vary
  * (designs of different length, several environment samples each).  A server keeps the
- * robots it has admitted resident on the device and advances them together; queued
- * robots are admitted as soon as a slot and device memory free up, so long and short
- * jobs share the device without waiting for each other's batch to drain.
+ * robots it has admitted resident on the device; queued robots are admitted as soon as
+ * a slot and device memory free up and start at once, next to the robots already
+ * running, so long and short jobs share the device without waiting for each other.
  *
  * Device memory is a budget, not a worst case: a robot of n links and K obstacles takes
  * n rows of a row pool (joint angle, sPAM coverage and one growth step's records per
  * row, 84 bytes) and K entries of an obstacle pool (36 bytes), allocated first-fit on
- * admission and freed when it retires.  Admission is first come, first served: the
+ * admission and freed when it is read back.  Admission is first come, first served: the
  * robot at the head of the queue waits until a slot and room in both pools are free.
  *
- * A tick enqueues its work on the stream and returns without waiting for it: the
- * admitted robots' rows are copied in from pinned host staging (asynchronously), every
- * resident robot advances by `steps` growth steps (one launch per chain-length class;
- * robots already at full length do nothing), and the link counts are copied out
- * asynchronously.  The host reads a tick's link counts two ticks later (waiting on an
- * event of that tick, by then normally complete, so the device always has the next
- * tick queued); a robot seen at full length has its results copied out then and read,
- * with its memory freed, two ticks after that.  A request is a set of robots (e.g. one
- * design on S environment samples) and completes when all of its robots are read back.
- * Results are bitwise those of the same robots run through vine_sim_create /
- * vine_sim_rollout (robots never interact, and the kernels are the same). */
+ * vine_server_tick never waits for the device.  It reads back the groups whose
+ * launches have finished (their results are copied out asynchronously and handed over
+ * on a later call, their memory freed then), and admits the queued robots that fit as
+ * one group: their rows are copied in from pinned host staging (asynchronously) and the
+ * group grows to full length in one launch per chain-length class, each on a stream of
+ * the server's own pool, alongside the groups already running.  A request is a set of
+ * robots (e.g. one design on S environment samples) and completes when all of its
+ * robots are read back.  Results are bitwise those of the same robots run through
+ * vine_sim_create / vine_sim_rollout (robots never interact, and the kernels are the
+ * same). */
 typedef struct vine_server vine_server;
 
 /* slots: robots resident at once; hbm_bytes: device memory for the pools and per-slot
- * rows, split so that the pools hold floor((hbm_bytes - 148 slots) / (84 max_links +
+ * rows, split so that the pools hold floor((hbm_bytes - 140 slots) / (84 max_links +
  * 36 max_obstacles)) robots at the bounds (more of smaller ones); max_links /
  * max_obstacles / max_spams bound each robot (<= VINE_MAX_LINKS / VINE_MAX_OBSTACLES /
  * VINE_MAX_SPAMS).  Device and pinned host memory are allocated here, once.  Up to 8
@@ -368,12 +373,11 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
                            int32_t n_inst, const vine_spam* spams, int32_t n_spams,
                            const vine_obstacle* obstacles, int32_t n_obstacles);
 
-/* One scheduling round, enqueued on `stream` (see above): read back the round two
- * ticks earlier, admit queued robots, advance every resident robot by `steps` growth
- * steps.  Returns the number of requests completed by this call (their results read
- * back), or a negative VINE_E* code.  Call it while requests are queued or resident
- * (vine_server_stats) to drain the server. */
-int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream);
+/* One scheduling round (see above): hand over the groups read back, start reading back
+ * the groups that finished, admit and launch the queued robots that fit.  Returns the
+ * number of requests completed by this call, or a negative VINE_E* code.  It does not
+ * block: call it repeatedly while requests are queued or resident (vine_server_stats). */
+int32_t vine_server_tick(vine_server* s);
 
 /* Completed requests not yet polled, oldest first: their ids into ids[] (host, up to
  * cap entries) and, if worst_status is non-NULL, the largest per-step status over the
@@ -390,10 +394,10 @@ int32_t vine_server_result(const vine_server* s, int64_t request_id, int32_t rob
 /* Forget a completed request's results. */
 int32_t vine_server_release(vine_server* s, int64_t request_id);
 
-/* Counters: [0] robots queued, [1] robots resident (advancing or being read back),
- * [2] requests completed, [3] joint-updates done (sum over growth steps of the link
- * count, as of the last snapshot read), [4] rows in use, [5] row capacity, [6] device
- * bytes of the pools and slot rows, [7] robots being read back. */
+/* Counters: [0] robots queued, [1] robots resident (running or being read back),
+ * [2] requests completed, [3] joint-updates of the robots read back (sum over growth
+ * steps of the link count), [4] rows in use, [5] row capacity, [6] device bytes of the
+ * pools and slot rows, [7] groups in flight. */
 void vine_server_stats(const vine_server* s, int64_t out[8]);
 
 void vine_server_destroy(vine_server* s);

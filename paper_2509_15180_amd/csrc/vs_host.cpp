@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <string>
 #include <unordered_map>
@@ -33,6 +34,7 @@ hipError_t launch_reset(const KData& D, hipStream_t stream);
 hipError_t launch_seg_load(const KData& Dseg, const int* ii_handle, const double* ckpt,
                            const int* tcur, int n_ckpt, int q, int ce, hipStream_t stream);
 hipError_t scratch_address(void** out);
+hipError_t rollout_occupancy(int nmax_class, int* per_cu);
 }
 
 using vs::SpamTable;
@@ -1319,6 +1321,20 @@ int32_t vine_sim_trace_read(const vine_sim* hc, double* dst, int32_t capacity) {
   return n;
 }
 
+int32_t vine_sim_occupancy(int32_t per_cu[4], int32_t* compute_units) {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
+    int k = 0;
+    e = vs::rollout_occupancy(kClassLinks[c], &k);
+    if (per_cu) per_cu[c] = k;
+  }
+  if (e != hipSuccess) return fail(nullptr, VINE_EDEVICE, std::string("occupancy: ") + hipGetErrorString(e));
+  if (compute_units) *compute_units = cus;
+  return VINE_OK;
+}
+
 int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double* eps, double* G,
                           double* dG, double* IG) {
   vine_sim* h = const_cast<vine_sim*>(hc);
@@ -1354,10 +1370,10 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
 // arrays live in pools: a row pool (one row per link: joint angle, sPAM coverage and
 // one step's records; a robot of n links holds n consecutive rows) and an obstacle
 // pool, each with a first-fit free list, so the device memory a robot takes follows its
-// size and admission is by a byte budget.  A tick enqueues its work without waiting for
-// it: the copies in (from pinned staging), the launches, and an asynchronous snapshot of
-// the link counts; the host acts on a tick's snapshot two ticks later, so the device
-// always has the next tick queued while the host does its bookkeeping.
+// size and admission is by a byte budget.  Each call admits the queued robots that fit
+// as one group and launches the group to full length at once, one launch per
+// chain-length class, each on a stream of the server's own pool, so a group runs
+// alongside the groups before it and never waits for them; the host only polls events.
 
 namespace vs {
 hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream);
@@ -1387,6 +1403,11 @@ struct FreeList {
       }
     return -1;
   }
+  int64_t largest() const {
+    int64_t m = 0;
+    for (const auto& f : free) m = std::max(m, f.second);
+    return m;
+  }
   void give(int64_t off, int64_t len) {
     if (len <= 0) return;
     used -= len;
@@ -1413,7 +1434,7 @@ hipError_t halloc(T** p, size_t count) {  // pinned host staging
 
 constexpr int64_t kRowBytes = 8 + 24 + 8 + 4 + 4 + 4 + 8 + 8 + 16;  // theta, records, coverage
 constexpr int64_t kObsBytes = 4 + 32;
-constexpr int64_t kSlotBytes = 4 * vs::kII + 48 + 8 + 40 + 4 + 8;  // ii, dd, counts, counters, lists
+constexpr int64_t kSlotBytes = 4 * vs::kII + 48 + 8 + 40 + 4;       // ii, dd, counts, counters, order
 
 }  // namespace
 
@@ -1422,6 +1443,7 @@ struct vine_server {
   int slots = 0, max_links = 0, max_obs = 0, max_spams = 0;
   int64_t hbm_bytes = 0;
   static constexpr int kMaxTables = 8;
+  static constexpr int kStreams = 8;
   struct Robot {
     int64_t req = 0;
     int index = 0;  // within the request
@@ -1429,38 +1451,40 @@ struct vine_server {
     std::vector<vine_spam> spams;
     std::vector<vine_obstacle> obs;
     int64_t row = -1, obs_off = -1;
-    int n_known = 0;  // link count at the last snapshot read
   };
   struct Request {
     int n_robots = 0, n_done = 0, worst = 0;
     std::vector<double> tips;                 // 3 per robot
     std::vector<std::vector<double>> theta;   // per robot
   };
-  enum SlotState : int { kFree = 0, kActive = 1, kRetiring = 2 };
+  struct Group {
+    int64_t order_off = -1;            // its robots' slots at order[order_off, + count)
+    int count = 0;
+    std::vector<hipEvent_t> ev_run;    // one per class launch
+    hipEvent_t ev_out = nullptr;       // results copied out
+    int stream = 0;                    // pool stream of its copies
+    int state = 0;                     // 1 running, 2 being read back
+  };
   std::deque<Robot> queue;
-  std::vector<Robot> live;                    // by slot
-  std::vector<int> state;                     // SlotState by slot
-  FreeList rows, obst;
+  std::vector<Robot> live;  // by slot
+  std::vector<int> busy;    // by slot
+  FreeList rows, obst, order_ranges;
+  std::list<Group> groups;
   std::unordered_map<int64_t, Request> reqs;
   std::deque<int64_t> completed;
-  int64_t joint_updates = 0, n_completed = 0, tick = 0;
-  // pinned staging: inputs at the pools' offsets, per-tick slot lists, snapshots, results
+  int64_t joint_updates = 0, n_completed = 0, resident = 0, reading = 0;
+  hipStream_t pool[kStreams] = {};
+  int next_stream = 0;
+  // pinned staging at the pools' offsets: inputs, launch orders, results
   int* st_ii = nullptr;
   double* st_dd = nullptr;
   double* st_cover = nullptr;
   int* st_okind = nullptr;
   double* st_obs = nullptr;
-  int* st_adm[2] = {nullptr, nullptr};
-  int* st_order[2] = {nullptr, nullptr};
-  int* st_snap[2] = {nullptr, nullptr};
+  int* st_order = nullptr;
   double* st_theta = nullptr;
   double* st_tip = nullptr;
   int* st_status = nullptr;
-  int* d_adm[2] = {nullptr, nullptr};
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool ev_live[2] = {false, false};
-  std::vector<int> snap_slots[2];   // slots whose link counts the snapshot of that tick holds
-  std::vector<int> gather[2];       // slots whose results that tick copied out
   std::string err;
 };
 
@@ -1486,17 +1510,35 @@ int table_for(vine_server* sv, double l) {
   return t;
 }
 
+void drop_group_events(vine_server::Group& g) {
+  for (hipEvent_t e : g.ev_run)
+    if (e) (void)hipEventDestroy(e);
+  g.ev_run.clear();
+  if (g.ev_out) (void)hipEventDestroy(g.ev_out);
+  g.ev_out = nullptr;
+}
+
 void free_server(vine_server* s) {
-  void* pinned[] = {s->st_ii, s->st_dd, s->st_cover, s->st_okind, s->st_obs, s->st_adm[0],
-                    s->st_adm[1], s->st_order[0], s->st_order[1], s->st_snap[0], s->st_snap[1],
+  for (hipStream_t st : s->pool)
+    if (st) (void)hipStreamSynchronize(st);
+  for (auto& g : s->groups) drop_group_events(g);
+  s->groups.clear();
+  for (hipStream_t st : s->pool)
+    if (st) (void)hipStreamDestroy(st);
+  void* pinned[] = {s->st_ii, s->st_dd, s->st_cover, s->st_okind, s->st_obs, s->st_order,
                     s->st_theta, s->st_tip, s->st_status};
   for (void* p : pinned)
     if (p) (void)hipHostFree(p);
-  for (int k = 0; k < 2; ++k) {
-    if (s->d_adm[k]) (void)hipFree(s->d_adm[k]);
-    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
-  }
   if (s->h) vine_sim_destroy(s->h);
+}
+
+// hipSuccess when every event has completed, hipErrorNotReady while one has not
+hipError_t events_done(const std::vector<hipEvent_t>& evs) {
+  for (hipEvent_t e : evs) {
+    const hipError_t q = hipEventQuery(e);
+    if (q != hipSuccess) return q;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -1538,8 +1580,9 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
   const int64_t R = units * max_links, Ko = std::max<int64_t>(1, units * max_obstacles);
   s->rows.init(R);
   s->obst.init(units * max_obstacles);
+  s->order_ranges.init(slots);
   s->live.resize(slots);
-  s->state.assign(slots, vine_server::kFree);
+  s->busy.assign(slots, 0);
   // replace the slab's per-robot arrays by pools of the budget's size
   void* old[] = {h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->theta, h->ncur, h->tcur,
                  h->tip, h->rho, h->iters, h->status, h->ncont, h->chash, h->maxpen, h->jevals,
@@ -1579,18 +1622,14 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
                   hipMemcpyHostToDevice);
   (void)hipFree(h->tables);
   h->tables = t8;
-  for (int k = 0; k < 2; ++k) {
-    A(dalloc(&s->d_adm[k], B));
-    A(halloc(&s->st_adm[k], B));
-    A(halloc(&s->st_order[k], B));
-    A(halloc(&s->st_snap[k], B));
-    A(hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming));
-  }
+  for (int k = 0; k < vine_server::kStreams; ++k)
+    A(hipStreamCreateWithFlags(&s->pool[k], hipStreamNonBlocking));
   A(halloc(&s->st_ii, B * vs::kII));
   A(halloc(&s->st_dd, B * 6));
   A(halloc(&s->st_cover, (size_t)R * 2));
   A(halloc(&s->st_okind, (size_t)Ko));
   A(halloc(&s->st_obs, (size_t)Ko * 4));
+  A(halloc(&s->st_order, B));
   A(halloc(&s->st_theta, (size_t)R));
   A(halloc(&s->st_tip, (size_t)R * 3));
   A(halloc(&s->st_status, (size_t)R));
@@ -1667,47 +1706,27 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
   return VINE_OK;
 }
 
-int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
-  if (!s || steps < 1) return sfail(s, VINE_EINVAL, "null server or steps < 1");
+int32_t vine_server_tick(vine_server* s) {
+  if (!s) return sfail(s, VINE_EINVAL, "null server");
   vine_sim* h = s->h;
-  hipStream_t st = (hipStream_t)stream;
-  const int par = (int)(s->tick & 1);
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
   };
   int done_now = 0;
-  // 1. the tick two back: its results and its snapshot (copies complete with its event)
-  if (s->ev_live[par]) {
-    A(hipEventSynchronize(s->ev[par]));
-    if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("wait: ") + hipGetErrorString(e));
-    s->ev_live[par] = false;
-    for (int slot : s->gather[par]) {  // results copied out by that tick: the robot is done
-      vine_server::Robot& r = s->live[slot];
-      vine_server::Request& R = s->reqs[r.req];
-      const int n = r.inst.n_links;
-      const int64_t row = r.row;
-      R.theta[r.index].assign(s->st_theta + row, s->st_theta + row + n);
-      std::copy(s->st_tip + 3 * (row + n - 1), s->st_tip + 3 * (row + n), R.tips.begin() + 3 * (size_t)r.index);
-      for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, s->st_status[row + t]);
-      if (++R.n_done == R.n_robots) {
-        s->completed.push_back(r.req);
-        ++s->n_completed;
-        ++done_now;
+  // 1. groups that finished: copy their results out; groups read back: hand them over
+  for (auto it = s->groups.begin(); it != s->groups.end() && e == hipSuccess;) {
+    vine_server::Group& g = *it;
+    if (g.state == 1) {
+      const hipError_t q = events_done(g.ev_run);
+      if (q == hipErrorNotReady) {
+        ++it;
+        continue;
       }
-      s->rows.give(r.row, n);
-      s->obst.give(r.obs_off, (int64_t)r.obs.size());
-      s->state[slot] = vine_server::kFree;
-      r = vine_server::Robot();
-    }
-    s->gather[par].clear();
-    for (const int slot : s->snap_slots[par]) {  // link counts after that tick
-      vine_server::Robot& r = s->live[slot];
-      const int n0 = r.n_known, n1 = s->st_snap[par][slot];
-      s->joint_updates += (int64_t)n1 * (n1 + 1) / 2 - (int64_t)n0 * (n0 + 1) / 2;
-      r.n_known = n1;
-      if (n1 >= r.inst.n_links && s->state[slot] == vine_server::kActive) {
-        // finished: copy its angles, last tip and statuses out (read two ticks on)
+      A(q);
+      hipStream_t st = s->pool[g.stream];
+      for (int i = 0; i < g.count; ++i) {
+        const vine_server::Robot& r = s->live[s->st_order[g.order_off + i]];
         const int n = r.inst.n_links;
         const int64_t row = r.row;
         A(hipMemcpyAsync(s->st_theta + row, h->theta + row, sizeof(double) * n,
@@ -1716,16 +1735,55 @@ int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
                          sizeof(double) * 3, hipMemcpyDeviceToHost, st));
         A(hipMemcpyAsync(s->st_status + row, h->status + row, sizeof(int) * n,
                          hipMemcpyDeviceToHost, st));
-        s->state[slot] = vine_server::kRetiring;
-        s->gather[par].push_back(slot);
       }
+      A(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
+      A(hipEventRecord(g.ev_out, st));
+      g.state = 2;
+      s->reading += g.count;
+      ++it;
+      continue;
     }
-    s->snap_slots[par].clear();
+    const hipError_t q = hipEventQuery(g.ev_out);
+    if (q == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    A(q);
+    for (int i = 0; i < g.count && e == hipSuccess; ++i) {
+      const int slot = s->st_order[g.order_off + i];
+      vine_server::Robot& r = s->live[slot];
+      vine_server::Request& R = s->reqs[r.req];
+      const int n = r.inst.n_links;
+      const int64_t row = r.row;
+      R.theta[r.index].assign(s->st_theta + row, s->st_theta + row + n);
+      std::copy(s->st_tip + 3 * (row + n - 1), s->st_tip + 3 * (row + n),
+                R.tips.begin() + 3 * (size_t)r.index);
+      for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, s->st_status[row + t]);
+      s->joint_updates += (int64_t)n * (n + 1) / 2;
+      if (++R.n_done == R.n_robots) {
+        s->completed.push_back(r.req);
+        ++s->n_completed;
+        ++done_now;
+      }
+      s->rows.give(r.row, n);
+      s->obst.give(r.obs_off, (int64_t)r.obs.size());
+      s->busy[slot] = 0;
+      r = vine_server::Robot();
+    }
+    s->order_ranges.give(g.order_off, g.count);
+    s->resident -= g.count;
+    s->reading -= g.count;
+    drop_group_events(g);
+    it = s->groups.erase(it);
   }
-  // 2. admission: queued robots (first come, first served) into a free slot and free rows
-  int nadm = 0;
-  for (int slot = 0; slot < s->slots && !s->queue.empty() && e == hipSuccess; ++slot) {
-    if (s->state[slot] != vine_server::kFree) continue;
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
+  // 2. admission: queued robots (first come, first served) into free slots and free rows,
+  // as many as the longest free run of the order array holds (a group's launch order is
+  // contiguous there)
+  std::vector<int> adm;
+  const int64_t room = s->order_ranges.largest();
+  for (int slot = 0; slot < s->slots && !s->queue.empty() && (int64_t)adm.size() < room; ++slot) {
+    if (s->busy[slot]) continue;
     vine_server::Robot& q = s->queue.front();
     const int n = q.inst.n_links, K = (int)q.obs.size();
     const int64_t row = s->rows.take(n);
@@ -1746,13 +1804,37 @@ int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
     s->queue.pop_front();
     r.row = row;
     r.obs_off = oo;
-    r.n_known = 0;
+    s->live[slot] = std::move(r);
+    s->busy[slot] = 1;
+    adm.push_back(slot);
+  }
+  if (adm.empty()) return done_now;
+  vine_server::Group g;
+  g.count = (int)adm.size();
+  g.order_off = s->order_ranges.take(g.count);  // fits: count <= the longest free run
+  g.stream = s->next_stream;
+  s->next_stream = (s->next_stream + 1) % vine_server::kStreams;
+  hipStream_t sa = s->pool[g.stream];
+  // launch order: by class, longest expected work first
+  auto cost = [&](int b) {
+    const vine_instance& I = s->live[b].inst;
+    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
+  };
+  std::stable_sort(adm.begin(), adm.end(), [&](int a, int b) {
+    const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
+    if (ca != cb) return ca < cb;
+    return cost(a) > cost(b);
+  });
+  for (int slot : adm) {
+    const vine_server::Robot& r = s->live[slot];
+    const int n = r.inst.n_links, K = (int)r.obs.size();
+    const int64_t row = r.row, oo = r.obs_off;
     const vine_instance& I = r.inst;
     int* ii = s->st_ii + vs::kII * (size_t)slot;
     ii[vs::kNTarget] = n;
     ii[vs::kObsOff] = (int)oo;
     ii[vs::kObsCnt] = K;
-    ii[vs::kTableId] = tid;
+    ii[vs::kTableId] = table_for(s, I.link_len);
     ii[vs::kCoverOff] = (int)row;
     ii[vs::kSpamOff] = 0;
     ii[vs::kSpamCnt] = 0;
@@ -1779,61 +1861,52 @@ int32_t vine_server_tick(vine_server* s, int32_t steps, void* stream) {
       o[3] = O.kind == 1 ? O.b : 0.0;
     }
     // asynchronous copies from pinned staging; a staging row is rewritten only after its
-    // robot has retired, long after these copies ran
+    // robot has been read back, long after these copies ran
     A(hipMemcpyAsync(h->ii + vs::kII * (size_t)slot, ii, sizeof(int) * vs::kII,
-                     hipMemcpyHostToDevice, st));
-    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, st));
+                     hipMemcpyHostToDevice, sa));
+    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, sa));
     A(hipMemcpyAsync(h->cover + 2 * row, s->st_cover + 2 * row, sizeof(double) * 2 * n,
-                     hipMemcpyHostToDevice, st));
+                     hipMemcpyHostToDevice, sa));
     if (K > 0) {
-      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, st));
+      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, sa));
       A(hipMemcpyAsync(h->obs + 4 * oo, s->st_obs + 4 * oo, sizeof(double) * 4 * K,
-                       hipMemcpyHostToDevice, st));
+                       hipMemcpyHostToDevice, sa));
     }
-    s->live[slot] = std::move(r);
-    s->state[slot] = vine_server::kActive;
-    s->st_adm[par][nadm++] = slot;
   }
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("admission: ") + hipGetErrorString(e));
-  if (nadm > 0) {
-    A(hipMemcpyAsync(s->d_adm[par], s->st_adm[par], sizeof(int) * nadm, hipMemcpyHostToDevice, st));
-    A(vs::launch_slot_reset(kdata(h), s->d_adm[par], nadm, st));
+  std::copy(adm.begin(), adm.end(), s->st_order + g.order_off);
+  A(hipMemcpyAsync(h->order + g.order_off, s->st_order + g.order_off, sizeof(int) * g.count,
+                   hipMemcpyHostToDevice, sa));
+  vs::KData D = kdata(h);
+  A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
+  hipEvent_t ev_in = nullptr;
+  A(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  A(hipEventRecord(ev_in, sa));
+  // one launch per class, each on the next stream of the pool, after the copies
+  const vs::KParams kp = kparams(h->prm);
+  for (int i = 0; i < g.count && e == hipSuccess;) {
+    const int c = link_class(s->live[adm[i]].inst.n_links);
+    int j = i, nmax = 0;
+    while (j < g.count && link_class(s->live[adm[j]].inst.n_links) == c) {
+      nmax = std::max(nmax, s->live[adm[j]].inst.n_links);
+      ++j;
+    }
+    hipStream_t sc = s->pool[s->next_stream];
+    s->next_stream = (s->next_stream + 1) % vine_server::kStreams;
+    A(hipStreamWaitEvent(sc, ev_in, 0));
+    D.launch_first = (int)g.order_off + i;
+    D.launch_count = j - i;
+    A(vs::launch_rollout(kp, D, nmax, kClassLinks[c], sc));
+    hipEvent_t ev = nullptr;
+    A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    A(hipEventRecord(ev, sc));
+    g.ev_run.push_back(ev);
+    i = j;
   }
-  // 3. launches: active robots by class, longest expected work first
-  std::vector<int> order;
-  for (int slot = 0; slot < s->slots; ++slot)
-    if (s->state[slot] == vine_server::kActive) order.push_back(slot);
-  if (!order.empty()) {
-    auto cost = [&](int b) {
-      const vine_instance& I = s->live[b].inst;
-      return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
-      if (ca != cb) return ca < cb;
-      return cost(a) > cost(b);
-    });
-    for (int c = 0; c < vine_sim::kClasses; ++c) h->cls_count[c] = 0;
-    for (int b : order) h->cls_count[link_class(s->live[b].inst.n_links)]++;
-    h->cls_first[0] = 0;
-    for (int c = 1; c < vine_sim::kClasses; ++c)
-      h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
-    std::copy(order.begin(), order.end(), s->st_order[par]);
-    A(hipMemcpyAsync(h->order, s->st_order[par], sizeof(int) * order.size(),
-                     hipMemcpyHostToDevice, st));
-    const vs::KParams kp = kparams(h->prm);
-    if (e == hipSuccess)
-      e = for_each_class(h, st, [&](int links, const vs::KData& D, hipStream_t ss) {
-        return vs::launch_rollout(kp, D, steps, links, ss);
-      });
-    // 4. snapshot of the link counts of the robots launched, for two ticks on
-    s->snap_slots[par] = order;
-    A(hipMemcpyAsync(s->st_snap[par], h->ncur, sizeof(int) * s->slots, hipMemcpyDeviceToHost, st));
-  }
-  A(hipEventRecord(s->ev[par], st));
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("tick: ") + hipGetErrorString(e));
-  s->ev_live[par] = true;
-  ++s->tick;
+  g.ev_run.push_back(ev_in);  // released with the group
+  g.state = 1;
+  s->resident += g.count;
+  s->groups.push_back(std::move(g));
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   return done_now;
 }
 
@@ -1875,19 +1948,14 @@ int32_t vine_server_release(vine_server* s, int64_t request_id) {
 
 void vine_server_stats(const vine_server* s, int64_t out[8]) {
   if (!s || !out) return;
-  int64_t active = 0, retiring = 0;
-  for (int st : s->state) {
-    active += st == vine_server::kActive;
-    retiring += st == vine_server::kRetiring;
-  }
   out[0] = (int64_t)s->queue.size();
-  out[1] = active + retiring;
+  out[1] = s->resident;
   out[2] = s->n_completed;
   out[3] = s->joint_updates;
   out[4] = s->rows.used;
   out[5] = s->rows.cap;
   out[6] = s->hbm_bytes;
-  out[7] = retiring;
+  out[7] = (int64_t)s->groups.size();
 }
 
 void vine_server_destroy(vine_server* s) {

@@ -1439,6 +1439,20 @@ hipError_t launch_reset(const KData& D, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// Robots (workgroups) of one chain-length class resident per compute unit.
+hipError_t rollout_occupancy(int nmax_class, int* per_cu) {
+  const int block = 2 * kWave;
+  if (nmax_class == 64)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<64>, block, 0);
+  if (nmax_class == 128)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<128>, block, 0);
+  if (nmax_class == 256)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<256>, block, 0);
+  if (nmax_class == 512)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<512>, block, 0);
+  return hipErrorInvalidValue;
+}
+
 // host-side launcher (instantiated for the supported chain lengths)
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
                           hipStream_t stream) {

@@ -73,6 +73,7 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
+           "vine_sim_occupancy",
            "vine_server_create",
            "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
            "vine_server_release", "vine_server_stats", "vine_server_destroy",
@@ -119,6 +120,8 @@ def lib():
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.vine_sim_spam_law.restype = C.c_int32
+        L.vine_sim_occupancy.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.vine_sim_occupancy.restype = C.c_int32
         L.vine_sim_trace.argtypes = [vp, C.c_int32, C.c_int32]
         L.vine_sim_trace.restype = C.c_int32
         L.vine_sim_trace_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
@@ -136,7 +139,7 @@ def lib():
                                          C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle),
                                          C.c_int32]
         L.vine_server_submit.restype = C.c_int32
-        L.vine_server_tick.argtypes = [vp, C.c_int32, vp]
+        L.vine_server_tick.argtypes = [vp]
         L.vine_server_tick.restype = C.c_int32
         L.vine_server_poll.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32]
         L.vine_server_poll.restype = C.c_int32
@@ -161,6 +164,17 @@ def default_params(**over) -> Params:
     for k, v in over.items():
         setattr(p, k, v)
     return p
+
+
+def occupancy():
+    """(robots per compute unit for the 64-, 128-, 256- and 512-link classes, compute units)
+    of the current device (vine_sim_occupancy)."""
+    per = (C.c_int32 * 4)()
+    cus = C.c_int32()
+    rc = lib().vine_sim_occupancy(per, C.byref(cus))
+    if rc != VINE_OK:
+        raise VineError(rc, lib().vine_sim_last_error(None).decode())
+    return [int(x) for x in per], int(cus.value)
 
 
 def _stream_ptr(stream):
@@ -362,7 +376,7 @@ class VineServer:
         L = lib()
         self._p = params if params is not None else default_params(**over)
         if hbm_bytes is None:
-            hbm_bytes = int(slots) * (84 * int(max_links) + 36 * int(max_obstacles) + 148)
+            hbm_bytes = int(slots) * (84 * int(max_links) + 36 * int(max_obstacles) + 140)
         h = C.c_void_p()
         rc = L.vine_server_create(C.byref(self._p), int(slots), int(hbm_bytes), int(max_links),
                                   int(max_obstacles), int(max_spams), C.byref(h))
@@ -382,8 +396,9 @@ class VineServer:
         self._check(lib().vine_server_submit(self.h, int(request_id), inst, B, spams, ns, obs, no))
         self.n_links[int(request_id)] = [int(v) for v in work.inst_i[:, 0]]
 
-    def tick(self, steps: int = 16, stream=None) -> int:
-        return self._check(lib().vine_server_tick(self.h, int(steps), _stream_ptr(stream)))
+    def tick(self) -> int:
+        """One non-blocking scheduling round; the number of requests it completed."""
+        return self._check(lib().vine_server_tick(self.h))
 
     def poll(self, cap: int = 4096):
         ids = (C.c_int64 * cap)()
@@ -407,7 +422,7 @@ class VineServer:
         out = (C.c_int64 * 8)()
         lib().vine_server_stats(self.h, out)
         return dict(queued=out[0], active=out[1], completed=out[2], joint_updates=out[3],
-                    rows_used=out[4], rows=out[5], hbm_bytes=out[6], retiring=out[7])
+                    rows_used=out[4], rows=out[5], hbm_bytes=out[6], groups=out[7])
 
     def close(self):
         if getattr(self, "h", None):
