@@ -317,8 +317,8 @@ int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* 
 int32_t vine_sim_occupancy(int32_t per_cu[4], int32_t* compute_units);
 
 /* Diagnostics: record one row per accepted Newton iteration of robot `robot`
- * (step, sub-step, iteration, rho, mu, slope, step factor alpha, energy, 0,
- * contacts) into a device buffer of `capacity` rows on later step/rollout calls.
+ * (step, sub-step, iteration, rho, mu, slope, step factor alpha, energy, step kind:
+ * 1 damped Newton, 2 negative curvature; contacts) into a device buffer of `capacity` rows on later step/rollout calls.
  * robot = -1 switches tracing off. */
 int32_t vine_sim_trace(vine_sim* h, int32_t robot, int32_t capacity);
 
@@ -332,25 +332,29 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
  * The paper's planner (Sec. 5) issues many short simulation jobs whose sizes vary
  * (designs of different length, several environment samples each).  A server keeps the
  * robots it has admitted resident on the device; queued robots are admitted as soon as
- * a slot and device memory free up and start at once, next to the robots already
- * running, so long and short jobs share the device without waiting for each other.
+ * a lane, a slot and device memory are free and start at once, next to the robots
+ * already running, so long and short jobs share the device.
  *
  * Device memory is a budget, not a worst case: a robot of n links and K obstacles takes
  * n rows of a row pool (joint angle, sPAM coverage and one growth step's records per
  * row, 84 bytes) and K entries of an obstacle pool (36 bytes), allocated first-fit on
- * admission and freed when it is read back.  Admission is first come, first served: the
- * robot at the head of the queue waits until a slot and room in both pools are free.
+ * admission and freed when it is read back.
  *
- * vine_server_tick never waits for the device.  It reads back the groups whose
- * launches have finished (their results are copied out asynchronously and handed over
- * on a later call, their memory freed then), and admits the queued robots that fit as
- * one group: their rows are copied in from pinned host staging (asynchronously) and the
- * group grows to full length in one launch per chain-length class, each on a stream of
- * the server's own pool, alongside the groups already running.  A request is a set of
- * robots (e.g. one design on S environment samples) and completes when all of its
- * robots are read back.  Results are bitwise those of the same robots run through
- * vine_sim_create / vine_sim_rollout (robots never interact, and the kernels are the
- * same). */
+ * vine_server_tick never waits for the device.  It reads back the groups whose launch
+ * has finished (their results are copied out asynchronously and handed over on a later
+ * call, their memory freed then) and starts a group on each idle lane.  A lane is one of
+ * the server's four streams (HIP's default number of hardware queues per process) and
+ * carries one group at a time.  A group takes the chain-length class (up to 64, 128, 256
+ * or 512 links) of the oldest queued robot and every queued robot of that class that
+ * fits (a free slot and room in both pools), in arrival order; robots of other classes
+ * keep their places, and when the oldest robot does not fit nothing overtakes it.  Its
+ * rows are copied in from pinned host staging (asynchronously) and it grows to full
+ * length in one launch, longest expected work first.  A lightly loaded server so starts
+ * each request on arrival; under load the queue builds up while the lanes are busy and
+ * the groups grow.  A request is a set of robots (e.g. one design on S environment
+ * samples) and completes when all of its robots are read back.  Results are bitwise
+ * those of the same robots run through vine_sim_create / vine_sim_rollout (robots never
+ * interact, and the kernels are the same). */
 typedef struct vine_server vine_server;
 
 /* slots: robots resident at once; hbm_bytes: device memory for the pools and per-slot
@@ -367,8 +371,9 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
 
 /* Queue one request (FIFO).  Host arrays as for vine_sim_create (offsets relative to
  * these arrays); copied.  request_id is the caller's and must not be queued twice at
- * once.  Robots above the server's bounds give VINE_ECAPACITY, invalid input
- * VINE_EINVAL; nothing is queued then. */
+ * once.  Robots above the server's bounds, or a ninth distinct link length, give
+ * VINE_ECAPACITY, invalid input VINE_EINVAL; nothing is queued then.  The force-law
+ * table of a new link length is built and uploaded here (a blocking copy). */
 int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instance* inst,
                            int32_t n_inst, const vine_spam* spams, int32_t n_spams,
                            const vine_obstacle* obstacles, int32_t n_obstacles);

@@ -1443,7 +1443,10 @@ struct vine_server {
   int slots = 0, max_links = 0, max_obs = 0, max_spams = 0;
   int64_t hbm_bytes = 0;
   static constexpr int kMaxTables = 8;
-  static constexpr int kStreams = 8;
+  // Lanes: streams that each carry at most one group at a time.  HIP gives a process four
+  // hardware queues by default and streams share them in turn, so a fifth stream's launch
+  // would queue behind another stream's running group.
+  static constexpr int kStreams = 4;
   struct Robot {
     int64_t req = 0;
     int index = 0;  // within the request
@@ -1462,7 +1465,7 @@ struct vine_server {
     int count = 0;
     std::vector<hipEvent_t> ev_run;    // one per class launch
     hipEvent_t ev_out = nullptr;       // results copied out
-    int stream = 0;                    // pool stream of its copies
+    int stream = 0;                    // its lane: copies in, launch, copies out
     int state = 0;                     // 1 running, 2 being read back
   };
   std::deque<Robot> queue;
@@ -1474,7 +1477,7 @@ struct vine_server {
   std::deque<int64_t> completed;
   int64_t joint_updates = 0, n_completed = 0, resident = 0, reading = 0;
   hipStream_t pool[kStreams] = {};
-  int next_stream = 0;
+  bool lane_busy[kStreams] = {};
   // pinned staging at the pools' offsets: inputs, launch orders, results
   int* st_ii = nullptr;
   double* st_dd = nullptr;
@@ -1539,6 +1542,96 @@ hipError_t events_done(const std::vector<hipEvent_t>& evs) {
     if (q != hipSuccess) return q;
   }
   return hipSuccess;
+}
+
+// Launch the admitted robots `adm` (slots, all of one chain-length class) as a group on
+// lane `lane`: inputs staged in pinned memory and copied asynchronously, the slots'
+// state cleared, one rollout launch to full length, all on the lane's stream.
+int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
+  vine_sim* h = s->h;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  vine_server::Group g;
+  g.count = (int)adm.size();
+  g.order_off = s->order_ranges.take(g.count);  // fits: count <= the longest free run
+  g.stream = lane;
+  hipStream_t sa = s->pool[lane];
+  // launch order: longest expected work first
+  auto cost = [&](int b) {
+    const vine_instance& I = s->live[b].inst;
+    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
+  };
+  std::stable_sort(adm.begin(), adm.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  int nmax = 0;
+  for (int slot : adm) {
+    const vine_server::Robot& r = s->live[slot];
+    const int n = r.inst.n_links, K = (int)r.obs.size();
+    nmax = std::max(nmax, n);
+    const int64_t row = r.row, oo = r.obs_off;
+    const vine_instance& I = r.inst;
+    int* ii = s->st_ii + vs::kII * (size_t)slot;
+    ii[vs::kNTarget] = n;
+    ii[vs::kObsOff] = (int)oo;
+    ii[vs::kObsCnt] = K;
+    ii[vs::kTableId] = table_for(s, I.link_len);  // a lookup: built at submit
+    ii[vs::kCoverOff] = (int)row;
+    ii[vs::kSpamOff] = 0;
+    ii[vs::kSpamCnt] = 0;
+    ii[vs::kThetaOff] = (int)row;
+    ii[vs::kRecOff] = (int)row;
+    ii[vs::kRecCap] = n;
+    double* dd = s->st_dd + 6 * (size_t)slot;
+    dd[0] = I.link_len;
+    dd[1] = I.tube_radius;
+    dd[2] = I.body_pressure;
+    dd[3] = I.base_x;
+    dd[4] = I.base_y;
+    dd[5] = I.base_heading;
+    std::vector<double> cover;
+    append_cover(I, r.spams.data(), cover);
+    std::copy(cover.begin(), cover.end(), s->st_cover + 2 * row);
+    for (int k = 0; k < K; ++k) {
+      const vine_obstacle& O = r.obs[k];
+      s->st_okind[oo + k] = O.kind;
+      double* o = s->st_obs + 4 * (oo + k);
+      o[0] = O.cx;
+      o[1] = O.cy;
+      o[2] = O.a;
+      o[3] = O.kind == 1 ? O.b : 0.0;
+    }
+    // asynchronous copies from pinned staging; a staging row is rewritten only after its
+    // robot has been read back, long after these copies ran
+    A(hipMemcpyAsync(h->ii + vs::kII * (size_t)slot, ii, sizeof(int) * vs::kII,
+                     hipMemcpyHostToDevice, sa));
+    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, sa));
+    A(hipMemcpyAsync(h->cover + 2 * row, s->st_cover + 2 * row, sizeof(double) * 2 * n,
+                     hipMemcpyHostToDevice, sa));
+    if (K > 0) {
+      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, sa));
+      A(hipMemcpyAsync(h->obs + 4 * oo, s->st_obs + 4 * oo, sizeof(double) * 4 * K,
+                       hipMemcpyHostToDevice, sa));
+    }
+  }
+  std::copy(adm.begin(), adm.end(), s->st_order + g.order_off);
+  A(hipMemcpyAsync(h->order + g.order_off, s->st_order + g.order_off, sizeof(int) * g.count,
+                   hipMemcpyHostToDevice, sa));
+  vs::KData D = kdata(h);
+  A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
+  D.launch_first = (int)g.order_off;
+  D.launch_count = g.count;
+  A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], sa));
+  hipEvent_t ev = nullptr;
+  A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  A(hipEventRecord(ev, sa));
+  g.ev_run.push_back(ev);
+  g.state = 1;
+  s->resident += g.count;
+  s->lane_busy[lane] = true;
+  s->groups.push_back(std::move(g));
+  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return VINE_OK;
 }
 
 }  // namespace
@@ -1686,6 +1779,13 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
         return sfail(s, VINE_EINVAL, "invalid obstacle");
     }
   }
+  // the sPAM table of each link length (built and uploaded on its first use)
+  for (int b = 0; b < n_inst; ++b) {
+    const int tid = table_for(s, inst[b].link_len);
+    if (tid < 0)
+      return sfail(s, tid == -1 ? VINE_ECAPACITY : VINE_EDEVICE,
+                   tid == -1 ? "more than 8 distinct link lengths" : "table upload failed");
+  }
   vine_server::Request R;
   R.n_robots = n_inst;
   R.tips.assign(3 * (size_t)n_inst, 0.0);
@@ -1773,140 +1873,49 @@ int32_t vine_server_tick(vine_server* s) {
     s->order_ranges.give(g.order_off, g.count);
     s->resident -= g.count;
     s->reading -= g.count;
+    s->lane_busy[g.stream] = false;
     drop_group_events(g);
     it = s->groups.erase(it);
   }
   if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
-  // 2. admission: queued robots (first come, first served) into free slots and free rows,
-  // as many as the longest free run of the order array holds (a group's launch order is
-  // contiguous there)
-  std::vector<int> adm;
-  const int64_t room = s->order_ranges.largest();
-  for (int slot = 0; slot < s->slots && !s->queue.empty() && (int64_t)adm.size() < room; ++slot) {
-    if (s->busy[slot]) continue;
-    vine_server::Robot& q = s->queue.front();
-    const int n = q.inst.n_links, K = (int)q.obs.size();
-    const int64_t row = s->rows.take(n);
-    if (row < 0) break;
-    const int64_t oo = s->obst.take(K);
-    if (oo < 0) {
-      s->rows.give(row, n);
-      break;
+  // 2. admission, one group per idle lane: the queue's oldest robot fixes the group's
+  // chain-length class, and the queued robots of that class join it in arrival order
+  // while free slots, rows, obstacle space and a contiguous run of the order array (a
+  // group's launch order is contiguous there) hold them.  Robots of other classes keep
+  // their places.  A lightly loaded server runs each request as soon as it arrives; under
+  // load the queue builds up while the lanes are busy and the groups grow.
+  for (int lane = 0; lane < vine_server::kStreams && e == hipSuccess; ++lane) {
+    if (s->lane_busy[lane] || s->queue.empty()) continue;
+    const int cls = link_class(s->queue.front().inst.n_links);
+    const int64_t room = s->order_ranges.largest();
+    std::vector<int> adm;
+    int slot = 0;
+    for (auto it = s->queue.begin(); it != s->queue.end() && (int64_t)adm.size() < room;) {
+      if (link_class(it->inst.n_links) != cls) {
+        ++it;
+        continue;
+      }
+      while (slot < s->slots && s->busy[slot]) ++slot;
+      if (slot == s->slots) break;
+      const int n = it->inst.n_links, K = (int)it->obs.size();
+      const int64_t row = s->rows.take(n);
+      if (row < 0) break;
+      const int64_t oo = s->obst.take(K);
+      if (oo < 0) {
+        s->rows.give(row, n);
+        break;
+      }
+      vine_server::Robot r = std::move(*it);
+      it = s->queue.erase(it);
+      r.row = row;
+      r.obs_off = oo;
+      s->live[slot] = std::move(r);
+      s->busy[slot] = 1;
+      adm.push_back(slot);
     }
-    const int tid = table_for(s, q.inst.link_len);
-    if (tid < 0) {
-      s->rows.give(row, n);
-      s->obst.give(oo, K);
-      return sfail(s, tid == -1 ? VINE_ECAPACITY : VINE_EDEVICE,
-                   tid == -1 ? "more than 8 distinct link lengths" : "table upload failed");
-    }
-    vine_server::Robot r = std::move(q);
-    s->queue.pop_front();
-    r.row = row;
-    r.obs_off = oo;
-    s->live[slot] = std::move(r);
-    s->busy[slot] = 1;
-    adm.push_back(slot);
+    if (adm.empty()) break;  // the oldest robot does not fit yet: keep the arrival order
+    if (launch_group(s, lane, adm) != VINE_OK) return VINE_EDEVICE;
   }
-  if (adm.empty()) return done_now;
-  vine_server::Group g;
-  g.count = (int)adm.size();
-  g.order_off = s->order_ranges.take(g.count);  // fits: count <= the longest free run
-  g.stream = s->next_stream;
-  s->next_stream = (s->next_stream + 1) % vine_server::kStreams;
-  hipStream_t sa = s->pool[g.stream];
-  // launch order: by class, longest expected work first
-  auto cost = [&](int b) {
-    const vine_instance& I = s->live[b].inst;
-    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
-  };
-  std::stable_sort(adm.begin(), adm.end(), [&](int a, int b) {
-    const int ca = link_class(s->live[a].inst.n_links), cb = link_class(s->live[b].inst.n_links);
-    if (ca != cb) return ca < cb;
-    return cost(a) > cost(b);
-  });
-  for (int slot : adm) {
-    const vine_server::Robot& r = s->live[slot];
-    const int n = r.inst.n_links, K = (int)r.obs.size();
-    const int64_t row = r.row, oo = r.obs_off;
-    const vine_instance& I = r.inst;
-    int* ii = s->st_ii + vs::kII * (size_t)slot;
-    ii[vs::kNTarget] = n;
-    ii[vs::kObsOff] = (int)oo;
-    ii[vs::kObsCnt] = K;
-    ii[vs::kTableId] = table_for(s, I.link_len);
-    ii[vs::kCoverOff] = (int)row;
-    ii[vs::kSpamOff] = 0;
-    ii[vs::kSpamCnt] = 0;
-    ii[vs::kThetaOff] = (int)row;
-    ii[vs::kRecOff] = (int)row;
-    ii[vs::kRecCap] = n;
-    double* dd = s->st_dd + 6 * (size_t)slot;
-    dd[0] = I.link_len;
-    dd[1] = I.tube_radius;
-    dd[2] = I.body_pressure;
-    dd[3] = I.base_x;
-    dd[4] = I.base_y;
-    dd[5] = I.base_heading;
-    std::vector<double> cover;
-    append_cover(I, r.spams.data(), cover);
-    std::copy(cover.begin(), cover.end(), s->st_cover + 2 * row);
-    for (int k = 0; k < K; ++k) {
-      const vine_obstacle& O = r.obs[k];
-      s->st_okind[oo + k] = O.kind;
-      double* o = s->st_obs + 4 * (oo + k);
-      o[0] = O.cx;
-      o[1] = O.cy;
-      o[2] = O.a;
-      o[3] = O.kind == 1 ? O.b : 0.0;
-    }
-    // asynchronous copies from pinned staging; a staging row is rewritten only after its
-    // robot has been read back, long after these copies ran
-    A(hipMemcpyAsync(h->ii + vs::kII * (size_t)slot, ii, sizeof(int) * vs::kII,
-                     hipMemcpyHostToDevice, sa));
-    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, sa));
-    A(hipMemcpyAsync(h->cover + 2 * row, s->st_cover + 2 * row, sizeof(double) * 2 * n,
-                     hipMemcpyHostToDevice, sa));
-    if (K > 0) {
-      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, sa));
-      A(hipMemcpyAsync(h->obs + 4 * oo, s->st_obs + 4 * oo, sizeof(double) * 4 * K,
-                       hipMemcpyHostToDevice, sa));
-    }
-  }
-  std::copy(adm.begin(), adm.end(), s->st_order + g.order_off);
-  A(hipMemcpyAsync(h->order + g.order_off, s->st_order + g.order_off, sizeof(int) * g.count,
-                   hipMemcpyHostToDevice, sa));
-  vs::KData D = kdata(h);
-  A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
-  hipEvent_t ev_in = nullptr;
-  A(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
-  A(hipEventRecord(ev_in, sa));
-  // one launch per class, each on the next stream of the pool, after the copies
-  const vs::KParams kp = kparams(h->prm);
-  for (int i = 0; i < g.count && e == hipSuccess;) {
-    const int c = link_class(s->live[adm[i]].inst.n_links);
-    int j = i, nmax = 0;
-    while (j < g.count && link_class(s->live[adm[j]].inst.n_links) == c) {
-      nmax = std::max(nmax, s->live[adm[j]].inst.n_links);
-      ++j;
-    }
-    hipStream_t sc = s->pool[s->next_stream];
-    s->next_stream = (s->next_stream + 1) % vine_server::kStreams;
-    A(hipStreamWaitEvent(sc, ev_in, 0));
-    D.launch_first = (int)g.order_off + i;
-    D.launch_count = j - i;
-    A(vs::launch_rollout(kp, D, nmax, kClassLinks[c], sc));
-    hipEvent_t ev = nullptr;
-    A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    A(hipEventRecord(ev, sc));
-    g.ev_run.push_back(ev);
-    i = j;
-  }
-  g.ev_run.push_back(ev_in);  // released with the group
-  g.state = 1;
-  s->resident += g.count;
-  s->groups.push_back(std::move(g));
-  if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   return done_now;
 }
 
