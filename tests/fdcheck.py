@@ -23,7 +23,16 @@ class Case:
     h: float
 
 
-def cases_for(work: W.Workload, robots, h_P: float = 0.1, h_s: float = 1e-5) -> list[Case]:
+# The finite-difference step: 1e-4 in the workloads' units, i.e. 1e-4 m for sPAM ends and
+# 1e-4 kPa = 0.1 Pa for pressures.  Central differences are second-order: at 1e-4 m their
+# truncation error in the placement derivatives is ~1e-3 relative on the differentiation
+# batch, so the tests also run 1e-5 m (~1e-5) to pin the adjoint more tightly.
+H_P, H_S = 0.1, 1e-4
+# (step for the ends, relative tolerance) pairs of the gradient tests
+STEPS = [(1e-4, 2e-3), (1e-5, 2e-5)]
+
+
+def cases_for(work: W.Workload, robots, h_P: float = H_P, h_s: float = H_S) -> list[Case]:
     """Every sPAM parameter of ``robots`` whose loss is smooth within +-h: ends
     closer than 2h to a link boundary or the robot's end are left out (the joint
     coverage has a kink there)."""

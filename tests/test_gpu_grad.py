@@ -12,7 +12,7 @@ import pytest
 import oracle as O
 from paper_2509_15180_amd import workloads as W
 
-from fdcheck import cases_for, fd_values, losses, perturbed, smooth
+from fdcheck import STEPS, cases_for, fd_values, losses, perturbed, smooth
 
 pytestmark = pytest.mark.gpu
 
@@ -69,10 +69,11 @@ def test_grad_matches_oracle(weighted):
         assert r.max() < 1e-6
 
 
-def test_grad_matches_fd_of_gpu_rollouts():
+@pytest.mark.parametrize("h_s,rtol", STEPS)
+def test_grad_matches_fd_of_gpu_rollouts(h_s, rtol):
     w = W.config4(16).subset(ROBOTS[:5])
     base, (dP, d0, d1, loss, st) = _gpu(w)
-    cases = cases_for(w, range(w.n_inst))
+    cases = cases_for(w, range(w.n_inst), h_s=h_s)
     wp = perturbed(w, cases)
     import torch
     with _sim(wp) as sim:
@@ -86,8 +87,8 @@ def test_grad_matches_fd_of_gpu_rollouts():
     adj = np.array([g[c.name][c.spam] for c in cases])
     assert ok.sum() >= 10
     r = _rel(adj[ok], fd[ok], 1e-3 * np.abs(adj[ok]).max())
-    print(f"FD: {ok.sum()} smooth cases, max rel {r.max():.2e}", flush=True)
-    assert r.max() < 2e-5
+    print(f"FD at h = {h_s:g} m: {ok.sum()} smooth cases, max rel {r.max():.2e}", flush=True)
+    assert r.max() < rtol
 
 
 def test_grad_needs_recorded_trajectory():

@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 from paper_2509_15180_amd import workloads as W
 
-from fdcheck import cases_for, fd_values, losses, perturbed, smooth
+from fdcheck import STEPS, cases_for, fd_values, losses, perturbed, smooth
 
 ROBOTS = [1, 2, 3, 6]  # config-4 robots whose full rollouts take well under a second
 
@@ -25,8 +25,9 @@ def base():
     return w, a
 
 
+@pytest.mark.parametrize("h_s,rtol", STEPS)
 @pytest.mark.parametrize("weighted", [False, True])
-def test_adjoint_matches_central_fd(base, weighted):
+def test_adjoint_matches_central_fd(base, weighted, h_s, rtol):
     w, a = base
     T = a["traj"].shape[1]
     weights = None
@@ -36,7 +37,7 @@ def test_adjoint_matches_central_fd(base, weighted):
         weights[-1] = 1.0
     dP, d0, d1, loss = O.gradient(w, a["traj"], weights=weights, threads=8)
     np.testing.assert_allclose(loss, losses(a["tip"], w.goal, weights), rtol=1e-12, atol=0)
-    cases = cases_for(w, range(w.n_inst))
+    cases = cases_for(w, range(w.n_inst), h_s=h_s)
     wp = perturbed(w, cases)
     o = O.rollout(wp, threads=8)
     fd = fd_values(cases, losses(o["tip"], wp.goal, weights))
@@ -46,8 +47,8 @@ def test_adjoint_matches_central_fd(base, weighted):
     assert ok.sum() >= 10, "too few smooth cases to pin the adjoint"
     err = np.abs(adj - fd)[ok]
     scale = np.maximum(np.abs(fd[ok]), 1e-3 * np.abs(adj[ok]).max())
-    # central-difference truncation at h = 1e-5 m is below 4e-6 relative here
-    assert (err / scale).max() < 2e-5, (adj[ok], fd[ok])
+    # central-difference truncation: below 7e-4 relative at h = 1e-4 m, 7e-6 at 1e-5 m
+    assert (err / scale).max() < rtol, (adj[ok], fd[ok])
     # every name is exercised
     assert {c.name for c, k in zip(cases, ok) if k} == {"P", "s0", "s1"}
 
