@@ -194,6 +194,16 @@ def compare(got, ref, T):
             "tolerances": {"theta_rad": 1e-5, "tip_m": 1e-4}}
 
 
+def golden_source_hash() -> str:
+    """SHA-256 of the sources that wrote the stored oracle outputs (each file records the
+    hash it was written with); the files are hashed as bytes, no oracle code runs here."""
+    h = hashlib.sha256()
+    for f in ("oracle/vine_oracle.c", "oracle/__init__.py", "paper_2509_15180_amd/workloads.py"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def golden_accuracy(wl, out):
     """The batch against the oracle's stored outputs of the same robots (tests/golden),
     while they match the oracle and workload sources."""
@@ -203,10 +213,8 @@ def golden_accuracy(wl, out):
     path = os.path.join(ROOT, "tests", "golden", names[wl][0])
     if not os.path.exists(path):
         return None
-    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
-    import make_oracle_outputs as MK
     g = np.load(path)
-    if str(g["source_sha256"]) != MK.source_hash():
+    if str(g["source_sha256"]) != golden_source_hash():
         return None
     idx = g["idx"]
     got = {k: out[k][idx] for k in ("theta", "tip", "chash")}
@@ -226,6 +234,8 @@ def main():
     ap.add_argument("--hbm-mb", type=float, default=512.0, help="serve: device memory of the robot pools")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: measured seconds")
     ap.add_argument("--warm", type=float, default=5.0, help="serve: warm-up seconds")
+    ap.add_argument("--drain", type=float, default=40.0,
+                    help="serve: seconds to keep ticking after the last arrival")
     ap.add_argument("--slots", type=int, default=4096, help="serve: resident robots")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
@@ -398,11 +408,7 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": {"vs_cpu_baseline_sample": acc_live,
                      "vs_stored_oracle_outputs": golden_accuracy(wl, out)},
-        "quality": {"converged_steps": int((status == 0).sum()),
-                    "other_steps": int(((status != 0) & (status != -1)).sum()),
-                    "max_penetration_m": float(out["maxpen"].max()),
-                    "p99_9_penetration_m": float(np.percentile(out["maxpen"][out["ncont"] > 0], 99.9))
-                    if (out["ncont"] > 0).any() else 0.0},
+        "quality": quality(status, out),
         "wall_s": R["wall"],
     }
     if extra is not None:
@@ -412,9 +418,30 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def quality(status, out):
+    """Step statuses and the penetration of the converged states that carry contacts
+    (deepest disk per state)."""
+    conv = (status == 0) & (out["ncont"] > 0)
+    pen = out["maxpen"][conv]
+    q = {"converged_steps": int((status == 0).sum()),
+         "other_steps": int(((status != 0) & (status != -1)).sum()),
+         "converged_contact_states": int(conv.sum()),
+         "max_penetration_m": float(out["maxpen"].max())}
+    if pen.size:
+        q.update({"p50_penetration_m": float(np.percentile(pen, 50)),
+                  "p99_penetration_m": float(np.percentile(pen, 99)),
+                  "p99_9_penetration_m": float(np.percentile(pen, 99.9)),
+                  "fraction_within_1mm": float((pen <= 1e-3).mean())})
+    return q
+
+
 def serve_once(args, torch, V, W, rate):
     """Open-loop stream: requests arrive on their Poisson clock whether or not the
-    server keeps up; latency = completion (results read back) - arrival."""
+    server keeps up, for warm + duration seconds; then no more arrive and the server
+    drains (up to args.drain seconds).  Latency = completion (results read back) -
+    arrival, over the requests that arrived after the warm-up, including those that
+    completed while draining; throughput = joint-updates completed during the measured
+    window over its length."""
     horizon = args.warm + args.duration
     n_req = max(1, int(rate * horizon * 1.05) + 1)
     # requests are generated lazily in blocks (a saturated stream would otherwise build
@@ -434,14 +461,15 @@ def serve_once(args, torch, V, W, rate):
     arrival, size = {}, {}
     done_at = {}
     t0 = time.perf_counter()
-    ju0, tw = None, 0.0
+    ju0 = ju1 = None
     ticks = 0
     peak_rows = 0
+    at_horizon = None
     while True:
         now = time.perf_counter() - t0
-        if now > horizon:
+        if now > horizon + args.drain:
             break
-        r = upcoming()
+        r = upcoming() if now <= horizon else None
         while r is not None and r.arrival <= now:
             srv.submit(r.rid, r.work)
             arrival[r.rid] = r.arrival
@@ -451,8 +479,13 @@ def serve_once(args, torch, V, W, rate):
         st = srv.stats()
         peak_rows = max(peak_rows, st["rows_used"])
         if ju0 is None and now >= args.warm:
-            ju0, tw = st["joint_updates"], now
+            ju0 = st["joint_updates"]
+        if ju1 is None and now >= horizon:
+            ju1 = st["joint_updates"]
+            at_horizon = {"queued": st["queued"], "resident": st["active"]}
         if st["active"] + st["queued"] == 0:
+            if now > horizon:
+                break  # drained
             if r is not None:
                 time.sleep(max(0.0, min(r.arrival - now, 0.01)))
             continue
@@ -467,15 +500,22 @@ def serve_once(args, torch, V, W, rate):
             time.sleep(0.0005)
     st = srv.stats()
     t_end = time.perf_counter() - t0
-    ju_rate = (st["joint_updates"] - (ju0 or 0)) / max(t_end - tw, 1e-9)
-    lat = np.array([done_at[i] - arrival[i] for i in done_at if arrival[i] >= args.warm])
+    if ju1 is None:
+        ju1 = st["joint_updates"]
+        at_horizon = {"queued": st["queued"], "resident": st["active"]}
+    ju_rate = (ju1 - (ju0 or 0)) / args.duration
+    window = [i for i in arrival if arrival[i] >= args.warm]
+    lat = np.array([done_at[i] - arrival[i] for i in window if i in done_at])
     offered = float(np.mean(list(size.values()))) * rate if size else 0.0
-    rec = {"rate_per_s": rate, "submitted": len(arrival), "completed": len(done_at),
-           "completed_after_warmup": int(lat.size), "joint_updates_per_s": ju_rate,
-           "offered_joint_updates_per_s": offered,
+    rec = {"rate_per_s": rate, "submitted": len(arrival), "arrived_after_warmup": len(window),
+           "completed_after_warmup": int(lat.size),
+           "unfinished_after_drain": len(window) - int(lat.size),
+           "joint_updates_per_s": ju_rate, "offered_joint_updates_per_s": offered,
            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
-           "queued_at_end": st["queued"], "resident_at_end": st["active"],
+           "max_latency_s": float(lat.max()) if lat.size else None,
+           "queued_at_horizon": at_horizon["queued"], "resident_at_horizon": at_horizon["resident"],
+           "drain_s": max(0.0, t_end - horizon),
            "peak_rows": peak_rows, "rows": st["rows"], "hbm_bytes": st["hbm_bytes"],
            "ticks": ticks, "wall_s": t_end}
     srv.close()
@@ -488,22 +528,24 @@ def serve(args, torch, V, W):
     for rate in rates:
         print(f"bench: serving at {rate}/s", file=sys.stderr, flush=True)
         runs.append(serve_once(args, torch, V, W, rate))
-    # the highest rate whose p99 stays bounded: the queue drained and p99 within three
-    # times that of the lowest rate measured
+    # the highest rate whose p99 stays bounded: every request of the window completed
+    # (within the drain) and p99 within three times that of the lowest rate measured
     base = runs[0]["p99_latency_s"]
-    bounded = [r for r in runs if r["p99_latency_s"] is not None and r["queued_at_end"] == 0
+    bounded = [r for r in runs if r["p99_latency_s"] is not None
+               and r["unfinished_after_drain"] == 0
                and base is not None and r["p99_latency_s"] <= 3.0 * base]
     best = max(bounded, key=lambda r: r["rate_per_s"]) if bounded else runs[0]
     rec = {
         "metric": METRIC, "value": best["joint_updates_per_s"], "unit": "joint-updates/s",
-        "n_gpus": 1, "steps": best["ticks"], "warmup": 0,
-        "ms_per_step": 1e3 * best["wall_s"] / max(best["ticks"], 1),
+        # a "step" of the serving loop: one request completed in the measured window
+        "n_gpus": 1, "steps": best["completed_after_warmup"], "warmup": 0,
+        "ms_per_step": 1e3 * args.duration / max(best["completed_after_warmup"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "request stream: Poisson arrivals, designs of 16-512 links and "
                                "0-128 obstacles on 1-64 jittered environment samples; "
                                f"{args.slots} slots, {args.hbm_mb:.0f} MB of robot pools; "
-                               f"each admitted group grown to full length in its own launches",
+                               f"one group of one chain-length class per idle lane (4 lanes), grown to full length",
                    "warmup_s": args.warm, "measured_s": args.duration},
         "serving": {"highest_rate_with_bounded_p99": best["rate_per_s"], "runs": runs},
         "roofline": None, "cpu_baseline": None,

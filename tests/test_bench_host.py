@@ -38,3 +38,20 @@ def test_compare_counts_misses_and_tolerances():
     r = bench.compare(got, ref, 8)
     assert r["robots"] == 5 and r["identical_contact_sets"] == 4 and r["within_tolerance"] == 3
     assert abs(r["max_abs_dtheta_rad"] - 2e-5) < 1e-12
+
+
+def test_quality_counts_converged_contact_states_only():
+    status = np.array([[0, 0, 0, 2, -1]])
+    out = {"ncont": np.array([[0, 3, 1, 4, 0]]),
+           "maxpen": np.array([[0.0, 2e-3, 5e-4, 9e-3, 0.0]])}
+    q = bench.quality(status, out)
+    assert q["converged_steps"] == 3 and q["other_steps"] == 1
+    assert q["converged_contact_states"] == 2 and q["fraction_within_1mm"] == 0.5
+    assert q["max_penetration_m"] == 9e-3 and q["p50_penetration_m"] == 1.25e-3
+
+
+def test_golden_hash_is_the_writers():
+    import sys
+    sys.path.insert(0, os.path.join(bench.ROOT, "tests", "golden"))
+    import make_oracle_outputs as MK
+    assert bench.golden_source_hash() == MK.source_hash()
