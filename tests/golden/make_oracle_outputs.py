@@ -22,7 +22,7 @@ Files (numpy .npz, compressed):
   oracle_cfg4_grad.npz  the differentiation batch, robots 0..511: final-step and
                     weighted-loss gradients with respect to every sPAM's pressure and ends
 
-The uniform and differentiation files also hold the contact hashes of the same robots
+The uniform, uneven and differentiation files also hold the contact hashes of the same robots
 with every body pressure scaled by 1 + 1e-14 (``perturbed_chash``): how often the
 oracle's own descent changes its result under a rounding-size change of an input.
 """
@@ -164,7 +164,9 @@ def main():
         idx = cfg3_strata(full)
         sub = full.subset(idx)
         out = O.rollout(sub, threads=th)
-        save("oracle_cfg3.npz", idx=idx, **rollout_arrays(sub, out, 256))
+        pert = O.rollout(pressure_perturbed(sub), threads=th)
+        save("oracle_cfg3.npz", idx=idx, perturbed_chash=pert["chash"],
+             **rollout_arrays(sub, out, 256))
         print(f"cfg3 {time.time() - t:.0f} s", flush=True)
 
 

@@ -118,9 +118,10 @@ def compare(name, work_sub, got, g, T, max_miss_frac):
     assert np.all(ok[same]), np.nonzero(same & ~ok)[0]
     for b in np.nonzero(~ok)[0]:
         inst = work_sub.instance(int(b))
-        alone = _gpu_traj(inst, T)
-        assert np.array_equal(alone["chash"][0, :T], got["chash"][b, :T])  # batch-independent
-        k, rho, lam = check_valid(inst, alone, g["chash"][b], T)
+        Tb = min(T, int(inst["n"]))  # the robot's own growth steps (later ones record DONE)
+        alone = _gpu_traj(inst, Tb)
+        assert np.array_equal(alone["chash"][0, :Tb], got["chash"][b, :Tb])  # batch-independent
+        k, rho, lam = check_valid(inst, alone, g["chash"][b], Tb)
         first = int(np.argmax(got["chash"][b, :T] != g["chash"][b, :T]))
         print(f"  other minimum: robot {b} ({inst['n']} links, {len(inst['kind'])} obstacles) "
               f"from step {first}; {k} differing steps valid by the oracle (worst residual "
