@@ -23,13 +23,14 @@ class Case:
     h: float
 
 
-# The finite-difference step: 1e-4 in the workloads' units, i.e. 1e-4 m for sPAM ends and
-# 1e-4 kPa = 0.1 Pa for pressures.  Central differences are second-order: at 1e-4 m their
-# truncation error in the placement derivatives is ~1e-3 relative on the differentiation
-# batch, so the tests also run 1e-5 m (~1e-5) to pin the adjoint more tightly.
-H_P, H_S = 0.1, 1e-4
-# (step for the ends, relative tolerance) pairs of the gradient tests
-STEPS = [(1e-4, 2e-3), (1e-5, 2e-5)]
+# Finite-difference steps (h_P in Pa for pressures, h_s in m for sPAM ends, relative
+# tolerance).  The first is the stated step, h = 1e-4 in SI units for every variable:
+# central differences are second-order, and at 1e-4 m their truncation error in the
+# placement derivatives is ~7e-4 relative on the differentiation batch, while 1e-4 Pa is
+# near the rounding floor of the converged losses (~3e-4 relative).  The second pins the
+# adjoint more tightly: 0.1 Pa and 1e-5 m (errors ~2e-7 and ~7e-6).
+H_P, H_S = 1e-4, 1e-4
+STEPS = [(1e-4, 1e-4, 2e-3), (0.1, 1e-5, 2e-5)]
 
 
 def cases_for(work: W.Workload, robots, h_P: float = H_P, h_s: float = H_S) -> list[Case]:

@@ -69,11 +69,11 @@ def test_grad_matches_oracle(weighted):
         assert r.max() < 1e-6
 
 
-@pytest.mark.parametrize("h_s,rtol", STEPS)
-def test_grad_matches_fd_of_gpu_rollouts(h_s, rtol):
+@pytest.mark.parametrize("h_P,h_s,rtol", STEPS)
+def test_grad_matches_fd_of_gpu_rollouts(h_P, h_s, rtol):
     w = W.config4(16).subset(ROBOTS[:5])
     base, (dP, d0, d1, loss, st) = _gpu(w)
-    cases = cases_for(w, range(w.n_inst), h_s=h_s)
+    cases = cases_for(w, range(w.n_inst), h_P=h_P, h_s=h_s)
     wp = perturbed(w, cases)
     import torch
     with _sim(wp) as sim:
@@ -87,7 +87,7 @@ def test_grad_matches_fd_of_gpu_rollouts(h_s, rtol):
     adj = np.array([g[c.name][c.spam] for c in cases])
     assert ok.sum() >= 10
     r = _rel(adj[ok], fd[ok], 1e-3 * np.abs(adj[ok]).max())
-    print(f"FD at h = {h_s:g} m: {ok.sum()} smooth cases, max rel {r.max():.2e}", flush=True)
+    print(f"FD at h = {h_P:g} Pa, {h_s:g} m: {ok.sum()} smooth cases, max rel {r.max():.2e}", flush=True)
     assert r.max() < rtol
 
 

@@ -25,9 +25,9 @@ def base():
     return w, a
 
 
-@pytest.mark.parametrize("h_s,rtol", STEPS)
+@pytest.mark.parametrize("h_P,h_s,rtol", STEPS)
 @pytest.mark.parametrize("weighted", [False, True])
-def test_adjoint_matches_central_fd(base, weighted, h_s, rtol):
+def test_adjoint_matches_central_fd(base, weighted, h_P, h_s, rtol):
     w, a = base
     T = a["traj"].shape[1]
     weights = None
@@ -37,7 +37,7 @@ def test_adjoint_matches_central_fd(base, weighted, h_s, rtol):
         weights[-1] = 1.0
     dP, d0, d1, loss = O.gradient(w, a["traj"], weights=weights, threads=8)
     np.testing.assert_allclose(loss, losses(a["tip"], w.goal, weights), rtol=1e-12, atol=0)
-    cases = cases_for(w, range(w.n_inst), h_s=h_s)
+    cases = cases_for(w, range(w.n_inst), h_P=h_P, h_s=h_s)
     wp = perturbed(w, cases)
     o = O.rollout(wp, threads=8)
     fd = fd_values(cases, losses(o["tip"], wp.goal, weights))
@@ -47,7 +47,7 @@ def test_adjoint_matches_central_fd(base, weighted, h_s, rtol):
     assert ok.sum() >= 10, "too few smooth cases to pin the adjoint"
     err = np.abs(adj - fd)[ok]
     scale = np.maximum(np.abs(fd[ok]), 1e-3 * np.abs(adj[ok]).max())
-    # central-difference truncation: below 7e-4 relative at h = 1e-4 m, 7e-6 at 1e-5 m
+    # truncation and rounding: below 7e-4 relative at h = 1e-4 (SI), 7e-6 at 1e-5 m / 0.1 Pa
     assert (err / scale).max() < rtol, (adj[ok], fd[ok])
     # every name is exercised
     assert {c.name for c, k in zip(cases, ok) if k} == {"P", "s0", "s1"}
