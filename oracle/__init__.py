@@ -17,10 +17,10 @@ _lib = None
 
 # parameter vector layout (see prm_from in vine_oracle.c)
 PARAM_NAMES = ("Rc", "Ract", "acorr", "epsc", "kc", "tol", "max_iter", "substeps", "fd_h", "c1",
-               "c_mu", "cheb_n", "step_max", "mu_up", "pd_shift")
+               "c_mu", "cheb_n", "step_max", "mu_up", "pd_shift", "wg")
 DEFAULTS = dict(Rc=0.005, Ract=0.01718, acorr=1e-4, epsc=0.01, kc=1e4, tol=1e-10, max_iter=500,
                 substeps=2, fd_h=0.0, c1=1e-4, c_mu=1.0, cheb_n=128,
-                step_max=0.05, mu_up=10.0, pd_shift=1e-8)
+                step_max=0.05, mu_up=10.0, pd_shift=1e-8, wg=0.0)
 
 
 def params(**over) -> np.ndarray:
@@ -63,6 +63,12 @@ def lib():
         L.vo_chain_solve.restype = C.c_int
         L.vo_chain_solve.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int, ip, dp, dp, C.c_double, dp,
                                      dp]
+        L.vo_chain_eval_soft.restype = C.c_double
+        L.vo_chain_eval_soft.argtypes = L.vo_chain_eval.argtypes
+        L.vo_chain_hessian_soft.restype = None
+        L.vo_chain_hessian_soft.argtypes = L.vo_chain_hessian.argtypes
+        L.vo_chain_solve_soft.restype = C.c_int
+        L.vo_chain_solve_soft.argtypes = L.vo_chain_solve.argtypes
         L.vo_gfit_eval.restype = None
         L.vo_gfit_eval.argtypes = [C.c_double, dp, C.c_int, dp, dp, dp, dp, dp]
         L.vo_spam_coverage.restype = None
@@ -71,7 +77,7 @@ def lib():
         L.vo_joint_law.argtypes = [dp, C.c_double, C.c_double, dp, C.c_int, dp, dp, dp]
         L.vo_rollout.restype = C.c_int
         L.vo_rollout.argtypes = [C.c_int, ip, dp, dp, ip, dp, dp, C.c_int, C.c_int, C.c_int, dp,
-                                 dp, dp, ip, ip, ip, C.POINTER(C.c_uint64), dp, dp, dp]
+                                 dp, dp, ip, ip, ip, C.POINTER(C.c_uint64), dp, dp, dp, dp]
         L.vo_gradient.restype = C.c_int
         L.vo_gradient.argtypes = [C.c_int, ip, dp, dp, ip, dp, dp, C.c_int, C.c_int, dp, dp, dp,
                                   C.c_int, dp, dp, dp, dp]
@@ -212,6 +218,45 @@ def chain_hessian(inst: dict, th, prm=None, last_len=0.0):
     return H
 
 
+def chain_eval_soft(inst: dict, x, tgt, prm=None):
+    """Soft growth: (Pi, r, contacts) at x = (theta_0..theta_{n-1}, u), the tip link's length
+    u l, with the growth term's target tgt (link lengths); r has n + 1 entries."""
+    prm = params() if prm is None else prm
+    d, spam, kind, obs = _chain_args(inst)
+    x = _f64(x)
+    n = len(x) - 1
+    r = np.zeros(n + 1)
+    cap = max(1, 2 * n * max(1, len(kind)))
+    cont = np.zeros((cap, 8))
+    nc = C.c_int()
+    Pi = lib().vo_chain_eval_soft(n, _d(d), _d(spam), len(spam), len(kind), _i(kind), _d(obs),
+                                  _d(prm), tgt, _d(x), _d(r), C.byref(nc), _d(cont), cap)
+    return Pi, r, cont[:nc.value].copy()
+
+
+def chain_hessian_soft(inst: dict, x, tgt, prm=None):
+    """Soft growth: the analytic (n + 1) x (n + 1) Hessian at x = (theta, u)."""
+    prm = params() if prm is None else prm
+    d, spam, kind, obs = _chain_args(inst)
+    x = _f64(x)
+    n = len(x) - 1
+    H = np.zeros((n + 1, n + 1))
+    lib().vo_chain_hessian_soft(n, _d(d), _d(spam), len(spam), len(kind), _i(kind), _d(obs),
+                                _d(prm), tgt, _d(x), _d(H))
+    return H
+
+
+def chain_solve_soft(inst: dict, x0, tgt, prm=None):
+    """Soft growth: the equilibrium from x0 = (theta, u): (x, status, info)."""
+    prm = params() if prm is None else prm
+    d, spam, kind, obs = _chain_args(inst)
+    x = _f64(x0).copy()
+    info = np.zeros(5)
+    st = lib().vo_chain_solve_soft(len(x) - 1, _d(d), _d(spam), len(spam), len(kind), _i(kind),
+                                   _d(obs), _d(prm), tgt, _d(x), _d(info))
+    return x, st, info
+
+
 def chain_solve(inst: dict, th0, prm=None, last_len=0.0):
     """Equilibrium from th0: (theta, status, info[iters, backtracks, mu raises, rho,
     steps along negative curvature])."""
@@ -239,7 +284,7 @@ def rollout(work, n_steps: int | None = None, prm=None, threads: int = 0, traj: 
         theta=np.zeros((B, n_max)), tip=np.zeros((B, T, 3)), rho=np.zeros((B, T)),
         iters=np.zeros((B, T), np.int32), status=np.zeros((B, T), np.int32),
         ncont=np.zeros((B, T), np.int32), chash=np.zeros((B, T), np.uint64),
-        maxpen=np.zeros((B, T)), stats=np.zeros((B, 6)))
+        maxpen=np.zeros((B, T)), stats=np.zeros((B, 6)), tiplen=np.zeros((B, T)))
     tr = np.zeros((B, T, n_max)) if traj else None
     inst_i, inst_d = _i32(work.inst_i), _f64(work.inst_d)
     spam, kind, obs = _f64(work.spam.reshape(-1, 4)), _i32(work.obs_kind), _f64(work.obs_d.reshape(-1, 4))
@@ -247,7 +292,7 @@ def rollout(work, n_steps: int | None = None, prm=None, threads: int = 0, traj: 
                      n_max, _d(out["theta"]), _d(out["tip"]), _d(out["rho"]), _i(out["iters"]),
                      _i(out["status"]), _i(out["ncont"]),
                      out["chash"].ctypes.data_as(C.POINTER(C.c_uint64)), _d(out["maxpen"]),
-                     _d(tr), _d(out["stats"]))
+                     _d(tr), _d(out["stats"]), _d(out["tiplen"]))
     if traj:
         out["traj"] = tr
     return out

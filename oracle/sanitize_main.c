@@ -9,7 +9,7 @@
  *
  * usage: sanitize_main <in.bin> <out.bin>
  *   in.bin:  int32 B, S, O, n_steps, n_max; int32 inst_i[B][5]; double inst_d[B][6];
- *            double spam[S][4]; int32 obs_kind[O]; double obs_d[O][4]; double prm[15];
+ *            double spam[S][4]; int32 obs_kind[O]; double obs_d[O][4]; double prm[16];
  *            double goal[B][2]
  *   out.bin: double theta[B][n_max]; double tip[B][T][3]; int32 status[B][T];
  *            uint64 chash[B][T]; double dP[S], ds0[S], ds1[S], loss[B]
@@ -22,7 +22,7 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
                const int* obs_kind, const double* obs_d, const double* prm, int n_steps,
                int n_threads, int n_max, double* theta, double* tip, double* rho, int* iters,
                int* status, int* ncont, uint64_t* chash, double* maxpen, double* traj,
-               double* stats);
+               double* stats, double* tiplen);
 int vo_gradient(int B, const int* inst_i, const double* inst_d, const double* spam,
                 const int* obs_kind, const double* obs_d, const double* prm, int T, int n_max,
                 const double* traj, const double* weights, const double* goal, int n_threads,
@@ -51,7 +51,7 @@ int main(int argc, char** argv) {
   double* spam = (double*)load(f, sizeof(double), (size_t)4 * S);
   int* kind = (int*)load(f, sizeof(int), (size_t)O);
   double* obs = (double*)load(f, sizeof(double), (size_t)4 * O);
-  double* prm = (double*)load(f, sizeof(double), 15);
+  double* prm = (double*)load(f, sizeof(double), 16);
   double* goal = (double*)load(f, sizeof(double), (size_t)2 * B);
   fclose(f);
   const size_t BT = (size_t)B * T;
@@ -66,7 +66,7 @@ int main(int argc, char** argv) {
   double* traj = calloc(BT * N, sizeof(double));
   double* stats = calloc((size_t)6 * B, sizeof(double));
   vo_rollout(B, inst_i, inst_d, spam, kind, obs, prm, T, 1, N, theta, tip, rho, iters, status,
-             ncont, chash, maxpen, traj, stats);
+             ncont, chash, maxpen, traj, stats, NULL);
   double* dP = calloc(S + 1, sizeof(double));
   double* d0 = calloc(S + 1, sizeof(double));
   double* d1 = calloc(S + 1, sizeof(double));

@@ -59,6 +59,9 @@ typedef struct {
   int cheb_n;               /* Chebyshev degree of the G fit */
   double pd_shift;          /* delta / M_max: a state is a minimum when H + delta I is
                                positive definite (1/rad) */
+  double wg;                /* growth stiffness, N/m: 0 = hard growth (each step appends a
+                               link of prescribed length); > 0 = soft growth (the tip link's
+                               length is free under the growth term of Eq. 4) */
 } vo_prm;
 
 static void prm_from(const double* p, vo_prm* P) {
@@ -77,6 +80,7 @@ static void prm_from(const double* p, vo_prm* P) {
   P->step_max = p[12];
   P->mu_up = p[13];
   P->pd_shift = p[14];
+  P->wg = p[15];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -493,7 +497,10 @@ typedef struct {
   const vo_gfit* G;
   int n;                 /* links present */
   double l, R, Pv, bx, by, bpsi;
-  double last_len;       /* length of the tip link (growth sub-steps) */
+  double last_len;       /* length of the tip link (hard growth: growth sub-steps) */
+  int soft;              /* soft growth: the variables are (theta_0..theta_{n-1}, u), the
+                            tip link's length u l, with the growth term (wg/2)(l (tgt - u))^2 */
+  double tgt;            /* soft growth: the tip link's target length in link lengths */
   double arm, Mmax;
   const double *Pp, *Pm; /* pressure-weighted sPAM coverage per joint, +/- side */
   int K;
@@ -525,6 +532,7 @@ static void joint_law(const vo_chain* c, int j, double th, double* q, double* E)
 typedef struct {
   int i, k;
   double lam, xx, xy, nx, ny, pen, kappa;
+  double f; /* the disk's place on its link as a fraction of the link's length */
 } vo_contact;
 
 /* scratch for one chain: poses and unit link directions */
@@ -547,6 +555,10 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
   const vo_prm* P = c->P;
   int n = c->n;
   double *px = w->px, *py = w->py, *tx = w->tx, *ty = w->ty;
+  /* soft growth: th[n] = u, the tip link's length in link lengths (a link of negative
+   * length has no energy: the line search never accepts one) */
+  if (c->soft && !(th[n] >= 0.0)) return INFINITY;
+  const double last = c->soft ? th[n] * c->l : c->last_len;
   double phi = c->bpsi;
   px[0] = c->bx;
   py[0] = c->by;
@@ -555,7 +567,7 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
     phi += th[i];
     tx[i] = cos(phi);
     ty[i] = sin(phi);
-    double L = (i == n - 1) ? c->last_len : c->l;
+    double L = (i == n - 1) ? last : c->l;
     px[i + 1] = px[i] + L * tx[i];
     py[i + 1] = py[i] + L * ty[i];
   }
@@ -565,9 +577,15 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
     if (want_E) Pi += E;
     if (r) r[j] = q;
   }
+  double ru = 0.0; /* soft growth: dPi/du */
+  if (c->soft) {
+    const double gap = c->l * (c->tgt - th[n]);
+    if (want_E) Pi += 0.5 * P->wg * gap * gap;
+    ru = -P->wg * c->l * gap;
+  }
   int cnt = 0;
   for (int i = 0; i < n; ++i) {
-    double L = (i == n - 1) ? c->last_len : c->l;
+    double L = (i == n - 1) ? last : c->l;
     for (int h = 1; h <= 2; ++h) {        /* disks at s = L/2 and s = L */
       double s = 0.5 * h * L;
       double xx = px[i] + s * tx[i], xy = py[i] + s * ty[i];
@@ -582,6 +600,8 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
           if (r) {
             /* dPi/dtheta_j for every joint j <= i: -lam times the moment arm (x - p_j) x n */
             for (int j = 0; j <= i; ++j) r[j] -= lam * ((xx - px[j]) * ny - (xy - py[j]) * nx);
+            /* soft growth: the disk moves by f l t per unit of u */
+            if (c->soft && i == n - 1) ru -= lam * 0.5 * h * c->l * (nx * tx[i] + ny * ty[i]);
           }
           if (cl && cnt < cap) {
             vo_contact* e = &cl[cnt];
@@ -594,6 +614,7 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
             e->ny = ny;
             e->pen = pen;
             e->kappa = kap;
+            e->f = 0.5 * h;
           }
           ++cnt;
         }
@@ -601,6 +622,7 @@ static double chain_eval(const vo_chain* c, const double* th, double* r, int wan
     }
   }
   if (ncl) *ncl = cnt;
+  if (r && c->soft) r[n] = ru;
   return Pi;
 }
 
@@ -637,8 +659,10 @@ static double joint_dq(const vo_chain* c, int j, double th) {
 static void chain_hessian(const vo_chain* c, const double* th, const vo_contact* cl, int ncl,
                           const vo_pose* w, double* H, double* a, double* b, double* u) {
   int n = c->n;
-  memset(H, 0, sizeof(double) * (size_t)n * n);
-  for (int j = 0; j < n; ++j) H[j * n + j] = joint_dq(c, j, th[j]);
+  const int m = n + c->soft; /* soft growth: row and column n belong to u */
+  memset(H, 0, sizeof(double) * (size_t)m * m);
+  for (int j = 0; j < n; ++j) H[j * m + j] = joint_dq(c, j, th[j]);
+  if (c->soft) H[n * m + n] = c->P->wg * c->l * c->l;
   for (int e = 0; e < ncl; ++e) {
     const vo_contact* q = &cl[e];
     int i = q->i;
@@ -652,10 +676,26 @@ static void chain_hessian(const vo_chain* c, const double* th, const vo_contact*
     double nxx = q->nx * q->xx + q->ny * q->xy;
     double kc = c->P->kc, lk = q->lam * q->kappa;
     for (int j = 0; j <= i; ++j)
-      for (int m = 0; m <= i; ++m) {
-        int mx = j > m ? j : m;
-        H[j * n + m] += kc * a[j] * a[m] - lk * b[j] * b[m] + q->lam * (nxx - u[mx]);
+      for (int k = 0; k <= i; ++k) {
+        int mx = j > k ? j : k;
+        H[j * m + k] += kc * a[j] * a[k] - lk * b[j] * b[k] + q->lam * (nxx - u[mx]);
       }
+    if (c->soft && i == n - 1) {
+      /* soft growth: x moves by f l t per unit of u, t the tip link's direction, and t
+       * turns with every joint (dt/dtheta_j = z x t); with n_t = n.t, tau_t = tau.t and
+       * nz = n.(z x t):
+       *   d2Pi/du2          = (f l)^2 (k_c n_t^2 - lam kappa tau_t^2),
+       *   d2Pi/du dtheta_j  = f l (k_c a_j n_t - lam kappa b_j tau_t - lam nz) */
+      const double ltx = w->tx[i], lty = w->ty[i], fl = q->f * c->l;
+      const double nt = q->nx * ltx + q->ny * lty, taut = tx * ltx + ty * lty;
+      const double nz = -q->nx * lty + q->ny * ltx;
+      H[n * m + n] += fl * fl * (kc * nt * nt - lk * taut * taut);
+      for (int j = 0; j <= i; ++j) {
+        const double x = fl * (kc * a[j] * nt - lk * b[j] * taut - q->lam * nz);
+        H[j * m + n] += x;
+        H[n * m + j] += x;
+      }
+    }
   }
 }
 
@@ -763,7 +803,8 @@ typedef struct {
  * 4 non-finite state. */
 static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_pose* w) {
   const vo_prm* P = c->P;
-  int n = c->n;
+  const int nj = c->n;       /* joints; the step cap applies to them */
+  const int n = nj + c->soft; /* variables: soft growth adds u = th[nj] */
   size_t nn = (size_t)n;
   double* buf = (double*)malloc(sizeof(double) * (2 * nn * nn + nn * (nn + 1) + 11 * nn + 16));
   double* H = buf;
@@ -847,10 +888,11 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       neg_curv_dir(n, A, k, d);
       double vmax = 0.0, rv = 0.0, v1 = 0.0;
       for (int i = 0; i < n; ++i) {
-        vmax = fmax(vmax, fabs(d[i]));
+        if (i < nj) vmax = fmax(vmax, fabs(d[i]));
         rv += r[i] * d[i];
         v1 += fabs(d[i]);
       }
+      if (vmax == 0.0) vmax = fabs(d[nj]); /* soft growth: curvature along u alone */
       /* the slope along v counts as zero when a residual within the tolerance could
        * produce it (always so at a converged saddle): then the tie rule, d_k > 0 */
       const int tie = fabs(rv) <= P->tol * c->Mmax * v1;
@@ -882,7 +924,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
     if (mode == 1) {
       /* cap the joint-space step length so that the iterates follow the flow */
       double dmax = 0.0;
-      for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(d[i]));
+      for (int i = 0; i < nj; ++i) dmax = fmax(dmax, fabs(d[i]));
       if (dmax > P->step_max) {
         double f = P->step_max / dmax;
         for (int i = 0; i < n; ++i) d[i] *= f;
@@ -970,12 +1012,26 @@ static void chain_init(vo_chain* c, const vo_prm* P, const double* prm, const do
  *  traj   [B][T][n_max]     joint angles after each step
  *  stats  [B][6]            total iterations, backtracks, damping raises, max contacts,
  *                           steps along negative curvature, those of them whose sign
- *                           the tie rule chose */
+ *                           the tie rule chose
+ *  tiplen [B][T]            length of the tip link after each step
+ *
+ * Hard growth (wg = 0): each step appends a link at zero angle whose length reaches l
+ * in `substeps` sub-steps (Sec. 4.1's growth at a rate, with the growth term of Eq. 4
+ * satisfied exactly).  Soft growth (wg > 0): the tip link's length u l is a variable
+ * of the minimisation, under the growth term (wg/2) (l (tgt - u))^2 of Eq. 4, whose
+ * target grows at the prescribed rate of one link length per step: at sub-step s of
+ * step t, tgt = t + s/substeps - (n - 1) (capped at 1 once the robot has its target
+ * link count).  A step appends a link only when the tip link has reached full length
+ * (u >= 1; the excess u - 1 starts the new link), so a blocked tip stops growing while
+ * its target, and with it the growth force, keeps rising; a tip link that has grown
+ * longer than a link within a sub-step (the growth released when a block gives way) is
+ * split into a full link and a new tip link at zero angle, and the sub-step solved
+ * again.  The robot is done when it has its target link count with a full tip link. */
 int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spam,
                const int* obs_kind, const double* obs_d, const double* prm, int n_steps,
                int n_threads, int n_max, double* theta, double* tip, double* rho, int* iters,
                int* status, int* ncont, uint64_t* chash, double* maxpen, double* traj,
-               double* stats) {
+               double* stats, double* tiplen) {
   vo_prm P;
   prm_from(prm, &P);
   gl_init();
@@ -995,33 +1051,64 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
     spam_coverage(ntar, c.l, spam + 4 * (size_t)ii[1], ii[2], Pp, Pm);
     c.Pp = Pp;
     c.Pm = Pm;
-    double* th = (double*)calloc((size_t)nalloc, sizeof(double));
+    double* th = (double*)calloc((size_t)nalloc + 1, sizeof(double)); /* + u (soft) */
     vo_pose w;
     pose_alloc(&w, nalloc);
     int capc = 2 * nalloc * (c.K > 0 ? c.K : 1) + 1;
     vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
     double tot_it = 0, tot_bt = 0, tot_mu = 0, max_c = 0, tot_neg = 0, tot_tie = 0;
     c.n = 0;
+    c.soft = P.wg > 0.0;
+    const double full = 1.0 - 1e-12; /* a tip link at full length */
     for (int t = 0; t < n_steps; ++t) {
       int st_worst = 0, it_sum = 0;
       double rho_last = 0.0;
-      if (c.n < ntar) {
-        c.n += 1;
-        th[c.n - 1] = 0.0;
+      int grow;
+      if (c.soft) {
+        if (c.n == 0 || (th[c.n] >= full && c.n < ntar)) {
+          const double u = c.n == 0 ? 0.0 : fmax(th[c.n] - 1.0, 0.0);
+          c.n += 1;
+          th[c.n - 1] = 0.0;
+          th[c.n] = u;
+        }
+        grow = !(c.n == ntar && th[c.n] >= full);
+      } else {
+        grow = c.n < ntar;
+        if (grow) {
+          c.n += 1;
+          th[c.n - 1] = 0.0;
+        }
+      }
+      if (grow) {
         for (int s = 1; s <= P.substeps; ++s) {
-          c.last_len = c.l * (double)s / P.substeps;
-          vo_solve_stats st;
-          chain_solve(&c, th, &st, &w);
-          it_sum += st.iters;
-          tot_bt += st.backtracks;
-          tot_mu += st.mu_raises;
-          tot_neg += st.neg_steps;
-          tot_tie += st.tie_steps;
-          if (st.status > st_worst) st_worst = st.status;
-          rho_last = st.rho;
+          for (;;) {
+            if (c.soft) {
+              c.tgt = (double)t + (double)s / P.substeps - (double)(c.n - 1);
+              if (c.n == ntar && c.tgt > 1.0) c.tgt = 1.0;
+            } else {
+              c.last_len = c.l * (double)s / P.substeps;
+            }
+            vo_solve_stats st;
+            chain_solve(&c, th, &st, &w);
+            it_sum += st.iters;
+            tot_bt += st.backtracks;
+            tot_mu += st.mu_raises;
+            tot_neg += st.neg_steps;
+            tot_tie += st.tie_steps;
+            if (st.status > st_worst) st_worst = st.status;
+            rho_last = st.rho;
+            /* soft growth: a tip link longer than a link (growth released after a block)
+             * is split, its first l staying as link n - 1 and the rest starting a new link
+             * at zero angle, and the sub-step is solved again */
+            if (!(c.soft && c.n < ntar && th[c.n] > 1.0 + 1e-12)) break;
+            const double u = th[c.n] - 1.0;
+            th[c.n] = 0.0;
+            c.n += 1;
+            th[c.n] = u;
+          }
         }
       } else {
-        c.last_len = c.l;
+        if (!c.soft) c.last_len = c.l;
         st_worst = -1;
       }
       tot_it += it_sum;
@@ -1037,6 +1124,7 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
         tip[3 * bt + 2] = hd;
       }
       if (rho) rho[bt] = rho_last;
+      if (tiplen) tiplen[bt] = c.n == 0 ? 0.0 : (c.soft ? th[c.n] * c.l : c.last_len);
       if (iters) iters[bt] = it_sum;
       if (status) status[bt] = st_worst;
       {
@@ -1061,7 +1149,7 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
       if (traj)
         for (int i = 0; i < n_max; ++i) traj[bt * n_max + i] = (i < c.n) ? th[i] : 0.0;
     }
-    for (int i = 0; i < n_max; ++i) theta[(size_t)b * n_max + i] = (i < ntar) ? th[i] : 0.0;
+    for (int i = 0; i < n_max; ++i) theta[(size_t)b * n_max + i] = (i < c.n) ? th[i] : 0.0;
     if (stats) {
       stats[6 * b + 0] = tot_it;
       stats[6 * b + 1] = tot_bt;
@@ -1083,9 +1171,12 @@ int vo_rollout(int B, const int* inst_i, const double* inst_d, const double* spa
 
 /* Residual r [n], energy Pi (returned), contacts for one chain of n links.
  * contacts (nullable) receives up to cap rows (i, k, lam, x, y, nx, ny, pen). */
-double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, const int* kind,
-                     const double* obs, const double* prm, double last_len, const double* th,
-                     double* r, int* ncontact, double* contacts, int cap) {
+/* soft = 1: th and r hold n + 1 entries, the last being u (the tip link's length in
+ * link lengths), and tgt is its target (soft growth, see vo_rollout) */
+static double chain_eval_hook(int n, const double* d, const double* spam, int ns, int K,
+                              const int* kind, const double* obs, const double* prm,
+                              double last_len, int soft, double tgt, const double* th, double* r,
+                              int* ncontact, double* contacts, int cap) {
   vo_prm P;
   prm_from(prm, &P);
   gl_init();
@@ -1097,6 +1188,8 @@ double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, 
   c.Pm = Pp + n + 1;
   c.n = n;
   c.last_len = last_len > 0.0 ? last_len : c.l;
+  c.soft = soft;
+  c.tgt = tgt;
   vo_pose w;
   pose_alloc(&w, n + 1);
   int capc = 2 * n * (K > 0 ? K : 1) + 1;
@@ -1122,11 +1215,25 @@ double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, 
   return Pi;
 }
 
+double vo_chain_eval(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                     const double* obs, const double* prm, double last_len, const double* th,
+                     double* r, int* ncontact, double* contacts, int cap) {
+  return chain_eval_hook(n, d, spam, ns, K, kind, obs, prm, last_len, 0, 0.0, th, r, ncontact,
+                         contacts, cap);
+}
+
+double vo_chain_eval_soft(int n, const double* d, const double* spam, int ns, int K,
+                          const int* kind, const double* obs, const double* prm, double tgt,
+                          const double* x, double* r, int* ncontact, double* contacts, int cap) {
+  return chain_eval_hook(n, d, spam, ns, K, kind, obs, prm, 0.0, 1, tgt, x, r, ncontact,
+                         contacts, cap);
+}
+
 /* Solve one equilibrium from th (in place); returns status; info = iters, backtracks,
  * damping raises, rho, steps along negative curvature */
-int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, const int* kind,
-                   const double* obs, const double* prm, double last_len, double* th,
-                   double* info) {
+static int chain_solve_hook(int n, const double* d, const double* spam, int ns, int K,
+                            const int* kind, const double* obs, const double* prm,
+                            double last_len, int soft, double tgt, double* th, double* info) {
   vo_prm P;
   prm_from(prm, &P);
   gl_init();
@@ -1138,6 +1245,8 @@ int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, co
   c.Pm = Pp + n + 1;
   c.n = n;
   c.last_len = last_len > 0.0 ? last_len : c.l;
+  c.soft = soft;
+  c.tgt = tgt;
   vo_pose w;
   pose_alloc(&w, n + 1);
   vo_solve_stats st;
@@ -1152,6 +1261,18 @@ int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, co
   free(w.px);
   free(Pp);
   return st.status;
+}
+
+int vo_chain_solve(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                   const double* obs, const double* prm, double last_len, double* th,
+                   double* info) {
+  return chain_solve_hook(n, d, spam, ns, K, kind, obs, prm, last_len, 0, 0.0, th, info);
+}
+
+int vo_chain_solve_soft(int n, const double* d, const double* spam, int ns, int K,
+                        const int* kind, const double* obs, const double* prm, double tgt,
+                        double* x, double* info) {
+  return chain_solve_hook(n, d, spam, ns, K, kind, obs, prm, 0.0, 1, tgt, x, info);
 }
 
 /* G, dG/deps, int_0^eps G from the Chebyshev fit; info = G(0), eps_max, tail size */
@@ -1185,10 +1306,11 @@ void vo_joint_law(const double* d, double pp, double pm, const double* prm, int 
   for (int i = 0; i < n; ++i) joint_law(&c, 0, th[i], q ? &q[i] : NULL, E ? &E[i] : NULL);
 }
 
-/* analytic Hessian H [n][n] of Pi for one chain (for tests) */
-void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K, const int* kind,
-                      const double* obs, const double* prm, double last_len, const double* th,
-                      double* H) {
+/* analytic Hessian H [m][m] of Pi for one chain (m = n, or n + 1 for soft growth) */
+static void chain_hessian_hook(int n, const double* d, const double* spam, int ns, int K,
+                               const int* kind, const double* obs, const double* prm,
+                               double last_len, int soft, double tgt, const double* th,
+                               double* H) {
   vo_prm P;
   prm_from(prm, &P);
   gl_init();
@@ -1200,6 +1322,8 @@ void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K,
   c.Pm = Pp + n + 1;
   c.n = n;
   c.last_len = last_len > 0.0 ? last_len : c.l;
+  c.soft = soft;
+  c.tgt = tgt;
   vo_pose w;
   pose_alloc(&w, n + 1);
   int capc = 2 * n * (K > 0 ? K : 1) + 1, ncl = 0;
@@ -1211,6 +1335,18 @@ void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K,
   free(cl);
   free(w.px);
   free(Pp);
+}
+
+void vo_chain_hessian(int n, const double* d, const double* spam, int ns, int K, const int* kind,
+                      const double* obs, const double* prm, double last_len, const double* th,
+                      double* H) {
+  chain_hessian_hook(n, d, spam, ns, K, kind, obs, prm, last_len, 0, 0.0, th, H);
+}
+
+void vo_chain_hessian_soft(int n, const double* d, const double* spam, int ns, int K,
+                           const int* kind, const double* obs, const double* prm, double tgt,
+                           const double* x, double* H) {
+  chain_hessian_hook(n, d, spam, ns, K, kind, obs, prm, 0.0, 1, tgt, x, H);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1229,6 +1365,7 @@ int vo_gradient(int B, const int* inst_i, const double* inst_d, const double* sp
                 double* dP, double* ds0, double* ds1, double* loss) {
   vo_prm P;
   prm_from(prm, &P);
+  if (P.wg > 0.0) return -1; /* soft growth: the states also hold the tip length; not here */
   gl_init();
   for (int b = 0; b < B; ++b) gfit_get(inst_d[6 * b], prm);
   /* per-robot partial sums (robots may share sPAM records), added in robot order */

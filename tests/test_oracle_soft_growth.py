@@ -1,0 +1,120 @@
+"""Pins of the oracle's soft-growth mode (Sec. 4.1, Eq. 4: the tip link's length l_last is a
+variable of the minimisation, under a growth term whose target grows at a prescribed rate).
+
+The variables are (theta_0..theta_{n-1}, u), u = l_last / l, and the growth term is
+(wg/2) (l (tgt - u))^2.  Pinned here: the residual and Hessian in u are the derivatives of
+the energy; in free space soft growth reaches the hard-growth equilibria (the growth term
+is then satisfied exactly); a straight chain blocked head-on by a wall stays exactly
+straight while its tip length obeys the closed-form balance of the growth force and the
+penalty force; a blocked tip resumes once the growth force buckles the chain."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_15180_amd import workloads as W
+
+
+def _inst(n=12, spam=(), obs=(), kind=(), l=0.02, R=0.025, pv=4000.0):
+    return dict(n=n, d=(l, R, pv, 0.0, 0.0, 0.0), spam=np.asarray(spam, float).reshape(-1, 4),
+                kind=np.asarray(kind, np.int32), obs=np.asarray(obs, float).reshape(-1, 4))
+
+
+def test_soft_residual_and_hessian_are_the_energy_derivatives():
+    prm = O.params(wg=2000.0)
+    inst = _inst(spam=[(0.04, 0.16, 1.0, 9000.0), (0.1, 0.2, -1.0, 2000.0)],
+                 obs=[(0.2, 0.05, 0.04, 0.0), (0.12, -0.04, 0.05, 0.02)], kind=[0, 1])
+    rng = np.random.default_rng(1)
+    checked = 0
+    for _ in range(20):
+        x = np.concatenate([rng.normal(0, 0.15, 12), [rng.uniform(0.3, 1.0)]])
+        tgt = rng.uniform(0.3, 1.5)
+        Pi, r, cont = O.chain_eval_soft(inst, x, tgt, prm)
+        if not np.any(cont[:, 0] == 11):  # a contact on the tip link couples u to the joints
+            continue
+        h = 1e-6
+        E = np.eye(13)
+        fd_r = np.array([(O.chain_eval_soft(inst, x + h * e, tgt, prm)[0]
+                          - O.chain_eval_soft(inst, x - h * e, tgt, prm)[0]) / (2 * h) for e in E])
+        fd_H = np.array([(O.chain_eval_soft(inst, x + h * e, tgt, prm)[1]
+                          - O.chain_eval_soft(inst, x - h * e, tgt, prm)[1]) / (2 * h) for e in E])
+        H = O.chain_hessian_soft(inst, x, tgt, prm)
+        assert np.abs(fd_r - r).max() <= 1e-8 * np.abs(r).max()
+        assert np.abs(fd_H[12] - H[12]).max() <= 1e-7 * np.abs(H[12]).max()  # the u row
+        assert np.abs(fd_H - H).max() <= 1e-6 * np.abs(H).max()
+        np.testing.assert_allclose(H, H.T, rtol=0, atol=1e-14 * np.abs(H).max())
+        checked += 1
+    assert checked >= 5
+    # the growth term alone: r_u = -wg l^2 (tgt - u), H_uu = wg l^2
+    free = _inst()
+    Pi, r, cont = O.chain_eval_soft(free, np.r_[np.zeros(12), 0.25], 0.75, prm)
+    assert len(cont) == 0
+    assert r[12] == pytest.approx(-2000.0 * 0.02 ** 2 * 0.5, rel=1e-15)
+    assert Pi == pytest.approx(0.5 * 2000.0 * (0.02 * 0.5) ** 2, rel=1e-15)
+    assert O.chain_hessian_soft(free, np.r_[np.zeros(12), 0.25], 0.75, prm)[12, 12] == \
+        pytest.approx(2000.0 * 0.02 ** 2, rel=1e-15)
+
+
+def test_soft_growth_in_free_space_is_hard_growth():
+    w = W.pack([_inst(n=30, spam=[(0.1, 0.3, 1.0, 8000.0), (0.3, 0.42, -1.0, 3000.0)])], "free")
+    hard = O.rollout(w, traj=True)
+    for wg in (200.0, 5000.0):
+        soft = O.rollout(w, prm=O.params(wg=wg), traj=True)
+        assert np.all(soft["status"] == 0)
+        assert np.abs(soft["traj"] - hard["traj"]).max() <= 1e-12
+        assert np.abs(soft["tip"] - hard["tip"]).max() <= 1e-12
+        np.testing.assert_allclose(soft["tiplen"], 0.02, rtol=1e-12)
+
+
+WALL_X = 0.2  # the face of a box ahead of the base
+
+
+def _wall():
+    return _inst(n=24, obs=[(WALL_X + 0.1, 0.0, 0.1, 0.3)], kind=[1])
+
+
+def test_blocked_tip_stays_straight_and_balances_growth_against_contact():
+    """Straight chain, heading +x, tip pressed on the box face x = 0.2 by the growth force:
+    the force is along the chain, so every joint moment vanishes and theta stays exactly 0
+    (the straight state is stable under this small load); the tip disk alone penetrates, and
+    dPi/du = 0 gives u l (wg + k_c) = wg l tgt - k_c ((n - 1) l + R - x_wall)."""
+    wg, kc, l, R = 50.0, 1e4, 0.02, 0.025
+    w = W.pack([_wall()], "wall")
+    o = O.rollout(w, prm=O.params(wg=wg), traj=True)
+    T = o["status"].shape[1]
+    blocked = 0
+    for t in range(T):
+        u = o["tiplen"][0, t] / l
+        if u >= 1.0 - 1e-9 or o["tip"][0, t, 0] < WALL_X - R:
+            continue
+        th = o["traj"][0, t]
+        if np.any(th != 0.0):
+            break  # buckled: the closed form no longer applies
+        # links present: the tip x is (n - 1) l + u l on the axis
+        n = int(round((o["tip"][0, t, 0] - u * l) / l)) + 1
+        assert o["tip"][0, t, 1] == 0.0 and o["tip"][0, t, 2] == 0.0
+        tgt = t + 1.0 - (n - 1)  # the target at the step's last sub-step
+        u_cf = (wg * l * tgt - kc * ((n - 1) * l + R - WALL_X)) / (l * (wg + kc))
+        assert u == pytest.approx(u_cf, rel=1e-10, abs=1e-12), (t, n)
+        blocked += 1
+    assert blocked >= 5
+
+
+def test_blocked_tip_resumes_and_reaches_the_target_length():
+    """With the growth force rising while the tip is blocked, the chain buckles and grows on:
+    every step converges, the robot reaches its link count with a full tip link, and its
+    final state is a minimum of the hard-growth energy as well (the growth term is then
+    zero)."""
+    w = W.pack([_wall()], "wall")
+    for wg in (50.0, 500.0):
+        o = O.rollout(w, prm=O.params(wg=wg), traj=True)
+        assert np.all(o["status"] == 0)
+        assert o["tiplen"][0, -1] == pytest.approx(0.02, rel=1e-12)
+        assert np.count_nonzero(o["theta"][0]) > 0  # buckled
+        inst = _wall()
+        Pi, r, _ = O.chain_eval(inst, o["theta"][0])
+        Mmax = np.pi * 4000.0 * 0.025 ** 3
+        assert np.abs(r).max() <= 1e-9 * Mmax
+        assert np.linalg.eigvalsh(O.chain_hessian(inst, o["theta"][0]))[0] > 0.0
+    # a blocked stretch: some step ends with the tip link short of full length
+    o = O.rollout(w, prm=O.params(wg=50.0))
+    assert np.any(o["tiplen"][0] < 0.02 * (1 - 1e-6))
