@@ -62,7 +62,7 @@ extern "C" {
  * R_act = 17.18 mm, a = 1e-4 (Sec. 3.1); eps_crit = 0.01 (Sec. 3.2: fitted in the
  * paper, value not printed); k_c = 1e4 N/m; tol = 1e-10; pd_shift = 1e-8 /rad;
  * max_iter = 500; growth_substeps = 2; c_mu = 1 /rad; step_max = 0.05 rad;
- * armijo_c1 = 1e-4.
+ * armijo_c1 = 1e-4; growth_stiffness = 0 (hard growth).
  *
  * The descent (one growth sub-step): at each iterate the exact Hessian H of the energy
  * is factorised as H + mu I = U D U^T by a Riccati sweep that eliminates the joints from
@@ -84,6 +84,20 @@ typedef struct vine_params {
   double armijo_c1;      /* sufficient-decrease constant of the line search */
   double pd_shift;       /* delta / M_max (1/rad): a stationary state is accepted when
                             H + delta I is positive definite */
+  double growth_stiffness; /* w_g (N/m), Eq. 4's growth term.  0: hard growth, each step
+                            appends a link whose length is prescribed (l s / S at sub-step
+                            s).  > 0: soft growth, the tip link's length u l is a variable
+                            of the minimisation under the term (w_g/2) (l (tgt - u))^2,
+                            whose target tgt rises by one link length per step
+                            (tgt = t + s/S - (n - 1) at sub-step s of step t, at most 1
+                            once the robot has its target link count); a link is appended
+                            only when the tip link is full (u >= 1, its excess starting the
+                            new one), a tip link grown longer than a link within a sub-step
+                            is split and the sub-step solved again, and the robot is done
+                            with its target link count and a full tip link.  A blocked
+                            tip thus stops while the growth force builds (Sec. 4.1).  The
+                            tip length's residual is in N m per link length, like the
+                            joints' moments, and the step cap applies to the joints */
   int32_t max_iter;      /* iterations per equilibrium solve */
   int32_t growth_substeps; /* sub-steps in which an appended link reaches full length */
   int32_t reserved;
@@ -149,9 +163,11 @@ typedef enum vine_field {
   VINE_F_CKPT = 14,    /* double [B][C][N] checkpoints: row q is the state before step
                           q ckpt_every (joint angles, 0 beyond the link count then),
                           C = ceil(T / ckpt_every) */
-  VINE_F_TIME = 15     /* double [B]       seconds each robot's workgroup spent in rollout
+  VINE_F_TIME = 15,    /* double [B]       seconds each robot's workgroup spent in rollout
                           launches since the reset (device wall clock): its rollout latency
                           once it runs */
+  VINE_F_TIPLEN = 16   /* double [B][T]    length of the tip link after each step (m): l
+                          in hard growth; the variable u l in soft growth */
 } vine_field;
 
 typedef struct vine_sim vine_sim;
@@ -245,6 +261,8 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_e
  *                 singular or had more contacts than the contact list holds (that
  *                 step's term is then left out); bit 1 set when a weighted step had
  *                 not converged in the rollout (VINE_ST_* > 0).
+ * Soft growth (growth_stiffness > 0) gives VINE_ESTATE: its states include the tip
+ * length, which this adjoint does not differentiate.
  * Asynchronous on stream.  Errors: VINE_EINVAL (null pointers), VINE_ESTATE,
  * VINE_ENOMEM, VINE_EDEVICE. */
 int32_t vine_sim_grad(vine_sim* h, const double* goal, const double* step_weights,

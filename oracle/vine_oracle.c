@@ -501,6 +501,8 @@ typedef struct {
   int soft;              /* soft growth: the variables are (theta_0..theta_{n-1}, u), the
                             tip link's length u l, with the growth term (wg/2)(l (tgt - u))^2 */
   double tgt;            /* soft growth: the tip link's target length in link lengths */
+  int frozen;            /* soft growth: u sits on its bound u = 0 with dPi/du > 0 and is
+                            held there (the system is the joints' alone) */
   double arm, Mmax;
   const double *Pp, *Pm; /* pressure-weighted sPAM coverage per joint, +/- side */
   int K;
@@ -659,10 +661,11 @@ static double joint_dq(const vo_chain* c, int j, double th) {
 static void chain_hessian(const vo_chain* c, const double* th, const vo_contact* cl, int ncl,
                           const vo_pose* w, double* H, double* a, double* b, double* u) {
   int n = c->n;
-  const int m = n + c->soft; /* soft growth: row and column n belong to u */
+  const int uvar = c->soft && !c->frozen;
+  const int m = n + uvar; /* soft growth: row and column n belong to u */
   memset(H, 0, sizeof(double) * (size_t)m * m);
   for (int j = 0; j < n; ++j) H[j * m + j] = joint_dq(c, j, th[j]);
-  if (c->soft) H[n * m + n] = c->P->wg * c->l * c->l;
+  if (uvar) H[n * m + n] = c->P->wg * c->l * c->l;
   for (int e = 0; e < ncl; ++e) {
     const vo_contact* q = &cl[e];
     int i = q->i;
@@ -680,7 +683,7 @@ static void chain_hessian(const vo_chain* c, const double* th, const vo_contact*
         int mx = j > k ? j : k;
         H[j * m + k] += kc * a[j] * a[k] - lk * b[j] * b[k] + q->lam * (nxx - u[mx]);
       }
-    if (c->soft && i == n - 1) {
+    if (uvar && i == n - 1) {
       /* soft growth: x moves by f l t per unit of u, t the tip link's direction, and t
        * turns with every joint (dt/dtheta_j = z x t); with n_t = n.t, tau_t = tau.t and
        * nz = n.(z x t):
@@ -801,11 +804,13 @@ typedef struct {
  *    decrease of the full step is below 1e-12 M_max (round-off level of Pi).
  * status: 0 converged, 1 iteration limit, 2 no descent / line search failure,
  * 4 non-finite state. */
-static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_pose* w) {
+static void chain_solve(const vo_chain* c0, double* th, vo_solve_stats* st, vo_pose* w) {
+  vo_chain cc = *c0;
+  vo_chain* c = &cc;
   const vo_prm* P = c->P;
-  const int nj = c->n;       /* joints; the step cap applies to them */
-  const int n = nj + c->soft; /* variables: soft growth adds u = th[nj] */
-  size_t nn = (size_t)n;
+  const int nj = c->n;        /* joints; the step cap applies to them */
+  const int nv = nj + c->soft; /* values: soft growth adds u = th[nj] (the buffers' size) */
+  size_t nn = (size_t)nv;
   double* buf = (double*)malloc(sizeof(double) * (2 * nn * nn + nn * (nn + 1) + 11 * nn + 16));
   double* H = buf;
   double* A = H + nn * nn;
@@ -820,13 +825,17 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
   double* hu = hb + nn;
   double* piv = hu + nn;
   double* Hd = piv + nn;
-  int capc = 2 * n * (c->K > 0 ? c->K : 1) + 1, ncl = 0;
+  int capc = 2 * nv * (c->K > 0 ? c->K : 1) + 1, ncl = 0;
   vo_contact* cl = (vo_contact*)malloc(sizeof(vo_contact) * (size_t)capc);
   const double delta = P->pd_shift * c->Mmax;
   memset(st, 0, sizeof(*st));
   st->status = 1;
   double Pi = chain_eval(c, th, r, 1, cl, capc, &ncl, w);
   for (int it = 0; it <= P->max_iter; ++it) {
+    /* soft growth: u >= 0; on the bound with dPi/du > 0 it is held there and the
+     * iteration works on the joints alone */
+    c->frozen = c->soft && th[nj] <= 0.0 && r[nj] > 0.0;
+    const int n = nj + (c->soft && !c->frozen); /* this iteration's variables */
     double rmax = 0.0;
     for (int j = 0; j < n; ++j) rmax = fmax(rmax, fabs(r[j]));
     st->rho = rmax / c->Mmax;
@@ -839,7 +848,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
       /* Hessian by central differences of r (cross-check mode) */
       double h = P->fd_h;
       for (int j = 0; j < n; ++j) {
-        memcpy(tt, th, sizeof(double) * nn);
+        memcpy(tt, th, sizeof(double) * nn); /* (u, when held, stays) */
         tt[j] = th[j] + h;
         chain_eval(c, tt, rp, 0, NULL, 0, NULL, w);
         tt[j] = th[j] - h;
@@ -935,9 +944,23 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
     int accepted = 0;
     int skip = (-(slope + 0.5 * curv) < 1e-12 * c->Mmax);
     for (int ls = 0; ls < 40; ++ls) {
-      for (int i = 0; i < n; ++i) tt[i] = th[i] + alpha * d[i];
+      for (int i = 0; i < nj; ++i) tt[i] = th[i] + alpha * d[i];
+      /* soft growth: a trial tip length below zero is projected onto u = 0, and the
+       * predicted change then takes the tip length's actual move */
+      double lin = alpha * slope;
+      if (c->soft) {
+        tt[nj] = th[nj];
+        if (!c->frozen) {
+          const double ut = th[nj] + alpha * d[nj];
+          tt[nj] = ut;
+          if (ut < 0.0) {
+            tt[nj] = 0.0;
+            lin += r[nj] * (-th[nj] - alpha * d[nj]);
+          }
+        }
+      }
       Pn = chain_eval(c, tt, rm, 1, cl, capc, &ncl, w);
-      if (skip || Pn <= Pi + P->c1 * (alpha * slope + 0.5 * alpha * alpha * curv)) {
+      if (skip || Pn <= Pi + P->c1 * (lin + 0.5 * alpha * alpha * curv)) {
         accepted = 1;
         break;
       }
@@ -955,6 +978,7 @@ static void chain_solve(const vo_chain* c, double* th, vo_solve_stats* st, vo_po
     memcpy(r, rm, sizeof(double) * nn);
     Pi = Pn;
   }
+  c->frozen = 0;
   free(cl);
   free(buf);
 }

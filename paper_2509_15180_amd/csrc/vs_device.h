@@ -53,6 +53,7 @@ struct WrTable {
 struct KParams {
   double epsc, kc, tol, c_mu, step_max, c1, Ract;
   double pd_shift;    // delta / M_max: converged states have H + delta I positive definite
+  double wg;          // growth stiffness (N/m): 0 hard growth, > 0 soft growth
   int max_iter, substeps;
 };
 
@@ -95,6 +96,7 @@ struct KData {
   double* theta;      // robot b: [ii[b][kThetaOff], + n_target)
   int* ncur;          // [B]
   int* tcur;          // [B] steps recorded so far
+  double* ulast;      // [B] soft growth: the tip link's length in link lengths
   // per-step records, robot b at [ii[b][kRecOff], + ii[b][kRecCap])...
   double* tip;        // ...times 3 (x, y, heading)
   double* rho;
@@ -103,6 +105,7 @@ struct KData {
   int* ncont;
   unsigned long long* chash;
   double* maxpen;
+  double* tiplen;     // the tip link's length
   double* traj;       // [B][n_rec][N] or null: joint angles after every rec_every-th step
   int rec_every, n_rec;  // (row t / rec_every after step t; the last step always)
   double* ckpt;       // [B][n_ckpt][N] or null: the state before every ckpt_every-th step

@@ -386,6 +386,8 @@ struct vine_sim {
   int* ncont = nullptr;
   unsigned long long* chash = nullptr;
   double* maxpen = nullptr;
+  double* tiplen = nullptr;  // per step: the tip link's length
+  double* ulast = nullptr;   // [B] soft growth: the tip link's length in link lengths
   double* traj = nullptr;    // [B][n_rec][N], allocated for rec_every on first use
   int rec_every = 0, n_rec = 0;
   double* ckpt = nullptr;    // [B][n_ckpt][N], allocated for ckpt_every on first use
@@ -401,7 +403,8 @@ struct vine_sim {
   struct Seg {
     double *theta = nullptr, *tip = nullptr, *rho = nullptr, *maxpen = nullptr,
            *traj = nullptr, *jevals = nullptr, *nsolves = nullptr, *negsteps = nullptr,
-           *cycles = nullptr, *wtime = nullptr, *gsums = nullptr, *gloss = nullptr;
+           *cycles = nullptr, *wtime = nullptr, *gsums = nullptr, *gloss = nullptr,
+           *tiplen = nullptr, *ulast = nullptr;
     int *ncur = nullptr, *tcur = nullptr, *iters = nullptr, *status = nullptr, *ncont = nullptr,
         *gstat = nullptr, *ii = nullptr;
     unsigned long long* chash = nullptr;
@@ -450,7 +453,7 @@ void free_seg(vine_sim* h) {
   vine_sim::Seg& g = h->seg;
   void* ptrs[] = {g.theta, g.tip, g.rho, g.maxpen, g.traj, g.jevals, g.nsolves, g.negsteps,
                   g.cycles, g.wtime, g.gsums, g.gloss, g.ncur, g.tcur, g.iters, g.status, g.ncont,
-                  g.gstat, g.ii, g.chash};
+                  g.gstat, g.ii, g.chash, g.tiplen, g.ulast};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   g = vine_sim::Seg();
@@ -468,7 +471,7 @@ void free_all(vine_sim* h) {
   void* ptrs[] = {h->order, h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->tables, h->wr, h->theta,
                   h->ncur, h->tcur, h->tip, h->rho, h->iters, h->status, h->ncont, h->chash,
                   h->maxpen, h->traj, h->ckpt, h->jevals, h->nsolves, h->negsteps, h->cycles,
-                  h->wtime,
+                  h->wtime, h->tiplen, h->ulast,
                   h->trace, h->trace_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -489,6 +492,7 @@ vs::KParams kparams(const vine_params& p) {
   k.c1 = p.armijo_c1;
   k.Ract = p.R_act;
   k.pd_shift = p.pd_shift;
+  k.wg = p.growth_stiffness;
   k.max_iter = p.max_iter;
   k.substeps = p.growth_substeps;
   return k;
@@ -521,6 +525,8 @@ vs::KData kdata(vine_sim* h) {
   D.ncont = h->ncont;
   D.chash = h->chash;
   D.maxpen = h->maxpen;
+  D.tiplen = h->tiplen;
+  D.ulast = h->ulast;
   D.traj = nullptr;  // set by the calls that record (advance)
   D.rec_every = h->rec_every;
   D.n_rec = h->n_rec;
@@ -602,6 +608,7 @@ void vine_params_default(vine_params* p) {
   p->step_max = 0.05;
   p->armijo_c1 = 1e-4;
   p->pd_shift = 1e-8;
+  p->growth_stiffness = 0.0;
   p->max_iter = 500;
   p->growth_substeps = 2;
   p->reserved = 0;
@@ -618,7 +625,8 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
       !std::isfinite(p.a_corr) || !(p.eps_crit > 0.0 && p.eps_crit < 1.0) || !finite_pos(p.k_c) ||
       !finite_pos(p.tol) || !(p.c_mu >= 0.0) || !std::isfinite(p.c_mu) ||
       !finite_pos(p.step_max) || !(p.armijo_c1 > 0.0 && p.armijo_c1 < 1.0) ||
-      !finite_pos(p.pd_shift) || p.max_iter < 0 || p.growth_substeps < 1)
+      !finite_pos(p.pd_shift) || p.max_iter < 0 || p.growth_substeps < 1 ||
+      !(p.growth_stiffness >= 0.0) || !std::isfinite(p.growth_stiffness))
     return fail(nullptr, VINE_EINVAL, "invalid vine_params");
   int N = 0;
   for (int b = 0; b < n_inst; ++b) {
@@ -748,6 +756,8 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
   A(dalloc(&h->ncont, B * TT));
   A(dalloc(&h->chash, B * TT));
   A(dalloc(&h->maxpen, B * TT));
+  A(dalloc(&h->tiplen, B * TT));
+  A(dalloc(&h->ulast, B));
   A(dalloc(&h->jevals, B));
   A(dalloc(&h->nsolves, B));
   A(dalloc(&h->negsteps, B));
@@ -1020,6 +1030,8 @@ static hipError_t ensure_seg(vine_sim* h) {
   A(dalloc(&g.ncont, B * C));
   A(dalloc(&g.chash, B * C));
   A(dalloc(&g.maxpen, B * C));
+  A(dalloc(&g.tiplen, B * C));
+  A(dalloc(&g.ulast, B));
   A(dalloc(&g.traj, B * C * N));
   A(dalloc(&g.jevals, B));
   A(dalloc(&g.nsolves, B));
@@ -1057,6 +1069,8 @@ static bool seg_view(void* base, size_t bytes, size_t B, size_t N, size_t C, vin
   take(&g->ncont, B * C);
   take(&g->chash, B * C);
   take(&g->maxpen, B * C);
+  take(&g->tiplen, B * C);
+  take(&g->ulast, B);
   take(&g->traj, B * C * N);
   take(&g->jevals, B);
   take(&g->nsolves, B);
@@ -1079,6 +1093,8 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   if (!goal || !loss || (h->S > 0 && (!dL_dP || !dL_ds_start || !dL_ds_end)))
     return fail(h, VINE_EINVAL, "null goal, loss or gradient pointer");
+  if (h->prm.growth_stiffness > 0.0)
+    return fail(h, VINE_ESTATE, "the adjoint covers hard growth only (growth_stiffness = 0)");
   const bool full_traj = h->traj_valid && h->traj_all && h->rec_every == 1;
   const bool from_ckpt = h->ckpt && h->ckpt_any && h->ckpt_all;
   if (step_weights && !full_traj && !from_ckpt)
@@ -1119,6 +1135,8 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
     Dseg.ncont = g->ncont;
     Dseg.chash = g->chash;
     Dseg.maxpen = g->maxpen;
+    Dseg.tiplen = g->tiplen;
+    Dseg.ulast = g->ulast;
     Dseg.traj = g->traj;
     Dseg.rec_every = 1;
     Dseg.n_rec = h->ckpt_every;
@@ -1229,6 +1247,7 @@ int64_t vine_sim_field_bytes(const vine_sim* h, int32_t field) {
     case VINE_F_NEGSTEPS: return 8 * B;
     case VINE_F_TIME: return 8 * B;
     case VINE_F_CKPT: return 8 * B * h->n_ckpt * N;
+    case VINE_F_TIPLEN: return 8 * B * T;
     default: return 0;
   }
 }
@@ -1261,6 +1280,7 @@ int32_t vine_sim_read(const vine_sim* hc, int32_t field, void* dst, int32_t dst_
       if (!h->ckpt_any) return fail(h, VINE_ESTATE, "no checkpoints were written");
       src = h->ckpt;
       break;
+    case VINE_F_TIPLEN: src = h->tiplen; break;
     default: return fail(h, VINE_EINVAL, "unknown field");
   }
   size_t bytes = (size_t)vine_sim_field_bytes(h, field);
@@ -1432,9 +1452,9 @@ hipError_t halloc(T** p, size_t count) {  // pinned host staging
   return hipHostMalloc((void**)p, sizeof(T) * (count > 0 ? count : 1), hipHostMallocDefault);
 }
 
-constexpr int64_t kRowBytes = 8 + 24 + 8 + 4 + 4 + 4 + 8 + 8 + 16;  // theta, records, coverage
+constexpr int64_t kRowBytes = 8 + 24 + 8 + 4 + 4 + 4 + 8 + 8 + 8 + 16;  // theta, records, coverage
 constexpr int64_t kObsBytes = 4 + 32;
-constexpr int64_t kSlotBytes = 4 * vs::kII + 48 + 8 + 40 + 4;       // ii, dd, counts, counters, order
+constexpr int64_t kSlotBytes = 4 * vs::kII + 48 + 8 + 8 + 40 + 4;  // ii, dd, counts, tip length, counters, order
 
 }  // namespace
 
@@ -1678,8 +1698,8 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
   s->busy.assign(slots, 0);
   // replace the slab's per-robot arrays by pools of the budget's size
   void* old[] = {h->ii, h->dd, h->cover, h->spam, h->okind, h->obs, h->theta, h->ncur, h->tcur,
-                 h->tip, h->rho, h->iters, h->status, h->ncont, h->chash, h->maxpen, h->jevals,
-                 h->nsolves, h->negsteps, h->cycles, h->wtime, h->order};
+                 h->tip, h->rho, h->iters, h->status, h->ncont, h->chash, h->maxpen, h->tiplen,
+                 h->ulast, h->jevals, h->nsolves, h->negsteps, h->cycles, h->wtime, h->order};
   for (void* p : old) (void)hipFree(p);
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) {
@@ -1702,6 +1722,8 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
   A(dalloc(&h->ncont, (size_t)R));
   A(dalloc(&h->chash, (size_t)R));
   A(dalloc(&h->maxpen, (size_t)R));
+  A(dalloc(&h->tiplen, (size_t)R));
+  A(dalloc(&h->ulast, B));
   A(dalloc(&h->jevals, B));
   A(dalloc(&h->nsolves, B));
   A(dalloc(&h->negsteps, B));

@@ -31,6 +31,7 @@
 namespace vs {
 
 constexpr int kMaxC = 128;
+constexpr double kFull = 1.0 - 1e-12;  // soft growth: a tip link at full length
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
@@ -203,6 +204,10 @@ struct Ctx {
   int* trace_n;
   int trace_cap;
   double l, R, Mmax, arm, bx, by, bpsi, last_len;
+  // soft growth: the tip link's length u l is a variable (S.u), under the growth term
+  // (wg/2) (l (tgt - u))^2 of Eq. 4 with this sub-step's target tgt (link lengths)
+  bool soft;
+  double tgt;
   const SpamTable* tab;
   const WrTable* wr;
   // this robot's obstacles in global memory (copied into LDS, see stage_resident)
@@ -337,6 +342,11 @@ struct Smem {
   double jevals, nsolves, negsteps;  // work counters (lane 0 updates)
   int cmd, cmd_seq, eval_n;  // solver wave -> helper wave: 1 = obstacle phase, 2 = end
   double eval_last;
+  // soft growth (the variable u after the joints): the accepted u, the u an evaluation
+  // uses, dPi/du there, its coupling to the joints (H_ju = cu . B_j) and diagonal H_uu, the
+  // right-hand side, step and pivot of the last sweep
+  double u, ue, ru, cu0, cu1, cu2, huu, bu, du, Du;
+  int uvar;  // the tip length is a variable of this iteration (not held on u = 0)
 };
 
 // Barrier of the solver's own wave.  A wave's LDS operations complete in the order it
@@ -529,6 +539,9 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   const int n = c.n;
   if (__builtin_amdgcn_readfirstlane(S.res_ok) == 0) stage_resident(S, c);
   if (lane == 0) S.jevals += n;
+  // the tip link's length: prescribed (hard growth) or u l (soft growth, u = S.ue)
+  const double ue = c.soft ? S.ue : 0.0;
+  const double last = c.soft ? ue * c.l : c.last_len;
   double cphi = c.bpsi, cx = c.bx, cy = c.by;
   for (int base = 0; base < n; base += kWave) {
     int j = base + lane;
@@ -536,7 +549,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     double phi = wscan_incl(on ? th[j] : 0.0, lane) + cphi;
     double sj, cj;
     sincos(phi, &sj, &cj);
-    double L = (j == n - 1) ? c.last_len : c.l;
+    double L = (j == n - 1) ? last : c.l;
     double ex = on ? L * cj : 0.0, ey = on ? L * sj : 0.0;
     double sx = wscan_incl(ex, lane) + cx, sy = wscan_incl(ey, lane) + cy;
     if (on) {
@@ -556,7 +569,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   if constexpr (SM::kHelper) {
     if (lane == 0) {
       S.eval_n = n;
-      S.eval_last = c.last_len;
+      S.eval_last = last;
       S.cmd = 1;
       S.cmd_seq += 1;
     }
@@ -580,7 +593,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   if constexpr (SM::kHelper) {
     __syncthreads();  // the helper wave's contacts and contact sums are in LDS
   } else {
-    obstacle_phase(S, c, n, c.last_len, lane);
+    obstacle_phase(S, c, n, last, lane);
     bsync<SM>();
   }
   const int nc = S.ncl;
@@ -601,8 +614,25 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
   }
   double pen2 = 0.0;
   for (int e = lane; e < nc; e += kWave) pen2 += 0.5 * c.P.kc * S.cpen[e] * S.cpen[e];
+  double grow = 0.0;
+  if (c.soft) {
+    // dPi/du: the growth term, and each contact on the tip link, whose disk at fraction f
+    // of the link moves by f l t per unit of u
+    const double gap = c.l * (c.tgt - ue);
+    grow = 0.5 * c.P.wg * gap * gap;
+    const double tx = S.tx[n - 1], ty = S.ty[n - 1], px = S.px[n - 1], py = S.py[n - 1];
+    double acc = 0.0;
+    for (int e = lane; e < nc; e += kWave) {
+      if (S.ci[e] != n - 1) continue;
+      const double sd = (S.cxx[e] - px) * tx + (S.cxy[e] - py) * ty;
+      const double f = sd > 0.75 * last ? 1.0 : 0.5;
+      acc += S.cl[e] * f * (S.cnx[e] * tx + S.cny[e] * ty);
+    }
+    acc = wsum(acc);
+    if (lane == 0) S.ru = -c.P.wg * c.l * gap - c.l * acc;
+  }
   bsync<SM>();
-  return wsum(Esum) + wsum(pen2);
+  return wsum(Esum) + wsum(pen2) + grow;
 }
 
 // Per-iteration set-up of the Newton system at the state last evaluated: the joint
@@ -634,6 +664,39 @@ __device__ void newton_setup(SM& S, const Ctx& c) {
     if (j < n) S.cg[j] = c.l * (S.tx[j] * (sx - fx) + S.ty[j] * (sy - fy)) + q;
     cfx = __shfl(sx, 0, kWave);
     cfy = __shfl(sy, 0, kWave);
+  }
+  if (c.soft && __builtin_amdgcn_readfirstlane(S.uvar)) {
+    // soft growth: the tip length's row of the Hessian.  A contact on the tip link at
+    // fraction f, with n_t = n.t, tau_t = tau.t and nz = n.(z x t) for the link direction
+    // t (which turns with every joint), adds (f l)^2 (k_c n_t^2 - lam kappa tau_t^2) to
+    // H_uu and f l (k_c n_t a - lam kappa tau_t b - lam nz e_0) to the coupling vector cu
+    // (H_ju = cu . B_j, a and b the contact's vectors of the chain form).
+    const double tx = S.tx[n - 1], ty = S.ty[n - 1], px = S.px[n - 1], py = S.py[n - 1];
+    const double last = S.ue * c.l;
+    double h = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0;
+    for (int e = lane; e < nc; e += kWave) {
+      if (S.ci[e] != n - 1) continue;
+      const double x = S.cxx[e], y = S.cxy[e], nx = S.cnx[e], ny = S.cny[e];
+      const double sd = (x - px) * tx + (y - py) * ty;
+      const double fl = (sd > 0.75 * last ? 1.0 : 0.5) * c.l;
+      const double lam = S.cl[e], lk = lam * S.ckap[e], kc = c.P.kc;
+      const double nt = nx * tx + ny * ty, taut = -ny * tx + nx * ty, nz = -nx * ty + ny * tx;
+      h += fl * fl * (kc * nt * nt - lk * taut * taut);
+      const double wa = kc * nt, wb = lk * taut;
+      k0 += fl * (wa * (ny * x - nx * y) - wb * (nx * x + ny * y) - lam * nz);
+      k1 += fl * (wa * -ny - wb * -nx);
+      k2 += fl * (wa * nx - wb * -ny);
+    }
+    h = wsum(h);
+    k0 = wsum(k0);
+    k1 = wsum(k1);
+    k2 = wsum(k2);
+    if (lane == 0) {
+      S.huu = c.P.wg * c.l * c.l + h;
+      S.cu0 = k0;
+      S.cu1 = k1;
+      S.cu2 = k2;
+    }
   }
   bsync<SM>();
 }
@@ -669,6 +732,7 @@ constexpr int kSweepIndef = 2;  // a negative pivot: H + mu I is indefinite
 template <class SM>
 __device__ int chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rhs) {
   const int lane = threadIdx.x, n = c.n, nc = S.ncl;
+  const bool uv = c.soft && __builtin_amdgcn_readfirstlane(S.uvar);
   double* s00 = S.sw0;
   double* s01 = S.sw1;
   double* s02 = S.sw2;
@@ -707,6 +771,25 @@ __device__ int chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rhs
     // pivots after the walk (a vanishing pivot makes the remaining values non-finite).
     double A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0;  // symmetric 00 01 02 11 12 22
     double z0 = 0, z1 = 0, z2 = 0;
+    double iDu = 0.0;
+    if (uv) {
+      // soft growth: the tip length is eliminated first (pivot H_uu + mu); its coupling
+      // H_ju = cu . B_j to every joint leaves A = -cu cu^T / D_u and z = cu b_u / D_u
+      const double Du = S.huu + mu;
+      iDu = rcp_nr(Du);
+      const double k0 = S.cu0, k1 = S.cu1, k2 = S.cu2;
+      const double g0 = k0 * iDu, g1 = k1 * iDu, g2 = k2 * iDu, wu = S.bu * iDu;
+      A0 = -k0 * g0;
+      A1 = -k0 * g1;
+      A2 = -k0 * g2;
+      A3 = -k1 * g1;
+      A4 = -k1 * g2;
+      A5 = -k2 * g2;
+      z0 = k0 * wu;
+      z1 = k1 * wu;
+      z2 = k2 * wu;
+      S.Du = Du;
+    }
     struct In {
       double s0, s1, s2, s3, s4, s5, B1, B2, d, r;
     };
@@ -778,6 +861,8 @@ __device__ int chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rhs
       ob = load_out(k + 3);
     }
     if (k < n) outward(oa, k);
+    // soft growth: d_u = (b_u - cu . V_{n-1}) / D_u
+    if (uv) S.du = (S.bu - fma(S.cu2, V2, fma(S.cu1, V1, S.cu0 * V0))) * iDu;
   }
   bsync<SM>();
   // the pivots D = (q' + mu) + B^T A B, rounded as in the walk
@@ -787,6 +872,12 @@ __device__ int chain_solve_seq(SM& S, const Ctx& c, double mu, const double* rhs
     fin = fin && isfinite(D) && fabs(D) > 1e-14 * (fabs(dk) + fabs(bh));
     pos = pos && D > 0.0;
     dfin = dfin && isfinite(S.d[j]);
+  }
+  if (uv) {
+    const double Du = S.Du;
+    fin = fin && isfinite(Du) && Du != 0.0;
+    pos = pos && Du > 0.0;
+    dfin = dfin && isfinite(S.du);
   }
   if (!__all(fin)) return kSweepFail;
   if (!__all(pos)) return kSweepIndef;
@@ -819,16 +910,27 @@ __device__ double neg_curv_dir(SM& S, const Ctx& c, double mu) {
       bk = oi;
     }
   }
+  // soft growth: the tip length's pivot, eliminated first, comes after every joint
+  const bool uv = c.soft && __builtin_amdgcn_readfirstlane(S.uvar);
+  if (uv && S.Du < best) {
+    best = S.Du;
+    bk = n;
+  }
   bsync<SM>();
   if (lane == 0) {
-    double V0 = 1.0, V1 = S.px[bk], V2 = S.py[bk];
-    S.d[bk] = 1.0;
-    for (int j = bk + 1; j < n; ++j) {
-      const double x = -fma(S.sw2[j], V2, fma(S.sw1[j], V1, S.sw0[j] * V0));
-      V0 += x;
-      V1 = fma(S.px[j], x, V1);
-      V2 = fma(S.py[j], x, V2);
-      S.d[j] = x;
+    if (bk == n) {  // along the tip length alone
+      S.du = 1.0;
+    } else {
+      double V0 = 1.0, V1 = S.px[bk], V2 = S.py[bk];
+      S.d[bk] = 1.0;
+      for (int j = bk + 1; j < n; ++j) {
+        const double x = -fma(S.sw2[j], V2, fma(S.sw1[j], V1, S.sw0[j] * V0));
+        V0 += x;
+        V1 = fma(S.px[j], x, V1);
+        V2 = fma(S.py[j], x, V2);
+        S.d[j] = x;
+      }
+      if (uv) S.du = -fma(S.cu2, V2, fma(S.cu1, V1, S.cu0 * V0)) / S.Du;
     }
   }
   bsync<SM>();
@@ -853,6 +955,8 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
   const KParams& P = c.P;
   const double delta = P.pd_shift * c.Mmax;
   int status = 1;
+  if (c.soft && lane == 0) S.ue = S.u;
+  bsync<SM>();
   double Pi = evaluate(S, c, S.th, true);
   for (int it = 0; it <= P.max_iter; ++it) {
     if (S.overflow) {
@@ -866,6 +970,14 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
       fin = fin && isfinite(S.r[j]);
     }
     rm = wmax(rm);
+    // soft growth: u >= 0; on the bound with dPi/du > 0 it is held there and the
+    // iteration works on the joints alone
+    const bool uv = c.soft && !(S.u <= 0.0 && S.ru > 0.0);
+    if (uv) {  // the tip length's residual (N m per link length, like the moments)
+      rm = fmax(rm, fabs(S.ru));
+      fin = fin && isfinite(S.ru);
+    }
+    if (c.soft && lane == 0) S.uvar = uv;
     rho = rm / c.Mmax;
     if (!__all(fin) || !isfinite(Pi)) {
       status = 4;
@@ -874,6 +986,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     const bool small = rho <= P.tol;
     newton_setup(S, c);
     for (int j = lane; j < n; j += kWave) S.b[j] = -S.r[j];
+    if (c.soft && lane == 0) S.bu = -S.ru;
     bsync<SM>();
     double mu = fmax(P.c_mu * rm, delta), slope = 0.0, curv = 0.0;
     int mode = 0;  // 1 Newton step, 2 curvature step, 3 converged
@@ -890,6 +1003,7 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
         double s = 0.0;
         for (int j = lane; j < n; j += kWave) s += S.r[j] * S.d[j];
         slope = wsum(s);
+        if (uv) slope += S.ru * S.du;
         if (slope < 0.0) {
           mode = 1;
           break;
@@ -908,9 +1022,20 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
       rv = wsum(rv);
       vv = wsum(vv);
       v1 = wsum(v1);
+      if (uv) {
+        const double du = S.du;
+        rv += S.ru * du;
+        vv += du * du;
+        v1 += fabs(du);
+        if (vm == 0.0) vm = fabs(du);  // curvature along the tip length alone
+      }
       const bool tie = fabs(rv) <= P.tol * c.Mmax * v1;
       const double s = (tie ? 1.0 : (rv > 0.0 ? -1.0 : 1.0)) * P.step_max / vm;
       for (int j = lane; j < n; j += kWave) S.d[j] *= s;
+      if (uv) {
+        bsync<SM>();
+        if (lane == 0) S.du *= s;
+      }
       slope = s * rv;
       curv = (Dk - mu * vv) * (s * s);
       if (lane == 0) S.negsteps += 1.0;
@@ -931,9 +1056,13 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
       double dm = 0.0;
       for (int j = lane; j < n; j += kWave) dm = fmax(dm, fabs(S.d[j]));
       dm = wmax(dm);
-      if (dm > P.step_max) {
+      if (dm > P.step_max) {  // the joints' step; the tip length's scales with it
         double f = P.step_max / dm;
         for (int j = lane; j < n; j += kWave) S.d[j] *= f;
+        if (uv) {
+          bsync<SM>();
+          if (lane == 0) S.du *= f;
+        }
         slope *= f;
       }
     }
@@ -944,9 +1073,23 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
     bool acc = false;
     for (int ls = 0; ls < 40; ++ls) {
       for (int j = lane; j < n; j += kWave) tt[j] = S.th[j] + alpha * S.d[j];
+      // soft growth: a trial tip length below zero is projected onto u = 0, and the
+      // predicted change then takes the tip length's actual move
+      double lin = alpha * slope;
+      if (c.soft) {
+        double ut = S.u;
+        if (uv) {
+          ut = S.u + alpha * S.du;
+          if (ut < 0.0) {
+            lin += S.ru * (-S.u - alpha * S.du);
+            ut = 0.0;
+          }
+        }
+        if (lane == 0) S.ue = ut;
+      }
       bsync<SM>();
       Pn = evaluate(S, c, tt, true);
-      if (skip || Pn <= Pi + P.c1 * (alpha * slope + 0.5 * alpha * alpha * curv)) {
+      if (skip || Pn <= Pi + P.c1 * (lin + 0.5 * alpha * alpha * curv)) {
         acc = true;
         break;
       }
@@ -966,10 +1109,15 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
       }
     }
     for (int j = lane; j < n; j += kWave) S.th[j] = tt[j];
+    if (c.soft && lane == 0) S.u = S.ue;
     Pi = Pn;
     bsync<SM>();
   }
-  if (status != 0) evaluate(S, c, S.th, false);  // poses/contacts of the kept state
+  if (status != 0) {  // poses/contacts of the kept state
+    if (c.soft && lane == 0) S.ue = S.u;
+    bsync<SM>();
+    evaluate(S, c, S.th, false);
+  }
   return status;
 }
 
@@ -1012,6 +1160,8 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
   c.trace_n = D.trace_n;
   c.trace_cap = D.trace_cap;
   c.last_len = c.l;
+  c.soft = P.wg > 0.0;
+  c.tgt = 1.0;
   c.obs = D.obs + 4 * (size_t)ii[kObsOff];
   c.okind = D.okind + ii[kObsOff];
 }
@@ -1021,7 +1171,7 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
 // tip, residual, iterations, status and contact set; with D.traj the joint angles after
 // every rec_every-th step (and the last); with D.ckpt the state before every
 // ckpt_every-th step (the checkpoints from which the adjoint recomputes the states).
-template <int NMAX>
+template <int NMAX, bool SOFT>
 __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(
     KParams P, KData D, int n_steps) {
   using SMT = Smem<NMAX, true>;
@@ -1031,9 +1181,11 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
   const int lane = threadIdx.x;
   const int* ii = D.ii + kII * b;
   const int ntar = ii[kNTarget];
-  if (D.skip_done && D.ncur[b] >= ntar) return;  // both waves: nothing to grow
+  // a robot at its target length (soft growth: with a full tip link) has nothing to grow
+  if (D.skip_done && D.ncur[b] >= ntar && (!SOFT || D.ulast[b] >= kFull)) return;
   Ctx c;
   robot_ctx(c, P, D, b);
+  c.soft = SOFT;  // a constant of the launch, so hard growth carries none of the soft code
   c.trace = (b == D.trace_robot) ? D.trace : nullptr;
   double* theta = D.theta + ii[kThetaOff];
   const size_t rec0 = (size_t)ii[kRecOff];
@@ -1059,6 +1211,8 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     S.jevals = 0.0;
     S.nsolves = 0.0;
     S.negsteps = 0.0;
+    S.u = c.soft ? D.ulast[b] : 1.0;
+    S.ue = S.u;
   }
   for (int j = lane; j < n; j += kWave) S.th[j] = theta[j];
   bsync<SMT>();
@@ -1069,23 +1223,66 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     }
     int st_worst = 0, its = 0;
     double rho = 0.0;
-    if (n < ntar) {
-      ++n;
-      if (lane == 0) S.th[n - 1] = 0.0;
+    // hard growth: append a link when short of the target.  Soft growth: append only
+    // when the tip link is full (its excess starts the new link); done with the target
+    // link count and a full tip link.
+    bool grow;
+    if (c.soft) {
+      const double u = S.u;  // uniform: every lane reads the value lane 0 wrote
+      if (n == 0 || (u >= kFull && n < ntar)) {
+        ++n;
+        if (lane == 0) {
+          S.th[n - 1] = 0.0;
+          S.u = n == 1 ? 0.0 : fmax(u - 1.0, 0.0);
+        }
+      }
       bsync<SMT>();
+      grow = !(n == ntar && S.u >= kFull);
+    } else {
+      grow = n < ntar;
+      if (grow) {
+        ++n;
+        if (lane == 0) S.th[n - 1] = 0.0;
+        bsync<SMT>();
+      }
+    }
+    if (grow) {
       c.n = n;
       for (int s = 1; s <= P.substeps; ++s) {
-        c.last_len = c.l * (double)s / (double)P.substeps;
-        c.step = t;
-        c.sub = s;
-        int st = solve(S, c, its, rho);
-        st_worst = st > st_worst ? st : st_worst;
+        for (;;) {
+          if (c.soft) {
+            double tg = (double)t + (double)s / (double)P.substeps - (double)(n - 1);
+            c.tgt = (n == ntar && tg > 1.0) ? 1.0 : tg;
+          } else {
+            c.last_len = c.l * (double)s / (double)P.substeps;
+          }
+          c.step = t;
+          c.sub = s;
+          int st = solve(S, c, its, rho);
+          st_worst = st > st_worst ? st : st_worst;
+          // soft growth: a tip link grown longer than a link is split, its first l
+          // staying as link n - 1 and the rest starting a new link at zero angle; the
+          // sub-step is solved again
+          if (!(c.soft && n < ntar && S.u > 1.0 + 1e-12)) break;
+          bsync<SMT>();
+          if (lane == 0) {
+            S.th[n] = 0.0;
+            S.u = S.u - 1.0;
+          }
+          ++n;
+          c.n = n;
+          bsync<SMT>();
+        }
       }
     } else {
       c.n = n;
-      c.last_len = c.l;
+      if (!c.soft) c.last_len = c.l;
       st_worst = -1;
-      if (n > 0) evaluate(S, c, S.th, false);
+      if (n > 0) {
+        if (c.soft && lane == 0) S.ue = S.u;
+        bsync<SMT>();
+        evaluate(S, c, S.th, false);
+      }
     }
     // record the state after this step
     const size_t bt = rec0 + t;
@@ -1121,6 +1318,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
       D.ncont[bt] = npair;
       D.chash[bt] = hv;
       D.maxpen[bt] = mp;
+      D.tiplen[bt] = n == 0 ? 0.0 : (c.soft ? S.u * c.l : c.last_len);
     }
     if (D.traj && ((t + 1) % D.rec_every == 0 || t == rec_cap - 1)) {
       double* row = D.traj + ((size_t)b * D.n_rec + t / D.rec_every) * D.n_max;
@@ -1132,6 +1330,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
   if (lane == 0) {
     D.ncur[b] = n;
     D.tcur[b] = t;
+    if (c.soft) D.ulast[b] = S.u;
     D.jevals[b] += S.jevals;
     D.nsolves[b] += S.nsolves;
     D.negsteps[b] += S.negsteps;
@@ -1277,7 +1476,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) v
 static bool state_complete(const KData& D) {
   return D.ii && D.dd && D.cover && D.okind && D.obs && D.tables && D.wr && D.order && D.theta &&
          D.ncur && D.tcur && D.tip && D.rho && D.iters && D.status && D.ncont && D.chash &&
-         D.maxpen && D.jevals && D.nsolves && D.negsteps && D.cycles && D.wtime;
+         D.maxpen && D.tiplen && D.ulast && D.jevals && D.nsolves && D.negsteps &&
+         D.cycles && D.wtime;
 }
 
 __global__ void zero3_kernel(double* a, double* b, double* c, int n) {
@@ -1339,10 +1539,12 @@ __global__ void reset_kernel(KData D) {
     D.ncont[i] = 0;
     D.chash[i] = 0ull;
     D.maxpen[i] = 0.0;
+    D.tiplen[i] = 0.0;
   }
   for (size_t i = i0; i < B; i += stride) {
     D.ncur[i] = 0;
     D.tcur[i] = 0;
+    D.ulast[i] = 0.0;
     D.jevals[i] = 0.0;
     D.nsolves[i] = 0.0;
     D.negsteps[i] = 0.0;
@@ -1368,10 +1570,12 @@ __global__ void slot_reset_kernel(KData D, const int* slots, int count) {
     D.ncont[bt] = 0;
     D.chash[bt] = 0ull;
     D.maxpen[bt] = 0.0;
+    D.tiplen[bt] = 0.0;
   }
   if (threadIdx.x == 0) {
     D.ncur[b] = 0;
     D.tcur[b] = 0;
+    D.ulast[b] = 0.0;
     D.jevals[b] = 0.0;
     D.nsolves[b] = 0.0;
     D.negsteps[b] = 0.0;
@@ -1443,13 +1647,13 @@ hipError_t launch_reset(const KData& D, hipStream_t stream) {
 hipError_t rollout_occupancy(int nmax_class, int* per_cu) {
   const int block = 2 * kWave;
   if (nmax_class == 64)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<64>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<64, false>, block, 0);
   if (nmax_class == 128)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<128>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<128, false>, block, 0);
   if (nmax_class == 256)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<256>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<256, false>, block, 0);
   if (nmax_class == 512)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<512>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<512, false>, block, 0);
   return hipErrorInvalidValue;
 }
 
@@ -1461,16 +1665,24 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nma
   if (D.traj && D.rec_every < 1) return hipErrorInvalidValue;
   if (D.ckpt && D.ckpt_every < 1) return hipErrorInvalidValue;
   dim3 grid(D.launch_count), block(2 * kWave);
-  if (nmax_class == 64)
-    hipLaunchKernelGGL((rollout_kernel<64>), grid, block, 0, stream, P, D, n_steps);
-  else if (nmax_class == 128)
-    hipLaunchKernelGGL((rollout_kernel<128>), grid, block, 0, stream, P, D, n_steps);
-  else if (nmax_class == 256)
-    hipLaunchKernelGGL((rollout_kernel<256>), grid, block, 0, stream, P, D, n_steps);
-  else if (nmax_class == 512)
-    hipLaunchKernelGGL((rollout_kernel<512>), grid, block, 0, stream, P, D, n_steps);
-  else
+  const bool soft = P.wg > 0.0;
+#define VS_ROLL(NM)                                                                         \
+  if (soft)                                                                                 \
+    hipLaunchKernelGGL((rollout_kernel<NM, true>), grid, block, 0, stream, P, D, n_steps);  \
+  else                                                                                      \
+    hipLaunchKernelGGL((rollout_kernel<NM, false>), grid, block, 0, stream, P, D, n_steps);
+  if (nmax_class == 64) {
+    VS_ROLL(64)
+  } else if (nmax_class == 128) {
+    VS_ROLL(128)
+  } else if (nmax_class == 256) {
+    VS_ROLL(256)
+  } else if (nmax_class == 512) {
+    VS_ROLL(512)
+  } else {
     return hipErrorInvalidValue;
+  }
+#undef VS_ROLL
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ FIELDS = dict(theta=(0, np.float64, "BN"), nlinks=(1, np.int32, "B"), tip=(2, np
               traj=(9, np.float64, "BRN"), jevals=(10, np.float64, "B"),
               nsolves=(11, np.float64, "B"), cycles=(12, np.float64, "B"),
               negsteps=(13, np.float64, "B"), ckpt=(14, np.float64, "BCN"),
-              time=(15, np.float64, "B"))
+              time=(15, np.float64, "B"), tiplen=(16, np.float64, "BT"))
 
 MAX_LINKS = 512
 MAX_OBSTACLES = 128
@@ -46,7 +46,7 @@ class Params(C.Structure):
     _fields_ = [("R_c", C.c_double), ("R_act", C.c_double), ("a_corr", C.c_double),
                 ("eps_crit", C.c_double), ("k_c", C.c_double), ("tol", C.c_double),
                 ("c_mu", C.c_double), ("step_max", C.c_double), ("armijo_c1", C.c_double),
-                ("pd_shift", C.c_double), ("max_iter", C.c_int32),
+                ("pd_shift", C.c_double), ("growth_stiffness", C.c_double), ("max_iter", C.c_int32),
                 ("growth_substeps", C.c_int32), ("reserved", C.c_int32)]
 
 

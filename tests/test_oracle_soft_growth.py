@@ -118,3 +118,14 @@ def test_blocked_tip_resumes_and_reaches_the_target_length():
     # a blocked stretch: some step ends with the tip link short of full length
     o = O.rollout(w, prm=O.params(wg=50.0))
     assert np.any(o["tiplen"][0] < 0.02 * (1 - 1e-6))
+
+
+def test_tip_length_bound_is_held():
+    """u >= 0: where contact pushes the tip link back past zero length (a link appended
+    against an obstacle), the trial tip length is projected onto u = 0 and held there while
+    dPi/du > 0; the step still converges.  Uniform-batch robot 2 meets it at step 32."""
+    w = W.config2(32).subset([2])
+    o = O.rollout(w, n_steps=40, prm=O.params(wg=5000.0))
+    assert np.all(o["status"] == 0)
+    assert o["tiplen"][0, 32] == 0.0
+    assert np.all(o["tiplen"][0] >= 0.0)
