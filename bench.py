@@ -133,8 +133,13 @@ def timed_batch(torch, V, work, wl, args, stream):
     torch.cuda.synchronize()
     first_ms = f0.elapsed_time(f1)
     tuned = not args.no_tune
+    autotune = None
     if tuned:  # launch order from the cycles the first rollout measured per robot
         sim.tune_order(stream=stream)
+        # waves per robot of each class, measured (or taken from the configuration's cache)
+        a0 = time.perf_counter()
+        autotune = sim.autotune(stream=stream)
+        autotune["seconds"] = time.perf_counter() - a0
 
     def one_step():
         if args.eager:
@@ -167,7 +172,7 @@ def timed_batch(torch, V, work, wl, args, stream):
     k1.record(stream)
     torch.cuda.synchronize()
     res = dict(ms=ms, wall=wall, first_ms=first_ms, tuned=tuned, kern_ms=k0.elapsed_time(k1),
-               out=out, robot_s=sim.read("time"))
+               out=out, robot_s=sim.read("time"), autotune=autotune)
     if grad:
         g0, g1 = _events(torch)
         g0.record(stream)
@@ -290,7 +295,10 @@ def main():
     status = out["status"]
     # how busy the rollout keeps the device: robot-seconds over the launch's robot slots
     # (compute units x robots resident per compute unit of the most resident class)
-    per_cu, cus = V.occupancy()
+    occ = {w: V.occupancy(w) for w in (1, 2)}
+    cus = occ[2][1]
+    waves = (R["autotune"] or {}).get("waves") or [2, 2, 2, 2]
+    per_cu = [occ[waves[c] or 2][0][c] for c in range(4)]
     classes = [c for c, lim in enumerate((64, 128, 256, 512)) if ((n <= lim) & (n > (0, 64, 128, 256)[c])).any()]
     slots_dev = cus * max(per_cu[c] for c in classes)
     busy = float(robot_s.sum()) / (R["kern_ms"] * 1e-3 * slots_dev)
@@ -386,6 +394,7 @@ def main():
         "config": {"workload": desc, "robots": B, "links_max": int(n.max()),
                    "graph": not args.eager,
                    "schedule": "measured by the first rollout" if R["tuned"] else "create-time estimate",
+                   "autotune": R["autotune"],
                    "obstacles_work_weighted": K_mean, "joint_updates_per_step": ju},
         "latency": {"unit": "s", "what": "per-robot rollout latency (its workgroup's time in the launch)",
                     "p50": float(np.percentile(robot_s, 50)),

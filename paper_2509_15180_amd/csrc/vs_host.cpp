@@ -7,10 +7,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <deque>
 #include <list>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <type_traits>
@@ -24,7 +26,7 @@ static_assert(vs::kScratchBytes == VINE_GRAD_SCRATCH_BYTES, "scratch size of the
 
 namespace vs {
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
-                          hipStream_t stream);
+                          int waves, hipStream_t stream);
 hipError_t launch_grad(const KParams& P, const KData& D, const double* goal,
                        const double* weights, int T, int t0, const double* traj, int traj_rows,
                        const GradPart& part, double* dP, double* ds0, double* ds1, double* loss,
@@ -34,7 +36,7 @@ hipError_t launch_reset(const KData& D, hipStream_t stream);
 hipError_t launch_seg_load(const KData& Dseg, const int* ii_handle, const double* ckpt,
                            const int* tcur, int n_ckpt, int q, int ce, hipStream_t stream);
 hipError_t scratch_address(void** out);
-hipError_t rollout_occupancy(int nmax_class, int* per_cu);
+hipError_t rollout_occupancy(int nmax_class, int waves, int* per_cu);
 }
 
 using vs::SpamTable;
@@ -367,6 +369,7 @@ struct vine_sim {
   std::vector<double> link_lens;      // distinct link lengths (table ids)
   std::vector<SpamTable> tables_h;
   std::vector<vine_instance> inst_h;  // as given at create (sPAM ranges, lengths)
+  uint64_t config_hash = 0;  // of the parameters and every input at create (autotune cache)
   // device arrays
   int* ii = nullptr;
   double* dd = nullptr;
@@ -416,6 +419,7 @@ struct vine_sim {
   int* order = nullptr;
   std::vector<int> order_h;  // host copy of the launch order
   int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
+  int waves[kClasses] = {2, 2, 2, 2};  // per robot in the class's rollout launches
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   // vine_sim_rollout_graph: reset + full rollout captured once per (rec_every, ckpt_every)
@@ -587,6 +591,9 @@ hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch
   return e;
 }
 
+// waves per robot of the rollout launches of the class of `links` (autotuned: 1 or 2)
+int class_waves(const vine_sim* h, int links) { return h->waves[link_class(links)]; }
+
 template <typename F>
 hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
   return for_each_class(h, stream, kdata(h), launch);
@@ -708,6 +715,19 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     append_cover(I, spams, cover);
   }
   h->inst_h.assign(inst, inst + n_inst);
+  {
+    // FNV-1a over the parameters and the inputs: the key of the autotuner's cache
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void* data, size_t bytes) {
+      const unsigned char* q = (const unsigned char*)data;
+      for (size_t i = 0; i < bytes; ++i) x = (x ^ q[i]) * 1099511628211ull;
+    };
+    mix(&p, sizeof(p));
+    mix(inst, sizeof(vine_instance) * (size_t)n_inst);
+    if (n_spams > 0) mix(spams, sizeof(vine_spam) * (size_t)n_spams);
+    if (n_obstacles > 0) mix(obstacles, sizeof(vine_obstacle) * (size_t)n_obstacles);
+    h->config_hash = x;
+  }
   // launch order: by class, then by decreasing n^2 (4 + K), a proxy of the work
   std::vector<int> order(n_inst);
   for (int b = 0; b < n_inst; ++b) order[b] = b;
@@ -914,7 +934,8 @@ static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_every, int32
   const vs::KParams kp = kparams(h->prm);
   hipError_t e = for_each_class(h, (hipStream_t)stream, kdata_rec(h, record_every, ckpt_every),
                                 [&](int links, const vs::KData& D, hipStream_t s) {
-                                  return vs::launch_rollout(kp, D, n_steps, links, s);
+                                  return vs::launch_rollout(kp, D, n_steps, links,
+                                                            class_waves(h, links), s);
                                 });
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   note_rec(h, record_every, ckpt_every);
@@ -952,6 +973,85 @@ int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
   return VINE_OK;
 }
 
+int32_t vine_sim_set_waves(vine_sim* h, const int32_t waves[4]) {
+  if (!h || !waves) return fail(h, VINE_EINVAL, "null handle or waves");
+  for (int c = 0; c < vine_sim::kClasses; ++c)
+    if (waves[c] != 1 && waves[c] != 2) return fail(h, VINE_EINVAL, "waves per robot must be 1 or 2");
+  bool changed = false;
+  for (int c = 0; c < vine_sim::kClasses; ++c) {
+    changed = changed || h->waves[c] != waves[c];
+    h->waves[c] = waves[c];
+  }
+  if (changed) drop_graphs(h);  // the captures hold the launches' block sizes
+  return VINE_OK;
+}
+
+namespace {
+// the autotuner's measurements, per configuration (hash of the parameters and inputs)
+std::mutex g_tune_mu;
+std::map<uint64_t, std::array<int32_t, vine_sim::kClasses>> g_tune;
+}  // namespace
+
+int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* cached,
+                          void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  hipStream_t s = (hipStream_t)stream;
+  std::array<int32_t, vine_sim::kClasses> best = {2, 2, 2, 2};
+  double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool hit = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(h->config_hash);
+    if (it != g_tune.end()) {
+      best = it->second;
+      hit = true;
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (!hit) {
+    // each class alone, from zero length to full, with two waves per robot and with one
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const vs::KParams kp = kparams(h->prm);
+    for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
+      if (h->cls_count[c] == 0) continue;
+      vs::KData D = kdata(h);
+      D.launch_first = h->cls_first[c];
+      D.launch_count = h->cls_count[c];
+      for (int w = 2; w >= 1 && e == hipSuccess; --w) {
+        e = vs::launch_reset(kdata(h), s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = vs::launch_rollout(kp, D, h->T, kClassLinks[c], w, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        t[2 * c + (w - 1)] = f;
+      }
+      best[c] = t[2 * c] < t[2 * c + 1] ? 1 : 2;  // one wave only when it measured faster
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = vs::launch_reset(kdata(h), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    h->traj_valid = false;
+    h->traj_all = h->ckpt_all = true;
+    h->ckpt_any = false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[h->config_hash] = best;
+  }
+  int32_t r = vine_sim_set_waves(h, best.data());
+  if (r != VINE_OK) return r;
+  if (waves)
+    for (int c = 0; c < vine_sim::kClasses; ++c) waves[c] = h->cls_count[c] > 0 ? best[c] : 0;
+  if (ms)
+    for (int k = 0; k < 8; ++k) ms[k] = t[k];
+  if (cached) *cached = hit ? 1 : 0;
+  return VINE_OK;
+}
+
 int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_every,
                                void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
@@ -986,7 +1086,8 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_e
       if (le == hipSuccess)
         le = for_each_class(h, h->cap_stream, kdata_rec(h, record_every, ckpt_every),
                             [&](int links, const vs::KData& D, hipStream_t s) {
-                              return vs::launch_rollout(kp, D, h->T, links, s);
+                              return vs::launch_rollout(kp, D, h->T, links,
+                                                        class_waves(h, links), s);
                             });
       e = hipStreamEndCapture(h->cap_stream, &graph);  // ends the capture in every case
       if (e == hipSuccess) e = le;
@@ -1153,7 +1254,7 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
       e = vs::launch_seg_load(Dseg, h->ii, h->ckpt, h->tcur, h->n_ckpt, q, ce, s);
       if (e == hipSuccess)
         e = for_each_class(h, s, Dseg, [&](int links, const vs::KData& D, hipStream_t cs) {
-          return vs::launch_rollout(kp, D, len, links, cs);
+          return vs::launch_rollout(kp, D, len, links, class_waves(h, links), cs);
         });
       const vs::GradPart part{g->gsums, g->gloss, g->gstat, q == 0, q == h->n_ckpt - 1};
       if (e == hipSuccess)
@@ -1341,13 +1442,14 @@ int32_t vine_sim_trace_read(const vine_sim* hc, double* dst, int32_t capacity) {
   return n;
 }
 
-int32_t vine_sim_occupancy(int32_t per_cu[4], int32_t* compute_units) {
+int32_t vine_sim_occupancy(int32_t waves, int32_t per_cu[4], int32_t* compute_units) {
+  if (waves != 1 && waves != 2) return fail(nullptr, VINE_EINVAL, "waves per robot must be 1 or 2");
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
     int k = 0;
-    e = vs::rollout_occupancy(kClassLinks[c], &k);
+    e = vs::rollout_occupancy(kClassLinks[c], waves, &k);
     if (per_cu) per_cu[c] = k;
   }
   if (e != hipSuccess) return fail(nullptr, VINE_EDEVICE, std::string("occupancy: ") + hipGetErrorString(e));
@@ -1641,7 +1743,7 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
   A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
   D.launch_first = (int)g.order_off;
   D.launch_count = g.count;
-  A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], sa));
+  A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], 2, sa));
   hipEvent_t ev = nullptr;
   A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   A(hipEventRecord(ev, sa));

@@ -1171,10 +1171,10 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
 // tip, residual, iterations, status and contact set; with D.traj the joint angles after
 // every rec_every-th step (and the last); with D.ckpt the state before every
 // ckpt_every-th step (the checkpoints from which the adjoint recomputes the states).
-template <int NMAX, bool SOFT>
+template <int NMAX, bool SOFT, bool TWO>
 __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(
     KParams P, KData D, int n_steps) {
-  using SMT = Smem<NMAX, true>;
+  using SMT = Smem<NMAX, TWO>;
   __shared__ SMT S;
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x];
@@ -1190,9 +1190,11 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
   double* theta = D.theta + ii[kThetaOff];
   const size_t rec0 = (size_t)ii[kRecOff];
   const int rec_cap = ii[kRecCap];
-  if (threadIdx.x >= kWave) {
-    obstacle_helper(S, c);
-    return;
+  if constexpr (TWO) {
+    if (threadIdx.x >= kWave) {
+      obstacle_helper(S, c);
+      return;
+    }
   }
   if (lane == 0) {
     S.res_ok = 0;  // staged by the first evaluation
@@ -1337,11 +1339,13 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     D.cycles[b] += (double)(clock64() - t_begin);
     D.wtime[b] += (double)(wall_clock64() - w_begin) * D.wall_period;
   }
-  if (lane == 0) {
-    S.cmd = 2;
-    S.cmd_seq += 1;
+  if constexpr (TWO) {
+    if (lane == 0) {
+      S.cmd = 2;
+      S.cmd_seq += 1;
+    }
+    __syncthreads();  // releases the helper wave, which then ends
   }
-  __syncthreads();  // releases the helper wave, which then ends
 }
 
 // ---------------------------------------------------------------------------
@@ -1643,34 +1647,44 @@ hipError_t launch_reset(const KData& D, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Robots (workgroups) of one chain-length class resident per compute unit.
-hipError_t rollout_occupancy(int nmax_class, int* per_cu) {
-  const int block = 2 * kWave;
-  if (nmax_class == 64)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<64, false>, block, 0);
-  if (nmax_class == 128)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<128, false>, block, 0);
-  if (nmax_class == 256)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<256, false>, block, 0);
-  if (nmax_class == 512)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<512, false>, block, 0);
+// Robots (workgroups) of one chain-length class resident per compute unit, with one or
+// two waves per robot.
+hipError_t rollout_occupancy(int nmax_class, int waves, int* per_cu) {
+  const int block = waves * kWave;
+#define VS_OCC(NM)                                                                          \
+  return waves == 2                                                                         \
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<NM, false, true>, \
+                                                            block, 0)                       \
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<NM, false, false>, \
+                                                            block, 0);
+  if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+  if (nmax_class == 64) VS_OCC(64)
+  if (nmax_class == 128) VS_OCC(128)
+  if (nmax_class == 256) VS_OCC(256)
+  if (nmax_class == 512) VS_OCC(512)
+#undef VS_OCC
   return hipErrorInvalidValue;
 }
 
 // host-side launcher (instantiated for the supported chain lengths)
 hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nmax_class,
-                          hipStream_t stream) {
+                          int waves, hipStream_t stream) {
   if (D.launch_count <= 0) return hipSuccess;
   if (!state_complete(D)) return hipErrorInvalidValue;
   if (D.traj && D.rec_every < 1) return hipErrorInvalidValue;
   if (D.ckpt && D.ckpt_every < 1) return hipErrorInvalidValue;
-  dim3 grid(D.launch_count), block(2 * kWave);
-  const bool soft = P.wg > 0.0;
-#define VS_ROLL(NM)                                                                         \
-  if (soft)                                                                                 \
-    hipLaunchKernelGGL((rollout_kernel<NM, true>), grid, block, 0, stream, P, D, n_steps);  \
-  else                                                                                      \
-    hipLaunchKernelGGL((rollout_kernel<NM, false>), grid, block, 0, stream, P, D, n_steps);
+  if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+  dim3 grid(D.launch_count), block(waves * kWave);
+  const bool soft = P.wg > 0.0, two = waves == 2;
+#define VS_ROLL(NM)                                                                            \
+  if (soft && two)                                                                             \
+    hipLaunchKernelGGL((rollout_kernel<NM, true, true>), grid, block, 0, stream, P, D, n_steps);  \
+  else if (soft)                                                                               \
+    hipLaunchKernelGGL((rollout_kernel<NM, true, false>), grid, block, 0, stream, P, D, n_steps); \
+  else if (two)                                                                                \
+    hipLaunchKernelGGL((rollout_kernel<NM, false, true>), grid, block, 0, stream, P, D, n_steps); \
+  else                                                                                         \
+    hipLaunchKernelGGL((rollout_kernel<NM, false, false>), grid, block, 0, stream, P, D, n_steps);
   if (nmax_class == 64) {
     VS_ROLL(64)
   } else if (nmax_class == 128) {

@@ -73,7 +73,7 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
-           "vine_sim_occupancy",
+           "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune",
            "vine_server_create",
            "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
            "vine_server_release", "vine_server_stats", "vine_server_destroy",
@@ -120,8 +120,13 @@ def lib():
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.vine_sim_spam_law.restype = C.c_int32
-        L.vine_sim_occupancy.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.vine_sim_occupancy.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.vine_sim_occupancy.restype = C.c_int32
+        L.vine_sim_set_waves.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.vine_sim_set_waves.restype = C.c_int32
+        L.vine_sim_autotune.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int32), vp]
+        L.vine_sim_autotune.restype = C.c_int32
         L.vine_sim_trace.argtypes = [vp, C.c_int32, C.c_int32]
         L.vine_sim_trace.restype = C.c_int32
         L.vine_sim_trace_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
@@ -166,12 +171,12 @@ def default_params(**over) -> Params:
     return p
 
 
-def occupancy():
+def occupancy(waves: int = 2):
     """(robots per compute unit for the 64-, 128-, 256- and 512-link classes, compute units)
-    of the current device (vine_sim_occupancy)."""
+    of the current device with `waves` waves per robot (vine_sim_occupancy)."""
     per = (C.c_int32 * 4)()
     cus = C.c_int32()
-    rc = lib().vine_sim_occupancy(per, C.byref(cus))
+    rc = lib().vine_sim_occupancy(waves, per, C.byref(cus))
     if rc != VINE_OK:
         raise VineError(rc, lib().vine_sim_last_error(None).decode())
     return [int(x) for x in per], int(cus.value)
@@ -254,6 +259,22 @@ class VineSim:
     def tune_order(self, stream=None):
         """Launch order by the cycles each robot measured since the last reset (longest first)."""
         self._check(lib().vine_sim_tune_order(self.h, _stream_ptr(stream)))
+
+    def set_waves(self, waves):
+        """Waves per robot (1 or 2) of the 64-, 128-, 256- and 512-link classes."""
+        w = (C.c_int32 * 4)(*[int(x) for x in waves])
+        self._check(lib().vine_sim_set_waves(self.h, w))
+
+    def autotune(self, stream=None) -> dict:
+        """Measure one and two waves per robot for each class, keep the faster
+        (vine_sim_autotune); the robots end reset."""
+        w = (C.c_int32 * 4)()
+        ms = (C.c_double * 8)()
+        cached = C.c_int32()
+        self._check(lib().vine_sim_autotune(self.h, w, ms, C.byref(cached), _stream_ptr(stream)))
+        return {"waves": [int(x) for x in w], "cached": bool(cached.value),
+                "ms_one_wave": [ms[2 * c] for c in range(4)],
+                "ms_two_waves": [ms[2 * c + 1] for c in range(4)]}
 
     def reset(self, stream=None):
         self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))
