@@ -295,7 +295,7 @@ def main():
     status = out["status"]
     # how busy the rollout keeps the device: robot-seconds over the launch's robot slots
     # (compute units x robots resident per compute unit of the most resident class)
-    occ = {w: V.occupancy(w) for w in (1, 2)}
+    occ = {w: V.occupancy(w) for w in (1, 2, 4)}
     cus = occ[2][1]
     waves = (R["autotune"] or {}).get("waves") or [2, 2, 2, 2]
     per_cu = [occ[waves[c] or 2][0][c] for c in range(4)]

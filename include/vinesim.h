@@ -329,29 +329,32 @@ int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* 
                           double* dG, double* IG);
 
 /* Occupancy of the current device: robots of each chain-length class (up to 64, 128,
- * 256 and 512 links) resident per compute unit in a rollout launch with `waves` (1 or 2)
- * 64-lane waves per robot, and the number of compute units.  For reports of how busy a
+ * 256 and 512 links) resident per compute unit in a rollout launch with `waves` (1, 2 or
+ * 4) 64-lane waves per robot, and the number of compute units.  For reports of how busy a
  * launch keeps the device.  Errors: VINE_EINVAL (waves), VINE_EDEVICE. */
 int32_t vine_sim_occupancy(int32_t waves, int32_t per_cu[4], int32_t* compute_units);
 
 /* Waves per robot of each class's rollout launches (classes of up to 64, 128, 256 and
- * 512 links): 2 (default) runs the obstacle phase of every evaluation on a second wave
- * beside the joint law; 1 runs both on one wave, which leaves room for more robots per
- * compute unit where registers, not LDS, bound the class.  Results are bitwise the same
- * either way.  Drops the captured rollouts when a value changes.  Errors: VINE_EINVAL. */
+ * 512 links).  1: one wave does every evaluation's joint law and obstacle phase; 2
+ * (default): the obstacle phase runs on a helper wave beside the joint law; 4: three
+ * helpers, one taking the joint law of the second half of the chunks of 64 links and two
+ * the obstacle phase of each half (a second contact-list region, appended after the
+ * first), which shortens each evaluation of a long robot at the price of more LDS and
+ * fewer robots per compute unit.  Results are bitwise the same in every case.  Drops the
+ * captured rollouts when a value changes.  Errors: VINE_EINVAL. */
 int32_t vine_sim_set_waves(vine_sim* h, const int32_t waves[4]);
 
 /* Autotuner: for each chain-length class present, time the class's rollout from zero
- * length to full with two waves per robot and with one, in the handle's current launch
- * order, keep the faster (vine_sim_set_waves), and remember the choice for this
- * configuration (a hash of the parameters and every input given at create) in a cache
- * of the process, so that later handles of the same configuration take it without
- * measuring.  waves (host, 4, or NULL): the choice, 0 for empty classes; ms (host, 8, or
- * NULL): [2 c] the one-wave and [2 c + 1] the two-wave time of class c (0 when not
- * measured); cached (host or NULL): 1 when taken from the cache.  Measuring runs the
- * rollouts, so the robots end reset to zero length.  Synchronises the stream.  Errors:
- * VINE_EINVAL, VINE_EDEVICE. */
-int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* cached,
+ * length to full with 1, 2 and 4 waves per robot, in the handle's current launch order,
+ * keep the fastest (vine_sim_set_waves; 2 unless another measured faster), and remember
+ * the choice for this configuration (a hash of the parameters and every input given at
+ * create) in a cache of the process, so that later handles of the same configuration take
+ * it without measuring.  waves (host, 4, or NULL): the choice, 0 for empty classes; ms
+ * (host, 12, or NULL): [3 c + k] the time of class c with 1, 2, 4 waves for k = 0, 1, 2
+ * (0 when not measured); cached (host or NULL): 1 when taken from the cache.  Measuring
+ * runs the rollouts, so the robots end reset to zero length.  Synchronises the stream.
+ * Errors: VINE_EINVAL, VINE_EDEVICE. */
+int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t* cached,
                           void* stream);
 
 /* Diagnostics: record one row per accepted Newton iteration of robot `robot`

@@ -976,7 +976,8 @@ int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
 int32_t vine_sim_set_waves(vine_sim* h, const int32_t waves[4]) {
   if (!h || !waves) return fail(h, VINE_EINVAL, "null handle or waves");
   for (int c = 0; c < vine_sim::kClasses; ++c)
-    if (waves[c] != 1 && waves[c] != 2) return fail(h, VINE_EINVAL, "waves per robot must be 1 or 2");
+    if (waves[c] != 1 && waves[c] != 2 && waves[c] != 4)
+      return fail(h, VINE_EINVAL, "waves per robot must be 1, 2 or 4");
   bool changed = false;
   for (int c = 0; c < vine_sim::kClasses; ++c) {
     changed = changed || h->waves[c] != waves[c];
@@ -992,12 +993,12 @@ std::mutex g_tune_mu;
 std::map<uint64_t, std::array<int32_t, vine_sim::kClasses>> g_tune;
 }  // namespace
 
-int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* cached,
+int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t* cached,
                           void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   hipStream_t s = (hipStream_t)stream;
   std::array<int32_t, vine_sim::kClasses> best = {2, 2, 2, 2};
-  double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double t[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   bool hit = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1009,7 +1010,7 @@ int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* 
   }
   hipError_t e = hipSuccess;
   if (!hit) {
-    // each class alone, from zero length to full, with two waves per robot and with one
+    // each class alone, from zero length to full, with 1, 2 and 4 waves per robot
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1019,17 +1020,25 @@ int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* 
       vs::KData D = kdata(h);
       D.launch_first = h->cls_first[c];
       D.launch_count = h->cls_count[c];
-      for (int w = 2; w >= 1 && e == hipSuccess; --w) {
+      const int ws[3] = {1, 2, 4};
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
         e = vs::launch_reset(kdata(h), s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = vs::launch_rollout(kp, D, h->T, kClassLinks[c], w, s);
+        if (e == hipSuccess) e = vs::launch_rollout(kp, D, h->T, kClassLinks[c], ws[k], s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float f = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
-        t[2 * c + (w - 1)] = f;
+        t[3 * c + k] = f;
       }
-      best[c] = t[2 * c] < t[2 * c + 1] ? 1 : 2;  // one wave only when it measured faster
+      // the fastest; two waves (the default) unless another measured faster
+      best[c] = 2;
+      double tb = t[3 * c + 1];
+      if (t[3 * c] < tb) {
+        best[c] = 1;
+        tb = t[3 * c];
+      }
+      if (t[3 * c + 2] < tb) best[c] = 4;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1047,7 +1056,7 @@ int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[8], int32_t* 
   if (waves)
     for (int c = 0; c < vine_sim::kClasses; ++c) waves[c] = h->cls_count[c] > 0 ? best[c] : 0;
   if (ms)
-    for (int k = 0; k < 8; ++k) ms[k] = t[k];
+    for (int k = 0; k < 12; ++k) ms[k] = t[k];
   if (cached) *cached = hit ? 1 : 0;
   return VINE_OK;
 }
@@ -1443,7 +1452,8 @@ int32_t vine_sim_trace_read(const vine_sim* hc, double* dst, int32_t capacity) {
 }
 
 int32_t vine_sim_occupancy(int32_t waves, int32_t per_cu[4], int32_t* compute_units) {
-  if (waves != 1 && waves != 2) return fail(nullptr, VINE_EINVAL, "waves per robot must be 1 or 2");
+  if (waves != 1 && waves != 2 && waves != 4)
+    return fail(nullptr, VINE_EINVAL, "waves per robot must be 1, 2 or 4");
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

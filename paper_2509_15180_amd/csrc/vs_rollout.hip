@@ -314,11 +314,16 @@ __device__ __forceinline__ bool obs_near(int kind, double ox, double oy, double 
 }
 
 // ---------------------------------------------------------------------------
-// LDS working set of one robot.  HELP_: a second wave takes the obstacle phase of each
-// evaluation (the rollout launches); without it one wave does everything (the adjoint).
-template <int NMAX, bool HELP_>
+// LDS working set of one robot.  HELP_: helper waves beside the solver wave take the
+// obstacle phase of each evaluation (the rollout launches); without them one wave does
+// everything (the adjoint, and one-wave rollouts).  FOUR_: three helper waves, which split
+// the joint law and the obstacle phase by chunks of 64 links (the second half of the
+// chunks' contacts goes to a second region of the contact list, appended after the first).
+template <int NMAX, bool HELP_, bool FOUR_ = false>
 struct Smem {
   static constexpr bool kHelper = HELP_;
+  static constexpr bool kFour = FOUR_;
+  static constexpr int kRegions = FOUR_ ? 2 : 1;
   struct {
     double ox[kMaxObs], oy[kMaxObs], oa[kMaxObs], ob[kMaxObs];
     int okind[kMaxObs];
@@ -335,10 +340,15 @@ struct Smem {
   double ps1[NMAX], ps2[NMAX], aux[NMAX], v[NMAX];
   double sw0[NMAX], sw1[NMAX], sw2[NMAX];
   int lidx[NMAX];  // 1 when link j carries a contact
-  int ci[kMaxC], ck[kMaxC];
-  double cl[kMaxC], cxx[kMaxC], cxy[kMaxC], cnx[kMaxC], cny[kMaxC], ckap[kMaxC], cpen[kMaxC];
+  int ci[kRegions * kMaxC], ck[kRegions * kMaxC];
+  double cl[kRegions * kMaxC], cxx[kRegions * kMaxC], cxy[kRegions * kMaxC],
+      cnx[kRegions * kMaxC], cny[kRegions * kMaxC], ckap[kRegions * kMaxC],
+      cpen[kRegions * kMaxC];
   int ncl;
   int overflow;
+  int cnt0, cnt1;                 // pairs found in each region's chunks (may exceed kMaxC)
+  double ech[NMAX / kWave];       // joint energy of each chunk of 64 joints
+  int eval_trial, eval_E;         // solver -> helpers: angles in b (trial) or th; energy wanted
   double jevals, nsolves, negsteps;  // work counters (lane 0 updates)
   int cmd, cmd_seq, eval_n;  // solver wave -> helper wave: 1 = obstacle phase, 2 = end
   double eval_last;
@@ -380,17 +390,19 @@ __device__ void stage_resident(SM& S, const Ctx& c) {
 }
 
 // The contact part of an evaluation at the poses in S (n links, the last of length
-// last_len), on one wave whose lane index is lane: penetrating (disk, obstacle) pairs
-// into the contact list, each link's contact sums into ps1, ps2, aux and v, and ncl and
-// overflow.
+// last_len) for the chunks of 64 links [ch0, ch1), on one wave whose lane index is lane:
+// penetrating (disk, obstacle) pairs into the contact list from position base (at most
+// kMaxC of them), each link's contact sums into ps1, ps2, aux and v.  Returns the number
+// of pairs found (uniform; more than kMaxC when the list is too short).
 template <class SM>
-__device__ void obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int lane) {
+__device__ int obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int lane, int ch0,
+                              int ch1, int base_pos) {
   // penetrating (disk, obstacle) pairs, compacted in (obstacle, disk, link) order per
   // chunk.  The exact gap (square root, divisions) is taken only for pairs whose
   // cheap pre-test some lane of the wave passes.
   int cnt = 0;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int base = 0; base < n; base += kWave) {
+  for (int base = ch0 * kWave; base < n && base < ch1 * kWave; base += kWave) {
     const int j = base + lane;
     const bool on = j < n;
     const double L = (j == n - 1) ? last_len : c.l;
@@ -495,15 +507,16 @@ __device__ void obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int 
             const int pos = cnt + __popcll(m & lt);
             if (hit && pos < kMaxC) {
               const double pen = -g, lam = c.P.kc * pen;
-              S.ci[pos] = j;
-              S.ck[pos] = ks[u];
-              S.cl[pos] = lam;
-              S.cxx[pos] = xs[hh];
-              S.cxy[pos] = ys[hh];
-              S.cnx[pos] = nx;
-              S.cny[pos] = ny;
-              S.ckap[pos] = kap;
-              S.cpen[pos] = pen;
+              const int at = base_pos + pos;
+              S.ci[at] = j;
+              S.ck[at] = ks[u];
+              S.cl[at] = lam;
+              S.cxx[at] = xs[hh];
+              S.cxy[at] = ys[hh];
+              S.cnx[at] = nx;
+              S.cny[at] = ny;
+              S.ckap[at] = kap;
+              S.cpen[at] = pen;
               a_s1 += lam * (xs[hh] * ny - ys[hh] * nx);
               a_fx += lam * nx;
               a_fy += lam * ny;
@@ -522,10 +535,33 @@ __device__ void obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int 
       S.v[j] = a_q;
     }
   }
-  const int nc = cnt < kMaxC ? cnt : kMaxC;
-  if (lane == 0) {
-    S.ncl = nc;
-    S.overflow = cnt > kMaxC;
+  return cnt;
+}
+
+// The joint law of chunks [ch0, ch1) of 64 joints at angles th, on one wave: moments into
+// r, slopes into dq (when a helper wave shares the evaluation: the Newton set-up that
+// follows an evaluation is always at the angles last evaluated), and each chunk's energy,
+// summed over its lanes, into ech.
+template <class SM>
+__device__ void joint_law_chunks(SM& S, const Ctx& c, const double* th, bool want_E, int ch0,
+                                 int ch1, int lane) {
+  const int n = c.n;
+  for (int k = ch0; k < ch1; ++k) {
+    const int j = k * kWave + lane;
+    double E = 0.0;
+    if (j < n) {
+      double q;
+      if constexpr (SM::kHelper) {
+        double dqj;
+        joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, &dqj, want_E ? &E : nullptr);
+        S.dq[j] = dqj;
+      } else {
+        joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
+      }
+      S.r[j] = q;
+    }
+    E = wsum(E);
+    if (lane == 0) S.ech[k] = E;
   }
 }
 
@@ -566,34 +602,58 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     S.px[0] = c.bx;
     S.py[0] = c.by;
   }
+  const int nch = (n + kWave - 1) / kWave;
   if constexpr (SM::kHelper) {
     if (lane == 0) {
       S.eval_n = n;
       S.eval_last = last;
+      S.eval_trial = th != S.th;
+      S.eval_E = want_E;
       S.cmd = 1;
       S.cmd_seq += 1;
     }
-    __syncthreads();  // the poses are in LDS: the helper wave starts the obstacle phase
+    __syncthreads();  // the poses are in LDS: the helper waves start
   } else {
     bsync<SM>();
   }
-  double Esum = 0.0;
-  for (int j = lane; j < n; j += kWave) {
-    double q, E = 0.0;
-    if constexpr (SM::kHelper) {
-      double dqj;
-      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, &dqj, want_E ? &E : nullptr);
-      S.dq[j] = dqj;
-    } else {
-      joint_law(c, *c.tab, *c.wr, th[j], S.pp[j], S.pm[j], &q, nullptr, want_E ? &E : nullptr);
-    }
-    S.r[j] = q;
-    Esum += E;
-  }
+  // the joint law of the solver's chunks (with four waves the first half of them; a
+  // helper takes the rest): moments into r, slopes into dq (with helpers), and each
+  // chunk's energy into ech
+  joint_law_chunks<SM>(S, c, th, want_E, 0, SM::kFour ? (nch + 1) / 2 : nch, lane);
   if constexpr (SM::kHelper) {
-    __syncthreads();  // the helper wave's contacts and contact sums are in LDS
+    __syncthreads();  // the helpers' contacts, contact sums and joint laws are in LDS
   } else {
-    obstacle_phase(S, c, n, last, lane);
+    const int cnt = obstacle_phase(S, c, n, last, lane, 0, nch, 0);
+    if (lane == 0) {
+      S.cnt0 = cnt;
+      S.cnt1 = 0;
+    }
+    bsync<SM>();
+  }
+  {
+    // the contact list: the first region's pairs, then (four waves) the second's
+    const int c0 = S.cnt0, c1 = SM::kFour ? S.cnt1 : 0;
+    const int n0 = c0 < kMaxC ? c0 : kMaxC;
+    if constexpr (SM::kFour) {
+      const int n1 = c1 < kMaxC - n0 ? c1 : kMaxC - n0;
+      for (int e = lane; e < n1; e += kWave) {
+        const int from = kMaxC + e, to = n0 + e;
+        S.ci[to] = S.ci[from];
+        S.ck[to] = S.ck[from];
+        S.cl[to] = S.cl[from];
+        S.cxx[to] = S.cxx[from];
+        S.cxy[to] = S.cxy[from];
+        S.cnx[to] = S.cnx[from];
+        S.cny[to] = S.cny[from];
+        S.ckap[to] = S.ckap[from];
+        S.cpen[to] = S.cpen[from];
+      }
+    }
+    if (lane == 0) {
+      const int tot = c0 + c1;
+      S.ncl = tot < kMaxC ? tot : kMaxC;
+      S.overflow = tot > kMaxC;
+    }
     bsync<SM>();
   }
   const int nc = S.ncl;
@@ -612,6 +672,8 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     c2x = __shfl(s2x, 0, kWave);
     c2y = __shfl(s2y, 0, kWave);
   }
+  double Esum = 0.0;  // the chunks' joint energies in chunk order (the same in every mode)
+  for (int k = 0; k < nch; ++k) Esum += S.ech[k];
   double pen2 = 0.0;
   for (int e = lane; e < nc; e += kWave) pen2 += 0.5 * c.P.kc * S.cpen[e] * S.cpen[e];
   double grow = 0.0;
@@ -632,7 +694,7 @@ __device__ double evaluate(SM& S, const Ctx& c, const double* th, bool want_E) {
     if (lane == 0) S.ru = -c.P.wg * c.l * gap - c.l * acc;
   }
   bsync<SM>();
-  return wsum(Esum) + wsum(pen2) + grow;
+  return Esum + wsum(pen2) + grow;
 }
 
 // Per-iteration set-up of the Newton system at the state last evaluated: the joint
@@ -1127,16 +1189,36 @@ __device__ int solve(SM& S, const Ctx& c, int& iters, double& rho) {
 // wave posts (between the two barriers of evaluate()), until the solver wave posts its
 // end.  A barrier with no new command also ends the loop: a barrier completes without
 // waves that have ended, so the helper never waits on a solver wave that is gone.
+// With four waves the helpers split the work by chunks of 64 links: wave 1 the joint law
+// of the second half of the chunks, wave 2 the obstacle phase of the first half (first
+// region of the contact list), wave 3 that of the second half (second region).
 template <class SM>
-__device__ void obstacle_helper(SM& S, const Ctx& c) {
+__device__ void obstacle_helper(SM& S, const Ctx& c0) {
   const int lane = threadIdx.x & (kWave - 1);
+  const int role = (int)(threadIdx.x / kWave);
+  Ctx c = c0;
   int seen = 0;
   for (;;) {
     __syncthreads();
     const int seq = S.cmd_seq, cmd = S.cmd;
     if (seq == seen || cmd != 1) break;
     seen = seq;
-    obstacle_phase(S, c, S.eval_n, S.eval_last, lane);
+    const int n = S.eval_n, nch = (n + kWave - 1) / kWave, half = (nch + 1) / 2;
+    if constexpr (SM::kFour) {
+      if (role == 1) {
+        c.n = n;
+        joint_law_chunks<SM>(S, c, S.eval_trial ? S.b : S.th, S.eval_E != 0, half, nch, lane);
+      } else if (role == 2) {
+        const int cnt = obstacle_phase(S, c, n, S.eval_last, lane, 0, half, 0);
+        if (lane == 0) S.cnt0 = cnt;
+      } else {
+        const int cnt = obstacle_phase(S, c, n, S.eval_last, lane, half, nch, kMaxC);
+        if (lane == 0) S.cnt1 = cnt;
+      }
+    } else {
+      const int cnt = obstacle_phase(S, c, n, S.eval_last, lane, 0, nch, 0);
+      if (lane == 0) S.cnt0 = cnt;
+    }
     __syncthreads();
   }
 }
@@ -1171,10 +1253,10 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
 // tip, residual, iterations, status and contact set; with D.traj the joint angles after
 // every rec_every-th step (and the last); with D.ckpt the state before every
 // ckpt_every-th step (the checkpoints from which the adjoint recomputes the states).
-template <int NMAX, bool SOFT, bool TWO>
-__global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(
+template <int NMAX, bool SOFT, int WAVES>
+__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(
     KParams P, KData D, int n_steps) {
-  using SMT = Smem<NMAX, TWO>;
+  using SMT = Smem<NMAX, (WAVES > 1), (WAVES == 4)>;
   __shared__ SMT S;
   if ((int)blockIdx.x >= D.launch_count) return;
   const int b = D.order[D.launch_first + blockIdx.x];
@@ -1190,7 +1272,7 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
   double* theta = D.theta + ii[kThetaOff];
   const size_t rec0 = (size_t)ii[kRecOff];
   const int rec_cap = ii[kRecCap];
-  if constexpr (TWO) {
+  if constexpr (WAVES > 1) {
     if (threadIdx.x >= kWave) {
       obstacle_helper(S, c);
       return;
@@ -1339,12 +1421,12 @@ __global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1)
     D.cycles[b] += (double)(clock64() - t_begin);
     D.wtime[b] += (double)(wall_clock64() - w_begin) * D.wall_period;
   }
-  if constexpr (TWO) {
+  if constexpr (WAVES > 1) {
     if (lane == 0) {
       S.cmd = 2;
       S.cmd_seq += 1;
     }
-    __syncthreads();  // releases the helper wave, which then ends
+    __syncthreads();  // releases the helper waves, which then end
   }
 }
 
@@ -1647,17 +1729,18 @@ hipError_t launch_reset(const KData& D, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Robots (workgroups) of one chain-length class resident per compute unit, with one or
-// two waves per robot.
+// Robots (workgroups) of one chain-length class resident per compute unit, with 1, 2 or 4
+// waves per robot.
 hipError_t rollout_occupancy(int nmax_class, int waves, int* per_cu) {
   const int block = waves * kWave;
-#define VS_OCC(NM)                                                                          \
-  return waves == 2                                                                         \
-             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<NM, false, true>, \
-                                                            block, 0)                       \
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, rollout_kernel<NM, false, false>, \
-                                                            block, 0);
-  if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+#define VS_OCC(NM)                                                                            \
+  return waves == 4   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                          \
+                          per_cu, rollout_kernel<NM, false, 4>, block, 0)                     \
+         : waves == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                          \
+                          per_cu, rollout_kernel<NM, false, 2>, block, 0)                     \
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(                          \
+                          per_cu, rollout_kernel<NM, false, 1>, block, 0);
+  if (waves != 1 && waves != 2 && waves != 4) return hipErrorInvalidValue;
   if (nmax_class == 64) VS_OCC(64)
   if (nmax_class == 128) VS_OCC(128)
   if (nmax_class == 256) VS_OCC(256)
@@ -1673,18 +1756,21 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nma
   if (!state_complete(D)) return hipErrorInvalidValue;
   if (D.traj && D.rec_every < 1) return hipErrorInvalidValue;
   if (D.ckpt && D.ckpt_every < 1) return hipErrorInvalidValue;
-  if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+  if (waves != 1 && waves != 2 && waves != 4) return hipErrorInvalidValue;
   dim3 grid(D.launch_count), block(waves * kWave);
-  const bool soft = P.wg > 0.0, two = waves == 2;
-#define VS_ROLL(NM)                                                                            \
-  if (soft && two)                                                                             \
-    hipLaunchKernelGGL((rollout_kernel<NM, true, true>), grid, block, 0, stream, P, D, n_steps);  \
-  else if (soft)                                                                               \
-    hipLaunchKernelGGL((rollout_kernel<NM, true, false>), grid, block, 0, stream, P, D, n_steps); \
-  else if (two)                                                                                \
-    hipLaunchKernelGGL((rollout_kernel<NM, false, true>), grid, block, 0, stream, P, D, n_steps); \
-  else                                                                                         \
-    hipLaunchKernelGGL((rollout_kernel<NM, false, false>), grid, block, 0, stream, P, D, n_steps);
+  const bool soft = P.wg > 0.0;
+#define VS_ROLL1(NM, SO, W) \
+  hipLaunchKernelGGL((rollout_kernel<NM, SO, W>), grid, block, 0, stream, P, D, n_steps);
+#define VS_ROLL(NM)                                          \
+  if (soft) {                                                \
+    if (waves == 4) { VS_ROLL1(NM, true, 4) }                \
+    else if (waves == 2) { VS_ROLL1(NM, true, 2) }           \
+    else { VS_ROLL1(NM, true, 1) }                           \
+  } else {                                                   \
+    if (waves == 4) { VS_ROLL1(NM, false, 4) }               \
+    else if (waves == 2) { VS_ROLL1(NM, false, 2) }          \
+    else { VS_ROLL1(NM, false, 1) }                          \
+  }
   if (nmax_class == 64) {
     VS_ROLL(64)
   } else if (nmax_class == 128) {
@@ -1697,6 +1783,7 @@ hipError_t launch_rollout(const KParams& P, const KData& D, int n_steps, int nma
     return hipErrorInvalidValue;
   }
 #undef VS_ROLL
+#undef VS_ROLL1
   return hipGetLastError();
 }
 

@@ -261,20 +261,21 @@ class VineSim:
         self._check(lib().vine_sim_tune_order(self.h, _stream_ptr(stream)))
 
     def set_waves(self, waves):
-        """Waves per robot (1 or 2) of the 64-, 128-, 256- and 512-link classes."""
+        """Waves per robot (1, 2 or 4) of the 64-, 128-, 256- and 512-link classes."""
         w = (C.c_int32 * 4)(*[int(x) for x in waves])
         self._check(lib().vine_sim_set_waves(self.h, w))
 
     def autotune(self, stream=None) -> dict:
-        """Measure one and two waves per robot for each class, keep the faster
+        """Measure 1, 2 and 4 waves per robot for each class, keep the fastest
         (vine_sim_autotune); the robots end reset."""
         w = (C.c_int32 * 4)()
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * 12)()
         cached = C.c_int32()
         self._check(lib().vine_sim_autotune(self.h, w, ms, C.byref(cached), _stream_ptr(stream)))
         return {"waves": [int(x) for x in w], "cached": bool(cached.value),
-                "ms_one_wave": [ms[2 * c] for c in range(4)],
-                "ms_two_waves": [ms[2 * c + 1] for c in range(4)]}
+                "ms_one_wave": [ms[3 * c] for c in range(4)],
+                "ms_two_waves": [ms[3 * c + 1] for c in range(4)],
+                "ms_four_waves": [ms[3 * c + 2] for c in range(4)]}
 
     def reset(self, stream=None):
         self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))
