@@ -378,7 +378,7 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
  *
  * Device memory is a budget, not a worst case: a robot of n links and K obstacles takes
  * n rows of a row pool (joint angle, sPAM coverage and one growth step's records per
- * row, 84 bytes) and K entries of an obstacle pool (36 bytes), allocated first-fit on
+ * row, 92 bytes) and K entries of an obstacle pool (36 bytes), allocated first-fit on
  * admission and freed when it is read back.
  *
  * vine_server_tick never waits for the device.  It reads back the groups whose launch
@@ -399,7 +399,7 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
 typedef struct vine_server vine_server;
 
 /* slots: robots resident at once; hbm_bytes: device memory for the pools and per-slot
- * rows, split so that the pools hold floor((hbm_bytes - 140 slots) / (84 max_links +
+ * rows, split so that the pools hold floor((hbm_bytes - 148 slots) / (92 max_links +
  * 36 max_obstacles)) robots at the bounds (more of smaller ones); max_links /
  * max_obstacles / max_spams bound each robot (<= VINE_MAX_LINKS / VINE_MAX_OBSTACLES /
  * VINE_MAX_SPAMS).  Device and pinned host memory are allocated here, once.  Up to 8

@@ -398,7 +398,7 @@ class VineServer:
         L = lib()
         self._p = params if params is not None else default_params(**over)
         if hbm_bytes is None:
-            hbm_bytes = int(slots) * (84 * int(max_links) + 36 * int(max_obstacles) + 140)
+            hbm_bytes = int(slots) * (92 * int(max_links) + 36 * int(max_obstacles) + 148)
         h = C.c_void_p()
         rc = L.vine_server_create(C.byref(self._p), int(slots), int(hbm_bytes), int(max_links),
                                   int(max_obstacles), int(max_spams), C.byref(h))

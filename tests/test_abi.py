@@ -92,8 +92,8 @@ def test_server_rejects_bad_sizes_before_the_device():
     assert L.vine_server_create(C.byref(p), 0, 1 << 30, 64, 8, 4, C.byref(h)) == V.VINE_EINVAL
     assert L.vine_server_create(C.byref(p), 8, 1 << 30, V.MAX_LINKS + 1, 8, 4, C.byref(h)) == \
         V.VINE_ECAPACITY
-    # a budget below one robot at the bounds (84 B per link row, 36 B per obstacle)
-    assert L.vine_server_create(C.byref(p), 8, 84 * 64 + 36 * 8, 64, 8, 4, C.byref(h)) == \
+    # a budget below one robot at the bounds (92 B per link row, 36 B per obstacle)
+    assert L.vine_server_create(C.byref(p), 8, 92 * 64 + 36 * 8, 64, 8, 4, C.byref(h)) == \
         V.VINE_EINVAL
     assert L.vine_server_tick(None, 4, None) == V.VINE_EINVAL
     assert L.vine_server_poll(None, None, None, 0) == V.VINE_EINVAL

@@ -17,9 +17,9 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def _alone(work, stream):
+def _alone(work, stream, **params):
     from paper_2509_15180_amd import vinesim as V
-    with V.VineSim(work) as sim:
+    with V.VineSim(work, V.default_params(**params)) as sim:
         sim.rollout(-1, stream=stream)
         stream.synchronize()
         return sim.read_all()
@@ -53,9 +53,9 @@ def _drive(srv, reqs, per_round=2, limit_s=600.0):
     return done, rounds, peak_rows
 
 
-def _check_alone(srv, reqs, stream):
+def _check_alone(srv, reqs, stream, **params):
     for r in reqs:
-        out = _alone(r.work, stream)
+        out = _alone(r.work, stream, **params)
         for k in range(r.work.n_inst):
             tip, th = srv.result(r.rid, k)
             n = int(r.work.inst_i[k, 0])
@@ -63,21 +63,24 @@ def _check_alone(srv, reqs, stream):
             assert np.array_equal(tip, out["tip"][k, n - 1]), (r.rid, k)
 
 
-def test_mixed_stream_equals_alone():
+@pytest.mark.parametrize("wg", [0.0, 2000.0])
+def test_mixed_stream_equals_alone(wg):
+    """Hard growth, and soft growth (the tip length and the growth schedule served too)."""
     import torch
 
     from paper_2509_15180_amd import vinesim as V
     torch.cuda.set_device(0)
     reqs = W.config5_requests(10, n_max=160, k_max=48, s_max=6)
     stream = torch.cuda.current_stream()
-    with V.VineServer(slots=24, max_links=160, max_obstacles=48, max_spams=8) as srv:
+    with V.VineServer(slots=24, max_links=160, max_obstacles=48, max_spams=8,
+                      growth_stiffness=wg) as srv:
         done, rounds, peak = _drive(srv, reqs)
         st = srv.stats()
         print(f"server: {rounds} rounds, {st['joint_updates']} joint-updates, "
               f"worst statuses {sorted(set(done.values()))}", flush=True)
         assert st["completed"] == len(reqs) and st["queued"] == 0 and st["active"] == 0
         assert st["joint_updates"] == sum(r.work.joint_updates() for r in reqs)
-        _check_alone(srv, reqs, stream)
+        _check_alone(srv, reqs, stream, growth_stiffness=wg)
         for r in reqs:
             srv.release(r.rid)
 
