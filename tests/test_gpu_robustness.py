@@ -36,6 +36,8 @@ def _check(work):
           f"sets identical {same.sum()}/{len(same)}", flush=True)
     ok = (dth <= TOL_TH) & (dtip <= TOL_TIP) & same
     assert ok.sum() >= len(ok) - 1, np.nonzero(~ok)[0]
+    from test_gpu_parity import _misses_are_minima
+    _misses_are_minima(work, ref, ok, T)
     return got
 
 
