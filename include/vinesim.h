@@ -215,8 +215,12 @@ int32_t vine_sim_rollout(vine_sim* h, int32_t n_steps, int32_t record_every, int
  * is a work estimate (links^2 x (4 + obstacles), longest first); this call replaces it,
  * inside each class, by the cycles each robot measured in the rollouts since the last
  * reset (VINE_F_CYCLES), longest first, for the launches that follow (repeated rollouts
- * of the same batch, as in a design search).  Robots never interact, so results do not
- * depend on the order.  Synchronises the stream.  Errors: VINE_EINVAL, VINE_EDEVICE. */
+ * of the same batch, as in a design search).  The class launches, which run
+ * concurrently, are issued longest chains first at create; this call reorders them by
+ * their slowest robot, slowest first, so that robot's workgroup finds the compute units
+ * free (captured rollouts are recaptured if the order changes).  Robots never interact,
+ * so results do not depend on either order.  Synchronises the stream.  Errors:
+ * VINE_EINVAL, VINE_EDEVICE. */
 int32_t vine_sim_tune_order(vine_sim* h, void* stream);
 
 /* vine_sim_reset followed by vine_sim_rollout(h, -1, record_every, ckpt_every, stream)

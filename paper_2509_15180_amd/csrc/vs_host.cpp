@@ -420,6 +420,11 @@ struct vine_sim {
   std::vector<int> order_h;  // host copy of the launch order
   int cls_first[kClasses] = {0, 0, 0, 0}, cls_count[kClasses] = {0, 0, 0, 0};
   int waves[kClasses] = {2, 2, 2, 2};  // per robot in the class's rollout launches
+  // the order in which the class launches are issued: a launch lasts as long as its
+  // slowest robot, so the class holding the slowest robot goes first and its first
+  // workgroups (that robot) find the compute units free; longest chains first until
+  // measured
+  int cls_order[kClasses] = {3, 2, 1, 0};
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   // vine_sim_rollout_graph: reset + full rollout captured once per (rec_every, ckpt_every)
@@ -579,7 +584,8 @@ hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch
     return launch(kClassLinks[only], D, stream);
   }
   hipError_t e = hipEventRecord(h->ev_fork, stream);
-  for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
+  for (int i = 0; i < vine_sim::kClasses && e == hipSuccess; ++i) {
+    const int c = h->cls_order[i];
     if (h->cls_count[c] == 0) continue;
     e = hipStreamWaitEvent(h->cls_stream[c], h->ev_fork, 0);
     D.launch_first = h->cls_first[c];
@@ -961,10 +967,20 @@ int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("read cycles: ") + hipGetErrorString(e));
+  double slowest[vine_sim::kClasses] = {0.0, 0.0, 0.0, 0.0};
   for (int c = 0; c < vine_sim::kClasses; ++c) {
     auto first = h->order_h.begin() + h->cls_first[c];
     std::stable_sort(first, first + h->cls_count[c],
                      [&](int a, int b) { return cyc[a] > cyc[b]; });
+    if (h->cls_count[c] > 0) slowest[c] = cyc[*first];
+  }
+  // issue the class launches slowest robot first (ties: longer chains first)
+  int ord[vine_sim::kClasses] = {3, 2, 1, 0};
+  std::stable_sort(ord, ord + vine_sim::kClasses,
+                   [&](int a, int b) { return slowest[a] > slowest[b]; });
+  if (!std::equal(ord, ord + vine_sim::kClasses, h->cls_order)) {
+    std::copy(ord, ord + vine_sim::kClasses, h->cls_order);
+    drop_graphs(h);  // the captures hold the launch order
   }
   e = hipMemcpyAsync(h->order, h->order_h.data(), sizeof(int) * h->order_h.size(),
                      hipMemcpyHostToDevice, s);
