@@ -136,10 +136,17 @@ def timed_batch(torch, V, work, wl, args, stream):
     autotune = None
     if tuned:  # launch order from the cycles the first rollout measured per robot
         sim.tune_order(stream=stream)
-        # waves per robot of each class, measured (or taken from the configuration's cache)
-        a0 = time.perf_counter()
-        autotune = sim.autotune(stream=stream)
-        autotune["seconds"] = time.perf_counter() - a0
+        if args.waves:  # a given configuration (as the counter runs take the timed one)
+            sim.set_waves([int(x) for x in args.waves.split(",")])
+            sim.set_head(args.head, 4, stream=stream)
+            autotune = {"waves": [int(x) for x in args.waves.split(",")], "given": True,
+                        "head": sim.head()}
+        else:
+            # waves per robot of each class and the head of the slowest robots, measured
+            # (or taken from the configuration's cache)
+            a0 = time.perf_counter()
+            autotune = sim.autotune(stream=stream)
+            autotune["seconds"] = time.perf_counter() - a0
 
     def one_step():
         if args.eager:
@@ -251,6 +258,12 @@ def main():
                     help="time eager reset + rollout calls instead of the captured graph")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the create-time launch order (no vine_sim_tune_order)")
+    ap.add_argument("--waves", default="",
+                    help="waves per robot of the 64/128/256/512-link classes, e.g. 2,2,2,2, "
+                         "instead of the autotuner's choice (with --head)")
+    ap.add_argument("--head", type=float, default=0.0,
+                    help="with --waves: the head fraction (robots at or above it of the "
+                         "slowest's measured cycles run with four waves in a launch of their own)")
     ap.add_argument("--calibrate-copy-mb", type=float, default=0.0,
                     help="first run one plain device copy of this many MB (read + write), the "
                          "reference for scaling hardware byte counters")

@@ -348,16 +348,42 @@ int32_t vine_sim_occupancy(int32_t waves, int32_t per_cu[4], int32_t* compute_un
  * captured rollouts when a value changes.  Errors: VINE_EINVAL. */
 int32_t vine_sim_set_waves(vine_sim* h, const int32_t waves[4]);
 
+/* The head: the robots whose cycles, as vine_sim_tune_order last measured them, are at
+ * least `fraction` of the slowest robot's, of any class, taken out of their classes and
+ * run as one launch of their own (sized for the longest of them) with `waves` per robot,
+ * issued before the classes' launches and concurrent with them.  A batch lasts at least
+ * as long as its slowest robot, which more waves per robot shorten, while fewer waves per
+ * robot keep more robots on the device; the head gives the few slowest robots the first
+ * and the rest the second.  fraction 0 (the default) or no measured cycles: no head.
+ * Results are bitwise the same with or without a head.  Drops the captured rollouts when
+ * the launches change; writes the launch order on the stream and synchronises it.
+ * Errors: VINE_EINVAL (fraction outside [0, 1], waves not 1, 2 or 4), VINE_EDEVICE. */
+int32_t vine_sim_set_head(vine_sim* h, double fraction, int32_t waves, void* stream);
+
+/* The head as set (fraction, waves per robot, robots in it; each argument host or NULL)
+ * and ms (host, 6, or NULL): the autotuner's times of the whole batch, [3 k + j] with the
+ * classes' wave counts of candidate k (0: each class's fastest alone, 1: two waves in
+ * every class) and head fraction j (0, 1/2, 1/4); 0 when not measured.
+ * Errors: VINE_EINVAL. */
+int32_t vine_sim_head(const vine_sim* h, double* fraction, int32_t* waves, int32_t* count,
+                      double ms[6]);
+
 /* Autotuner: for each chain-length class present, time the class's rollout from zero
- * length to full with 1, 2 and 4 waves per robot, in the handle's current launch order,
- * keep the fastest (vine_sim_set_waves; 2 unless another measured faster), and remember
- * the choice for this configuration (a hash of the parameters and every input given at
- * create) in a cache of the process, so that later handles of the same configuration take
- * it without measuring.  waves (host, 4, or NULL): the choice, 0 for empty classes; ms
- * (host, 12, or NULL): [3 c + k] the time of class c with 1, 2, 4 waves for k = 0, 1, 2
- * (0 when not measured); cached (host or NULL): 1 when taken from the cache.  Measuring
- * runs the rollouts, so the robots end reset to zero length.  Synchronises the stream.
- * Errors: VINE_EINVAL, VINE_EDEVICE. */
+ * length to full with 1, 2 and 4 waves per robot (without a head), in the handle's
+ * current launch order, and keep the fastest (vine_sim_set_waves; 2 unless another
+ * measured faster); then, if vine_sim_tune_order has measured the robots, time the whole
+ * batch as it is launched with those wave counts and with two waves in every class, each
+ * with no head and with heads of four waves per robot at fractions 1/2 and 1/4
+ * (vine_sim_set_head), and keep the fastest (ties: the earlier).  The
+ * choice is remembered for this configuration (a hash of the parameters and every input
+ * given at create) in a cache of the process, so that later handles of the same
+ * configuration take it without measuring (the head part is measured, once, by the first
+ * call on a handle whose robots are measured; a head needs the handle's own cycles).
+ * waves (host, 4, or NULL): the choice, 0 for classes with no robot; ms (host, 12, or
+ * NULL): [3 c + k] the time of class c with 1, 2, 4 waves for k = 0, 1, 2 (0 when not
+ * measured); cached (host or NULL): 1 when the wave counts were taken from the cache.
+ * Measuring runs the rollouts, so the robots end reset to zero length.  Synchronises the
+ * stream.  Errors: VINE_EINVAL, VINE_EDEVICE. */
 int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t* cached,
                           void* stream);
 

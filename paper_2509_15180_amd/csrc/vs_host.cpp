@@ -425,6 +425,15 @@ struct vine_sim {
   // workgroups (that robot) find the compute units free; longest chains first until
   // measured
   int cls_order[kClasses] = {3, 2, 1, 0};
+  std::vector<int> cls_h;     // each robot's class
+  std::vector<double> cyc_h;  // each robot's cycles, as vine_sim_tune_order last read them
+  // The head: the robots whose measured cycles are at least head_frac of the slowest's,
+  // of any class, placed first in the launch order and run as one launch of their own
+  // (sized for the longest of them) with head_waves per robot, beside the classes'
+  // launches of the rest.  Empty until measured, or with head_frac = 0.
+  double head_frac = 0.0;
+  int head_waves = 4, head_count = 0, head_links = 0;
+  double head_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // the autotuner's whole-batch times
   hipStream_t cls_stream[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {nullptr, nullptr, nullptr, nullptr};
   // vine_sim_rollout_graph: reset + full rollout captured once per (rec_every, ckpt_every)
@@ -566,39 +575,99 @@ int link_class(int n) {
   return c;
 }
 
-// Run launch(class_links, D) for every non-empty class.  A single class goes on the
-// caller's stream; several fork onto the handle's class streams and join back, so
-// that short and long chains share the device.
+// Run launch(links, waves, D) for the head and every non-empty class (links: the class's
+// longest chain, waves: per robot in its rollout launches).  A single launch goes on the
+// caller's stream; several fork onto the handle's class streams and join back, so that
+// short and long chains share the device; the head, issued first, runs on the caller's
+// stream after the fork.
 template <typename F>
 hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch) {
-  int used = 0, only = -1;
+  int used = h->head_count > 0 ? 1 : 0, only = -1;
   for (int c = 0; c < vine_sim::kClasses; ++c)
     if (h->cls_count[c] > 0) {
       ++used;
       only = c;
     }
   if (used <= 1) {
+    if (h->head_count > 0) {
+      D.launch_first = 0;
+      D.launch_count = h->head_count;
+      return launch(h->head_links, h->head_waves, D, stream);
+    }
     if (only < 0) return hipSuccess;
     D.launch_first = h->cls_first[only];
     D.launch_count = h->cls_count[only];
-    return launch(kClassLinks[only], D, stream);
+    return launch(kClassLinks[only], h->waves[only], D, stream);
   }
   hipError_t e = hipEventRecord(h->ev_fork, stream);
+  if (e == hipSuccess && h->head_count > 0) {
+    D.launch_first = 0;
+    D.launch_count = h->head_count;
+    e = launch(h->head_links, h->head_waves, D, stream);
+  }
   for (int i = 0; i < vine_sim::kClasses && e == hipSuccess; ++i) {
     const int c = h->cls_order[i];
     if (h->cls_count[c] == 0) continue;
     e = hipStreamWaitEvent(h->cls_stream[c], h->ev_fork, 0);
     D.launch_first = h->cls_first[c];
     D.launch_count = h->cls_count[c];
-    if (e == hipSuccess) e = launch(kClassLinks[c], D, h->cls_stream[c]);
+    if (e == hipSuccess) e = launch(kClassLinks[c], h->waves[c], D, h->cls_stream[c]);
     if (e == hipSuccess) e = hipEventRecord(h->ev_join[c], h->cls_stream[c]);
     if (e == hipSuccess) e = hipStreamWaitEvent(stream, h->ev_join[c], 0);
   }
   return e;
 }
 
-// waves per robot of the rollout launches of the class of `links` (autotuned: 1 or 2)
-int class_waves(const vine_sim* h, int links) { return h->waves[link_class(links)]; }
+// The launch order from the robots' measured cycles (none measured: the current order):
+// the head (robots at or above head_frac of the slowest's cycles, slowest first), then
+// each class's other robots, slowest first; the class launches are issued with the class
+// of the slowest remaining robot first (ties: longer chains first).  Drops the captured
+// rollouts if the order changed, and copies it to the device on stream s.
+hipError_t arrange(vine_sim* h, hipStream_t s) {
+  const std::vector<double>& cyc = h->cyc_h;
+  const bool measured = cyc.size() == (size_t)h->B;
+  double top = 0.0;
+  if (measured)
+    for (double x : cyc) top = std::max(top, x);
+  const bool use_head = measured && h->head_frac > 0.0 && top > 0.0;
+  std::vector<int> head, cls[vine_sim::kClasses];
+  for (int b : h->order_h) {
+    if (use_head && cyc[b] >= h->head_frac * top) head.push_back(b);
+    else cls[h->cls_h[b]].push_back(b);
+  }
+  auto slower = [&](int a, int b) { return cyc[a] > cyc[b]; };
+  double slowest[vine_sim::kClasses] = {0.0, 0.0, 0.0, 0.0};
+  if (measured) {
+    std::stable_sort(head.begin(), head.end(), slower);
+    for (int c = 0; c < vine_sim::kClasses; ++c) {
+      std::stable_sort(cls[c].begin(), cls[c].end(), slower);
+      if (!cls[c].empty()) slowest[c] = cyc[cls[c].front()];
+    }
+  }
+  std::vector<int> order(head);
+  int links = 0;
+  for (int b : head) links = std::max(links, kClassLinks[h->cls_h[b]]);
+  for (int c = 0; c < vine_sim::kClasses; ++c) {
+    h->cls_first[c] = (int)order.size();
+    h->cls_count[c] = (int)cls[c].size();
+    order.insert(order.end(), cls[c].begin(), cls[c].end());
+  }
+  int ord[vine_sim::kClasses] = {3, 2, 1, 0};
+  std::stable_sort(ord, ord + vine_sim::kClasses,
+                   [&](int a, int b) { return slowest[a] > slowest[b]; });
+  bool changed = order != h->order_h || (int)head.size() != h->head_count ||
+                 links != h->head_links ||
+                 !std::equal(ord, ord + vine_sim::kClasses, h->cls_order);
+  h->order_h = order;
+  h->head_count = (int)head.size();
+  h->head_links = links;
+  std::copy(ord, ord + vine_sim::kClasses, h->cls_order);
+  if (changed) drop_graphs(h);  // the captures hold the launches
+  hipError_t e = hipMemcpyAsync(h->order, h->order_h.data(), sizeof(int) * h->order_h.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
 
 template <typename F>
 hipError_t for_each_class(vine_sim* h, hipStream_t stream, F launch) {
@@ -745,7 +814,11 @@ int32_t vine_sim_create(const vine_params* params, const vine_instance* inst, in
     if (ca != cb) return ca < cb;
     return cost(a) > cost(b);
   });
-  for (int b = 0; b < n_inst; ++b) h->cls_count[link_class(inst[b].n_links)]++;
+  h->cls_h.resize(n_inst);
+  for (int b = 0; b < n_inst; ++b) {
+    h->cls_h[b] = link_class(inst[b].n_links);
+    h->cls_count[h->cls_h[b]]++;
+  }
   for (int c = 1; c < vine_sim::kClasses; ++c)
     h->cls_first[c] = h->cls_first[c - 1] + h->cls_count[c - 1];
   h->tables_h.resize(h->link_lens.size());
@@ -939,9 +1012,9 @@ static int32_t advance(vine_sim* h, int32_t n_steps, int32_t record_every, int32
   if (n_steps == 0) return VINE_OK;
   const vs::KParams kp = kparams(h->prm);
   hipError_t e = for_each_class(h, (hipStream_t)stream, kdata_rec(h, record_every, ckpt_every),
-                                [&](int links, const vs::KData& D, hipStream_t s) {
+                                [&](int links, int waves, const vs::KData& D, hipStream_t s) {
                                   return vs::launch_rollout(kp, D, n_steps, links,
-                                                            class_waves(h, links), s);
+                                                            waves, s);
                                 });
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   note_rec(h, record_every, ckpt_every);
@@ -967,25 +1040,34 @@ int32_t vine_sim_tune_order(vine_sim* h, void* stream) {
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("read cycles: ") + hipGetErrorString(e));
-  double slowest[vine_sim::kClasses] = {0.0, 0.0, 0.0, 0.0};
-  for (int c = 0; c < vine_sim::kClasses; ++c) {
-    auto first = h->order_h.begin() + h->cls_first[c];
-    std::stable_sort(first, first + h->cls_count[c],
-                     [&](int a, int b) { return cyc[a] > cyc[b]; });
-    if (h->cls_count[c] > 0) slowest[c] = cyc[*first];
-  }
-  // issue the class launches slowest robot first (ties: longer chains first)
-  int ord[vine_sim::kClasses] = {3, 2, 1, 0};
-  std::stable_sort(ord, ord + vine_sim::kClasses,
-                   [&](int a, int b) { return slowest[a] > slowest[b]; });
-  if (!std::equal(ord, ord + vine_sim::kClasses, h->cls_order)) {
-    std::copy(ord, ord + vine_sim::kClasses, h->cls_order);
-    drop_graphs(h);  // the captures hold the launch order
-  }
-  e = hipMemcpyAsync(h->order, h->order_h.data(), sizeof(int) * h->order_h.size(),
-                     hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  h->cyc_h = cyc;
+  e = arrange(h, s);
   if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("write order: ") + hipGetErrorString(e));
+  return VINE_OK;
+}
+
+int32_t vine_sim_set_head(vine_sim* h, double fraction, int32_t waves, void* stream) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  if (!(fraction >= 0.0 && fraction <= 1.0))
+    return fail(h, VINE_EINVAL, "head fraction must be in [0, 1]");
+  if (waves != 1 && waves != 2 && waves != 4)
+    return fail(h, VINE_EINVAL, "waves per robot must be 1, 2 or 4");
+  h->head_frac = fraction;
+  if (h->head_waves != waves) drop_graphs(h);
+  h->head_waves = waves;
+  hipError_t e = arrange(h, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("write order: ") + hipGetErrorString(e));
+  return VINE_OK;
+}
+
+int32_t vine_sim_head(const vine_sim* h, double* fraction, int32_t* waves, int32_t* count,
+                      double ms[6]) {
+  if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
+  if (fraction) *fraction = h->head_frac;
+  if (waves) *waves = h->head_waves;
+  if (count) *count = h->head_count;
+  if (ms)
+    for (int k = 0; k < 6; ++k) ms[k] = h->head_ms[k];
   return VINE_OK;
 }
 
@@ -1004,17 +1086,23 @@ int32_t vine_sim_set_waves(vine_sim* h, const int32_t waves[4]) {
 }
 
 namespace {
-// the autotuner's measurements, per configuration (hash of the parameters and inputs)
+// the autotuner's choices, per configuration (hash of the parameters and inputs)
+struct Tuned {
+  std::array<int32_t, vine_sim::kClasses> waves;
+  double head_frac;
+  bool head_tuned;  // the head was measured (needs the robots' measured cycles)
+};
 std::mutex g_tune_mu;
-std::map<uint64_t, std::array<int32_t, vine_sim::kClasses>> g_tune;
+std::map<uint64_t, Tuned> g_tune;
 }  // namespace
 
 int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t* cached,
                           void* stream) {
   if (!h) return fail(nullptr, VINE_EINVAL, "null handle");
   hipStream_t s = (hipStream_t)stream;
-  std::array<int32_t, vine_sim::kClasses> best = {2, 2, 2, 2};
+  Tuned best{{2, 2, 2, 2}, 0.0, false};
   double t[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double th[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   bool hit = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1024,13 +1112,20 @@ int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t*
       hit = true;
     }
   }
+  const bool measured = h->cyc_h.size() == (size_t)h->B;
+  const bool tune_head = measured && !(hit && best.head_tuned);
   hipError_t e = hipSuccess;
-  if (!hit) {
-    // each class alone, from zero length to full, with 1, 2 and 4 waves per robot
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!hit || tune_head) {
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const vs::KParams kp = kparams(h->prm);
+  }
+  const vs::KParams kp = kparams(h->prm);
+  if (!hit) {
+    // each class alone (the head dissolved), from zero length to full, with 1, 2 and 4
+    // waves per robot
+    h->head_frac = 0.0;
+    if (e == hipSuccess) e = arrange(h, s);
     for (int c = 0; c < vine_sim::kClasses && e == hipSuccess; ++c) {
       if (h->cls_count[c] == 0) continue;
       vs::KData D = kdata(h);
@@ -1048,29 +1143,77 @@ int32_t vine_sim_autotune(vine_sim* h, int32_t waves[4], double ms[12], int32_t*
         t[3 * c + k] = f;
       }
       // the fastest; two waves (the default) unless another measured faster
-      best[c] = 2;
+      best.waves[c] = 2;
       double tb = t[3 * c + 1];
       if (t[3 * c] < tb) {
-        best[c] = 1;
+        best.waves[c] = 1;
         tb = t[3 * c];
       }
-      if (t[3 * c + 2] < tb) best[c] = 4;
+      if (t[3 * c + 2] < tb) best.waves[c] = 4;
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+  }
+  auto set_waves = [&](const std::array<int32_t, vine_sim::kClasses>& w) {
+    for (int c = 0; c < vine_sim::kClasses; ++c) {
+      if (h->waves[c] != w[c]) drop_graphs(h);
+      h->waves[c] = w[c];
+    }
+  };
+  if (h->head_waves != 4) drop_graphs(h);
+  h->head_waves = 4;
+  if (tune_head) {
+    // The whole batch as it is launched: the classes with their fastest wave counts alone,
+    // or with two waves each, and with no head or with the robots at or above 1/2 or 1/4
+    // of the slowest's measured cycles in a head of four waves per robot.  The batch lasts
+    // at least as long as its slowest robot, which more waves shorten, while fewer waves
+    // per robot keep more robots on the device; which balance wins depends on the batch.
+    const std::array<int32_t, vine_sim::kClasses> cand[2] = {best.waves, {2, 2, 2, 2}};
+    const double fr[3] = {0.0, 0.5, 0.25};
+    int kb = 0;  // the fastest (ties: the earlier candidate)
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+      if (k >= 3 && cand[1] == cand[0]) break;
+      set_waves(cand[k / 3]);
+      h->head_frac = fr[k % 3];
+      e = arrange(h, s);
+      if (e == hipSuccess) e = vs::launch_reset(kdata(h), s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = for_each_class(h, s, [&](int links, int w, const vs::KData& D, hipStream_t cs) {
+          return vs::launch_rollout(kp, D, h->T, links, w, cs);
+        });
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float f = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+      th[k] = f;
+      if (th[k] < th[kb]) kb = k;
+    }
+    best.waves = cand[kb / 3];
+    best.head_frac = fr[kb % 3];
+    best.head_tuned = true;
+  }
+  set_waves(best.waves);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!hit || tune_head) {  // the measurements ran rollouts: end reset
     if (e == hipSuccess) e = vs::launch_reset(kdata(h), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
     h->traj_valid = false;
     h->traj_all = h->ckpt_all = true;
     h->ckpt_any = false;
+  }
+  h->head_frac = best.head_frac;
+  if (e == hipSuccess) e = arrange(h, s);
+  if (e != hipSuccess) return fail(h, VINE_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  if (!hit || tune_head) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[h->config_hash] = best;
   }
-  int32_t r = vine_sim_set_waves(h, best.data());
-  if (r != VINE_OK) return r;
-  if (waves)
-    for (int c = 0; c < vine_sim::kClasses; ++c) waves[c] = h->cls_count[c] > 0 ? best[c] : 0;
+  for (int k = 0; k < 6; ++k) h->head_ms[k] = th[k];
+  if (waves) {
+    bool present[vine_sim::kClasses] = {false, false, false, false};
+    for (int c : h->cls_h) present[c] = true;
+    for (int c = 0; c < vine_sim::kClasses; ++c) waves[c] = present[c] ? best.waves[c] : 0;
+  }
   if (ms)
     for (int k = 0; k < 12; ++k) ms[k] = t[k];
   if (cached) *cached = hit ? 1 : 0;
@@ -1110,9 +1253,9 @@ int32_t vine_sim_rollout_graph(vine_sim* h, int32_t record_every, int32_t ckpt_e
       hipError_t le = vs::launch_reset(kdata(h), h->cap_stream);
       if (le == hipSuccess)
         le = for_each_class(h, h->cap_stream, kdata_rec(h, record_every, ckpt_every),
-                            [&](int links, const vs::KData& D, hipStream_t s) {
+                            [&](int links, int waves, const vs::KData& D, hipStream_t s) {
                               return vs::launch_rollout(kp, D, h->T, links,
-                                                        class_waves(h, links), s);
+                                                        waves, s);
                             });
       e = hipStreamEndCapture(h->cap_stream, &graph);  // ends the capture in every case
       if (e == hipSuccess) e = le;
@@ -1241,7 +1384,7 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
   e = vs::launch_zero3(dL_dP, dL_ds_start, dL_ds_end, h->S, s);
   if (e == hipSuccess && (!step_weights || full_traj)) {
     const vs::GradPart one{nullptr, nullptr, nullptr, 1, 1};
-    e = for_each_class(h, s, [&](int links, const vs::KData& D, hipStream_t cs) {
+    e = for_each_class(h, s, [&](int links, int, const vs::KData& D, hipStream_t cs) {
       return vs::launch_grad(kp, D, goal, step_weights, h->T, 0, h->traj, h->n_rec, one, dL_dP,
                              dL_ds_start, dL_ds_end, loss, adj_status, links, cs);
     });
@@ -1278,12 +1421,12 @@ static int32_t grad_impl(vine_sim* h, const double* goal, const double* step_wei
       const int t0 = q * ce, len = std::min(ce, h->T - t0);
       e = vs::launch_seg_load(Dseg, h->ii, h->ckpt, h->tcur, h->n_ckpt, q, ce, s);
       if (e == hipSuccess)
-        e = for_each_class(h, s, Dseg, [&](int links, const vs::KData& D, hipStream_t cs) {
-          return vs::launch_rollout(kp, D, len, links, class_waves(h, links), cs);
+        e = for_each_class(h, s, Dseg, [&](int links, int waves, const vs::KData& D, hipStream_t cs) {
+          return vs::launch_rollout(kp, D, len, links, waves, cs);
         });
       const vs::GradPart part{g->gsums, g->gloss, g->gstat, q == 0, q == h->n_ckpt - 1};
       if (e == hipSuccess)
-        e = for_each_class(h, s, [&](int links, const vs::KData& D, hipStream_t cs) {
+        e = for_each_class(h, s, [&](int links, int, const vs::KData& D, hipStream_t cs) {
           return vs::launch_grad(kp, D, goal, step_weights + t0, len, t0, g->traj, ce, part,
                                  dL_dP, dL_ds_start, dL_ds_end, loss, adj_status, links, cs);
         });

@@ -1248,13 +1248,23 @@ __device__ __forceinline__ void robot_ctx(Ctx& c, const KParams& P, const KData&
   c.okind = D.okind + ii[kObsOff];
 }
 
-// One robot per workgroup of two waves: the solver wave runs the growth steps, the
-// helper wave takes the obstacle phase of every evaluation.  Per step it records the
-// tip, residual, iterations, status and contact set; with D.traj the joint angles after
-// every rec_every-th step (and the last); with D.ckpt the state before every
-// ckpt_every-th step (the checkpoints from which the adjoint recomputes the states).
+// One robot per workgroup of WAVES waves: the solver wave runs the growth steps, the
+// helper waves take the obstacle phase (and with four waves half the joint law) of every
+// evaluation.  Per step it records the tip, residual, iterations, status and contact set;
+// with D.traj the joint angles after every rec_every-th step (and the last); with D.ckpt
+// the state before every ckpt_every-th step (the checkpoints from which the adjoint
+// recomputes the states).
+// Registers: one wave per robot needs all of a SIMD's (the whole evaluation on one wave);
+// with helper waves each wave fits in half, so two waves share a SIMD and a compute unit
+// holds twice the robots (told that one wave per SIMD is the target, the compiler pads
+// the allocation past half).  The 512-link class holds one robot per compute unit by its
+// LDS alone.
 template <int NMAX, bool SOFT, int WAVES>
-__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(1, 1))) void rollout_kernel(
+constexpr int kWavesPerEu = (WAVES == 1 || NMAX > 256) ? 1 : 2;
+
+template <int NMAX, bool SOFT, int WAVES>
+__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(
+    kWavesPerEu<NMAX, SOFT, WAVES>, kWavesPerEu<NMAX, SOFT, WAVES>))) void rollout_kernel(
     KParams P, KData D, int n_steps) {
   using SMT = Smem<NMAX, (WAVES > 1), (WAVES == 4)>;
   __shared__ SMT S;

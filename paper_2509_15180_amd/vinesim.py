@@ -73,7 +73,8 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_reset", "vine_sim_read", "vine_sim_field_bytes", "vine_sim_dims",
            "vine_sim_destroy", "vine_sim_last_error", "vine_sim_spam_law", "vine_sim_trace",
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
-           "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune",
+           "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune", "vine_sim_set_head",
+           "vine_sim_head",
            "vine_server_create",
            "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
            "vine_server_release", "vine_server_stats", "vine_server_destroy",
@@ -127,6 +128,11 @@ def lib():
         L.vine_sim_autotune.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                         C.POINTER(C.c_int32), vp]
         L.vine_sim_autotune.restype = C.c_int32
+        L.vine_sim_set_head.argtypes = [vp, C.c_double, C.c_int32, vp]
+        L.vine_sim_set_head.restype = C.c_int32
+        L.vine_sim_head.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.vine_sim_head.restype = C.c_int32
         L.vine_sim_trace.argtypes = [vp, C.c_int32, C.c_int32]
         L.vine_sim_trace.restype = C.c_int32
         L.vine_sim_trace_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
@@ -265,9 +271,27 @@ class VineSim:
         w = (C.c_int32 * 4)(*[int(x) for x in waves])
         self._check(lib().vine_sim_set_waves(self.h, w))
 
+    def set_head(self, fraction: float, waves: int = 4, stream=None):
+        """Robots at or above `fraction` of the slowest's measured cycles in a launch of
+        their own with `waves` per robot (vine_sim_set_head); 0: none."""
+        self._check(lib().vine_sim_set_head(self.h, float(fraction), int(waves),
+                                            _stream_ptr(stream)))
+
+    def head(self) -> dict:
+        """The head as set, and the autotuner's whole-batch times (vine_sim_head)."""
+        f, w, n = C.c_double(), C.c_int32(), C.c_int32()
+        ms = (C.c_double * 6)()
+        self._check(lib().vine_sim_head(self.h, C.byref(f), C.byref(w), C.byref(n), ms))
+        fr = ("0", "1/2", "1/4")
+        return {"fraction": f.value, "waves": w.value, "robots": n.value,
+                "ms_whole_batch": {
+                    "fastest_alone": {fr[j]: ms[j] for j in range(3)},
+                    "two_waves": {fr[j]: ms[3 + j] for j in range(3)}}}
+
     def autotune(self, stream=None) -> dict:
-        """Measure 1, 2 and 4 waves per robot for each class, keep the fastest
-        (vine_sim_autotune); the robots end reset."""
+        """Measure 1, 2 and 4 waves per robot for each class, then the whole batch with
+        and without a head of the slowest robots, keep the fastest (vine_sim_autotune);
+        the robots end reset."""
         w = (C.c_int32 * 4)()
         ms = (C.c_double * 12)()
         cached = C.c_int32()
@@ -275,7 +299,8 @@ class VineSim:
         return {"waves": [int(x) for x in w], "cached": bool(cached.value),
                 "ms_one_wave": [ms[3 * c] for c in range(4)],
                 "ms_two_waves": [ms[3 * c + 1] for c in range(4)],
-                "ms_four_waves": [ms[3 * c + 2] for c in range(4)]}
+                "ms_four_waves": [ms[3 * c + 2] for c in range(4)],
+                "head": self.head()}
 
     def reset(self, stream=None):
         self._check(lib().vine_sim_reset(self.h, _stream_ptr(stream)))

@@ -82,6 +82,8 @@ def test_null_handle_calls_fail_cleanly():
     assert L.vine_sim_reset(None, None) == V.VINE_EINVAL
     assert L.vine_sim_rollout_graph(None, 0, 0, None) == V.VINE_EINVAL
     assert L.vine_sim_tune_order(None, None) == V.VINE_EINVAL
+    assert L.vine_sim_set_head(None, 0.5, 4, None) == V.VINE_EINVAL
+    assert L.vine_sim_head(None, None, None, None, None) == V.VINE_EINVAL
 
 
 def test_server_rejects_bad_sizes_before_the_device():
