@@ -577,9 +577,11 @@ int link_class(int n) {
 
 // Run launch(links, waves, D) for the head and every non-empty class (links: the class's
 // longest chain, waves: per robot in its rollout launches).  A single launch goes on the
-// caller's stream; several fork onto the handle's class streams and join back, so that
-// short and long chains share the device; the head, issued first, runs on the caller's
-// stream after the fork.
+// caller's stream; several fork onto the handle's streams, the head first, one stream per
+// launch in issue order, and join back, so that short and long chains share the device.
+// The caller's stream waits for the joins only once every launch is issued: a stream can
+// share a hardware queue with another, and a wait enqueued there earlier would hold back
+// the launches issued behind it.
 template <typename F>
 hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch) {
   int used = h->head_count > 0 ? 1 : 0, only = -1;
@@ -600,21 +602,23 @@ hipError_t for_each_class(vine_sim* h, hipStream_t stream, vs::KData D, F launch
     return launch(kClassLinks[only], h->waves[only], D, stream);
   }
   hipError_t e = hipEventRecord(h->ev_fork, stream);
-  if (e == hipSuccess && h->head_count > 0) {
-    D.launch_first = 0;
-    D.launch_count = h->head_count;
-    e = launch(h->head_links, h->head_waves, D, stream);
-  }
+  int slot = 0;
+  auto fork = [&](int first, int count, int links, int waves) {
+    const int k = slot++ % vine_sim::kClasses;  // five launches: the last shares the first's
+    hipStream_t cs = h->cls_stream[k];
+    e = hipStreamWaitEvent(cs, h->ev_fork, 0);
+    D.launch_first = first;
+    D.launch_count = count;
+    if (e == hipSuccess) e = launch(links, waves, D, cs);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_join[k], cs);
+  };
+  if (e == hipSuccess && h->head_count > 0) fork(0, h->head_count, h->head_links, h->head_waves);
   for (int i = 0; i < vine_sim::kClasses && e == hipSuccess; ++i) {
     const int c = h->cls_order[i];
-    if (h->cls_count[c] == 0) continue;
-    e = hipStreamWaitEvent(h->cls_stream[c], h->ev_fork, 0);
-    D.launch_first = h->cls_first[c];
-    D.launch_count = h->cls_count[c];
-    if (e == hipSuccess) e = launch(kClassLinks[c], h->waves[c], D, h->cls_stream[c]);
-    if (e == hipSuccess) e = hipEventRecord(h->ev_join[c], h->cls_stream[c]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(stream, h->ev_join[c], 0);
+    if (h->cls_count[c] > 0) fork(h->cls_first[c], h->cls_count[c], kClassLinks[c], h->waves[c]);
   }
+  for (int k = 0; k < std::min(slot, vine_sim::kClasses) && e == hipSuccess; ++k)
+    e = hipStreamWaitEvent(stream, h->ev_join[k], 0);
   return e;
 }
 
