@@ -334,7 +334,9 @@ def main():
                  "roofline_frac": j2 * flops_per_joint_eval(20.0) / (R2["kern_ms"] * 1e-3) / 1e12
                  / PEAK_FP64_TFLOPS,
                  "latency_s": {"p50": float(np.percentile(R2["robot_s"], 50)),
-                               "p99": float(np.percentile(R2["robot_s"], 99))},
+                               "p99": float(np.percentile(R2["robot_s"], 99)),
+                               "max": float(R2["robot_s"].max())},
+                 "autotune": R2["autotune"],
                  "accuracy_vs_stored_oracle_outputs": golden_accuracy("uniform", R2["out"])}
         s2.close()
 
