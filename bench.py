@@ -18,7 +18,7 @@ Other workloads (``--workload``), same JSON fields:
           ``--rate`` requests/s for ``--duration`` s after a warm-up; reports the
           sustained joint-updates/s and the p50/p99 request latency
 
-Prints one JSON line with the driver's fields plus:
+Prints one JSON line with the standard benchmark fields plus:
   latency       per-robot rollout latency (seconds its workgroup took, device wall
                 clock): p50, p99, max; and the first rollout in the create-time order
                 next to the tuned ones;

@@ -114,8 +114,8 @@ def test_spam_chebyshev_fit_accuracy():
     assert Gs[0] == 0.0 and dGs[0] == 0.0
 
 
-def test_spam_survey_sanity_values():
-    """Values recomputed with an independent scipy probe when the model was surveyed
+def test_spam_sanity_values_from_an_independent_solve():
+    """Values of Eq. 1 computed separately with scipy's elliptic integrals and root finder
     (G = F_t / P_act at l0 = 2.5 cm and 2 cm)."""
     for l0, pts in ((0.025, ((0.0, 2.8909190e-3), (0.1, 5.7144622e-4), (0.2, 2.8397449e-4),
                              (0.3, 1.0578961e-4))),
@@ -274,7 +274,7 @@ def test_single_actuator_closed_form():
     ts = optimize.brentq(f, 1e-6, 0.5, xtol=1e-16)
     assert np.allclose(th[10:21], ts, atol=1e-12) and np.all(np.abs(th[:10]) < 1e-14)
     assert np.all(np.abs(th[21:]) < 1e-14)
-    # values from the survey's independent scipy probe
+    # values computed separately with scipy (root of the joint balance, forward kinematics)
     assert abs(ts - 0.059696599816) < 1e-9
     assert abs(th.sum() - 0.6566625980) < 1e-8
     assert np.allclose(out["tip"][0, -1, :2], (0.8791988315, 0.3846745140), atol=1e-8)
