@@ -528,7 +528,7 @@ __device__ int obstacle_phase(SM& S, const Ctx& c, int n, double last_len, int l
         }
       }
     }
-    if (on) {  // read by the suffix sums below and by structured_setup
+    if (on) {  // read by evaluate()'s suffix sums and by newton_setup
       S.ps1[j] = a_s1;
       S.ps2[j] = a_fx;
       S.aux[j] = a_fy;
