@@ -449,6 +449,24 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
                            int32_t n_inst, const vine_spam* spams, int32_t n_spams,
                            const vine_obstacle* obstacles, int32_t n_obstacles);
 
+/* vine_server_submit with a starting state per robot: robot b starts grown to
+ * start_links[b] links (0 <= start_links[b] < n_links; 0 = from zero) with the joint
+ * angles start_theta[o_b .. o_b + start_links[b]), o_b the sum of the counts before it
+ * (host array, copied), and takes growth steps start_links[b] .. n_links - 1.  A growth
+ * step depends on the state only through the joint angles and the link count (Alg. 1),
+ * so a robot started from the first s links of an earlier rollout of a design with the
+ * same sPAMs over those links ends bitwise where a rollout of its design from zero
+ * ends: the planner (Alg. 2) propagates a child T steps from its parent this way.  Its
+ * records (status, tip) exist for steps start_links[b] on; the request's worst status
+ * covers those steps.  Hard growth only: with growth_stiffness > 0 a nonzero start is
+ * VINE_ESTATE.  start_links NULL: as vine_server_submit.  Errors as vine_server_submit,
+ * and VINE_EINVAL for a count outside the range, a NULL start_theta with a nonzero
+ * count or a non-finite angle; nothing is queued then. */
+int32_t vine_server_submit_from(vine_server* s, int64_t request_id, const vine_instance* inst,
+                                int32_t n_inst, const vine_spam* spams, int32_t n_spams,
+                                const vine_obstacle* obstacles, int32_t n_obstacles,
+                                const int32_t* start_links, const double* start_theta);
+
 /* One scheduling round (see above): hand over the groups read back, start reading back
  * the groups that finished, admit and launch the queued robots that fit.  Returns the
  * number of requests completed by this call, or a negative VINE_E* code.  It does not

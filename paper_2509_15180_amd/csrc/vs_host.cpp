@@ -1672,6 +1672,8 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
 
 namespace vs {
 hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream);
+hipError_t launch_slot_start(const KData& D, const int* slots, const int* start,
+                             const double* theta0, int count, hipStream_t stream);
 }
 
 namespace {
@@ -1749,6 +1751,8 @@ struct vine_server {
     std::vector<vine_spam> spams;
     std::vector<vine_obstacle> obs;
     int64_t row = -1, obs_off = -1;
+    int start = 0;               // links it starts with (vine_server_submit_from)
+    std::vector<double> theta0;  // their joint angles
   };
   struct Request {
     int n_robots = 0, n_done = 0, worst = 0;
@@ -1780,7 +1784,11 @@ struct vine_server {
   int* st_okind = nullptr;
   double* st_obs = nullptr;
   int* st_order = nullptr;
+  int* st_start = nullptr;  // links each robot of a group starts with, at the order offsets
   double* st_theta = nullptr;
+  // device-visible addresses of st_start and st_theta (read by the start kernel)
+  const int* dv_start = nullptr;
+  const double* dv_theta = nullptr;
   double* st_tip = nullptr;
   int* st_status = nullptr;
   std::string err;
@@ -1824,7 +1832,7 @@ void free_server(vine_server* s) {
   for (hipStream_t st : s->pool)
     if (st) (void)hipStreamDestroy(st);
   void* pinned[] = {s->st_ii, s->st_dd, s->st_cover, s->st_okind, s->st_obs, s->st_order,
-                    s->st_theta, s->st_tip, s->st_status};
+                    s->st_start, s->st_theta, s->st_tip, s->st_status};
   for (void* p : pinned)
     if (p) (void)hipHostFree(p);
   if (s->h) vine_sim_destroy(s->h);
@@ -1855,8 +1863,9 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
   hipStream_t sa = s->pool[lane];
   // launch order: longest expected work first
   auto cost = [&](int b) {
-    const vine_instance& I = s->live[b].inst;
-    return (double)I.n_links * I.n_links * (4.0 + I.obs_count);
+    const vine_server::Robot& r = s->live[b];
+    const double n = r.inst.n_links, s0 = r.start;
+    return (n * n - s0 * s0) * (4.0 + r.inst.obs_count);
   };
   std::stable_sort(adm.begin(), adm.end(), [&](int a, int b) { return cost(a) > cost(b); });
   int nmax = 0;
@@ -1887,6 +1896,7 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
     std::vector<double> cover;
     append_cover(I, r.spams.data(), cover);
     std::copy(cover.begin(), cover.end(), s->st_cover + 2 * row);
+    if (r.start > 0) std::copy(r.theta0.begin(), r.theta0.end(), s->st_theta + row);
     for (int k = 0; k < K; ++k) {
       const vine_obstacle& O = r.obs[k];
       s->st_okind[oo + k] = O.kind;
@@ -1912,8 +1922,16 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
   std::copy(adm.begin(), adm.end(), s->st_order + g.order_off);
   A(hipMemcpyAsync(h->order + g.order_off, s->st_order + g.order_off, sizeof(int) * g.count,
                    hipMemcpyHostToDevice, sa));
+  bool resumed = false;
+  for (int i = 0; i < g.count; ++i) {
+    s->st_start[g.order_off + i] = s->live[adm[i]].start;
+    resumed = resumed || s->live[adm[i]].start > 0;
+  }
   vs::KData D = kdata(h);
   A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
+  if (resumed)
+    A(vs::launch_slot_start(D, h->order + g.order_off, s->dv_start + g.order_off, s->dv_theta,
+                            g.count, sa));
   D.launch_first = (int)g.order_off;
   D.launch_count = g.count;
   A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], 2, sa));
@@ -2020,9 +2038,17 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
   A(halloc(&s->st_okind, (size_t)Ko));
   A(halloc(&s->st_obs, (size_t)Ko * 4));
   A(halloc(&s->st_order, B));
+  A(halloc(&s->st_start, B));
   A(halloc(&s->st_theta, (size_t)R));
   A(halloc(&s->st_tip, (size_t)R * 3));
   A(halloc(&s->st_status, (size_t)R));
+  if (e == hipSuccess) {
+    void *ds = nullptr, *dt = nullptr;
+    A(hipHostGetDevicePointer(&ds, s->st_start, 0));
+    A(hipHostGetDevicePointer(&dt, s->st_theta, 0));
+    s->dv_start = (const int*)ds;
+    s->dv_theta = (const double*)dt;
+  }
   h->B = slots;
   h->N = max_links;
   h->T = max_links;
@@ -2053,6 +2079,14 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
 int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instance* inst,
                            int32_t n_inst, const vine_spam* spams, int32_t n_spams,
                            const vine_obstacle* obstacles, int32_t n_obstacles) {
+  return vine_server_submit_from(s, request_id, inst, n_inst, spams, n_spams, obstacles,
+                                 n_obstacles, nullptr, nullptr);
+}
+
+int32_t vine_server_submit_from(vine_server* s, int64_t request_id, const vine_instance* inst,
+                                int32_t n_inst, const vine_spam* spams, int32_t n_spams,
+                                const vine_obstacle* obstacles, int32_t n_obstacles,
+                                const int32_t* start_links, const double* start_theta) {
   if (!s || !inst || n_inst < 1 || n_spams < 0 || n_obstacles < 0 || (n_spams > 0 && !spams) ||
       (n_obstacles > 0 && !obstacles))
     return sfail(s, VINE_EINVAL, "null pointer or negative count");
@@ -2076,6 +2110,20 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
         return sfail(s, VINE_EINVAL, "invalid obstacle");
     }
   }
+  // starting states: 0 <= s < n_links, finite angles, hard growth only
+  int64_t n_theta = 0;
+  if (start_links) {
+    for (int b = 0; b < n_inst; ++b) {
+      if (start_links[b] < 0 || start_links[b] >= inst[b].n_links)
+        return sfail(s, VINE_EINVAL, "starting link count outside [0, n_links)");
+      n_theta += start_links[b];
+    }
+    if (n_theta > 0 && !start_theta) return sfail(s, VINE_EINVAL, "null starting joint angles");
+    for (int64_t k = 0; k < n_theta; ++k)
+      if (!std::isfinite(start_theta[k])) return sfail(s, VINE_EINVAL, "non-finite joint angle");
+    if (n_theta > 0 && s->h->prm.growth_stiffness != 0.0)
+      return sfail(s, VINE_ESTATE, "a starting state needs hard growth (growth_stiffness 0)");
+  }
   // the sPAM table of each link length (built and uploaded on its first use)
   for (int b = 0; b < n_inst; ++b) {
     const int tid = table_for(s, inst[b].link_len);
@@ -2088,10 +2136,16 @@ int32_t vine_server_submit(vine_server* s, int64_t request_id, const vine_instan
   R.tips.assign(3 * (size_t)n_inst, 0.0);
   R.theta.resize(n_inst);
   s->reqs.emplace(request_id, std::move(R));
+  int64_t at = 0;  // this robot's first starting angle
   for (int b = 0; b < n_inst; ++b) {
     vine_server::Robot r;
     r.req = request_id;
     r.index = b;
+    if (start_links && start_links[b] > 0) {
+      r.start = start_links[b];
+      r.theta0.assign(start_theta + at, start_theta + at + r.start);
+      at += r.start;
+    }
     r.inst = inst[b];
     r.spams.assign(spams + inst[b].spam_offset, spams + inst[b].spam_offset + inst[b].spam_count);
     r.obs.assign(obstacles + inst[b].obs_offset,
@@ -2156,7 +2210,7 @@ int32_t vine_server_tick(vine_server* s) {
       std::copy(s->st_tip + 3 * (row + n - 1), s->st_tip + 3 * (row + n),
                 R.tips.begin() + 3 * (size_t)r.index);
       for (int t = 0; t < n; ++t) R.worst = std::max(R.worst, s->st_status[row + t]);
-      s->joint_updates += (int64_t)n * (n + 1) / 2;
+      s->joint_updates += (int64_t)n * (n + 1) / 2 - (int64_t)r.start * (r.start + 1) / 2;
       if (++R.n_done == R.n_robots) {
         s->completed.push_back(r.req);
         ++s->n_completed;

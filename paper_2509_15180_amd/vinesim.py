@@ -75,9 +75,8 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
            "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune", "vine_sim_set_head",
            "vine_sim_head",
-           "vine_server_create",
-           "vine_server_submit", "vine_server_tick", "vine_server_poll", "vine_server_result",
-           "vine_server_release", "vine_server_stats", "vine_server_destroy",
+           "vine_server_create", "vine_server_submit", "vine_server_submit_from",
+           "vine_server_tick", "vine_server_poll", "vine_server_result", "vine_server_release", "vine_server_stats", "vine_server_destroy",
            "vine_server_last_error")
 
 _lib = None
@@ -150,6 +149,11 @@ def lib():
                                          C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle),
                                          C.c_int32]
         L.vine_server_submit.restype = C.c_int32
+        L.vine_server_submit_from.argtypes = [vp, C.c_int64, C.POINTER(Instance), C.c_int32,
+                                              C.POINTER(Spam), C.c_int32, C.POINTER(Obstacle),
+                                              C.c_int32, C.POINTER(C.c_int32),
+                                              C.POINTER(C.c_double)]
+        L.vine_server_submit_from.restype = C.c_int32
         L.vine_server_tick.argtypes = [vp]
         L.vine_server_tick.restype = C.c_int32
         L.vine_server_poll.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32]
@@ -442,6 +446,27 @@ class VineServer:
         inst, B, spams, ns, obs, no = _pack(work)
         self._check(lib().vine_server_submit(self.h, int(request_id), inst, B, spams, ns, obs, no))
         self.n_links[int(request_id)] = [int(v) for v in work.inst_i[:, 0]]
+
+    def submit_each(self, first_id: int, work, start=None):
+        """Queue instance b of a Workload as its own request first_id + b (so that poll
+        reports each robot's worst status); the arrays are packed once and each call
+        copies only the robot's own sPAMs and obstacles.  start: None, or per robot the
+        joint angles it starts with (an empty array: from zero), as
+        vine_server_submit_from."""
+        inst, B, spams, ns, obs, no = _pack(work)
+        L = lib()
+        for b in range(B):
+            rid = int(first_id) + b
+            th = None if start is None else np.ascontiguousarray(start[b], np.float64)
+            if th is None or th.size == 0:
+                rc = L.vine_server_submit(self.h, rid, C.byref(inst[b]), 1, spams, ns, obs, no)
+            else:
+                cnt = C.c_int32(th.size)
+                rc = L.vine_server_submit_from(self.h, rid, C.byref(inst[b]), 1, spams, ns, obs,
+                                               no, C.byref(cnt),
+                                               th.ctypes.data_as(C.POINTER(C.c_double)))
+            self._check(rc)
+            self.n_links[rid] = [int(work.inst_i[b, 0])]
 
     def tick(self) -> int:
         """One non-blocking scheduling round; the number of requests it completed."""

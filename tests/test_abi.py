@@ -98,4 +98,21 @@ def test_server_rejects_bad_sizes_before_the_device():
     assert L.vine_server_create(C.byref(p), 8, 92 * 64 + 36 * 8, 64, 8, 4, C.byref(h)) == \
         V.VINE_EINVAL
     assert L.vine_server_tick(None, 4, None) == V.VINE_EINVAL
+    inst = V.Instance(n_links=4, link_len=0.02, tube_radius=0.025, body_pressure=3000.0)
+    cnt, th = C.c_int32(2), (C.c_double * 2)()
+    assert L.vine_server_submit_from(None, 1, C.byref(inst), 1, None, 0, None, 0, C.byref(cnt),
+                                     th) == V.VINE_EINVAL
     assert L.vine_server_poll(None, None, None, 0) == V.VINE_EINVAL
+
+
+def test_server_submit_each_marshals_one_robot_per_request():
+    """submit_each hands the library one instance at a time from one packed array (the
+    planner's path); on a null server the call is rejected before any device work."""
+    srv = object.__new__(V.VineServer)
+    srv.h, srv.n_links = None, {}
+    work = W.pack([dict(n=5, d=(0.02, 0.025, 4000.0, 0, 0, 0), spam=[(0.0, 0.04, 1.0, 3000.0)],
+                        kind=[0], obs=[(0.5, 0.0, 0.05, 0.0)]),
+                   dict(n=7, d=(0.02, 0.025, 4000.0, 0, 0, 0), spam=[], kind=[], obs=[])], "two")
+    with pytest.raises(V.VineError) as e:
+        srv.submit_each(10, work)
+    assert e.value.code == V.VINE_EINVAL

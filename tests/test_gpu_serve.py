@@ -144,3 +144,69 @@ def test_full_size_requests_under_a_tight_budget():
                 assert np.abs(r).max() / Mmax <= 1e-8 and lam > -1e-6
         for r in reqs:
             srv.release(r.rid)
+
+
+def test_started_robots_continue_the_rollout_bitwise():
+    """vine_server_submit_from: robots started from the state a handle reached after s
+    growth steps (sPAMs, obstacles and contacts on the way; s = 0 included) end bitwise
+    where their rollout from zero ends, and the joint-update counter counts only the
+    steps they took; invalid starts are refused with nothing queued, and soft growth
+    refuses a start."""
+    import ctypes as C
+    import time
+
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    reqs = W.config5_requests(6, n_max=160, k_max=48, s_max=4)
+    L = V.lib()
+    with V.VineServer(slots=32, max_links=160, max_obstacles=48, max_spams=8) as srv:
+        expect, steps = {}, 0
+        for r in reqs:
+            n = [int(v) for v in r.work.inst_i[:, 0]]
+            s = [n[b] * b // len(n) for b in range(len(n))]  # robot 0 from zero
+            starts = []
+            with V.VineSim(r.work) as h:  # the state after s[b] steps, robot by robot
+                for b, sb in enumerate(s):
+                    h.reset(stream=stream)
+                    if sb:
+                        h.step(sb, stream=stream)
+                    stream.synchronize()
+                    starts.append(h.read("theta")[b, :sb].copy())
+            full = _alone(r.work, stream)
+            srv.submit_each(1000 * r.rid, r.work, start=starts)
+            for b in range(len(n)):
+                expect[1000 * r.rid + b] = (full["tip"][b, n[b] - 1, :3], full["theta"][b, :n[b]])
+                steps += n[b] * (n[b] + 1) // 2 - s[b] * (s[b] + 1) // 2
+        done = {}
+        t0 = time.perf_counter()
+        while len(done) < len(expect) and time.perf_counter() - t0 < 300:
+            srv.tick()
+            for rid, st in srv.poll():
+                done[rid] = st
+        print(f"started robots: {len(expect)}, worst statuses {sorted(set(done.values()))}",
+              flush=True)
+        assert len(done) == len(expect)
+        for rid, (tip, th) in expect.items():
+            got_tip, got_th = srv.result(rid, 0)
+            assert np.array_equal(got_tip, tip) and np.array_equal(got_th, th), rid
+        assert srv.stats()["joint_updates"] == steps
+        # refused: a start at the target length, a negative one, a NULL angle array
+        inst, _, spams, ns, obs, no = V._pack(reqs[0].work)
+        n0 = int(reqs[0].work.inst_i[0, 0])
+        th = np.zeros(n0)
+        for cnt, ptr in ((n0, th.ctypes.data_as(C.POINTER(C.c_double))),
+                         (-1, th.ctypes.data_as(C.POINTER(C.c_double))), (2, None)):
+            c = C.c_int32(cnt)
+            assert L.vine_server_submit_from(srv.h, 99999, C.byref(inst[0]), 1, spams, ns, obs,
+                                             no, C.byref(c), ptr) == V.VINE_EINVAL
+        assert srv.stats()["queued"] == 0
+    with V.VineServer(slots=4, max_links=160, max_obstacles=48, max_spams=8,
+                      growth_stiffness=5.0) as soft:
+        c = C.c_int32(2)
+        th = np.zeros(2)
+        assert L.vine_server_submit_from(soft.h, 1, C.byref(inst[0]), 1, spams, ns, obs, no,
+                                         C.byref(c), th.ctypes.data_as(C.POINTER(C.c_double))) \
+            == V.VINE_ESTATE
