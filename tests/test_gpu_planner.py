@@ -1,0 +1,92 @@
+"""The batched SST* search (Sec. 5.2, Alg. 2) with the HIP path (libvinesim's server) as
+its simulator against the same search with the FP64 oracle as its simulator: every design
+the search simulates is compared with the oracle robot by robot (tolerances as in the
+parity tests, contact sets identical, statuses identical), the server's tips (each child
+started from its parent's joint angles) are bitwise those of one handle rolling the same
+designs out from zero, and with the same seed both searches build the same tree (parents, link counts, actions, which nodes are active) with tips within the tip
+tolerance.
+
+The problem's link is 23 mm: straight passive growth puts tips at multiples of the link
+length, and with 20 mm links two of them lie exactly 60 mm (the initial radius) apart, a
+tie that rounding in the last place decides either way (both are correct prunings).
+Multiples of 23 mm stay off the radii 60, 48 and 38.4 mm the schedule reaches."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_15180_amd import planner as PL
+
+pytestmark = pytest.mark.gpu
+
+TOL_TH, TOL_TIP = 1e-5, 1e-4
+
+
+def _oracle_simulator(prob):
+    def sim(designs, starts=None):  # every design from zero: starts are not used
+        work = PL.design_instances(prob, designs)
+        o = O.rollout(work, threads=16)
+        n = work.inst_i[:, 0]
+        idx = np.arange(len(n))
+        st = np.where(np.arange(o["status"].shape[1])[None, :] < n[:, None], o["status"], 0).max(1)
+        return o["tip"][idx, n - 1, :3], st, [o["theta"][q, :n[q]] for q in idx]
+    return sim
+
+
+def _recording(sim, log, tips=None):
+    def rec(designs, starts=None):
+        log.extend(designs)
+        out = sim(designs, starts)
+        if tips is not None:
+            tips.extend(out[0])
+        return out
+    return rec
+
+
+def _search(prob, sim, batch, seed, iters):
+    pl = PL.BatchedSST(prob, sim, batch, seed=seed)
+    for _ in range(iters):
+        pl.iterate()
+    return pl
+
+
+def test_planner_on_gpu_matches_the_oracle_search():
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    prob = PL.maze(0)
+    prob.max_links, prob.link_len = 40, 0.023
+    designs, served = [], []
+    server = PL.GpuSimulator(prob, 24)
+    gpu = _search(prob, _recording(server, designs, served), 24, 3, 4)
+    server.close()
+    ref = _search(prob, _oracle_simulator(prob), 24, 3, 4)
+    print(f"nodes {len(gpu.nodes)} / {len(ref.nodes)}, designs simulated {len(designs)}, "
+          f"rejected {gpu.rejected_status} / {ref.rejected_status}", flush=True)
+    assert len(gpu.nodes) == len(ref.nodes)
+    for a, b in zip(gpu.nodes, ref.nodes):
+        assert (a.parent, a.n, a.action, a.active, a.cost) == (b.parent, b.n, b.action, b.active, b.cost)
+        assert np.abs(a.tip - b.tip).max() <= TOL_TIP
+    assert gpu.r == ref.r and gpu.rejected_status == ref.rejected_status
+
+    # every design the GPU search simulated, robot by robot against the oracle
+    work = PL.design_instances(prob, designs)
+    torch.cuda.set_device(0)
+    with V.VineSim(work) as sim:
+        s = torch.cuda.current_stream()
+        sim.rollout(-1, stream=s)
+        s.synchronize()
+        got = sim.read_all()
+    o = O.rollout(work, threads=16)
+    T = work.n_max
+    n = work.inst_i[:, 0]
+    mask = np.arange(T)[None, :] < n[:, None]
+    dth = np.abs(got["theta"] - o["theta"]).max(1)
+    dtip = np.where(mask[:, :, None], np.abs(got["tip"][:, :T] - o["tip"][:, :T]), 0).max((1, 2))
+    same = np.all(np.where(mask, got["chash"][:, :T] == o["chash"][:, :T], True), 1)
+    st_same = np.array_equal(np.where(mask, got["status"][:, :T], 0), np.where(mask, o["status"][:, :T], 0))
+    print(f"designs: max dtheta {dth.max():.2e} max dtip {dtip.max():.2e} sets identical "
+          f"{same.sum()}/{len(same)} status identical {st_same}", flush=True)
+    assert dth.max() <= TOL_TH and dtip.max() <= TOL_TIP and same.all() and st_same
+    # the children started from their parents end bitwise where rollouts from zero end
+    assert np.array_equal(np.asarray(served), got["tip"][np.arange(len(n)), n - 1, :3])
+
