@@ -20,6 +20,7 @@
 
 #include "../../include/vinesim.h"
 #include "vs_device.h"
+#include "vs_server.h"
 
 static_assert(vs::kMaxObs == VINE_MAX_OBSTACLES, "obstacle capacity of the kernels");
 static_assert(vs::kScratchBytes == VINE_GRAD_SCRATCH_BYTES, "scratch size of the kernels");
@@ -1672,8 +1673,6 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
 
 namespace vs {
 hipError_t launch_slot_reset(const KData& D, const int* slots, int count, hipStream_t stream);
-hipError_t launch_slot_start(const KData& D, const int* slots, const int* start,
-                             const double* theta0, int count, hipStream_t stream);
 }
 
 namespace {
@@ -1786,11 +1785,9 @@ struct vine_server {
   int* st_order = nullptr;
   int* st_start = nullptr;  // links each robot of a group starts with, at the order offsets
   double* st_theta = nullptr;
-  // device-visible addresses of st_start and st_theta (read by the start kernel)
-  const int* dv_start = nullptr;
-  const double* dv_theta = nullptr;
   double* st_tip = nullptr;
   int* st_status = nullptr;
+  vs::SlotStage stage{};  // the staging at its device-visible addresses (the group kernels')
   std::string err;
 };
 
@@ -1906,32 +1903,20 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
       o[2] = O.a;
       o[3] = O.kind == 1 ? O.b : 0.0;
     }
-    // asynchronous copies from pinned staging; a staging row is rewritten only after its
-    // robot has been read back, long after these copies ran
-    A(hipMemcpyAsync(h->ii + vs::kII * (size_t)slot, ii, sizeof(int) * vs::kII,
-                     hipMemcpyHostToDevice, sa));
-    A(hipMemcpyAsync(h->dd + 6 * (size_t)slot, dd, sizeof(double) * 6, hipMemcpyHostToDevice, sa));
-    A(hipMemcpyAsync(h->cover + 2 * row, s->st_cover + 2 * row, sizeof(double) * 2 * n,
-                     hipMemcpyHostToDevice, sa));
-    if (K > 0) {
-      A(hipMemcpyAsync(h->okind + oo, s->st_okind + oo, sizeof(int) * K, hipMemcpyHostToDevice, sa));
-      A(hipMemcpyAsync(h->obs + 4 * oo, s->st_obs + 4 * oo, sizeof(double) * 4 * K,
-                       hipMemcpyHostToDevice, sa));
-    }
   }
+  // the group's inputs go from the staging to the slab in one launch, on the lane's stream
+  // (a staging region is rewritten only after its robot has been read back, long after)
   std::copy(adm.begin(), adm.end(), s->st_order + g.order_off);
-  A(hipMemcpyAsync(h->order + g.order_off, s->st_order + g.order_off, sizeof(int) * g.count,
-                   hipMemcpyHostToDevice, sa));
   bool resumed = false;
   for (int i = 0; i < g.count; ++i) {
     s->st_start[g.order_off + i] = s->live[adm[i]].start;
     resumed = resumed || s->live[adm[i]].start > 0;
   }
+  const vs::SlotInputs in{h->ii, h->dd, h->cover, h->okind, h->obs, h->order};
+  A(vs::launch_slot_load(in, s->stage, (int)g.order_off, g.count, sa));
   vs::KData D = kdata(h);
   A(vs::launch_slot_reset(D, h->order + g.order_off, g.count, sa));
-  if (resumed)
-    A(vs::launch_slot_start(D, h->order + g.order_off, s->dv_start + g.order_off, s->dv_theta,
-                            g.count, sa));
+  if (resumed) A(vs::launch_slot_start(D, s->stage, (int)g.order_off, g.count, sa));
   D.launch_first = (int)g.order_off;
   D.launch_count = g.count;
   A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], 2, sa));
@@ -2043,11 +2028,23 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
   A(halloc(&s->st_tip, (size_t)R * 3));
   A(halloc(&s->st_status, (size_t)R));
   if (e == hipSuccess) {
-    void *ds = nullptr, *dt = nullptr;
-    A(hipHostGetDevicePointer(&ds, s->st_start, 0));
-    A(hipHostGetDevicePointer(&dt, s->st_theta, 0));
-    s->dv_start = (const int*)ds;
-    s->dv_theta = (const double*)dt;
+    // the staging's device-visible addresses, for the group load and store kernels
+    auto dev = [&](void* host) {
+      void* d = nullptr;
+      A(hipHostGetDevicePointer(&d, host, 0));
+      return d;
+    };
+    vs::SlotStage& g = s->stage;
+    g.ii = (const int*)dev(s->st_ii);
+    g.dd = (const double*)dev(s->st_dd);
+    g.cover = (const double*)dev(s->st_cover);
+    g.okind = (const int*)dev(s->st_okind);
+    g.obs = (const double*)dev(s->st_obs);
+    g.order = (const int*)dev(s->st_order);
+    g.start = (const int*)dev(s->st_start);
+    g.theta = (double*)dev(s->st_theta);
+    g.tip = (double*)dev(s->st_tip);
+    g.status = (int*)dev(s->st_status);
   }
   h->B = slots;
   h->N = max_links;
@@ -2176,17 +2173,7 @@ int32_t vine_server_tick(vine_server* s) {
       }
       A(q);
       hipStream_t st = s->pool[g.stream];
-      for (int i = 0; i < g.count; ++i) {
-        const vine_server::Robot& r = s->live[s->st_order[g.order_off + i]];
-        const int n = r.inst.n_links;
-        const int64_t row = r.row;
-        A(hipMemcpyAsync(s->st_theta + row, h->theta + row, sizeof(double) * n,
-                         hipMemcpyDeviceToHost, st));
-        A(hipMemcpyAsync(s->st_tip + 3 * (row + n - 1), h->tip + 3 * (row + n - 1),
-                         sizeof(double) * 3, hipMemcpyDeviceToHost, st));
-        A(hipMemcpyAsync(s->st_status + row, h->status + row, sizeof(int) * n,
-                         hipMemcpyDeviceToHost, st));
-      }
+      A(vs::launch_slot_store(kdata(h), s->stage, (int)g.order_off, g.count, st));
       A(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
       A(hipEventRecord(g.ev_out, st));
       g.state = 2;
