@@ -321,7 +321,7 @@ void vine_sim_dims(const vine_sim* h, int32_t dims[3]);
 void vine_sim_destroy(vine_sim* h);
 
 /* Text of the last failure on this handle (owned by the handle, valid until the
- * next call on it).  With h == NULL: the last vine_sim_create failure of the
+ * next call on it).  With h == NULL: the last vine_sim_create or vine_spam_synth failure of the
  * calling thread. */
 const char* vine_sim_last_error(const vine_sim* h);
 
@@ -331,6 +331,41 @@ const char* vine_sim_last_error(const vine_sim* h);
  * of this simulation. */
 int32_t vine_sim_spam_law(const vine_sim* h, double l, int32_t n, const double* eps, double* G,
                           double* dG, double* IG);
+
+/* ------------------------------------------------------------------------- */
+/* Actuator synthesis (Sec. 4.2): the sPAM to build for a wanted bend.
+ *
+ * A joint whose link is covered by one sPAM of unit length l0 at pressure P rests in
+ * free space where Eq. 3b's net moment vanishes: the wrinkling moment of Eq. 2,
+ * pi P_vine R^3 h(theta), equals arm P G(eps; l0), the force of Eq. 1d at the strain
+ * eps = arm theta / l of Eq. 3a (arm = 2 R + R_act, l the link length).  Fabrication
+ * allows only a discrete set of pressures and unit lengths (a 1 mm grid in the paper).
+ * For each target joint angle this returns the highest pressure of the set for which
+ * some unit length of the grid rests within tol of the target, and of those unit lengths
+ * the one whose rest angle is nearest (the first, i.e. shortest, of equal ones):
+ * designs[3 i .. 3 i + 2] = (P, l0, rest angle), or (0, 0, 0) when no pressure fits.
+ * The paper prefers the highest feasible pressure because it gave the most repeatable
+ * bends; where it solves Eq. 1 by Levenberg-Marquardt from many starts, here every
+ * (pressure, unit length) pair of the grid is solved exactly (one device wave each:
+ * bisection on the sPAM's contraction parameter, each state solved from Eq. 1 with the
+ * elliptic integrals spread over the lanes), and one device thread per target applies
+ * the rule.
+ *   pressures     [n_pressures] Pa, positive, strictly rising (<= VINE_SYNTH_MAX)
+ *   unit_lengths  [n_lengths] m, positive, strictly rising (<= VINE_SYNTH_MAX)
+ *   targets       [n_targets] joint angles (rad); designs [3 n_targets] out
+ *   angles        NULL, or [n_pressures][n_lengths] out: every pair's rest angle
+ *   link_len, tube_radius, body_pressure: l, R_vine, P_vine of the body
+ * Host arrays; device memory is allocated and freed inside the call, which runs on
+ * `stream` and returns when the results are copied back.  Errors: VINE_EINVAL (also
+ * pressures or lengths not rising, a non-finite target or a negative tolerance),
+ * VINE_ECAPACITY, VINE_ENOMEM, VINE_EDEVICE; vine_sim_last_error(NULL) describes
+ * the failure. */
+#define VINE_SYNTH_MAX 4096
+int32_t vine_spam_synth(const vine_params* params, double link_len, double tube_radius,
+                        double body_pressure, const double* pressures, int32_t n_pressures,
+                        const double* unit_lengths, int32_t n_lengths, const double* targets,
+                        int32_t n_targets, double tol, double* designs, double* angles,
+                        void* stream);
 
 /* Occupancy of the current device: robots of each chain-length class (up to 64, 128,
  * 256 and 512 links) resident per compute unit in a rollout launch with `waves` (1, 2 or

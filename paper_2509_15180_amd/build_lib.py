@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("vs_host.cpp", "vs_rollout.hip", "vs_server.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("vs_host.cpp", "vs_rollout.hip", "vs_server.hip",
+                                                "vs_synth.hip")]
 LIB = os.path.join(HERE, "libvinesim.so")
 ARCH = os.environ.get("VINESIM_ARCH", "gfx950")
 

@@ -21,6 +21,7 @@
 #include "../../include/vinesim.h"
 #include "vs_device.h"
 #include "vs_server.h"
+#include "vs_synth.h"
 
 static_assert(vs::kMaxObs == VINE_MAX_OBSTACLES, "obstacle capacity of the kernels");
 static_assert(vs::kScratchBytes == VINE_GRAD_SCRATCH_BYTES, "scratch size of the kernels");
@@ -1656,6 +1657,77 @@ int32_t vine_sim_spam_law(const vine_sim* hc, double l, int32_t n, const double*
     if (dG) dG[i] = cheb_eval_host(T.dc[k], D - 1, x) * 2.0 / (b - a);
     if (IG) IG[i] = T.cum[k] + 0.5 * (b - a) * cheb_eval_host(T.ic[k], D + 1, x);
   }
+  return VINE_OK;
+}
+
+int32_t vine_spam_synth(const vine_params* params, double link_len, double tube_radius,
+                        double body_pressure, const double* pressures, int32_t n_pressures,
+                        const double* unit_lengths, int32_t n_lengths, const double* targets,
+                        int32_t n_targets, double tol, double* designs, double* angles,
+                        void* stream) {
+  if (!params || !pressures || !unit_lengths || n_pressures < 1 || n_lengths < 1 ||
+      n_targets < 0 || (n_targets > 0 && (!targets || !designs)))
+    return fail(nullptr, VINE_EINVAL, "null pointer or non-positive count");
+  if (n_pressures > VINE_SYNTH_MAX || n_lengths > VINE_SYNTH_MAX)
+    return fail(nullptr, VINE_ECAPACITY, "more pressures or unit lengths than VINE_SYNTH_MAX");
+  const vine_params& p = *params;
+  if (!finite_pos(p.R_c) || !finite_pos(p.R_act) || !(p.R_act > p.R_c) || !(p.a_corr >= 0.0) ||
+      !std::isfinite(p.a_corr) || !(p.eps_crit > 0.0 && p.eps_crit < 1.0))
+    return fail(nullptr, VINE_EINVAL, "invalid vine_params");
+  if (!finite_pos(link_len) || !finite_pos(tube_radius) || !finite_pos(body_pressure) ||
+      !(tol >= 0.0) || !std::isfinite(tol))
+    return fail(nullptr, VINE_EINVAL, "invalid link length, tube radius, body pressure or tolerance");
+  for (int k = 0; k < n_pressures; ++k)
+    if (!finite_pos(pressures[k]) || (k > 0 && !(pressures[k] > pressures[k - 1])))
+      return fail(nullptr, VINE_EINVAL, "pressures must be positive, finite and rising");
+  for (int j = 0; j < n_lengths; ++j)
+    if (!finite_pos(unit_lengths[j]) || (j > 0 && !(unit_lengths[j] > unit_lengths[j - 1])))
+      return fail(nullptr, VINE_EINVAL, "unit lengths must be positive, finite and rising");
+  for (int i = 0; i < n_targets; ++i)
+    if (!std::isfinite(targets[i])) return fail(nullptr, VINE_EINVAL, "non-finite target angle");
+  // the quadrature rule of the elliptic integrals (Eq. 1), nodes then weights
+  const GaussRule& g48 = gauss48();
+  std::vector<double> gl(g48.x);
+  gl.insert(gl.end(), g48.w.begin(), g48.w.end());
+  hipStream_t st = (hipStream_t)stream;
+  double *d_gl = nullptr, *d_p = nullptr, *d_l = nullptr, *d_ang = nullptr, *d_t = nullptr,
+         *d_des = nullptr;
+  const size_t na = (size_t)n_pressures * n_lengths;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  A(dalloc(&d_gl, gl.size()));
+  A(dalloc(&d_p, (size_t)n_pressures));
+  A(dalloc(&d_l, (size_t)n_lengths));
+  A(dalloc(&d_ang, na));
+  if (n_targets > 0) {
+    A(dalloc(&d_t, (size_t)n_targets));
+    A(dalloc(&d_des, 3 * (size_t)n_targets));
+  }
+  if (e == hipSuccess) {
+    A(hipMemcpyAsync(d_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(d_p, pressures, sizeof(double) * n_pressures, hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(d_l, unit_lengths, sizeof(double) * n_lengths, hipMemcpyHostToDevice, st));
+    if (n_targets > 0)
+      A(hipMemcpyAsync(d_t, targets, sizeof(double) * n_targets, hipMemcpyHostToDevice, st));
+    vs::SynthArgs a{d_gl, d_gl + 48, d_p, d_l, d_ang, n_pressures, n_lengths, p.R_c, p.R_act,
+                    p.a_corr, link_len, 2.0 * tube_radius + p.R_act,
+                    kPi * body_pressure * tube_radius * tube_radius * tube_radius, p.eps_crit};
+    A(vs::launch_synth_angles(a, st));
+    A(vs::launch_synth_select(a, d_t, n_targets, tol, d_des, st));
+    if (angles) A(hipMemcpyAsync(angles, d_ang, sizeof(double) * na, hipMemcpyDeviceToHost, st));
+    if (n_targets > 0)
+      A(hipMemcpyAsync(designs, d_des, sizeof(double) * 3 * n_targets, hipMemcpyDeviceToHost, st));
+    A(hipStreamSynchronize(st));
+  }
+  const bool oom = e == hipErrorOutOfMemory;
+  void* bufs[] = {d_gl, d_p, d_l, d_ang, d_t, d_des};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (e != hipSuccess)
+    return fail(nullptr, oom ? VINE_ENOMEM : VINE_EDEVICE,
+                std::string("synthesis: ") + hipGetErrorString(e));
   return VINE_OK;
 }
 

@@ -75,6 +75,7 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
            "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune", "vine_sim_set_head",
            "vine_sim_head",
+           "vine_spam_synth",
            "vine_server_create", "vine_server_submit", "vine_server_submit_from",
            "vine_server_tick", "vine_server_poll", "vine_server_result", "vine_server_release", "vine_server_stats", "vine_server_destroy",
            "vine_server_last_error")
@@ -120,6 +121,11 @@ def lib():
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.vine_sim_spam_law.restype = C.c_int32
+        dp_ = C.POINTER(C.c_double)
+        L.vine_spam_synth.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, dp_,
+                                      C.c_int32, dp_, C.c_int32, dp_, C.c_int32, C.c_double, dp_,
+                                      dp_, vp]
+        L.vine_spam_synth.restype = C.c_int32
         L.vine_sim_occupancy.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.vine_sim_occupancy.restype = C.c_int32
         L.vine_sim_set_waves.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -216,6 +222,29 @@ def _pack(work):
         o = work.obs_d[i]
         obs[i] = Obstacle(int(work.obs_kind[i]), 0, *(float(x) for x in o))
     return inst, B, spams, ns, obs, no
+
+
+def spam_synth(pressures, unit_lengths, targets, tol: float, link_len: float, tube_radius: float,
+               body_pressure: float, params: Params | None = None, stream=None,
+               want_angles: bool = True):
+    """Actuator synthesis (vine_spam_synth): (designs [n][3] = (P, l0, rest angle) or zeros,
+    rest angles [n_pressures][n_lengths] or None)."""
+    dp = C.POINTER(C.c_double)
+    P = np.ascontiguousarray(pressures, np.float64)
+    Lu = np.ascontiguousarray(unit_lengths, np.float64)
+    t = np.ascontiguousarray(np.atleast_1d(targets), np.float64)
+    des = np.zeros((len(t), 3))
+    ang = np.zeros((len(P), len(Lu))) if want_angles else None
+    prm = params if params is not None else default_params()
+    rc = lib().vine_spam_synth(C.byref(prm), float(link_len), float(tube_radius),
+                               float(body_pressure), P.ctypes.data_as(dp), len(P),
+                               Lu.ctypes.data_as(dp), len(Lu), t.ctypes.data_as(dp), len(t),
+                               float(tol), des.ctypes.data_as(dp),
+                               ang.ctypes.data_as(dp) if ang is not None else None,
+                               _stream_ptr(stream))
+    if rc != VINE_OK:
+        raise VineError(rc, lib().vine_sim_last_error(None).decode())
+    return des, ang
 
 
 class VineSim:

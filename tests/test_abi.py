@@ -116,3 +116,31 @@ def test_server_submit_each_marshals_one_robot_per_request():
     with pytest.raises(V.VineError) as e:
         srv.submit_each(10, work)
     assert e.value.code == V.VINE_EINVAL
+
+
+def test_synthesis_rejects_bad_inputs_before_the_device():
+    import ctypes as C
+    L = V.lib()
+    dp = C.POINTER(C.c_double)
+    p = V.default_params()
+
+    def call(P, Lu, t, tol=1e-3, geo=(0.025, 0.03335, 10342.0), prm=p):
+        P, Lu, t = (np.ascontiguousarray(x, np.float64) for x in (P, Lu, t))
+        des = np.zeros(3 * max(1, len(t)))
+        return L.vine_spam_synth(C.byref(prm) if prm is not None else None, *geo,
+                                 P.ctypes.data_as(dp), len(P), Lu.ctypes.data_as(dp), len(Lu),
+                                 t.ctypes.data_as(dp), len(t), tol, des.ctypes.data_as(dp), None,
+                                 None)
+
+    good_P, good_L, good_t = [2e3, 4e3], [0.02, 0.03], [0.01]
+    assert call(good_P, good_L, good_t, prm=None) == V.VINE_EINVAL
+    assert call([4e3, 2e3], good_L, good_t) == V.VINE_EINVAL        # pressures not rising
+    assert b"rising" in L.vine_sim_last_error(None)
+    assert call([2e3, 2e3], good_L, good_t) == V.VINE_EINVAL
+    assert call([-1.0, 2e3], good_L, good_t) == V.VINE_EINVAL
+    assert call(good_P, [0.03, 0.02], good_t) == V.VINE_EINVAL      # lengths not rising
+    assert call(good_P, [0.0, 0.02], good_t) == V.VINE_EINVAL
+    assert call(good_P, good_L, [math.nan]) == V.VINE_EINVAL
+    assert call(good_P, good_L, good_t, tol=-1.0) == V.VINE_EINVAL
+    assert call(good_P, good_L, good_t, geo=(0.0, 0.03335, 10342.0)) == V.VINE_EINVAL
+    assert call(np.arange(1, 4098) * 1e3, good_L, good_t) == V.VINE_ECAPACITY  # 4097 pressures

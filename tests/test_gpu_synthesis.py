@@ -1,0 +1,74 @@
+"""Actuator synthesis (Sec. 4.2) through the C ABI against the FP64 oracle's plain
+definition (oracle/synthesis.py): every (pressure, unit length) rest angle of a 10 x 61
+design grid (2-20 kPa in 2 kPa steps, unit lengths 20-80 mm on the 1 mm fabrication grid,
+the paper's 25 mm segment, 33.35 mm vine radius and 1.5 psi body pressure) within 1e-10
+rad of the oracle's, and the designs of 4096 seeded targets: bit for bit the oracle's rule
+applied to the same angles, and the oracle's own designs except where two candidates, or
+a candidate and the tolerance, lie within 1e-9 rad of each other."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import synthesis as S
+
+pytestmark = pytest.mark.gpu
+
+L, R, PV = 0.025, 0.03335, 10342.0
+PRESSURES = np.arange(2.0, 20.5, 2.0) * 1e3
+LENGTHS = np.arange(20, 81) * 1e-3
+TOL = math.radians(0.05)
+
+
+def _targets():
+    rng = np.random.default_rng(2509)
+    return np.concatenate([rng.uniform(math.radians(0.2), math.radians(4.0), 4090),
+                           [0.0, math.radians(5.0), math.radians(0.31), 1.0, -0.01,
+                            math.radians(3.7)]])
+
+
+def _near_tie(grid, t, tol, margin=1e-9):
+    for row in grid:
+        err = np.abs(row - t)
+        if np.any(np.abs(err - tol) <= margin):
+            return True
+        s = np.sort(err)
+        if len(s) > 1 and s[1] - s[0] <= margin:
+            return True
+    return False
+
+
+def test_synthesis_matches_the_oracle():
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    t = _targets()
+    des, ang = V.spam_synth(PRESSURES, LENGTHS, t, TOL, L, R, PV)
+    ref_grid = S.angle_grid(PRESSURES, LENGTHS, L, R, PV)
+    d = np.abs(ang - ref_grid)
+    print(f"rest angles: max |GPU - oracle| {d.max():.2e} rad over {ang.size} designs "
+          f"({np.degrees(ref_grid.min()):.3f} to {np.degrees(ref_grid.max()):.3f} deg)", flush=True)
+    assert d.max() <= 1e-10
+    # the rule on the GPU's angles: bit for bit
+    assert np.array_equal(des, S.select(ang, PRESSURES, LENGTHS, t, TOL))
+    # against the oracle's designs
+    ref = S.select(ref_grid, PRESSURES, LENGTHS, t, TOL)
+    same = np.all(des[:, :2] == ref[:, :2], axis=1)
+    diff = np.nonzero(~same)[0]
+    print(f"designs: {same.sum()}/{len(t)} identical, {np.count_nonzero(des[:, 0])} found, "
+          f"{len(diff)} differ", flush=True)
+    for i in diff:
+        assert _near_tie(ref_grid, t[i], TOL), i
+    assert np.all(np.abs(des[same, 2] - ref[same, 2]) <= 1e-10)
+    found = des[:, 0] > 0
+    assert np.all(np.abs(des[found, 2] - t[found]) <= TOL)
+    assert tuple(des[-3]) == (0.0, 0.0, 0.0) and tuple(des[-2]) == (0.0, 0.0, 0.0)
+
+
+def test_synthesis_without_targets_and_repeatable():
+    """No targets: only the angle grid; two calls give the same bits."""
+    from paper_2509_15180_amd import vinesim as V
+    d0, a0 = V.spam_synth(PRESSURES[:3], LENGTHS[::10], [], TOL, L, R, PV)
+    d1, a1 = V.spam_synth(PRESSURES[:3], LENGTHS[::10], [0.01, 0.02], TOL, L, R, PV)
+    assert d0.shape == (0, 3) and np.array_equal(a0, a1)
