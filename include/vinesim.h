@@ -321,8 +321,8 @@ void vine_sim_dims(const vine_sim* h, int32_t dims[3]);
 void vine_sim_destroy(vine_sim* h);
 
 /* Text of the last failure on this handle (owned by the handle, valid until the
- * next call on it).  With h == NULL: the last vine_sim_create or vine_spam_synth failure of the
- * calling thread. */
+ * next call on it).  With h == NULL: the last failure of the calling thread in a call
+ * without a handle (vine_sim_create, vine_spam_synth, vine_spam_solve, vine_mlp_forward). */
 const char* vine_sim_last_error(const vine_sim* h);
 
 /* Evaluate the sPAM force law table the library built for link length l at
@@ -366,6 +366,29 @@ int32_t vine_spam_synth(const vine_params* params, double link_len, double tube_
                         const double* unit_lengths, int32_t n_lengths, const double* targets,
                         int32_t n_targets, double tol, double* designs, double* angles,
                         void* stream);
+
+/* The sPAM state of a given strain, solved exactly from Eq. 1 (Sec. 3.1): for each
+ * sample i, the contraction parameter m in [m0, 1/2] whose strain (Eq. 1a) is eps[i]
+ * for unit length unit_lengths[i] (bisection; the strain rises with m), with phi the
+ * smallest root of Eq. 1b up to phi_Rc (unsaturated) or phi_Rc (saturated) and
+ * G = F_t / P_act of Eq. 1d: out[4 i .. 4 i + 3] = (m, phi, G, strain reached).  A strain
+ * at or above the slack strain gives the slack state (m = 1/2, G = 0); one at or below
+ * zero gives m0.  This is the map the paper's surrogate (Sec. 4.3) approximates; here
+ * it runs as one device wave per sample.  Host arrays of n doubles (out: 4 n); device
+ * memory is allocated inside; returns when the results are copied back.  Errors:
+ * VINE_EINVAL (non-finite strain, non-positive unit length), VINE_ENOMEM, VINE_EDEVICE. */
+int32_t vine_spam_solve(const vine_params* params, int32_t n, const double* eps,
+                        const double* unit_lengths, double* out, void* stream);
+
+/* The neural surrogate of Sec. 4.3, a 2-32-2 perceptron with ReLU:
+ * y = W2 relu(W1 x + b1) + b2 for each sample x[2 i .. 2 i + 1] into y[2 i .. 2 i + 1].
+ * weights: VINE_MLP_WEIGHTS doubles packed as W1 [32][2], b1 [32], W2 [2][32], b2 [2]
+ * (any input and output scaling is the caller's).  One device thread per sample; host
+ * arrays; device memory is allocated inside.  Errors: VINE_EINVAL, VINE_ENOMEM,
+ * VINE_EDEVICE. */
+#define VINE_MLP_WEIGHTS 162
+int32_t vine_mlp_forward(const double* weights, int32_t n, const double* x, double* y,
+                         void* stream);
 
 /* Occupancy of the current device: robots of each chain-length class (up to 64, 128,
  * 256 and 512 links) resident per compute unit in a rollout launch with `waves` (1, 2 or

@@ -90,3 +90,27 @@ def synthesize(targets, pressures, unit_lengths, tol: float, link_len: float, R:
     """(designs [n][3] = (P, l0, theta), angle grid)."""
     grid = angle_grid(pressures, unit_lengths, link_len, R, P_vine, prm)
     return select(grid, pressures, unit_lengths, targets, tol), grid
+
+
+def spam_inverse(eps: float, l0: float, prm=None):
+    """(m, phi, G): the sPAM state of strain eps (Eq. 1a inverted by bisection on m in
+    [m0, 1/2], where the strain rises with m); the slack state (m = 1/2) at or beyond the
+    slack strain, the state m0 at or below zero strain."""
+    a = zero_strain_m(l0, prm)
+    if eps >= spam_state(0.5, l0, prm)[0]:
+        m = 0.5
+    elif eps > 0.0:
+        b = 0.5
+        for _ in range(200):
+            if b - a <= 1e-17:
+                break
+            c = 0.5 * (a + b)
+            if spam_state(c, l0, prm)[0] < eps:
+                a = c
+            else:
+                b = c
+        m = 0.5 * (a + b)
+    else:
+        m = a
+    _, G, phi, _ = spam_state(m, l0, prm)
+    return m, phi, G

@@ -1731,6 +1731,84 @@ int32_t vine_spam_synth(const vine_params* params, double link_len, double tube_
   return VINE_OK;
 }
 
+int32_t vine_spam_solve(const vine_params* params, int32_t n, const double* eps,
+                        const double* unit_lengths, double* out, void* stream) {
+  if (!params || n < 0 || (n > 0 && (!eps || !unit_lengths || !out)))
+    return fail(nullptr, VINE_EINVAL, "null pointer or negative count");
+  const vine_params& p = *params;
+  if (!finite_pos(p.R_c) || !finite_pos(p.R_act) || !(p.R_act > p.R_c) || !(p.a_corr >= 0.0) ||
+      !std::isfinite(p.a_corr))
+    return fail(nullptr, VINE_EINVAL, "invalid vine_params");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(eps[i]) || !finite_pos(unit_lengths[i]))
+      return fail(nullptr, VINE_EINVAL, "non-finite strain or non-positive unit length");
+  if (n == 0) return VINE_OK;
+  const GaussRule& g48 = gauss48();
+  std::vector<double> gl(g48.x);
+  gl.insert(gl.end(), g48.w.begin(), g48.w.end());
+  hipStream_t st = (hipStream_t)stream;
+  double *d_gl = nullptr, *d_e = nullptr, *d_l = nullptr, *d_o = nullptr;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  A(dalloc(&d_gl, gl.size()));
+  A(dalloc(&d_e, (size_t)n));
+  A(dalloc(&d_l, (size_t)n));
+  A(dalloc(&d_o, 4 * (size_t)n));
+  if (e == hipSuccess) {
+    A(hipMemcpyAsync(d_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(d_e, eps, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(d_l, unit_lengths, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    vs::SynthArgs a{d_gl, d_gl + 48, nullptr, nullptr, nullptr, 0, 0, p.R_c, p.R_act, p.a_corr,
+                    0.0, 0.0, 0.0, 0.0};
+    A(vs::launch_spam_solve(a, d_e, d_l, n, d_o, st));
+    A(hipMemcpyAsync(out, d_o, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, st));
+    A(hipStreamSynchronize(st));
+  }
+  const bool oom = e == hipErrorOutOfMemory;
+  void* bufs[] = {d_gl, d_e, d_l, d_o};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (e != hipSuccess)
+    return fail(nullptr, oom ? VINE_ENOMEM : VINE_EDEVICE,
+                std::string("sPAM solve: ") + hipGetErrorString(e));
+  return VINE_OK;
+}
+
+int32_t vine_mlp_forward(const double* weights, int32_t n, const double* x, double* y,
+                         void* stream) {
+  if (!weights || n < 0 || (n > 0 && (!x || !y)))
+    return fail(nullptr, VINE_EINVAL, "null pointer or negative count");
+  for (int k = 0; k < VINE_MLP_WEIGHTS; ++k)
+    if (!std::isfinite(weights[k])) return fail(nullptr, VINE_EINVAL, "non-finite weight");
+  if (n == 0) return VINE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  double *d_w = nullptr, *d_x = nullptr, *d_y = nullptr;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  A(dalloc(&d_w, (size_t)VINE_MLP_WEIGHTS));
+  A(dalloc(&d_x, 2 * (size_t)n));
+  A(dalloc(&d_y, 2 * (size_t)n));
+  if (e == hipSuccess) {
+    A(hipMemcpyAsync(d_w, weights, sizeof(double) * VINE_MLP_WEIGHTS, hipMemcpyHostToDevice, st));
+    A(hipMemcpyAsync(d_x, x, sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
+    A(vs::launch_mlp_forward(d_w, d_x, n, d_y, st));
+    A(hipMemcpyAsync(y, d_y, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
+    A(hipStreamSynchronize(st));
+  }
+  const bool oom = e == hipErrorOutOfMemory;
+  void* bufs[] = {d_w, d_x, d_y};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (e != hipSuccess)
+    return fail(nullptr, oom ? VINE_ENOMEM : VINE_EDEVICE,
+                std::string("surrogate: ") + hipGetErrorString(e));
+  return VINE_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -24,4 +24,11 @@ hipError_t launch_synth_angles(const SynthArgs& a, hipStream_t stream);
 hipError_t launch_synth_select(const SynthArgs& a, const double* targets, int n_t, double tol,
                                double* designs, hipStream_t stream);
 
+// The sPAM state of each strain: out[4 i ..] = (m, phi, G, eps reached); a wave per sample.
+hipError_t launch_spam_solve(const SynthArgs& a, const double* eps, const double* l0s, int n,
+                             double* out, hipStream_t stream);
+// The 2-32-2 ReLU surrogate (weights: W1 [32][2], b1 [32], W2 [2][32], b2 [2]).
+hipError_t launch_mlp_forward(const double* w, const double* x, int n, double* y,
+                              hipStream_t stream);
+
 }  // namespace vs

@@ -59,7 +59,8 @@ __device__ double eq1b(const SynthArgs& A, double l0, double m, double phi, doub
 // Strain and force per unit pressure of the state m (Eq. 1a-d): unsaturated when Eq. 1b
 // has a root up to phi_Rc (a scan of 64 brackets, then safeguarded Newton), else
 // saturated at phi = phi_Rc with the active length from Eq. 1b.
-__device__ void spam_point(const SynthArgs& A, double l0, double m, double* eps, double* G) {
+__device__ void spam_point(const SynthArgs& A, double l0, double m, double* eps, double* G,
+                           double* phi_out = nullptr) {
   const double phi_rc = acos(A.R_c / A.R_act);
   double lo = 1e-12, flo = eq1b(A, l0, m, lo, nullptr), phi = -1.0;
   for (int k = 1; k <= 64 && phi < 0.0; ++k) {
@@ -93,6 +94,19 @@ __device__ void spam_point(const SynthArgs& A, double l0, double m, double* eps,
   const double c = cos(phi);
   *eps = (la - 2.0 * A.R_c * (E - 0.5 * F) / (sqrt(m) * c)) / l0;
   *G = kPi * A.R_c * A.R_c * (1.0 - 2.0 * m) / (2.0 * m * c * c);
+  if (phi_out) *phi_out = phi;
+}
+
+// m0: the state of zero strain (the strain of Eq. 1a rises with m on [m0, 1/2])
+__device__ double zero_strain_m(const SynthArgs& A, double l0) {
+  double lo = 1e-6, hi = 0.5, e, G;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    spam_point(A, l0, mid, &e, &G);
+    if (e < 0.0) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 // h = M / (pi P_vine R^3) of Eq. 2 above the wrinkling onset theta_on = 2 asin(eps_c),
@@ -114,17 +128,8 @@ __global__ void __launch_bounds__(kLanes) synth_angle_kernel(SynthArgs a) {
   const int k = pair / a.n_l, j = pair - k * a.n_l;
   const double P = a.pressures[k], l0 = a.lengths[j];
   double e, G;
-  // m0: the state of zero strain (the strain rises with m)
-  double lo = 1e-6, hi = 0.5;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    spam_point(a, l0, mid, &e, &G);
-    if (e < 0.0) lo = mid; else hi = mid;
-  }
   // the rest state: the first m in [m0, 1/2] where the balance q turns non-negative
-  lo = 0.5 * (lo + hi);
-  hi = 0.5;
+  double lo = zero_strain_m(a, l0), hi = 0.5;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
@@ -134,6 +139,56 @@ __global__ void __launch_bounds__(kLanes) synth_angle_kernel(SynthArgs a) {
   }
   spam_point(a, l0, 0.5 * (lo + hi), &e, &G);
   if (threadIdx.x == 0) a.angles[pair] = e * a.link_len / a.arm;
+}
+
+// The sPAM state of a given strain (the inverse of Eq. 1a): m in [m0, 1/2] with
+// eps(m) = eps by bisection, then phi and G there; strains at or beyond slack give the
+// slack state (m = 1/2, G = 0), strains at or below zero the state m0.
+__global__ void __launch_bounds__(kLanes) spam_solve_kernel(SynthArgs a, const double* eps,
+                                                            const double* l0s, int n,
+                                                            double* out) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const double target = eps[i], l0 = l0s[i];
+  double e, G, phi;
+  spam_point(a, l0, 0.5, &e, &G);
+  const bool slack = target >= e;
+  double lo = 0.5, hi = 0.5;
+  if (!slack) {
+    lo = zero_strain_m(a, l0);
+    for (int it = 0; it < 200 && target > 0.0; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      spam_point(a, l0, mid, &e, &G);
+      if (e < target) lo = mid; else hi = mid;
+    }
+  }
+  const double m = (slack || target <= 0.0) ? lo : 0.5 * (lo + hi);
+  spam_point(a, l0, m, &e, &G, &phi);
+  if (threadIdx.x == 0) {
+    out[4 * (size_t)i] = m;
+    out[4 * (size_t)i + 1] = phi;
+    out[4 * (size_t)i + 2] = G;
+    out[4 * (size_t)i + 3] = e;
+  }
+}
+
+// The surrogate of Sec. 4.3: a 2-32-2 perceptron with ReLU, y = W2 relu(W1 x + b1) + b2,
+// weights packed as W1 [32][2], b1 [32], W2 [2][32], b2 [2]; one thread per sample.
+__global__ void mlp_forward_kernel(const double* w, const double* x, int n, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x0 = x[2 * (size_t)i], x1 = x[2 * (size_t)i + 1];
+  const double *W1 = w, *b1 = w + 64, *W2 = w + 96, *b2 = w + 160;
+  double y0 = b2[0], y1 = b2[1];
+#pragma unroll 8
+  for (int k = 0; k < 32; ++k) {
+    const double h = fmax(W1[2 * k] * x0 + W1[2 * k + 1] * x1 + b1[k], 0.0);
+    y0 += W2[k] * h;
+    y1 += W2[32 + k] * h;
+  }
+  y[2 * (size_t)i] = y0;
+  y[2 * (size_t)i + 1] = y1;
 }
 
 __global__ void synth_select_kernel(SynthArgs a, const double* targets, int n_t, double tol,
@@ -180,6 +235,22 @@ hipError_t launch_synth_select(const SynthArgs& a, const double* targets, int n_
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(synth_select_kernel, dim3((n_t + 255) / 256), dim3(256), 0, stream, a,
                      targets, n_t, tol, designs);
+  return hipGetLastError();
+}
+
+hipError_t launch_spam_solve(const SynthArgs& a, const double* eps, const double* l0s, int n,
+                             double* out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (!a.gl_x || !a.gl_w || !eps || !l0s || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(spam_solve_kernel, dim3(n), dim3(kLanes), 0, stream, a, eps, l0s, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const double* w, const double* x, int n, double* y,
+                              hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (!w || !x || !y) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, w, x, n, y);
   return hipGetLastError();
 }
 

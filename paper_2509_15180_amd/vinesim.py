@@ -75,7 +75,7 @@ EXPORTS = ("vine_params_default", "vine_sim_create", "vine_sim_step", "vine_sim_
            "vine_sim_trace_read", "vine_sim_grad", "vine_sim_grad_noalloc", "vine_sim_set_spams",
            "vine_sim_occupancy", "vine_sim_set_waves", "vine_sim_autotune", "vine_sim_set_head",
            "vine_sim_head",
-           "vine_spam_synth",
+           "vine_spam_synth", "vine_spam_solve", "vine_mlp_forward",
            "vine_server_create", "vine_server_submit", "vine_server_submit_from",
            "vine_server_tick", "vine_server_poll", "vine_server_result", "vine_server_release", "vine_server_stats", "vine_server_destroy",
            "vine_server_last_error")
@@ -84,11 +84,15 @@ _lib = None
 
 
 def lib():
-    """Load libvinesim.so (raises if it has not been built)."""
+    """Load libvinesim.so (raises if it has not been built).  torch is imported first: the
+    library and torch then share torch's HIP runtime (the same soname), whereas a library
+    loaded first would bind the process, torch included, to the system's runtime, under
+    which torch finds no GPU."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (loads the process's HIP runtime)
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.vine_params_default.argtypes = [C.POINTER(Params)]
@@ -126,6 +130,10 @@ def lib():
                                       C.c_int32, dp_, C.c_int32, dp_, C.c_int32, C.c_double, dp_,
                                       dp_, vp]
         L.vine_spam_synth.restype = C.c_int32
+        L.vine_spam_solve.argtypes = [C.POINTER(Params), C.c_int32, dp_, dp_, dp_, vp]
+        L.vine_spam_solve.restype = C.c_int32
+        L.vine_mlp_forward.argtypes = [dp_, C.c_int32, dp_, dp_, vp]
+        L.vine_mlp_forward.restype = C.c_int32
         L.vine_sim_occupancy.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.vine_sim_occupancy.restype = C.c_int32
         L.vine_sim_set_waves.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -245,6 +253,35 @@ def spam_synth(pressures, unit_lengths, targets, tol: float, link_len: float, tu
     if rc != VINE_OK:
         raise VineError(rc, lib().vine_sim_last_error(None).decode())
     return des, ang
+
+
+def spam_solve(eps, unit_lengths, params: Params | None = None, stream=None):
+    """The sPAM state of each strain (vine_spam_solve): [n][4] = (m, phi, G, strain)."""
+    dp = C.POINTER(C.c_double)
+    e = np.ascontiguousarray(np.atleast_1d(eps), np.float64)
+    Lu = np.ascontiguousarray(np.broadcast_to(unit_lengths, e.shape), np.float64)
+    out = np.zeros((len(e), 4))
+    prm = params if params is not None else default_params()
+    rc = lib().vine_spam_solve(C.byref(prm), len(e), e.ctypes.data_as(dp), Lu.ctypes.data_as(dp),
+                               out.ctypes.data_as(dp), _stream_ptr(stream))
+    if rc != VINE_OK:
+        raise VineError(rc, lib().vine_sim_last_error(None).decode())
+    return out
+
+
+def mlp_forward(weights, x, stream=None):
+    """The 2-32-2 ReLU surrogate on the device (vine_mlp_forward): y [n][2]."""
+    dp = C.POINTER(C.c_double)
+    w = np.ascontiguousarray(weights, np.float64).ravel()
+    if w.size != 162:
+        raise ValueError("the surrogate has 162 weights")
+    xx = np.ascontiguousarray(x, np.float64).reshape(-1, 2)
+    y = np.zeros_like(xx)
+    rc = lib().vine_mlp_forward(w.ctypes.data_as(dp), len(xx), xx.ctypes.data_as(dp),
+                                y.ctypes.data_as(dp), _stream_ptr(stream))
+    if rc != VINE_OK:
+        raise VineError(rc, lib().vine_sim_last_error(None).decode())
+    return y
 
 
 class VineSim:

@@ -127,3 +127,17 @@ def test_selection_is_the_rule_over_every_pair():
     k, j = 1, 2
     d = S.select(grid, Ps, Ls, [grid[k][j]], 0.0)[0]
     assert d[2] == grid[k][j] and d[0] >= Ps[k]
+
+
+@pytest.mark.parametrize("eps,l0", [(0.05, 0.02), (0.2, 0.03), (0.1, 0.05), (0.15, 0.08),
+                                    (0.0, 0.04)])
+def test_inverse_state_reproduces_the_strain(eps, l0):
+    """The state the inverse returns has the asked strain and force by Eq. 1 evaluated with
+    scipy's elliptic integrals."""
+    m, phi, G = S.spam_inverse(eps, l0)
+    e2, G2, _ = eq1_state(m, phi, l0)
+    assert abs(e2 - eps) <= 1e-12
+    assert abs(G2 - G) <= 1e-12 * G
+    # beyond the slack strain: the slack state
+    m, phi, G = S.spam_inverse(5.0, l0)
+    assert m == 0.5 and G == 0.0
