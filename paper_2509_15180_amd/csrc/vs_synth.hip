@@ -6,7 +6,8 @@
 //   q = pi P_vine R^3 h(theta) - arm P G,   theta = eps l / arm.
 // Along the sPAM's states m in [m0, 1/2] (m0: zero strain) the strain eps(m) of Eq. 1a
 // rises to its slack value and the force per unit pressure G(m) of Eq. 1d falls to zero,
-// so q rises from negative to positive and bisection on m finds the one root.  Each state
+// so q rises from negative to positive and bisection on m finds the one root (below m0
+// the strain is negative and so is q).  Each state
 // is solved exactly from Eq. 1 (no fitted table: for unit lengths above about 35 mm the
 // actuator saturates inside the strain range, and G(eps) has a kink there).
 //
@@ -128,8 +129,10 @@ __global__ void __launch_bounds__(kLanes) synth_angle_kernel(SynthArgs a) {
   const int k = pair / a.n_l, j = pair - k * a.n_l;
   const double P = a.pressures[k], l0 = a.lengths[j];
   double e, G;
-  // the rest state: the first m in [m0, 1/2] where the balance q turns non-negative
-  double lo = zero_strain_m(a, l0), hi = 0.5;
+  // the rest state: the first m where the balance q turns non-negative.  Below the
+  // zero-strain state m0 the strain and the angle are negative and q < 0 too, so the
+  // bracket can start below m0 without finding it first.
+  double lo = 1e-6, hi = 0.5;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
@@ -154,9 +157,12 @@ __global__ void __launch_bounds__(kLanes) spam_solve_kernel(SynthArgs a, const d
   spam_point(a, l0, 0.5, &e, &G);
   const bool slack = target >= e;
   double lo = 0.5, hi = 0.5;
-  if (!slack) {
+  if (!slack && target <= 0.0) {
     lo = zero_strain_m(a, l0);
-    for (int it = 0; it < 200 && target > 0.0; ++it) {
+  } else if (!slack) {
+    // below m0 the strain is negative, below the target too: no need to find m0 first
+    lo = 1e-6;
+    for (int it = 0; it < 200; ++it) {
       const double mid = 0.5 * (lo + hi);
       if (mid <= lo || mid >= hi) break;
       spam_point(a, l0, mid, &e, &G);
