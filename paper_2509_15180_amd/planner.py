@@ -95,15 +95,24 @@ def se2_distances(tips, b) -> np.ndarray:
 
 
 def design_instances(prob: Problem, designs) -> W.Workload:
-    """One robot per design (n, spams) in the problem's environment."""
-    items = []
-    for n, spams in designs:
-        items.append(dict(n=int(n), d=(prob.link_len, prob.tube_radius, prob.body_pressure,
-                                       0.0, 0.0, 0.0),
-                          spam=np.asarray(spams, np.float64).reshape(-1, 4),
-                          kind=np.asarray(prob.kinds, np.int32),
-                          obs=np.asarray(prob.obstacles, np.float64).reshape(-1, 4)))
-    return W.pack(items, "plan")
+    """One robot per design (n, spams) in the problem's environment; every robot refers to
+    the same obstacle rows."""
+    B = len(designs)
+    n = np.fromiter((d[0] for d in designs), np.int32, B)
+    cnt = np.fromiter((len(d[1]) for d in designs), np.int32, B)
+    so = np.zeros(B, np.int32)
+    if B:
+        so[1:] = np.cumsum(cnt)[:-1]
+    spam = np.array([row for _, sp in designs for row in sp], np.float64).reshape(-1, 4)
+    K = len(prob.kinds)
+    inst_i = np.column_stack([n, so, cnt, np.zeros(B, np.int32),
+                              np.full(B, K, np.int32)]).astype(np.int32)
+    inst_d = np.tile(np.array([prob.link_len, prob.tube_radius, prob.body_pressure, 0.0, 0.0,
+                               0.0]), (B, 1))
+    return W.Workload("plan", inst_i, inst_d, np.ascontiguousarray(spam),
+                      np.ascontiguousarray(prob.kinds, np.int32),
+                      np.ascontiguousarray(np.asarray(prob.obstacles, np.float64).reshape(-1, 4)),
+                      np.zeros((B, 2)), {})
 
 
 class GpuSimulator:

@@ -214,21 +214,35 @@ def _stream_ptr(stream):
     return int(stream.cuda_stream)  # torch.cuda.Stream
 
 
+def _struct_dtype(S):
+    """A numpy dtype laid out like the ctypes Structure S (field offsets and size)."""
+    fmt = {C.c_int32: "<i4", C.c_double: "<f8"}
+    return np.dtype({"names": [f for f, _ in S._fields_],
+                     "formats": [fmt[t] for _, t in S._fields_],
+                     "offsets": [getattr(S, f).offset for f, _ in S._fields_],
+                     "itemsize": C.sizeof(S)})
+
+
 def _pack(work):
+    """The Workload's arrays as the C structs (numpy buffers viewed as ctypes arrays; a
+    zero count keeps one zeroed element so that every pointer is valid)."""
     B = work.n_inst
-    inst = (Instance * B)()
-    for b in range(B):
-        n, so, sc, oo, oc = (int(v) for v in work.inst_i[b])
-        d = work.inst_d[b]
-        inst[b] = Instance(n, so, sc, oo, oc, 0, *(float(x) for x in d))
+    ia = np.zeros(B, _struct_dtype(Instance))
+    for k, f in enumerate(("n_links", "spam_offset", "spam_count", "obs_offset", "obs_count")):
+        ia[f] = work.inst_i[:, k]
+    for k, f in enumerate(("link_len", "tube_radius", "body_pressure", "base_x", "base_y",
+                           "base_heading")):
+        ia[f] = work.inst_d[:, k]
+    inst = (Instance * B).from_buffer(ia) if B else (Instance * 0)()
     ns, no = len(work.spam), len(work.obs_kind)
-    spams = (Spam * max(1, ns))()
-    for i in range(ns):
-        spams[i] = Spam(*(float(x) for x in work.spam[i]))
-    obs = (Obstacle * max(1, no))()
-    for i in range(no):
-        o = work.obs_d[i]
-        obs[i] = Obstacle(int(work.obs_kind[i]), 0, *(float(x) for x in o))
+    sa = np.zeros((max(1, ns), 4))
+    sa[:ns] = work.spam
+    spams = (Spam * max(1, ns)).from_buffer(sa)
+    oa = np.zeros(max(1, no), _struct_dtype(Obstacle))
+    oa["kind"][:no] = work.obs_kind
+    for k, f in enumerate(("cx", "cy", "a", "b")):
+        oa[f][:no] = work.obs_d[:, k]
+    obs = (Obstacle * max(1, no)).from_buffer(oa)
     return inst, B, spams, ns, obs, no
 
 
