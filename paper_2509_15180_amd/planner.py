@@ -87,12 +87,6 @@ def se2_distance(a, b) -> float:
     return 1000.0 * dp + math.degrees(abs(dpsi))
 
 
-def se2_distances(tips, b) -> np.ndarray:
-    """se2_distance from each row of tips [N][3] to the pose b."""
-    dp = np.hypot(tips[:, 0] - b[0], tips[:, 1] - b[1])
-    dpsi = (tips[:, 2] - b[2] + math.pi) % (2.0 * math.pi) - math.pi
-    return 1000.0 * dp + np.degrees(np.abs(dpsi))
-
 
 def design_instances(prob: Problem, designs) -> W.Workload:
     """One robot per design (n, spams) in the problem's environment; every robot refers to
@@ -260,26 +254,43 @@ class BatchedSST:
         near_e = (cKDTree(self._tip[act, :2]).query_ball_point(ctip[:, :2], reach)
                   if len(act) else [[] for _ in children])
         near_c = cKDTree(ctip[:, :2]).query_ball_point(ctip[:, :2], reach)
-        alive = np.ones(len(act), bool)       # existing active nodes not yet deactivated
-        node_of = np.full(len(children), -1)  # tree index of each inserted child, while active
-        for q in sorted(range(len(children)), key=lambda q: (ccost[q], q)):
-            e = np.asarray(near_e[q], np.int64)
-            e = e[alive[e]]
-            e = e[se2_distances(self._tip[act[e]], ctip[q]) <= r]
-            c = np.asarray(near_c[q], np.int64)
-            c = c[node_of[c] >= 0]
-            c = c[se2_distances(ctip[c], ctip[q]) <= r]
-            if np.any(self._cost[act[e]] <= ccost[q]) or np.any(ccost[c] <= ccost[q]):
+        within_e = self._within(near_e, ctip, self._tip[act], r)
+        within_c = self._within(near_c, ctip, ctip, r)
+        cost_e = self._cost[act].tolist()
+        cost_c = ccost.tolist()
+        alive = [True] * len(act)       # existing active nodes not yet deactivated
+        node_of = [-1] * len(children)  # tree index of each inserted child, while active
+        for q in sorted(range(len(children)), key=lambda q: (cost_c[q], q)):
+            e = [k for k in within_e[q] if alive[k]]
+            c = [k for k in within_c[q] if node_of[k] >= 0]
+            if any(cost_e[k] <= cost_c[q] for k in e) or any(cost_c[k] <= cost_c[q] for k in c):
                 continue
-            for k in act[e]:
-                self._deactivate(int(k))
-            alive[e] = False
-            for k in node_of[c]:
-                self._deactivate(int(k))
-            node_of[c] = -1
+            for k in e:
+                self._deactivate(int(act[k]))
+                alive[k] = False
+            for k in c:
+                self._deactivate(node_of[k])
+                node_of[k] = -1
             node_of[q] = self._add(children[q])
-            added.append(int(node_of[q]))
+            added.append(node_of[q])
         return added
+
+    @staticmethod
+    def _within(cands, ctip, tips, r):
+        """Per child q, the candidates of cands[q] within r of it in the metric (one
+        vectorised evaluation over all candidate pairs)."""
+        sizes = [len(c) for c in cands]
+        if not sum(sizes):
+            return [[] for _ in cands]
+        q = np.repeat(np.arange(len(cands)), sizes)
+        k = np.fromiter((v for c in cands for v in c), np.int64, sum(sizes))
+        a, b = ctip[q], tips[k]
+        dpsi = (b[:, 2] - a[:, 2] + math.pi) % (2.0 * math.pi) - math.pi
+        ok = 1000.0 * np.hypot(b[:, 0] - a[:, 0], b[:, 1] - a[:, 1]) + np.degrees(np.abs(dpsi)) <= r
+        out = [[] for _ in cands]
+        for qq, kk in zip(q[ok].tolist(), k[ok].tolist()):
+            out[qq].append(kk)
+        return out
 
     def iterate(self):
         exp = self.select()
