@@ -210,3 +210,40 @@ def test_started_robots_continue_the_rollout_bitwise():
         assert L.vine_server_submit_from(soft.h, 1, C.byref(inst[0]), 1, spams, ns, obs, no,
                                          C.byref(c), th.ctypes.data_as(C.POINTER(C.c_double))) \
             == V.VINE_ESTATE
+
+
+def test_256_full_size_requests_in_the_mix_equal_one_batch():
+    """256 requests of the serving stream at full size (16-512 links among 0-128 obstacles,
+    1-8 environment samples each) streamed through the server: every robot's final joint
+    angles and tip bitwise those of one batch rollout of all of them (robots never
+    interact, so this is each robot run alone), every request's worst status that of its
+    robots there, and the joint-update count exact."""
+    import torch
+
+    from paper_2509_15180_amd import vinesim as V
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    reqs = W.config5_requests(256, s_max=8)
+    assert max(int(r.work.inst_i[:, 0].max()) for r in reqs) > 480
+    assert max(int(r.work.inst_i[:, 4].max()) for r in reqs) > 120
+    with V.VineServer(slots=2048, max_links=512, max_obstacles=128, max_spams=8) as srv:
+        done, rounds, peak = _drive(srv, reqs, per_round=16)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["queued"] == 0 and st["active"] == 0
+        assert st["joint_updates"] == sum(r.work.joint_updates() for r in reqs)
+        items = [r.work.instance(k) for r in reqs for k in range(r.work.n_inst)]
+        batch = W.pack(items, "all robots of the stream")
+        out = _alone(batch, stream)
+        b = 0
+        for r in reqs:
+            worst = 0
+            for k in range(r.work.n_inst):
+                n = int(r.work.inst_i[k, 0])
+                tip, th = srv.result(r.rid, k)
+                assert np.array_equal(th, out["theta"][b, :n]), (r.rid, k)
+                assert np.array_equal(tip, out["tip"][b, n - 1]), (r.rid, k)
+                worst = max(worst, int(out["status"][b, :n].max()))
+                b += 1
+            assert done[r.rid] == worst, r.rid
+        print(f"256 full-size requests, {b} robots: all bitwise equal to one batch; "
+              f"{rounds} rounds, worst statuses {sorted(set(done.values()))}", flush=True)
