@@ -7,8 +7,8 @@ selects B nodes to expand, lowest estimated total cost first, samples for each a
 or leave them passive -- and simulates all B children at once.  The children are pruned
 against the tree within a radius r of the SE(2) metric, keeping the cheapest state of
 each neighbourhood (the sparsity SST* maintains), and r decays on the schedule of Alg. 2.
-The search stops when a node's tip reaches the goal region; the design is the chain of
-actions from the root.
+The search stops when a node's tip reaches the goal region (the command line can keep
+searching for a cheaper design); the design is the chain of actions from the root.
 
 Readings (the paper leaves these open):
 
@@ -30,9 +30,9 @@ Readings (the paper leaves these open):
   state's SE(2) dimensions) and l = 2 (the action's actuation dimensions: side x
   pressure, and T), which the paper does not define.
 
-The simulator is a function designs -> (tip poses, worst statuses); ``GpuSimulator`` is
-the HIP path (libvinesim's server).  Run ``python -m paper_2509_15180_amd.planner`` for one search as a JSON
-line.
+The simulator is a function (designs, starting joint angles) -> (tip poses, worst step
+statuses, final joint angles); ``GpuSimulator`` is the HIP path (libvinesim's server).
+Run ``python -m paper_2509_15180_amd.planner`` for one search as a JSON line.
 """
 from __future__ import annotations
 
@@ -116,7 +116,7 @@ class GpuSimulator:
     starting from the joint angles in starts (None: every design from zero).  ``clock``
     accumulates the seconds spent queueing, running and reading back."""
 
-    def __init__(self, prob: Problem, batch: int, params=None):
+    def __init__(self, prob: Problem, batch: int, params=None, limit_s: float = 600.0):
         import torch
 
         from . import vinesim as V
@@ -127,6 +127,7 @@ class GpuSimulator:
                                 max_obstacles=max(1, len(prob.kinds)), max_spams=max_spams,
                                 params=params)
         self.next_id = 0
+        self.limit_s = limit_s  # per batch: raise rather than wait for ever
         self.clock = {"queue": 0.0, "run": 0.0, "read": 0.0}
 
     def __call__(self, designs, starts=None):
@@ -142,6 +143,8 @@ class GpuSimulator:
             for rid, st in self.srv.poll(cap=m):
                 status[rid - first] = st
                 left -= 1
+            if left and time.perf_counter() - t1 > self.limit_s:
+                raise RuntimeError(f"{left} of {m} designs not done after {self.limit_s} s")
         t2 = time.perf_counter()
         tips, thetas = np.zeros((m, 3)), []
         for q in range(m):
