@@ -1915,6 +1915,7 @@ struct vine_server {
     hipEvent_t ev_out = nullptr;       // results copied out
     int stream = 0;                    // its lane: copies in, launch, copies out
     int state = 0;                     // 1 running, 2 being read back
+    int waves = 2;                     // per robot
   };
   std::deque<Robot> queue;
   std::vector<Robot> live;  // by slot
@@ -1924,6 +1925,9 @@ struct vine_server {
   std::unordered_map<int64_t, Request> reqs;
   std::deque<int64_t> completed;
   int64_t joint_updates = 0, n_completed = 0, resident = 0, reading = 0;
+  // waves of the resident robots, and the waves the device holds at two per SIMD (what
+  // the two- and four-wave kernels of the classes up to 256 links fit in registers)
+  int64_t resident_waves = 0, wave_slots = 0;
   hipStream_t pool[kStreams] = {};
   bool lane_busy[kStreams] = {};
   // pinned staging at the pools' offsets: inputs, launch orders, results
@@ -2069,13 +2073,17 @@ int launch_group(vine_server* s, int lane, std::vector<int>& adm) {
   if (resumed) A(vs::launch_slot_start(D, s->stage, (int)g.order_off, g.count, sa));
   D.launch_first = (int)g.order_off;
   D.launch_count = g.count;
-  A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], 2, sa));
+  // four waves per robot (the same results, each robot's steps faster) while every
+  // resident robot keeps a wave slot; two once the device fills up
+  g.waves = link_class(nmax) < 3 && s->resident_waves + 4LL * g.count <= s->wave_slots ? 4 : 2;
+  A(vs::launch_rollout(kparams(h->prm), D, nmax, kClassLinks[link_class(nmax)], g.waves, sa));
   hipEvent_t ev = nullptr;
   A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   A(hipEventRecord(ev, sa));
   g.ev_run.push_back(ev);
   g.state = 1;
   s->resident += g.count;
+  s->resident_waves += (int64_t)g.waves * g.count;
   s->lane_busy[lane] = true;
   s->groups.push_back(std::move(g));
   if (e != hipSuccess) return sfail(s, VINE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
@@ -2219,6 +2227,12 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
                  std::string("server allocation: ") + hipGetErrorString(e));
   }
   s->hbm_bytes = kRowBytes * R + kObsBytes * Ko + kSlotBytes * (int64_t)slots;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      s->wave_slots = 8LL * cus;  // four SIMDs per compute unit, two waves each
+  }
   *out = s;
   return VINE_OK;
 }
@@ -2360,6 +2374,7 @@ int32_t vine_server_tick(vine_server* s) {
     }
     s->order_ranges.give(g.order_off, g.count);
     s->resident -= g.count;
+    s->resident_waves -= (int64_t)g.waves * g.count;
     s->reading -= g.count;
     s->lane_busy[g.stream] = false;
     drop_group_events(g);
