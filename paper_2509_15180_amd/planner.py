@@ -382,6 +382,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     sim = GpuSimulator(prob, args.batch)
     pl = BatchedSST(prob, sim, args.batch, seed=args.seed)
+    setup_s = time.perf_counter() - t0  # device set-up, the server and the root
     it_times, solve_s, first_cost, after = [], None, None, 0
     while pl.i <= args.iters and (pl.solution < 0 or after < args.refine):
         a = time.perf_counter()
@@ -395,7 +396,7 @@ def main(argv=None):
                 after += 1
     sol = pl.solution
     rec = {"environment": "synthetic maze", "iterations": pl.i - 1, "batch": args.batch,
-           "nodes": len(pl.nodes), "solved": sol >= 0, "solve_s": solve_s,
+           "nodes": len(pl.nodes), "solved": sol >= 0, "setup_s": setup_s, "solve_s": solve_s,
            "s_per_iteration": float(np.mean(it_times)) if it_times else None,
            "growth_steps": pl.grown_links, "wall_s": time.perf_counter() - t0,
            "radius_mm": pl.r, "rejected_nonconverged": pl.rejected_status,
