@@ -249,6 +249,9 @@ def main():
     ap.add_argument("--drain", type=float, default=40.0,
                     help="serve: seconds to keep ticking after the last arrival")
     ap.add_argument("--slots", type=int, default=4096, help="serve: resident robots")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="serve: hardware queues of the process (GPU_MAX_HW_QUEUES, set before "
+                         "HIP starts; the server runs one lane per queue)")
     ap.add_argument("--batch", type=int, default=0, help="robots (default: the workload's)")
     ap.add_argument("--per-instance", type=int, default=8, help="robots in the per-instance sample")
     ap.add_argument("--cpu-robots", type=int, default=48, help="robots in the CPU-oracle sample")
@@ -273,6 +276,8 @@ def main():
               f"independent, so several GPUs would each run their own share; not measured here.",
               flush=True)
         sys.exit(2)
+    if args.workload == "serve":  # before HIP starts
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(args.hw_queues, 32)))
 
     import torch
 
@@ -569,7 +574,9 @@ def serve(args, torch, V, W):
         "config": {"workload": "request stream: Poisson arrivals, designs of 16-512 links and "
                                "0-128 obstacles on 1-64 jittered environment samples; "
                                f"{args.slots} slots, {args.hbm_mb:.0f} MB of robot pools; "
-                               f"one group of one chain-length class per idle lane (4 lanes), grown to full length",
+                               "one group of one chain-length class per idle lane "
+                               f"({os.environ.get('GPU_MAX_HW_QUEUES')} lanes, one per hardware "
+                               "queue), grown to full length",
                    "warmup_s": args.warm, "measured_s": args.duration},
         "serving": {"highest_rate_with_bounded_p99": best["rate_per_s"], "runs": runs},
         "roofline": None, "cpu_baseline": None,

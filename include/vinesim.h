@@ -472,8 +472,8 @@ int32_t vine_sim_trace_read(const vine_sim* h, double* dst, int32_t capacity);
  * vine_server_tick never waits for the device.  It reads back the groups whose launch
  * has finished (their results are copied out asynchronously and handed over on a later
  * call, their memory freed then) and starts a group on each idle lane.  A lane is one of
- * the server's four streams (HIP's default number of hardware queues per process) and
- * carries one group at a time.  A group takes the chain-length class (up to 64, 128, 256
+ * the server's streams, one per hardware queue of the process (GPU_MAX_HW_QUEUES when it
+ * is set at create, at most 32; HIP's default is 4), and carries one group at a time.  A group takes the chain-length class (up to 64, 128, 256
  * or 512 links) of the oldest queued robot and every queued robot of that class that
  * fits (a free slot and room in both pools), in arrival order; robots of other classes
  * keep their places, and when the oldest robot does not fit nothing overtakes it.  Its

@@ -1889,10 +1889,11 @@ struct vine_server {
   int slots = 0, max_links = 0, max_obs = 0, max_spams = 0;
   int64_t hbm_bytes = 0;
   static constexpr int kMaxTables = 8;
-  // Lanes: streams that each carry at most one group at a time.  HIP gives a process four
-  // hardware queues by default and streams share them in turn, so a fifth stream's launch
-  // would queue behind another stream's running group.
-  static constexpr int kStreams = 4;
+  // Lanes: streams that each carry at most one group at a time, one per hardware queue of
+  // the process (HIP gives four by default, GPU_MAX_HW_QUEUES sets it).  Streams share the
+  // queues in turn, so a stream beyond them would wait behind another stream's group.
+  static constexpr int kMaxLanes = 32;
+  int lanes = 4;
   struct Robot {
     int64_t req = 0;
     int index = 0;  // within the request
@@ -1928,8 +1929,8 @@ struct vine_server {
   // waves of the resident robots, and the waves the device holds at two per SIMD (what
   // the two- and four-wave kernels of the classes up to 256 links fit in registers)
   int64_t resident_waves = 0, wave_slots = 0;
-  hipStream_t pool[kStreams] = {};
-  bool lane_busy[kStreams] = {};
+  hipStream_t pool[kMaxLanes] = {};
+  bool lane_busy[kMaxLanes] = {};
   // pinned staging at the pools' offsets: inputs, launch orders, results
   int* st_ii = nullptr;
   double* st_dd = nullptr;
@@ -2173,7 +2174,14 @@ int32_t vine_server_create(const vine_params* params, int32_t slots, int64_t hbm
                   hipMemcpyHostToDevice);
   (void)hipFree(h->tables);
   h->tables = t8;
-  for (int k = 0; k < vine_server::kStreams; ++k)
+  {
+    // one lane per hardware queue of the process (HIP's GPU_MAX_HW_QUEUES, default 4): a
+    // stream beyond them would share a queue, and its launches wait behind another lane's
+    const char* q = std::getenv("GPU_MAX_HW_QUEUES");
+    const int hwq = q ? std::atoi(q) : 0;
+    s->lanes = hwq >= 1 ? std::min(hwq, (int)vine_server::kMaxLanes) : 4;
+  }
+  for (int k = 0; k < s->lanes; ++k)
     A(hipStreamCreateWithFlags(&s->pool[k], hipStreamNonBlocking));
   A(halloc(&s->st_ii, B * vs::kII));
   A(halloc(&s->st_dd, B * 6));
@@ -2387,7 +2395,7 @@ int32_t vine_server_tick(vine_server* s) {
   // group's launch order is contiguous there) hold them.  Robots of other classes keep
   // their places.  A lightly loaded server runs each request as soon as it arrives; under
   // load the queue builds up while the lanes are busy and the groups grow.
-  for (int lane = 0; lane < vine_server::kStreams && e == hipSuccess; ++lane) {
+  for (int lane = 0; lane < s->lanes && e == hipSuccess; ++lane) {
     if (s->lane_busy[lane] || s->queue.empty()) continue;
     const int cls = link_class(s->queue.front().inst.n_links);
     const int64_t room = s->order_ranges.largest();
