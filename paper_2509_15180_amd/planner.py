@@ -369,6 +369,43 @@ def maze(seed: int = 0) -> Problem:
                    goal=(1.35, -0.1), goal_radius=0.06)
 
 
+def tube(seed: int = 0) -> Problem:
+    """A channel 18 cm wide from x = 0.15 to 0.85 m, its exit partly closed by a block, and
+    the goal up and to the side of the exit: the body must leave the channel and turn."""
+    rng = np.random.default_rng(seed)
+    obs = [(0.5, 0.12, 0.35, 0.03), (0.5, -0.12, 0.35, 0.03),
+           (1.05, -0.05 + rng.uniform(-0.02, 0.02), 0.03, 0.15)]
+    return Problem(obstacles=np.asarray(obs), kinds=np.ones(3, np.int32),
+                   goal=(1.15, 0.3), goal_radius=0.06)
+
+
+def gap(seed: int = 0) -> Problem:
+    """A wall across the way at x = 0.6 m with one 12 cm gap off the axis, the goal behind
+    it on the other side of the axis."""
+    rng = np.random.default_rng(seed)
+    g = 0.14 + rng.uniform(-0.02, 0.02)
+    lo, hi = g - 0.06, g + 0.06
+    obs = [(0.6, (lo - 0.7) / 2, 0.03, (lo + 0.7) / 2), (0.6, (hi + 0.7) / 2, 0.03, (0.7 - hi) / 2)]
+    return Problem(obstacles=np.asarray(obs), kinds=np.ones(2, np.int32),
+                   goal=(1.1, -0.1), goal_radius=0.06)
+
+
+def pillars(seed: int = 0) -> Problem:
+    """Ten circular pillars (radius 3-6 cm) scattered between x = 0.3 and 1.0 m, none
+    closer than 0.2 m to the base; the goal straight ahead behind them."""
+    rng = np.random.default_rng(seed)
+    obs = []
+    while len(obs) < 10:
+        c = (rng.uniform(0.3, 1.0), rng.uniform(-0.35, 0.35), rng.uniform(0.03, 0.06), 0.0)
+        if all(math.hypot(c[0] - o[0], c[1] - o[1]) > c[2] + o[2] + 0.07 for o in obs):
+            obs.append(c)
+    return Problem(obstacles=np.asarray(obs), kinds=np.zeros(10, np.int32),
+                   goal=(1.25, 0.0), goal_radius=0.06)
+
+
+ENVIRONMENTS = {"maze": maze, "tube": tube, "gap": gap, "pillars": pillars}
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser()
@@ -377,8 +414,9 @@ def main(argv=None):
     ap.add_argument("--refine", type=int, default=0,
                     help="iterations to keep searching for a cheaper design after the first")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--env", choices=sorted(ENVIRONMENTS), default="maze")
     args = ap.parse_args(argv)
-    prob = maze(args.seed)
+    prob = ENVIRONMENTS[args.env](args.seed)
     t0 = time.perf_counter()
     sim = GpuSimulator(prob, args.batch)
     pl = BatchedSST(prob, sim, args.batch, seed=args.seed)
@@ -395,7 +433,7 @@ def main(argv=None):
             else:
                 after += 1
     sol = pl.solution
-    rec = {"environment": "synthetic maze", "iterations": pl.i - 1, "batch": args.batch,
+    rec = {"environment": f"synthetic {args.env}", "iterations": pl.i - 1, "batch": args.batch,
            "nodes": len(pl.nodes), "solved": sol >= 0, "setup_s": setup_s, "solve_s": solve_s,
            "s_per_iteration": float(np.mean(it_times)) if it_times else None,
            "growth_steps": pl.grown_links, "wall_s": time.perf_counter() - t0,
