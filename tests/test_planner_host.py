@@ -142,3 +142,25 @@ def test_pruning_equals_the_rule_over_every_pair():
         assert added == list(range(m0, m0 + len(added)))
         assert [nd.active for nd in pl.nodes] == want_active
         assert list(pl._active[:len(pl.nodes)]) == want_active
+
+
+def _signed_distance(kind, o, x, y):
+    """Distance from (x, y) to a circle (kind 0, radius o[2]) or an axis-aligned rectangle
+    (kind 1, half sides o[2], o[3]); negative inside."""
+    if kind == 0:
+        return math.hypot(x - o[0], y - o[1]) - o[2]
+    dx, dy = abs(x - o[0]) - o[2], abs(y - o[1]) - o[3]
+    return math.hypot(max(dx, 0.0), max(dy, 0.0)) + min(max(dx, dy), 0.0)
+
+
+def test_environments_start_clear_and_their_goals_are_free():
+    """Every synthetic environment leaves the tube of the first links (base at the origin,
+    heading +x) and the goal region free of obstacles, for several seeds."""
+    for name, make in PL.ENVIRONMENTS.items():
+        for seed in range(4):
+            p = make(seed)
+            base = min(_signed_distance(k, o, x, 0.0) for k, o in zip(p.kinds, p.obstacles)
+                       for x in np.linspace(0.0, 0.1, 21))
+            goal = min(_signed_distance(k, o, *p.goal) for k, o in zip(p.kinds, p.obstacles))
+            assert base > p.tube_radius, (name, seed, base)
+            assert goal > p.goal_radius, (name, seed, goal)
