@@ -4,7 +4,7 @@ the search simulates is compared with the oracle robot by robot (tolerances as i
 parity tests, contact sets identical, statuses identical), the server's tips (each child
 started from its parent's joint angles) are bitwise those of one handle rolling the same
 designs out from zero, and with the same seed both searches build the same tree (parents, link counts, actions, which nodes are active) with tips within the tip
-tolerance.
+tolerance.  Two environments: the maze and the field of pillars.
 
 The problem's link is 23 mm: straight passive growth puts tips at multiples of the link
 length, and with 20 mm links two of them lie exactly 60 mm (the initial radius) apart, a
@@ -49,11 +49,12 @@ def _search(prob, sim, batch, seed, iters):
     return pl
 
 
-def test_planner_on_gpu_matches_the_oracle_search():
+@pytest.mark.parametrize("env", ["maze", "pillars"])
+def test_planner_on_gpu_matches_the_oracle_search(env):
     import torch
 
     from paper_2509_15180_amd import vinesim as V
-    prob = PL.maze(0)
+    prob = PL.ENVIRONMENTS[env](0)
     prob.max_links, prob.link_len = 40, 0.023
     import time
     designs, served = [], []
