@@ -80,3 +80,26 @@ def test_synthesis_without_targets_and_repeatable():
     d0, a0 = V.spam_synth(PRESSURES[:3], LENGTHS[::10], [], TOL, L, R, PV)
     d1, a1 = V.spam_synth(PRESSURES[:3], LENGTHS[::10], [0.01, 0.02], TOL, L, R, PV)
     assert d0.shape == (0, 3) and np.array_equal(a0, a1)
+
+
+def test_synthesis_on_another_body_and_grid():
+    """The batch workloads' body (20 mm links, 25 mm radius, 3 kPa), pressures on a
+    geometric set from 1 to 30 kPa and unit lengths of 15-60 mm in 3 mm steps: rest angles
+    within 1e-10 rad of the oracle's, designs the oracle's rule on the GPU's angles bit for
+    bit and the oracle's own designs up to near-ties."""
+    from paper_2509_15180_amd import vinesim as V
+    geo = (0.02, 0.025, 3000.0)
+    P = np.geomspace(1e3, 3e4, 12)
+    Lu = np.arange(15, 61, 3) * 1e-3
+    rng = np.random.default_rng(11)
+    t = rng.uniform(math.radians(0.1), math.radians(8.0), 2048)
+    des, ang = V.spam_synth(P, Lu, t, TOL, *geo)
+    ref_grid = S.angle_grid(P, Lu, *geo)
+    d = np.abs(ang - ref_grid)
+    print(f"second body: max |GPU - oracle| {d.max():.2e} rad over {ang.size} designs "
+          f"({np.degrees(ref_grid.min()):.3f} to {np.degrees(ref_grid.max()):.3f} deg)", flush=True)
+    assert d.max() <= 1e-10
+    assert np.array_equal(des, S.select(ang, P, Lu, t, TOL))
+    ref = S.select(ref_grid, P, Lu, t, TOL)
+    for i in np.nonzero(~np.all(des[:, :2] == ref[:, :2], axis=1))[0]:
+        assert _near_tie(ref_grid, t[i], TOL), i
